@@ -1,0 +1,537 @@
+"""Pins of the FP64 oracle against things other than itself.
+
+Closed forms, library routines reached by a different route (scipy rotations,
+Gauss-Legendre quadrature, numerical Jacobians), brute-force enumeration on
+tiny inputs and central finite differences.  CPU only.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+from scipy.spatial.transform import Rotation
+
+from paper_2512_20943_amd import scenes
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "closed_forms.json")
+Y00 = 0.5 / math.sqrt(math.pi)
+
+
+def hand_scene(means, log_scales, quats, logits, colours, deg=0):
+    """Scene dict from explicit per-Gaussian values (SH DC set so the DC
+    colour is ``colours``)."""
+    n = len(means)
+    ld = scenes.round_up(n)
+    K = (deg + 1) ** 2
+    s = dict(n=n, deg=deg, ld=ld, mean=np.zeros((3, ld), np.float32),
+             log_scale=np.zeros((3, ld), np.float32), quat=np.zeros((4, ld), np.float32),
+             opacity=np.zeros(ld, np.float32), sh=np.zeros((K, 3, ld), np.float32))
+    s["quat"][0, :] = 1.0
+    for i in range(n):
+        s["mean"][:, i] = means[i]
+        s["log_scale"][:, i] = log_scales[i]
+        s["quat"][:, i] = quats[i]
+        s["opacity"][i] = logits[i]
+        s["sh"][0, :, i] = (np.asarray(colours[i]) - 0.5) / Y00
+    return s
+
+
+def axis_cam(W=64, H=64):
+    return scenes.axis_camera(W, H, 4.0)
+
+
+# ---------------------------------------------------------------------------
+# rotation and quaternion algebra
+# ---------------------------------------------------------------------------
+
+def test_rotation_matches_scipy_and_is_orthonormal(oracle_mod):
+    g = np.random.default_rng(1)
+    for _ in range(50):
+        q = g.normal(size=4)
+        R = oracle_mod.quat_to_rot(q)
+        ref = Rotation.from_quat([q[1], q[2], q[3], q[0]]).as_matrix()
+        np.testing.assert_allclose(R, ref, atol=1e-13)
+        np.testing.assert_allclose(R @ R.T, np.eye(3), atol=1e-13)
+        assert abs(np.linalg.det(R) - 1.0) < 1e-13
+
+
+def test_rotation_about_z_is_textbook(oracle_mod):
+    for th in np.linspace(-3, 3, 7):
+        R = oracle_mod.quat_to_rot([math.cos(th / 2), 0, 0, math.sin(th / 2)])
+        ref = np.array([[math.cos(th), -math.sin(th), 0], [math.sin(th), math.cos(th), 0],
+                        [0, 0, 1]])
+        np.testing.assert_allclose(R, ref, atol=1e-14)
+
+
+def test_hamilton_product_composes_rotations(oracle_mod):
+    g = np.random.default_rng(2)
+    for _ in range(50):
+        a, b = g.normal(size=4), g.normal(size=4)
+        ab = oracle_mod.quat_mul(a, b)
+        np.testing.assert_allclose(np.linalg.norm(ab), np.linalg.norm(a) * np.linalg.norm(b),
+                                   rtol=1e-14)
+        Ra = Rotation.from_quat([a[1], a[2], a[3], a[0]])
+        Rb = Rotation.from_quat([b[1], b[2], b[3], b[0]])
+        np.testing.assert_allclose(oracle_mod.quat_to_rot(ab), (Ra * Rb).as_matrix(), atol=1e-13)
+    np.testing.assert_array_equal(oracle_mod.quat_mul([1, 0, 0, 0], [0.3, -0.2, 0.5, 0.1]),
+                                  [0.3, -0.2, 0.5, 0.1])
+
+
+# ---------------------------------------------------------------------------
+# spherical harmonics
+# ---------------------------------------------------------------------------
+
+def _sphere_quadrature(nt=24, nphi=48):
+    x, w = np.polynomial.legendre.leggauss(nt)
+    phi = np.arange(nphi) * 2 * math.pi / nphi
+    pts, wts = [], []
+    for ct, wt in zip(x, w):
+        st = math.sqrt(1 - ct * ct)
+        for p in phi:
+            pts.append((st * math.cos(p), st * math.sin(p), ct))
+            wts.append(wt * 2 * math.pi / nphi)
+    return np.array(pts), np.array(wts)
+
+
+def test_sh_orthonormal_by_quadrature(oracle_mod):
+    pts, wts = _sphere_quadrature()
+    Y = np.array([oracle_mod.sh_basis(3, p) for p in pts])  # (P, 16)
+    G = (Y * wts[:, None]).T @ Y
+    np.testing.assert_allclose(G, np.eye(16), atol=1e-10)
+
+
+def test_sh_addition_theorem(oracle_mod):
+    g = np.random.default_rng(3)
+    for _ in range(20):
+        d = g.normal(size=3)
+        d /= np.linalg.norm(d)
+        Y = oracle_mod.sh_basis(3, d)
+        for l in range(4):
+            s = np.sum(Y[l * l:(l + 1) * (l + 1)] ** 2)
+            assert abs(s - (2 * l + 1) / (4 * math.pi)) < 1e-12
+
+
+def test_degree0_colour_is_view_independent(oracle_mod):
+    sc = scenes.make_scene(200, 5, -1, 1, -4, 0.5, 0)
+    cams = scenes.arc_cameras(4, 4.0, 64, 64)
+    P = oracle_mod.project(sc, cams)
+    expect = 0.5 + Y00 * sc["sh"][0, :, :200].astype(np.float64).T  # (n, 3)
+    for v in range(4):
+        vis = P["flags"][v] & 32 > 0
+        np.testing.assert_allclose(P["rgb"][v][vis], np.maximum(expect[vis], 0), atol=1e-12)
+
+
+# ---------------------------------------------------------------------------
+# projection
+# ---------------------------------------------------------------------------
+
+def test_isotropic_on_axis_covariance_closed_form(oracle_mod):
+    g = np.random.default_rng(4)
+    W = H = 64
+    cams = axis_cam(W, H)
+    f = cams["f"][0, 0]
+    qs = [g.normal(size=4) for _ in range(6)]
+    zs = [0.5, 1.0, 2.0, -1.0, 0.0, 3.0]
+    ls = [-3.0, -2.5, -4.0, -3.5, -2.0, -3.2]
+    sc = hand_scene([(0, 0, z) for z in zs], [(l, l, l) for l in ls], qs, [0.0] * 6,
+                    [(0.5, 0.5, 0.5)] * 6)
+    P = oracle_mod.project(sc, cams)
+    for i, (z, l) in enumerate(zip(zs, ls)):
+        zc = z + 4.0
+        l32 = float(np.float32(l))  # parameters are stored in FP32
+        a = (f * math.exp(l32) / zc) ** 2 + 0.3
+        np.testing.assert_allclose(P["conic"][0, i], [1 / a, 0, 1 / a], rtol=1e-12, atol=1e-15)
+        np.testing.assert_array_equal(P["mean2d"][0, i], [W / 2, H / 2])
+        assert P["radius"][0, i] == math.ceil(3 * math.sqrt(a + math.sqrt(0.1)))
+
+
+def test_conic_equals_inverse_of_numerical_jacobian_covariance(oracle_mod):
+    """J W Sigma W^T J^T reached independently: scipy rotation for Sigma and a
+    central-difference Jacobian of the perspective map for J W."""
+    sc = scenes.make_scene(60, 7, -0.6, 0.6, -3.0, 0.5, 0)
+    cams = scenes.arc_cameras(3, 4.0, 96, 80)
+    P = oracle_mod.project(sc, cams)
+    for v in range(3):
+        R, t = cams["R"][v], cams["t"][v]
+        fx, fy, cx, cy = cams["f"][v]
+
+        def proj(x):
+            xc = R @ x + t
+            return np.array([fx * xc[0] / xc[2] + cx, fy * xc[1] / xc[2] + cy])
+
+        for i in range(60):
+            if not P["flags"][v, i] & 32 or P["flags"][v, i] & 24:
+                continue
+            mu = sc["mean"][:, i].astype(np.float64)
+            q = sc["quat"][:, i].astype(np.float64)
+            S = np.diag(np.exp(sc["log_scale"][:, i].astype(np.float64)))
+            Rq = Rotation.from_quat([q[1], q[2], q[3], q[0]]).as_matrix()
+            Sig = Rq @ S @ S @ Rq.T
+            h = 1e-6
+            Jn = np.stack([(proj(mu + h * e) - proj(mu - h * e)) / (2 * h) for e in np.eye(3)], 1)
+            cov = Jn @ Sig @ Jn.T
+            A, B, C = P["conic"][v, i]
+            got = np.linalg.inv(np.array([[A, B], [B, C]])) - 0.3 * np.eye(2)
+            np.testing.assert_allclose(got, cov, rtol=1e-6, atol=1e-9 * np.abs(cov).max())
+            np.testing.assert_allclose(P["mean2d"][v, i], proj(mu), rtol=1e-12)
+
+
+def test_joint_translation_leaves_projection_unchanged(oracle_mod):
+    sc = scenes.make_scene(100, 8, -1, 1, -3.5, 0.5, 2)
+    cams = scenes.arc_cameras(2, 4.0, 64, 48)
+    s = np.array([0.25, -0.5, 0.125])  # exact binary fractions
+    sc["mean"] = np.round(sc["mean"] * 4096.0).astype(np.float32) / np.float32(4096.0)
+    sc2 = {k: (v.copy() if isinstance(v, np.ndarray) else v) for k, v in sc.items()}
+    sc2["mean"][:, :100] += s[:, None].astype(np.float32)
+    cams2 = dict(cams)
+    cams2["t"] = np.stack([cams["t"][v] - cams["R"][v] @ s for v in range(2)])
+    P1, P2 = oracle_mod.project(sc, cams), oracle_mod.project(sc2, cams2)
+    for k in ("mean2d", "conic", "rgb", "depth"):
+        np.testing.assert_allclose(P1[k], P2[k], rtol=1e-9, atol=1e-9)
+    np.testing.assert_array_equal(P1["flags"], P2["flags"])
+
+
+def test_near_plane_and_degenerate_quaternion_cull(oracle_mod):
+    sc = hand_scene([(0, 0, -3.9), (0, 0, -3.7), (0, 0, 0)], [(-3, -3, -3)] * 3,
+                    [(1, 0, 0, 0), (1, 0, 0, 0), (0, 0, 0, 0)], [0, 0, 0], [(0.5, 0.5, 0.5)] * 3)
+    P = oracle_mod.project(sc, axis_cam())
+    # z = 0.1 <= near, z = 0.3 > near, |q| = 0
+    assert list(P["flags"][0, :3] & 32) == [0, 32, 0]
+    assert list(P["tiles"][0, :3] > 0) == [False, True, False]
+
+
+# ---------------------------------------------------------------------------
+# binning and ordering
+# ---------------------------------------------------------------------------
+
+def test_bin_sort_equals_brute_enumeration(oracle_mod):
+    sc = scenes.make_scene(150, 9, -1, 1, -3.0, 0.6, 0)
+    # equal depths on purpose: duplicate a few means so ties are exercised
+    sc["mean"][:, 10:20] = sc["mean"][:, 0:1]
+    cams = scenes.arc_cameras(3, 4.0, 72, 40)
+    P = oracle_mod.project(sc, cams)
+    L = oracle_mod.bin_sort(P, cams)
+    base, txv, nseg = oracle_mod.segment_bases(cams)
+    inst = []
+    for v in range(3):
+        for i in range(150):
+            if P["tiles"][v, i] <= 0:
+                continue
+            x0, y0, x1, y1 = P["rect"][v, i]
+            for ty in range(y0, y1):
+                for tx in range(x0, x1):
+                    inst.append((int(base[v] + ty * txv[v] + tx), int(P["depth_bits"][v, i]), i))
+    inst.sort()
+    assert L["count"] == len(inst) == int(P["tiles"].sum())
+    np.testing.assert_array_equal(L["keys"], [(s << 32) | d for s, d, _ in inst])
+    np.testing.assert_array_equal(L["vals"], [i for _, _, i in inst])
+    for s in range(nseg):
+        b, e = L["ranges"][s]
+        members = [k for k, it in enumerate(inst) if it[0] == s]
+        if members:
+            assert (b, e) == (members[0], members[-1] + 1)
+        else:
+            assert b == e
+
+
+def test_depth_bits_are_fp32_of_z(oracle_mod):
+    sc = scenes.make_scene(50, 10, -1, 1, -3, 0.5, 0)
+    cams = axis_cam()
+    P = oracle_mod.project(sc, cams)
+    z = sc["mean"][2, :50].astype(np.float64) + 4.0
+    np.testing.assert_array_equal(P["depth_bits"][0], z.astype(np.float32).view(np.uint32))
+
+
+# ---------------------------------------------------------------------------
+# compositing
+# ---------------------------------------------------------------------------
+
+def test_centred_gaussian_composites_to_opacity_times_colour(oracle_mod):
+    cams = axis_cam()
+    for logit, col in [(0.0, (0.2, 0.7, 0.9)), (2.0, (1.0, 0.5, 0.0)), (-3.0, (0.3, 0.3, 0.3))]:
+        sc = hand_scene([(0, 0, 0)], [(-3, -2.5, -3.2)], [(0.9, 0.1, -0.2, 0.3)], [logit], [col])
+        _, _, img = oracle_mod.forward(sc, cams)
+        a = 1 / (1 + math.exp(-logit))
+        np.testing.assert_allclose(img["image"][0, :, 32, 32], np.array(col) * a, rtol=1e-6)
+        assert img["n_contrib"][0, 32, 32] == 1
+        assert abs(img["final_T"][0, 32, 32] - (1 - a)) < 1e-6
+
+
+def test_two_gaussians_on_a_ray_and_ordering(oracle_mod):
+    gold = json.load(open(GOLDEN))["two_on_a_ray"]
+    cams = axis_cam()
+    lf, lb = gold["front_logit"], gold["back_logit"]
+    red, green = (1.0, 0.0, 0.0), (0.0, 1.0, 0.0)
+    sc = hand_scene([(0, 0, 0), (0, 0, 1)], [(-3, -3, -3)] * 2, [(1, 0, 0, 0)] * 2, [lf, lb],
+                    [red, green])
+    _, _, img = oracle_mod.forward(sc, cams)
+    # logits are stored in FP32, so sigmoid(logit) is exact only to ~1e-8
+    np.testing.assert_allclose(img["image"][0, :, 32, 32], gold["expected_pixel"], rtol=0,
+                               atol=1e-7)
+    assert abs(img["final_T"][0, 32, 32] - gold["expected_final_T"]) < 1e-7
+    # swap depths: the green one is now in front
+    sc2 = hand_scene([(0, 0, 1), (0, 0, 0)], [(-3, -3, -3)] * 2, [(1, 0, 0, 0)] * 2, [lf, lb],
+                     [red, green])
+    _, _, img2 = oracle_mod.forward(sc2, cams)
+    a1, a2 = 0.5, 0.75
+    np.testing.assert_allclose(img2["image"][0, :, 32, 32], [(1 - a2) * a1, a2, 0], rtol=0,
+                               atol=1e-7)
+    # equal depths: id order decides (id 0 in front)
+    sc3 = hand_scene([(0, 0, 0), (0, 0, 0)], [(-3, -3, -3)] * 2, [(1, 0, 0, 0)] * 2, [lf, lb],
+                     [red, green])
+    _, L3, img3 = oracle_mod.forward(sc3, cams)
+    np.testing.assert_allclose(img3["image"][0, :, 32, 32], gold["expected_pixel"], rtol=0,
+                               atol=1e-7)
+    s = L3["ranges"][(32 // 16) * 4 + 32 // 16]
+    assert list(L3["vals"][s[0]:s[1]]) == [0, 1]
+
+
+def test_alpha_stack_stops_after_five(oracle_mod):
+    gold = json.load(open(GOLDEN))["alpha_stack"]
+    n = gold["n_layers"]
+    sc = hand_scene([(0, 0, 0.1 * k) for k in range(n)], [(-3, -3, -3)] * n, [(1, 0, 0, 0)] * n,
+                    [gold["opacity_logit"]] * n, gold["colours"])
+    _, _, img = oracle_mod.forward(sc, axis_cam())
+    assert img["n_contrib"][0, 32, 32] == gold["expected_n_contrib"]
+    assert abs(img["final_T"][0, 32, 32] - gold["expected_final_T"]) < 1e-9
+    np.testing.assert_allclose(img["image"][0, :, 32, 32], gold["expected_pixel"], rtol=0,
+                               atol=1e-7)
+
+
+def test_product_of_one_minus_alpha_is_final_T(oracle_mod):
+    sc = scenes.make_scene(400, 11, -1, 1, -3.2, 0.5, 1)
+    cams = scenes.axis_camera(48, 40)
+    P, L, img = oracle_mod.forward(sc, cams)
+    base, txv, _ = oracle_mod.segment_bases(cams)
+    rng = np.random.default_rng(0)
+    for _ in range(60):
+        x, y = int(rng.integers(48)), int(rng.integers(40))
+        s = int(base[0] + (y // 16) * txv[0] + x // 16)
+        b, e = L["ranges"][s]
+        prod, nc = 1.0, img["n_contrib"][0, y, x]
+        for j in range(b, b + nc):
+            gid = L["vals"][j]
+            dx, dy = P["mean2d"][0, gid] - (x, y)
+            A, B, C = P["conic"][0, gid]
+            pw = -0.5 * (A * dx * dx + C * dy * dy) - B * dx * dy
+            al = min(0.99, P["alpha_hat"][0, gid] * math.exp(pw))
+            if pw > 0 or al < 1 / 255:
+                continue
+            prod *= 1 - al
+        assert abs(prod - img["final_T"][0, y, x]) <= 1e-12
+
+
+def test_brute_force_per_pixel_equals_tiled(oracle_mod):
+    sc = scenes.make_scene(300, 12, -1, 1, -3.4, 0.6, 2)
+    sc["mean"][:, 40:60] = sc["mean"][:, 0:1]  # ties in depth
+    for cams in (scenes.axis_camera(56, 40), scenes.arc_cameras(2, 3.5, 40, 56)):
+        P, L, img = oracle_mod.forward(sc, cams)
+        for v in range(P["V"]):
+            bf = oracle_mod.render_brute(P, cams, v)
+            np.testing.assert_array_equal(bf["image"], img["image"][v])
+            np.testing.assert_array_equal(bf["final_T"], img["final_T"][v])
+            np.testing.assert_array_equal(bf["n_contrib"], img["n_contrib"][v])
+
+
+def test_background_fills_transmittance(oracle_mod):
+    sc = scenes.make_scene(100, 13, -1, 1, -3.5, 0.5, 0)
+    cams = axis_cam(32, 32)
+    P, L, img0 = oracle_mod.forward(sc, cams)
+    bg = np.array([0.25, 0.5, 1.0])
+    img1 = oracle_mod.render_fwd(P, L, cams, bg)
+    np.testing.assert_allclose(img1["image"][0] - img0["image"][0],
+                               img0["final_T"][0][None] * bg[:, None, None], atol=1e-14)
+
+
+# ---------------------------------------------------------------------------
+# loss, optimizer
+# ---------------------------------------------------------------------------
+
+def test_l1_closed_form(oracle_mod):
+    img = np.array([[0.5, 0.25, 1.0, 0.0]])
+    tgt = np.array([[0.25, 0.25, 0.0, 0.5]])
+    loss, g = oracle_mod.l1(img, tgt)
+    assert loss == (0.25 + 0 + 1 + 0.5) / 4
+    np.testing.assert_array_equal(g, [[0.25, 0.0, 0.25, -0.25]])
+
+
+def test_first_adam_step_closed_form(oracle_mod):
+    gold = json.load(open(GOLDEN))["first_adam_step"]
+    th = np.array([1.0, -2.0, 0.5, 3.0])
+    g = np.array([0.3, -1e-3, 2.0, 0.0])
+    th1, m1, v1 = oracle_mod.adam(th, g, np.zeros(4), np.zeros(4), 1, lr=gold["lr"],
+                                  eps=gold["eps"])
+    np.testing.assert_allclose(th1, th - gold["lr"] * g / (np.abs(g) + gold["eps"]), rtol=1e-12,
+                               atol=1e-15)
+
+
+# ---------------------------------------------------------------------------
+# frame update
+# ---------------------------------------------------------------------------
+
+def test_apply_identities(oracle_mod):
+    n = 500
+    gw = gh = scenes.grid_side(n)
+    sc = scenes.make_scene(n, 14, -1, 1, -4, 0.5, 0)
+    d = scenes.make_delta(n, gw, gh, 15)
+    mask = scenes.prune_mask(d, n, 0.3)
+    out = oracle_mod.apply(sc, d, mask, gw, gh)
+    m = mask.reshape(-1)[:n].astype(bool)
+    # masked texels: bit-exact pass-through
+    for k in ("mean", "quat", "opacity"):
+        np.testing.assert_array_equal(out[k][..., :n][..., ~m], sc[k][..., :n][..., ~m])
+    # additive channels: one correctly rounded FP32 add
+    df = d.reshape(8, -1)
+    np.testing.assert_array_equal(out["mean"][:, :n][:, m], (sc["mean"][:, :n] + df[:3, :n])[:, m])
+    np.testing.assert_array_equal(out["opacity"][:n][m], (sc["opacity"][:n] + df[7, :n])[m])
+    # quaternion: R(dq (x) q) = R(dq) R(q)
+    for i in np.flatnonzero(m)[:40]:
+        dq, q = df[3:7, i].astype(np.float64), sc["quat"][:, i].astype(np.float64)
+        Rd = Rotation.from_quat([dq[1], dq[2], dq[3], dq[0]])
+        Rq = Rotation.from_quat([q[1], q[2], q[3], q[0]])
+        np.testing.assert_allclose(oracle_mod.quat_to_rot(out["quat"][:, i]),
+                                   (Rd * Rq).as_matrix(), atol=1e-6)
+    # identity update leaves everything unchanged
+    ident = np.zeros_like(d)
+    ident[3] = 1.0
+    out2 = oracle_mod.apply(sc, ident, np.ones_like(mask), gw, gh)
+    for k in ("mean", "quat", "opacity"):
+        np.testing.assert_array_equal(out2[k][..., :n], sc[k][..., :n])
+
+
+def test_cumulative_delta_equals_sequential_in_fp64(oracle_mod):
+    """Eq. (12): GS_t = GC + sum of the transmitted updates; for the additive
+    channels the cumulative image gives the same frame as applying the
+    increments one after another (checked before FP32 storage rounding)."""
+    n, gw = 64, 8
+    g = np.random.default_rng(16)
+    mu = g.normal(size=(3, n))
+    incs = [g.normal(scale=0.01, size=(3, n)) for _ in range(5)]
+    seq = mu.copy()
+    for d in incs:
+        seq = seq + d
+    cum = mu + sum(incs)
+    np.testing.assert_allclose(seq, cum, rtol=0, atol=1e-14)
+    # quaternion channel: composing increments = one composed delta (rotation)
+    q = g.normal(size=4)
+    dqs = [np.array([1, 0, 0, 0]) + g.normal(scale=0.01, size=4) for _ in range(4)]
+    a = q.copy()
+    for dq in dqs:
+        a = oracle_mod.quat_mul(dq, a)
+    D = np.array([1.0, 0, 0, 0])
+    for dq in dqs:
+        D = oracle_mod.quat_mul(dq, D)
+    np.testing.assert_allclose(oracle_mod.quat_mul(D, q), a, atol=1e-14)
+    assert gw * gw >= n
+
+
+# ---------------------------------------------------------------------------
+# finite differences of the whole forward (FP64)
+# ---------------------------------------------------------------------------
+
+def _fd_check(oracle_mod, sc, cams, target, analytic, names, n_samples, seed, rtol=1e-5):
+    rng = np.random.default_rng(seed)
+    base = {k: sc[k].astype(np.float64) for k in names}
+    checked = 0
+    gmax = max(np.abs(analytic[k]).max() for k in names)
+    for _ in range(n_samples):
+        k = names[int(rng.integers(len(names)))]
+        idx = tuple(int(rng.integers(s)) for s in base[k].shape[:-1]) + (int(rng.integers(sc["n"])),)
+        x = base[k][idx]
+        h = 1e-5 * max(1.0, abs(x))
+        vals, sigs = [], []
+        for sgn in (-1, 0, 1):
+            ov = {kk: vv.copy() for kk, vv in base.items()}
+            ov[k][idx] = x + sgn * h
+            l, s = oracle_mod.forward_loss(sc, cams, target, overrides=ov)
+            vals.append(l)
+            sigs.append(s)
+        if not (sigs[0] == sigs[1] == sigs[2]):
+            continue
+        fd = (vals[2] - vals[0]) / (2 * h)
+        an = analytic[k][idx]
+        assert abs(fd - an) <= rtol * abs(an) + 1e-7 * gmax, (k, idx, fd, an)
+        checked += 1
+    return checked
+
+
+@pytest.mark.parametrize("deg", [0, 3])
+def test_analytic_gradient_matches_central_differences(oracle_mod, deg):
+    sc = scenes.make_scene(40, 20 + deg, -0.5, 0.5, -2.6, 0.3, deg)
+    cams = scenes.arc_cameras(2, 3.0, 40, 32, azimuth_deg=60.0)
+    tgt_scene = scenes.jitter_means(sc, 0.02, 99)
+    _, _, timg = oracle_mod.forward(tgt_scene, cams)
+    target = timg["image"]
+    P, L, img = oracle_mod.forward(sc, cams)
+    loss, gI = oracle_mod.l1(img["image"], target)
+    lf, _ = oracle_mod.forward_loss(sc, cams, target)
+    assert abs(lf - loss) < 1e-13
+    _, grads = oracle_mod.backward(sc, cams, P, L, gI)
+    names = ["mean", "log_scale", "quat", "opacity", "sh"]
+    checked = _fd_check(oracle_mod, sc, cams, target, grads, names, 120, deg)
+    assert checked >= 60
+
+
+def test_single_gaussian_gradient_closed_forms(oracle_mod):
+    cams = axis_cam(32, 32)
+    logit, col = 0.4, (0.3, 0.6, 0.9)
+    sc = hand_scene([(0, 0, 0)], [(-3, -3, -3)], [(1, 0, 0, 0)], [logit], [col])
+    P, L, img = oracle_mod.forward(sc, cams)
+    gI = np.zeros_like(img["image"])
+    gI[0, 1, 16, 16] = 1.0  # d(green channel of the centre pixel)
+    _, g = oracle_mod.backward(sc, cams, P, L, gI)
+    a = 1 / (1 + math.exp(-float(sc["opacity"][0])))  # FP32-stored logit and colour
+    green = 0.5 + Y00 * float(sc["sh"][0, 1, 0])
+    assert abs(g["opacity"][0] - green * a * (1 - a)) < 1e-12
+    assert abs(g["sh"][0, 1, 0] - Y00 * a) < 1e-12
+    assert g["sh"][0, 0, 0] == 0.0 and g["sh"][0, 2, 0] == 0.0
+
+
+def test_apply_backward_matches_central_differences(oracle_mod):
+    n = 40
+    gw = gh = scenes.grid_side(n)
+    sc = scenes.make_scene(n, 30, -0.5, 0.5, -2.6, 0.3, 1)
+    cams = scenes.arc_cameras(2, 3.0, 40, 32, azimuth_deg=60.0)
+    d = scenes.make_delta(n, gw, gh, 31, 0.01, 0.02, 0.1)
+    mask = scenes.prune_mask(d, n, 0.25)
+    tgt = oracle_mod.forward(scenes.jitter_means(sc, 0.02, 32), cams)[2]["image"]
+    frame = oracle_mod.apply(sc, d, mask, gw, gh)
+    P, L, img = oracle_mod.forward(frame, cams)
+    _, gI = oracle_mod.l1(img["image"], tgt)
+    _, gf = oracle_mod.backward(frame, cams, P, L, gI)
+    gd = oracle_mod.apply_bwd(sc, mask, gw, gh, gf)
+    assert np.all(gd.reshape(8, -1)[:, n:] == 0)
+    mflat = mask.reshape(-1)
+    assert np.all(gd.reshape(8, -1)[:, :n][:, mflat[:n] == 0] == 0)
+    dd = d.astype(np.float64).reshape(8, -1)
+
+    def frame64(dv):
+        mu = sc["mean"].astype(np.float64).copy()
+        q = sc["quat"].astype(np.float64).copy()
+        o = sc["opacity"].astype(np.float64).copy()
+        for i in range(n):
+            if mflat[i]:
+                mu[:, i] += dv[:3, i]
+                q[:, i] = oracle_mod.quat_mul(dv[3:7, i], q[:, i])
+                o[i] += dv[7, i]
+        return dict(mean=mu, quat=q, opacity=o)
+
+    rng = np.random.default_rng(33)
+    checked = 0
+    gmax = np.abs(gd).max()
+    for _ in range(60):
+        c, i = int(rng.integers(8)), int(rng.integers(n))
+        h = 1e-5 * max(1.0, abs(dd[c, i]))
+        res = []
+        for sgn in (-1, 0, 1):
+            dv = dd.copy()
+            dv[c, i] += sgn * h
+            res.append(oracle_mod.forward_loss(sc, cams, tgt, overrides=frame64(dv)))
+        if not (res[0][1] == res[1][1] == res[2][1]):
+            continue
+        fd = (res[2][0] - res[0][0]) / (2 * h)
+        an = gd.reshape(8, -1)[c, i]
+        assert abs(fd - an) <= 1e-5 * abs(an) + 1e-7 * gmax, (c, i, fd, an)
+        checked += 1
+    assert checked >= 30
