@@ -539,12 +539,19 @@ typedef struct {
   const double* alpha_hat;
 } or_splats;
 
+/* Margins of the near-threshold report.  An FP32 evaluation of alpha carries
+ * a relative error of order OR_ERR_ALPHA (power, exp and log rounding); the
+ * relative error of T after compositing grows with sum alpha/(1-alpha) over
+ * the composited entries, so the stop test is reported near its threshold
+ * when |T(1-alpha) - 1e-4| is within that propagated bound. */
 #define OR_NEAR_REL 2e-4
+#define OR_ERR_ALPHA 2e-5
 
 static void composite_pixel(const or_splats* S, const uint32_t* list, int len, double px,
                             double py, const double bg[3], double out_c[3], double* out_T,
                             int* out_n, int* near_thr) {
   double T = 1.0, C[3] = {0.0, 0.0, 0.0};
+  double cond = 0.0; /* sum of alpha/(1-alpha) over composited entries */
   int last = 0;
   for (int j = 0; j < len; ++j) {
     const uint32_t g = list[j];
@@ -559,10 +566,13 @@ static void composite_pixel(const or_splats* S, const uint32_t* list, int len, d
     const double alpha = ea < OR_ALPHA_MAX ? ea : OR_ALPHA_MAX;
     if (alpha < OR_ALPHA_MIN) continue;
     const double Tn = T * (1.0 - alpha);
-    if (fabs(Tn - OR_T_STOP) <= 1e-3 * OR_T_STOP) *near_thr = 1;
+    const double a_cond = alpha / (1.0 - alpha);
+    const double rel = OR_ERR_ALPHA * (cond + a_cond) + 1e-6 * (double)(last + 1);
+    if (fabs(Tn - OR_T_STOP) <= rel * OR_T_STOP) *near_thr = 1;
     if (Tn < OR_T_STOP) break;
     for (int ch = 0; ch < 3; ++ch) C[ch] += S->rgb[3 * g + ch] * alpha * T;
     T = Tn;
+    cond += a_cond;
     last = j + 1;
   }
   for (int ch = 0; ch < 3; ++ch) out_c[ch] = C[ch] + T * bg[ch];
