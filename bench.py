@@ -1,0 +1,312 @@
+#!/usr/bin/env python3
+"""Benchmark of the MI355X Gaussian-splatting rasterizer.
+
+Workload (timed step): the per-frame training step on a synthetic frame of
+300,000 Gaussians (means U[-3,3]^3, log-scales N(-4,0.5), SH degree 3),
+20 cameras on a 120-degree arc at radius 5, 1352x1014 images: project, bin +
+depth sort, render forward, L1 loss, render backward, projection backward,
+fused Adam over all 59 parameter planes.  Inputs are resident in HBM before
+timing starts.  ``value`` = training iterations/s on one GPU.
+
+The same JSON line also carries: the temporal frame-update step (apply the
+548x548 delta images, render, backward to the deltas, Adam on the deltas);
+per-stage device times from HIP events; the roofline of the dominant kernel;
+and the FP64 CPU oracle timed on a bounded sample of the same workload.
+
+    python bench.py [--steps K] [--warmup W] [--no-cpu-baseline]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0
+# FP32 vector rate without packed FP32 instructions (they are not emitted by
+# this build): 256 CUs x 4 SIMDs x 16 lanes x 2 FLOP (FMA) x 2.4 GHz.
+PEAK_ALU_TFLOPS = 78.6
+
+# Algorithmic FP32 operations per (pixel, entry) pair, FMA counted as 2 and
+# a transcendental as 1 (see the design doc for the breakdown).
+FLOP_PER_PAIR_FWD = 24
+FLOP_PER_PAIR_BWD = 66
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-frame-step", action="store_true")
+    ap.add_argument("--views", type=int, default=20)
+    ap.add_argument("--gaussians", type=int, default=300_000)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain device copy of known size (counter calibration)")
+    return ap.parse_args()
+
+
+def copy_calibration():
+    import torch
+    n = 1 << 28  # 1 GiB of FP32
+    a = torch.ones(n, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n, "launches": 3}))
+
+
+class TrainStep:
+    """One per-frame training iteration on a fixed scene and camera set."""
+
+    def __init__(self, scene, cams, target_scene, frame_update=None):
+        import torch
+
+        from paper_2512_20943_amd import gs
+        from paper_2512_20943_amd.raster import Rasterizer, frame_of
+        self.torch = torch
+        self.gs = gs
+        self.ctx = gs.default_context()
+        n, deg, ld = scene["n"], scene["deg"], scene["ld"]
+        K = (deg + 1) ** 2
+        # all parameter planes in one buffer so that Adam is one launch
+        self.nparam = (3 + 3 + 4 + 1 + 3 * K) * ld
+        self.flat = torch.empty(self.nparam, device="cuda")
+        self.gflat = torch.zeros(self.nparam, device="cuda")
+        self.m = torch.zeros(self.nparam, device="cuda")
+        self.v = torch.zeros(self.nparam, device="cuda")
+
+        def views(buf):
+            o = 0
+            out = []
+            for shape in ((3, ld), (3, ld), (4, ld), (ld,), (K, 3, ld)):
+                cnt = math.prod(shape)
+                out.append(buf[o:o + cnt].view(*shape))
+                o += cnt
+            return out
+
+        planes = views(self.flat)
+        for t, key in zip(planes, ("mean", "log_scale", "quat", "opacity", "sh")):
+            t.copy_(torch.from_numpy(scene[key]))
+        self.g = gs.Gaussians(n, deg, ld, *planes)
+        self.grad = gs.Gaussians(n, deg, ld, *views(self.gflat))
+        self.cams = gs.Cameras(cams)
+        self.r = Rasterizer(capacity=1 << 25)
+        tg = gs.Gaussians.from_scene(target_scene)
+        self.target = self.r.forward(tg, self.cams)["image"].clone()
+        self.dimg = torch.empty_like(self.target)
+        self.loss = torch.zeros(1, dtype=torch.float64, device="cuda")
+        self.t = 0
+        self.frame_update = frame_update
+        if frame_update is not None:
+            d, mask, gw, gh = frame_update
+            self.delta = torch.from_numpy(d).cuda()
+            self.mask = torch.from_numpy(mask).cuda()
+            self.gw, self.gh = gw, gh
+            self.frame = frame_of(self.g)
+            self.dd = torch.zeros(8, gh, gw, device="cuda")
+            self.dm = torch.zeros_like(self.dd)
+            self.dv = torch.zeros_like(self.dd)
+        self.last = None
+
+    def step(self):
+        gs = self.gs
+        self.t += 1
+        g = self.g
+        if self.frame_update is not None:
+            gs.gs_apply_frame_update(self.ctx, self.g, self.delta, self.mask, self.gw, self.gh,
+                                     self.frame)
+            g = self.frame
+        out = self.r.forward(g, self.cams)
+        self.loss.zero_()
+        gs.gs_l1_loss_grad(self.ctx, out["image"], self.target, self.dimg, self.loss)
+        if self.frame_update is None:
+            self.r.backward(g, self.cams, out, self.dimg, self.grad)
+            gs.gs_adam_step(self.ctx, self.flat, self.gflat, self.m, self.v, self.t)
+        else:
+            self.r.backward(g, self.cams, out, self.dimg, self.grad,
+                            upd=(self.g.quat, self.mask, self.gw, self.gh), dL_ddelta=self.dd)
+            gs.gs_adam_step(self.ctx, self.delta, self.dd, self.dm, self.dv, self.t)
+        self.last = out
+
+
+def time_steps(ts, steps, warmup):
+    torch = ts.torch
+    for _ in range(warmup):
+        ts.step()
+    torch.cuda.synchronize()
+    ts.ctx.set_timing(True)
+    ts.ctx.collect_timing()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0.record()
+    for k in range(steps):
+        ts.step()
+    e1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    stages = ts.ctx.collect_timing()
+    ts.ctx.set_timing(False)
+    return wall, e0.elapsed_time(e1) / 1e3, stages
+
+
+def algorithmic_work(stage, ts, steps):
+    """(amount per launch, unit, bound) for a stage of one step."""
+    n, V, K = ts.g.n, ts.cams.V, (ts.g.deg + 1) ** 2
+    M = ts.last["lists"].count
+    pbytes = 4 * (11 + 3 * K)
+    if stage == "render_fwd" or stage == "render_bwd":
+        pairs = float(ts.last["n_contrib"].sum(dtype=ts.torch.float64).item())
+        f = FLOP_PER_PAIR_FWD if stage == "render_fwd" else FLOP_PER_PAIR_BWD
+        return pairs * f, "flop", "alu", pairs
+    if stage == "project":
+        return n * pbytes + V * n * 73.0, "byte", "hbm", None
+    if stage == "project_bwd":
+        return 2 * n * pbytes + V * n * (36.0 + 20 + 1), "byte", "hbm", None
+    if stage == "segment_sort":
+        passes = math.ceil(math.ceil(math.log2(max(ts.cams.n_segments(), 2))) / 8)
+        return M * (16.0 * passes + 4.0), "byte", "hbm", None
+    if stage == "depth_sort":
+        passes = math.ceil((32 + math.ceil(math.log2(max(V, 1)) if V > 1 else 0)) / 8)
+        return V * n * (24.0 * passes + 8 + 4 + 8 + 4), "byte", "hbm", None
+    if stage == "adam":
+        return 28.0 * ts.nparam, "byte", "hbm", None
+    if stage == "l1":
+        return 12.0 * ts.target.numel(), "byte", "hbm", None
+    if stage == "emit":
+        return V * n * 8.0 + M * 8.0, "byte", "hbm", None
+    return None
+
+
+def roofline(stages, ts, steps):
+    busy = {k: v for k, v in stages.items() if v[1] > 0}
+    dom = max(busy, key=lambda k: busy[k][0])
+    ms, launches = busy[dom]
+    per_launch_s = ms / launches / 1e3
+    w = algorithmic_work(dom, ts, steps)
+    if w is None:
+        return dom, None
+    amount, unit, bound, pairs = w
+    launches_per_step = launches / steps
+    amount_per_launch = amount / launches_per_step
+    if unit == "byte":
+        achieved = amount_per_launch / per_launch_s / 1e9
+        rf = dict(bound=bound, achieved=round(achieved, 2), peak=PEAK_HBM_GBS, unit="GB/s",
+                  frac=round(achieved / PEAK_HBM_GBS, 4), traffic=None)
+    else:
+        achieved = amount_per_launch / per_launch_s / 1e12
+        rf = dict(bound=bound, achieved=round(achieved, 3), peak=PEAK_ALU_TFLOPS, unit="TFLOP/s",
+                  frac=round(achieved / PEAK_ALU_TFLOPS, 4), traffic=None)
+    rf["kernel"] = dom
+    rf["launch_ms"] = round(per_launch_s * 1e3, 4)
+    if pairs is not None:
+        rf["pairs_per_launch"] = pairs / launches_per_step
+    return dom, rf
+
+
+def cpu_baseline(scene, cams, target_scene):
+    """FP64 oracle (as it stands) on one of the 20 views of the frame step:
+    projection, bin + sort, render, L1, render backward, projection backward;
+    plus Adam over all parameters once.  Scaled to a 20-view iteration."""
+    import numpy as np
+
+    import oracle
+    oracle.build(force=False)
+    cam1 = {k: v[:1] for k, v in cams.items()}
+    t0 = time.perf_counter()
+    _, _, timg = oracle.forward(target_scene, cam1)
+    t_target = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    P, L, img = oracle.forward(scene, cam1)
+    _, gI = oracle.l1(img["image"], timg["image"])
+    _, grads = oracle.backward(scene, cam1, P, L, gI)
+    t_view = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    flat = np.concatenate([scene[k].ravel() for k in ("mean", "log_scale", "quat", "opacity",
+                                                        "sh")]).astype(np.float64)
+    gflat = np.concatenate([grads[k].ravel() for k in ("mean", "log_scale", "quat", "opacity",
+                                                         "sh")])
+    oracle.adam(flat, gflat, np.zeros_like(flat), np.zeros_like(flat), 1)
+    t_adam = time.perf_counter() - t0
+    V = cams["R"].shape[0]
+    t_iter = V * t_view + t_adam
+    cores = int(os.environ.get("OMP_NUM_THREADS", "0")) or len(os.sched_getaffinity(0))
+    return dict(value=round(1.0 / t_iter, 6), unit="iters/s", cores=cores, kind="oracle",
+                sample=(f"1 of {V} views of the 300k-Gaussian frame step (project, bin+sort, "
+                        f"render, L1, render bwd, project bwd: {t_view:.2f} s) x {V} + Adam over "
+                        f"all parameters ({t_adam:.2f} s); target render {t_target:.2f} s "
+                        f"not counted"))
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported by this build "
+              f"(the multi-GPU sharding is described in DESIGN.md, not built)", file=sys.stderr)
+        sys.exit(2)
+    if args.copy_calibration:
+        copy_calibration()
+        return
+    import torch
+
+    from paper_2512_20943_amd import scenes
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    log("generating the 300k-Gaussian frame workload")
+    scene, cams, target_scene = scenes.workload_frame_300k(0, n=args.gaussians, n_views=args.views)
+    ts = TrainStep(scene, cams, target_scene)
+    log(f"instances per step: {ts.r.forward(ts.g, ts.cams)['lists'].count}")
+    wall, dev_s, stages = time_steps(ts, args.steps, args.warmup)
+    ms_per_step = wall / args.steps * 1e3
+    value = args.steps / wall
+    log(f"train step: {ms_per_step:.2f} ms ({value:.2f} it/s)")
+    dom, rf = roofline(stages, ts, args.steps)
+    stage_ms = {k: round(v[0] / args.steps, 4) for k, v in stages.items() if v[1] > 0}
+    result = {
+        "metric": "fwd+bwd train iters/s", "value": round(value, 4), "unit": "iters/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"frame training step: {args.gaussians} Gaussians SH3, "
+                               f"{args.views} views 1352x1014, L1 + Adam",
+                   "gaussians": args.gaussians, "views": args.views, "width": 1352,
+                   "height": 1014, "instances_per_step": ts.last["lists"].count},
+        "stage_ms_per_step": stage_ms,
+        "roofline": rf,
+    }
+    del ts
+    torch.cuda.empty_cache()
+    if not args.no_frame_step:
+        n = args.gaussians
+        gw = gh = scenes.grid_side(n)
+        d = scenes.make_delta(n, gw, gh, 1)
+        mask = scenes.prune_mask(d, n, 0.3)
+        fs = TrainStep(scene, cams, target_scene, frame_update=(d, mask, gw, gh))
+        wall2, _, st2 = time_steps(fs, max(args.steps // 2, 3), 2)
+        k2 = max(args.steps // 2, 3)
+        result["frame_update_step"] = {
+            "iters_per_s": round(k2 / wall2, 4), "ms_per_step": round(wall2 / k2 * 1e3, 3),
+            "grid": [gh, gw], "prune_level": 0.3,
+            "stage_ms_per_step": {k: round(v[0] / k2, 4) for k, v in st2.items() if v[1] > 0}}
+        log(f"frame-update step: {wall2 / k2 * 1e3:.2f} ms")
+        del fs
+    if not args.no_cpu_baseline:
+        log("timing the FP64 oracle on one view")
+        result["cpu_baseline"] = cpu_baseline(scene, cams, target_scene)
+    print(json.dumps(result))
+
+
+if __name__ == "__main__":
+    main()

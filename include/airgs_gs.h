@@ -1,0 +1,253 @@
+/*
+ * airgs_gs.h -- C ABI of the MI355X (gfx950) Gaussian-splatting rasterizer.
+ *
+ * The library renders one frame of a dynamic Gaussian scene and
+ * differentiates it.  A frame is an anchor Gaussian set plus an accumulated,
+ * pruned attribute delta (AirGS, Eq. (2), Eq. (5), Eq. (12)); attribute
+ * deltas travel as multi-channel 2D images with one texel per Gaussian
+ * (Eq. (3), Sec. III-C); each Gaussian carries mean, opacity, colour as
+ * spherical harmonics, rotation and scale (Sec. II).  The renderer itself is
+ * the differentiable splatting rasterizer the paper cites in Sec. II: EWA
+ * projection, 16x16-tile binning, a depth-ordered front-to-back composite,
+ * and its backward pass.
+ *
+ * Conventions shared by every call
+ *   - All array pointers are DEVICE pointers unless a parameter says "host".
+ *   - The caller owns every buffer.  The library keeps no pointer after a
+ *     call returns, except that enqueued kernels read and write them on the
+ *     given stream until they complete.
+ *   - Work is enqueued on `stream` (a hipStream_t; NULL = the null stream).
+ *     Only gs_bin_sort blocks the host (it reads the instance count back).
+ *   - Argument checks are synchronous; a failed check returns an error code
+ *     and enqueues nothing.  Kernel faults surface at the next synchronising
+ *     HIP call.  gs_last_error() returns the text of the latest error.
+ *   - No C++ exception crosses this boundary.
+ *   - One gs_ctx per host thread; calls on one context are not reentrant.
+ *   - Parameters are FP32 structure-of-arrays planes with a common plane
+ *     stride `ld` (>= n, a multiple of 64); Gaussian i of plane k of a
+ *     (P, ld) array is element k*ld + i.
+ */
+#ifndef AIRGS_GS_H
+#define AIRGS_GS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t gs_status;
+#define GS_OK 0
+#define GS_ERR_INVALID_ARG 1 /* null pointer, bad size, bad degree, bad stride */
+#define GS_ERR_CAPACITY 2    /* instance buffers too small; count holds the need */
+#define GS_ERR_OOM 3         /* workspace smaller than the *_workspace_size() */
+#define GS_ERR_HIP 4         /* a HIP runtime call failed */
+
+#define GS_TILE 16           /* tile side in pixels */
+#define GS_MAX_SH_DEGREE 3
+#define GS_MAX_INSTANCES ((int64_t)1 << 30)
+
+typedef struct gs_ctx gs_ctx;
+
+/* Gaussian set, FP32 planes of stride ld:
+ *   mean (3, ld); log_scale (3, ld) (scale = exp); quat (4, ld) as (w, x, y, z),
+ *   any nonzero norm; opacity (ld) as a logit (opacity = sigmoid);
+ *   sh (K, 3, ld), K = (sh_degree + 1)^2, coefficient index l*l + l + m.
+ * As a gradient set (gs_render_bwd output) the same planes hold dL/d(.). */
+typedef struct gs_gaussians {
+  int32_t n;
+  int32_t sh_degree;
+  int32_t ld;
+  int32_t reserved;
+  float* mean;
+  float* log_scale;
+  float* quat;
+  float* opacity;
+  float* sh;
+} gs_gaussians;
+
+/* Pinhole camera: x_cam = R * x_world + t (R row-major, OpenCV frame: x
+ * right, y down, z forward); pixel (u, v) samples the image plane at integer
+ * coordinates, u = fx * x/z + cx.  144 bytes, FP64. */
+typedef struct gs_camera {
+  double R[9];
+  double t[3];
+  double fx, fy, cx, cy;
+  int32_t width, height;
+  int32_t reserved[2];
+} gs_camera;
+
+/* Render options: background colour added with the final transmittance. */
+typedef struct gs_opts {
+  float bg[3];
+  float reserved;
+} gs_opts;
+
+/* Per (view, Gaussian) projection records, index v*ld + i:
+ *   splat (V, ld, 12) FP32: [px, py, A, B, C, opacity, r, g, b, depth, Q, 0]
+ *       screen mean, conic (power = -(A dx^2 + C dy^2)/2 - B dx dy), opacity
+ *       sigmoid(logit), clamped SH colour, camera-space depth, and the conic
+ *       determinant Q = A C - B^2 (from FP64, used for cancellation-free
+ *       evaluation of the quadratic form);
+ *   rect (V, ld, 4) int32: tile rectangle [tx0, ty0, tx1, ty1), all 0 if culled;
+ *   tiles_touched (V, ld) int32: (tx1 - tx0) * (ty1 - ty0), 0 if culled;
+ *   depth_bits (V, ld) uint32: bits of FP32(z);
+ *   flags (V, ld) uint8: 1,2,4 colour channel clamped at 0; 8, 16 guard band
+ *       clamp of x/z, y/z; 32 visible. */
+typedef struct gs_projected {
+  int32_t n_views;
+  int32_t n;       /* Gaussians per view (records i >= n are never read) */
+  int32_t ld;
+  int32_t reserved;
+  float* splat;
+  int32_t* rect;
+  int32_t* tiles_touched;
+  uint32_t* depth_bits;
+  uint8_t* flags;
+} gs_projected;
+
+/* Sorted tile lists.  Views are concatenated: view v's tiles are segments
+ * seg_base(v) .. seg_base(v) + TX_v*TY_v - 1 in row-major tile order, with
+ * seg_base(v) the sum of the tile counts of the views before it.
+ *   keys (capacity) uint64, optional (NULL = not written):
+ *       (segment << 32) | depth_bits, ascending;
+ *   vals (capacity) uint32: Gaussian id of each instance, in key order, ties
+ *       (equal segment and depth) in ascending id;
+ *   ranges (n_segments, 2) uint32: [start, end) of each segment in vals.
+ * capacity (in) bounds the instance count; count (out) is the instance count
+ * M; n_segments (out) is the total tile count. */
+typedef struct gs_tile_lists {
+  int64_t capacity;
+  int64_t count;
+  int64_t n_segments;
+  uint64_t* keys;
+  uint32_t* vals;
+  uint32_t* ranges;
+} gs_tile_lists;
+
+/* Frame update for the backward pass to the delta images. */
+typedef struct gs_frame_update {
+  const float* anchor_quat; /* (4, ld) anchor quaternions */
+  int32_t ld;
+  int32_t gw, gh;           /* texel grid, gw * gh >= n */
+  int32_t reserved;
+  const uint8_t* mask;      /* (gh, gw), 1 = the texel's update was applied */
+} gs_frame_update;
+
+/* ---- support ------------------------------------------------------------ */
+
+int gs_version(void);
+
+/* Create a context bound to HIP device `device` (allocates a small pinned
+ * host buffer for the instance-count readback).  *out is NULL on failure. */
+gs_status gs_create(gs_ctx** out, int device);
+void gs_destroy(gs_ctx* ctx);
+
+/* Text of the last error on this context (static storage if ctx is NULL). */
+const char* gs_last_error(const gs_ctx* ctx);
+
+/* Total number of tile segments of n_views host cameras. */
+int64_t gs_num_segments(const gs_camera* cams_host, int n_views);
+
+/* Workspace bytes for gs_bin_sort with the given views, stride, instance
+ * capacity and total segment count. */
+size_t gs_bin_sort_workspace_size(int n_views, int ld, int64_t capacity, int64_t n_segments);
+
+/* Workspace bytes for gs_render_bwd.  Its first n_views*ld*12 floats hold
+ * the per-(view, Gaussian) screen-space gradients after the call:
+ * [d px, d py, d A, d B, d C, d opacity, d r, d g, d b, 0, 0, 0]. */
+size_t gs_render_bwd_workspace_size(int n_views, int ld);
+
+/* Device-time measurement.  With timing enabled, every kernel stage a call
+ * enqueues is bracketed by HIP events on the call's stream.  Stages:
+ *   0 apply, 1 project, 2 depth sort, 3 count scan, 4 emit, 5 segment sort,
+ *   6 ranges, 7 render fwd, 8 render bwd, 9 project bwd, 10 apply bwd,
+ *   11 l1, 12 adam, 13 fill. */
+#define GS_STAGE_COUNT 14
+gs_status gs_set_timing(gs_ctx* ctx, int enable);
+/* Sum of event-measured milliseconds and number of launches per stage since
+ * the previous collection (host arrays of GS_STAGE_COUNT); blocks until the
+ * recorded events have completed, then resets the counters. */
+gs_status gs_collect_timing(gs_ctx* ctx, double* ms, int64_t* launches);
+const char* gs_stage_name(int stage);
+
+/* ---- hot path ----------------------------------------------------------- */
+
+/* Apply a decoded frame update to anchor Gaussians (Eq. (2)/(5)/(12): frame
+ * = anchor + accumulated delta; Eq. (3): one texel per Gaussian; Eq. (11):
+ * the pruning mask drops updates).  delta (8, gh, gw) FP32 planar channels
+ * [dx, dy, dz, dq_w, dq_x, dq_y, dq_z, d_opacity_logit]; Gaussian i reads
+ * texel (i / gw, i % gw); requires gw * gh >= anchor->n.  Where mask = 1:
+ * mean' = mean + d_mu, quat' = dq (x) quat (Hamilton product), logit' =
+ * logit + d_o; elsewhere the anchor values are copied.  Each result is
+ * computed in FP64 and rounded once to FP32.  Writes frame->mean, quat,
+ * opacity only (its log_scale and sh may alias the anchor's planes). */
+gs_status gs_apply_frame_update(gs_ctx* ctx, const gs_gaussians* anchor, const float* delta,
+                                const uint8_t* mask, int gw, int gh, gs_gaussians* frame,
+                                void* stream);
+
+/* EWA projection (Sec. II renderer): camera transform, near cull (z <= 0.2),
+ * 3D covariance R_q diag(exp s)^2 R_q^T, 2D covariance J W Sigma W^T J^T
+ * with a 1.3x guard band on J and +0.3 px^2 dilation, conic, screen mean,
+ * radius ceil(3 sqrt(lambda_max)) (eigenvalue floor 0.1), 16x16 tile
+ * rectangle, SH colour + 0.5 clamped at 0, sigmoid opacity, depth.  The
+ * binning quantities (depth, radius, rectangle) are computed in FP64.
+ * cams_host and cams_dev hold the same n_views cameras (host copy for
+ * validation and launch sizes, device copy for the kernels). */
+gs_status gs_project(gs_ctx* ctx, const gs_gaussians* g, const gs_camera* cams_host,
+                     const gs_camera* cams_dev, int n_views, gs_projected* out, void* stream);
+
+/* Binning and depth ordering: every (visible Gaussian, tile of its
+ * rectangle) pair is an instance; instances are ordered by (segment, FP32
+ * depth, Gaussian id) with an LDS-resident onesweep radix sort.  Reads the
+ * instance count back to the host (blocking).  Returns GS_ERR_CAPACITY with
+ * lists->count = M when M > lists->capacity (nothing else is written).
+ * workspace must hold gs_bin_sort_workspace_size() bytes. */
+gs_status gs_bin_sort(gs_ctx* ctx, const gs_projected* proj, const gs_camera* cams_host,
+                      const gs_camera* cams_dev, int n_views, gs_tile_lists* lists,
+                      void* workspace, size_t ws_bytes, void* stream);
+
+/* Front-to-back compositing per pixel over its tile's list:
+ * alpha = min(0.99, opacity * exp(power)); skip if power > 0 or alpha <
+ * 1/255; stop before compositing an entry that would take the
+ * transmittance below 1e-4.  Views must share width and height.
+ * image (V, 3, H, W), final_T (V, H, W), n_contrib (V, H, W) = 1 + index
+ * (within the tile list) of the last composited entry, 0 if none. */
+gs_status gs_render_fwd(gs_ctx* ctx, const gs_projected* proj, const gs_tile_lists* lists,
+                        const gs_camera* cams_host, const gs_camera* cams_dev, int n_views,
+                        const gs_opts* opts, float* image, float* final_T, int32_t* n_contrib,
+                        void* stream);
+
+/* Backward of gs_project + gs_render_fwd for dL/dimage (V, 3, H, W):
+ * transmittance is recovered by walking each pixel's list back from
+ * n_contrib.  Gradients w.r.t. the frame's mean, log_scale, quat, opacity
+ * logit and SH are ADDED to `grad` (same shape as `frame`; the caller zeroes
+ * it) summed over views.  If `upd` is non-NULL, dL/d(delta images) (8, gh,
+ * gw) is WRITTEN to dL_ddelta (zero at masked and padding texels). */
+gs_status gs_render_bwd(gs_ctx* ctx, const gs_gaussians* frame, const gs_projected* proj,
+                        const gs_tile_lists* lists, const gs_camera* cams_host,
+                        const gs_camera* cams_dev, int n_views, const gs_opts* opts,
+                        const float* final_T, const int32_t* n_contrib, const float* dL_dimage,
+                        gs_gaussians* grad, const gs_frame_update* upd, float* dL_ddelta,
+                        void* workspace, size_t ws_bytes, void* stream);
+
+/* ---- training support ----------------------------------------------------- */
+
+/* L1 photometric term (Eq. (1)): loss = mean |image - target| over count
+ * values, ACCUMULATED in FP64 into *loss_dev (device; caller zeroes);
+ * grad = sign(image - target) / count (sign(0) = 0) WRITTEN. */
+gs_status gs_l1_loss_grad(gs_ctx* ctx, const float* image, const float* target, int64_t count,
+                          float* grad, double* loss_dev, void* stream);
+
+/* One Adam step (Kingma & Ba 2015, Alg. 1) over count FP32 values, in
+ * place, bias-corrected for step number `step` >= 1. */
+gs_status gs_adam_step(gs_ctx* ctx, float* param, const float* grad, float* m, float* v,
+                       int64_t count, int step, float lr, float beta1, float beta2, float eps,
+                       void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* AIRGS_GS_H */

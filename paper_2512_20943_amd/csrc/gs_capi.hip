@@ -1,0 +1,449 @@
+// C ABI of the rasterizer: argument validation, workspace accounting and
+// kernel launches.  No C++ exception crosses this boundary.
+#include <cstdarg>
+#include <cstdio>
+#include <cmath>
+#include <cstring>
+#include <new>
+
+#include <vector>
+
+#include "gs_internal.h"
+
+namespace gs {
+thread_local StageTimer* g_timer = nullptr;
+}
+
+namespace {
+
+// HIP-event brackets around each stage a call enqueues.
+struct EventTimer final : gs::StageTimer {
+  struct Rec {
+    int stage;
+    hipEvent_t a, b;
+  };
+  std::vector<hipEvent_t> pool;
+  std::vector<Rec> recs;
+  std::vector<size_t> open;
+
+  hipEvent_t take() {
+    if (!pool.empty()) {
+      hipEvent_t e = pool.back();
+      pool.pop_back();
+      return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+  }
+  void begin(int stage, hipStream_t s) override {
+    Rec r{stage, take(), take()};
+    if (r.a) hipEventRecord(r.a, s);
+    open.push_back(recs.size());
+    recs.push_back(r);
+  }
+  void end(int stage, hipStream_t s) override {
+    (void)stage;
+    if (open.empty()) return;
+    Rec& r = recs[open.back()];
+    open.pop_back();
+    if (r.b) hipEventRecord(r.b, s);
+  }
+  hipError_t collect(double* ms, int64_t* launches) {
+    for (int k = 0; k < gs::kStageCount; ++k) {
+      ms[k] = 0.0;
+      launches[k] = 0;
+    }
+    hipError_t err = hipSuccess;
+    for (Rec& r : recs) {
+      float t = 0.f;
+      if (r.a && r.b) {
+        hipError_t e = hipEventSynchronize(r.b);
+        if (e == hipSuccess) e = hipEventElapsedTime(&t, r.a, r.b);
+        if (e != hipSuccess) err = e;
+      }
+      ms[r.stage] += t;
+      launches[r.stage] += 1;
+      if (r.a) pool.push_back(r.a);
+      if (r.b) pool.push_back(r.b);
+    }
+    recs.clear();
+    open.clear();
+    return err;
+  }
+  ~EventTimer() override {
+    for (Rec& r : recs) {
+      if (r.a) hipEventDestroy(r.a);
+      if (r.b) hipEventDestroy(r.b);
+    }
+    for (hipEvent_t e : pool) hipEventDestroy(e);
+  }
+};
+
+}  // namespace
+
+struct gs_ctx {
+  int device;
+  uint32_t* pinned;  // host-visible readback slot for the instance count
+  bool timing;
+  EventTimer timer;
+  char err[512];
+};
+
+namespace {
+// Makes the context's timer active for the duration of one C ABI call.
+struct TimerGuard {
+  gs::StageTimer* prev;
+  explicit TimerGuard(gs_ctx* c) : prev(gs::g_timer) {
+    gs::g_timer = (c && c->timing) ? &c->timer : nullptr;
+  }
+  ~TimerGuard() { gs::g_timer = prev; }
+};
+}  // namespace
+
+namespace {
+
+char g_err[512] = "";
+
+gs_status fail(gs_ctx* c, gs_status code, const char* fmt, ...) {
+  char* dst = c ? c->err : g_err;
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(dst, 512, fmt, ap);
+  va_end(ap);
+  return code;
+}
+
+gs_status hip_fail(gs_ctx* c, hipError_t e, const char* where) {
+  return fail(c, GS_ERR_HIP, "%s: %s", where, hipGetErrorString(e));
+}
+
+gs_status check_gaussians(gs_ctx* c, const gs_gaussians* g, const char* what) {
+  if (!g) return fail(c, GS_ERR_INVALID_ARG, "%s is NULL", what);
+  if (g->n < 0) return fail(c, GS_ERR_INVALID_ARG, "%s: n = %d < 0", what, g->n);
+  if (g->sh_degree < 0 || g->sh_degree > GS_MAX_SH_DEGREE)
+    return fail(c, GS_ERR_INVALID_ARG, "%s: sh_degree %d not in 0..3", what, g->sh_degree);
+  if (g->ld < g->n || g->ld <= 0 || (g->ld % 64) != 0)
+    return fail(c, GS_ERR_INVALID_ARG, "%s: ld %d must be >= n (%d) and a positive multiple of 64",
+                what, g->ld, g->n);
+  if (g->n > 0 && (!g->mean || !g->log_scale || !g->quat || !g->opacity || !g->sh))
+    return fail(c, GS_ERR_INVALID_ARG, "%s: NULL parameter plane", what);
+  return GS_OK;
+}
+
+gs_status check_cams(gs_ctx* c, const gs_camera* h, const gs_camera* d, int V) {
+  if (V <= 0) return fail(c, GS_ERR_INVALID_ARG, "n_views = %d must be > 0", V);
+  if (!h || !d) return fail(c, GS_ERR_INVALID_ARG, "camera array is NULL");
+  for (int v = 0; v < V; ++v) {
+    const gs_camera& k = h[v];
+    if (k.width <= 0 || k.height <= 0 || k.width > 65536 || k.height > 65536)
+      return fail(c, GS_ERR_INVALID_ARG, "camera %d: size %dx%d out of range", v, k.width,
+                  k.height);
+    if (!(k.fx > 0.0) || !(k.fy > 0.0))
+      return fail(c, GS_ERR_INVALID_ARG, "camera %d: focal lengths must be > 0", v);
+  }
+  return GS_OK;
+}
+
+gs_status check_projected(gs_ctx* c, const gs_projected* p, int V, int ld) {
+  if (!p) return fail(c, GS_ERR_INVALID_ARG, "projected is NULL");
+  if (p->n_views != V || p->ld != ld)
+    return fail(c, GS_ERR_INVALID_ARG, "projected: n_views/ld (%d, %d) != (%d, %d)", p->n_views,
+                p->ld, V, ld);
+  if (p->n < 0 || p->n > p->ld || p->ld <= 0 || (p->ld % 64) != 0)
+    return fail(c, GS_ERR_INVALID_ARG, "projected: n %d / ld %d invalid", p->n, p->ld);
+  if (!p->splat || !p->rect || !p->tiles_touched || !p->depth_bits || !p->flags)
+    return fail(c, GS_ERR_INVALID_ARG, "projected: NULL buffer");
+  return GS_OK;
+}
+
+gs_status use_device(gs_ctx* c) {
+  int cur = -1;
+  hipError_t e = hipGetDevice(&cur);
+  if (e != hipSuccess) return hip_fail(c, e, "hipGetDevice");
+  if (cur != c->device) {
+    e = hipSetDevice(c->device);
+    if (e != hipSuccess) return hip_fail(c, e, "hipSetDevice");
+  }
+  return GS_OK;
+}
+
+int64_t segments_of(const gs_camera* h, int V) {
+  int64_t s = 0;
+  for (int v = 0; v < V; ++v)
+    s += (int64_t)gs::tiles_across(h[v].width) * gs::tiles_across(h[v].height);
+  return s;
+}
+
+#define GS_TRY(expr)              \
+  do {                            \
+    const gs_status st_ = (expr); \
+    if (st_ != GS_OK) return st_; \
+  } while (0)
+
+#define GS_LAUNCHED(ctx, where)                          \
+  do {                                                   \
+    const hipError_t e_ = hipGetLastError();             \
+    if (e_ != hipSuccess) return hip_fail(ctx, e_, where); \
+  } while (0)
+
+}  // namespace
+
+extern "C" {
+
+int gs_version(void) { return 100; }
+
+gs_status gs_create(gs_ctx** out, int device) {
+  if (!out) return fail(nullptr, GS_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  int count = 0;
+  hipError_t e = hipGetDeviceCount(&count);
+  if (e != hipSuccess) return hip_fail(nullptr, e, "hipGetDeviceCount");
+  if (device < 0 || device >= count)
+    return fail(nullptr, GS_ERR_INVALID_ARG, "device %d not in [0, %d)", device, count);
+  gs_ctx* c = new (std::nothrow) gs_ctx();
+  if (!c) return fail(nullptr, GS_ERR_OOM, "context allocation failed");
+  c->device = device;
+  c->timing = false;
+  c->err[0] = 0;
+  int prev = 0;
+  hipGetDevice(&prev);
+  hipSetDevice(device);
+  e = hipHostMalloc(reinterpret_cast<void**>(&c->pinned), 64, hipHostMallocDefault);
+  hipSetDevice(prev);
+  if (e != hipSuccess) {
+    delete c;
+    return hip_fail(nullptr, e, "hipHostMalloc");
+  }
+  *out = c;
+  return GS_OK;
+}
+
+void gs_destroy(gs_ctx* c) {
+  if (!c) return;
+  if (c->pinned) hipHostFree(c->pinned);
+  delete c;
+}
+
+const char* gs_last_error(const gs_ctx* c) { return c ? c->err : g_err; }
+
+gs_status gs_set_timing(gs_ctx* c, int enable) {
+  if (!c) return fail(nullptr, GS_ERR_INVALID_ARG, "ctx is NULL");
+  c->timing = enable != 0;
+  return GS_OK;
+}
+
+gs_status gs_collect_timing(gs_ctx* c, double* ms, int64_t* launches) {
+  if (!c || !ms || !launches) return fail(c, GS_ERR_INVALID_ARG, "NULL argument");
+  const hipError_t e = c->timer.collect(ms, launches);
+  if (e != hipSuccess) return hip_fail(c, e, "timing events");
+  return GS_OK;
+}
+
+const char* gs_stage_name(int stage) {
+  static const char* names[GS_STAGE_COUNT] = {
+      "apply",  "project",    "depth_sort",  "count_scan", "emit", "segment_sort", "ranges",
+      "render_fwd", "render_bwd", "project_bwd", "apply_bwd", "l1",   "adam",         "fill"};
+  return (stage >= 0 && stage < GS_STAGE_COUNT) ? names[stage] : "?";
+}
+
+int64_t gs_num_segments(const gs_camera* cams, int V) {
+  if (!cams || V <= 0) return 0;
+  return segments_of(cams, V);
+}
+
+size_t gs_bin_sort_workspace_size(int V, int ld, int64_t capacity, int64_t n_segments) {
+  if (V <= 0 || ld <= 0 || capacity < 0 || n_segments < 0) return 0;
+  return gs::bin_sort_workspace_bytes(V, ld, capacity, n_segments);
+}
+
+size_t gs_render_bwd_workspace_size(int V, int ld) {
+  if (V <= 0 || ld <= 0) return 0;
+  return (size_t)V * (size_t)ld * gs::kGrad2dFloats * sizeof(float);
+}
+
+gs_status gs_apply_frame_update(gs_ctx* c, const gs_gaussians* anchor, const float* delta,
+                                const uint8_t* mask, int gw, int gh, gs_gaussians* frame,
+                                void* stream) {
+  if (!c) return fail(nullptr, GS_ERR_INVALID_ARG, "ctx is NULL");
+  TimerGuard timer_guard(c);
+  GS_TRY(check_gaussians(c, anchor, "anchor"));
+  if (!frame) return fail(c, GS_ERR_INVALID_ARG, "frame is NULL");
+  if (frame->n != anchor->n || frame->ld != anchor->ld)
+    return fail(c, GS_ERR_INVALID_ARG, "frame n/ld differ from the anchor's");
+  if (gw <= 0 || gh <= 0 || (int64_t)gw * gh < anchor->n)
+    return fail(c, GS_ERR_INVALID_ARG, "texel grid %dx%d cannot hold %d Gaussians", gw, gh,
+                anchor->n);
+  if (anchor->n > 0 && (!delta || !mask || !frame->mean || !frame->quat || !frame->opacity))
+    return fail(c, GS_ERR_INVALID_ARG, "NULL delta, mask or frame plane");
+  GS_TRY(use_device(c));
+  gs::launch_apply(*anchor, delta, mask, gw, gh, *frame, (hipStream_t)stream);
+  GS_LAUNCHED(c, "apply");
+  return GS_OK;
+}
+
+gs_status gs_project(gs_ctx* c, const gs_gaussians* g, const gs_camera* ch, const gs_camera* cd,
+                     int V, gs_projected* out, void* stream) {
+  if (!c) return fail(nullptr, GS_ERR_INVALID_ARG, "ctx is NULL");
+  TimerGuard timer_guard(c);
+  GS_TRY(check_gaussians(c, g, "gaussians"));
+  GS_TRY(check_cams(c, ch, cd, V));
+  GS_TRY(check_projected(c, out, V, g->ld));
+  if (out->n != g->n) return fail(c, GS_ERR_INVALID_ARG, "projected n != gaussians n");
+  GS_TRY(use_device(c));
+  gs::launch_project(*g, cd, V, *out, (hipStream_t)stream);
+  GS_LAUNCHED(c, "project");
+  return GS_OK;
+}
+
+gs_status gs_bin_sort(gs_ctx* c, const gs_projected* proj, const gs_camera* ch,
+                      const gs_camera* cd, int V, gs_tile_lists* lists, void* ws, size_t ws_bytes,
+                      void* stream) {
+  if (!c) return fail(nullptr, GS_ERR_INVALID_ARG, "ctx is NULL");
+  TimerGuard timer_guard(c);
+  GS_TRY(check_cams(c, ch, cd, V));
+  if (!proj) return fail(c, GS_ERR_INVALID_ARG, "projected is NULL");
+  GS_TRY(check_projected(c, proj, V, proj->ld));
+  if (!lists || !lists->vals || !lists->ranges)
+    return fail(c, GS_ERR_INVALID_ARG, "tile lists (vals, ranges) are NULL");
+  if (lists->capacity < 0 || lists->capacity > GS_MAX_INSTANCES)
+    return fail(c, GS_ERR_INVALID_ARG, "capacity %lld outside [0, 2^30]",
+                (long long)lists->capacity);
+  const int64_t nseg = segments_of(ch, V);
+  if (nseg >= ((int64_t)1 << 31))
+    return fail(c, GS_ERR_INVALID_ARG, "too many tile segments (%lld)", (long long)nseg);
+  if (!ws) return fail(c, GS_ERR_INVALID_ARG, "workspace is NULL");
+  if ((int64_t)V * proj->n >= ((int64_t)1 << 32))
+    return fail(c, GS_ERR_INVALID_ARG, "n_views * n too large");
+  gs::BinSortPlan plan{V, proj->n, proj->ld, lists->capacity, nseg};
+  const size_t need = gs::bin_sort_workspace_bytes(V, proj->ld, lists->capacity, nseg);
+  if (ws_bytes < need)
+    return fail(c, GS_ERR_OOM, "bin_sort workspace %zu < %zu bytes", ws_bytes, need);
+  GS_TRY(use_device(c));
+  hipStream_t s = (hipStream_t)stream;
+  lists->n_segments = nseg;
+  uint32_t* d_count = nullptr;
+  hipError_t e = gs::bin_sort_stage1(plan, *proj, cd, ws, s, &d_count);
+  if (e != hipSuccess) return hip_fail(c, e, "bin_sort (count)");
+  e = hipMemcpyAsync(c->pinned, d_count, sizeof(uint32_t), hipMemcpyDeviceToHost, s);
+  if (e != hipSuccess) return hip_fail(c, e, "instance count readback");
+  e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_fail(c, e, "hipStreamSynchronize");
+  const uint32_t M = *c->pinned;
+  lists->count = (int64_t)M;
+  if ((int64_t)M > lists->capacity)
+    return fail(c, GS_ERR_CAPACITY, "instance count %u exceeds capacity %lld", M,
+                (long long)lists->capacity);
+  e = gs::bin_sort_stage2(plan, *proj, cd, M, *lists, ws, s);
+  if (e != hipSuccess) return hip_fail(c, e, "bin_sort (sort)");
+  return GS_OK;
+}
+
+gs_status gs_render_fwd(gs_ctx* c, const gs_projected* proj, const gs_tile_lists* lists,
+                        const gs_camera* ch, const gs_camera* cd, int V, const gs_opts* opts,
+                        float* image, float* final_T, int32_t* n_contrib, void* stream) {
+  if (!c) return fail(nullptr, GS_ERR_INVALID_ARG, "ctx is NULL");
+  TimerGuard timer_guard(c);
+  GS_TRY(check_cams(c, ch, cd, V));
+  if (!proj) return fail(c, GS_ERR_INVALID_ARG, "projected is NULL");
+  GS_TRY(check_projected(c, proj, V, proj->ld));
+  if (!lists || !lists->vals || !lists->ranges)
+    return fail(c, GS_ERR_INVALID_ARG, "tile lists are NULL");
+  if (lists->n_segments != segments_of(ch, V))
+    return fail(c, GS_ERR_INVALID_ARG, "tile lists were built for other cameras");
+  for (int v = 1; v < V; ++v)
+    if (ch[v].width != ch[0].width || ch[v].height != ch[0].height)
+      return fail(c, GS_ERR_INVALID_ARG, "views must share width and height");
+  if (!image || !final_T || !n_contrib)
+    return fail(c, GS_ERR_INVALID_ARG, "NULL output buffer");
+  GS_TRY(use_device(c));
+  const float zero[3] = {0.f, 0.f, 0.f};
+  gs::launch_render_fwd(*proj, *lists, V, ch[0].width, ch[0].height, opts ? opts->bg : zero, image,
+                        final_T, n_contrib, (hipStream_t)stream);
+  GS_LAUNCHED(c, "render_fwd");
+  return GS_OK;
+}
+
+gs_status gs_render_bwd(gs_ctx* c, const gs_gaussians* frame, const gs_projected* proj,
+                        const gs_tile_lists* lists, const gs_camera* ch, const gs_camera* cd,
+                        int V, const gs_opts* opts, const float* final_T, const int32_t* n_contrib,
+                        const float* dL_dimage, gs_gaussians* grad, const gs_frame_update* upd,
+                        float* dL_ddelta, void* ws, size_t ws_bytes, void* stream) {
+  if (!c) return fail(nullptr, GS_ERR_INVALID_ARG, "ctx is NULL");
+  TimerGuard timer_guard(c);
+  GS_TRY(check_gaussians(c, frame, "frame"));
+  GS_TRY(check_gaussians(c, grad, "grad"));
+  if (grad->n != frame->n || grad->ld != frame->ld || grad->sh_degree != frame->sh_degree)
+    return fail(c, GS_ERR_INVALID_ARG, "grad shape differs from frame shape");
+  GS_TRY(check_cams(c, ch, cd, V));
+  GS_TRY(check_projected(c, proj, V, frame->ld));
+  if (proj->n != frame->n) return fail(c, GS_ERR_INVALID_ARG, "projected n != frame n");
+  if (!lists || !lists->vals || !lists->ranges)
+    return fail(c, GS_ERR_INVALID_ARG, "tile lists are NULL");
+  if (lists->n_segments != segments_of(ch, V))
+    return fail(c, GS_ERR_INVALID_ARG, "tile lists were built for other cameras");
+  for (int v = 1; v < V; ++v)
+    if (ch[v].width != ch[0].width || ch[v].height != ch[0].height)
+      return fail(c, GS_ERR_INVALID_ARG, "views must share width and height");
+  if (!final_T || !n_contrib || !dL_dimage)
+    return fail(c, GS_ERR_INVALID_ARG, "NULL forward state or image gradient");
+  if (upd) {
+    if (!dL_ddelta || !upd->anchor_quat || !upd->mask)
+      return fail(c, GS_ERR_INVALID_ARG, "frame update given without its buffers");
+    if (upd->ld != frame->ld || upd->gw <= 0 || upd->gh <= 0 ||
+        (int64_t)upd->gw * upd->gh < frame->n)
+      return fail(c, GS_ERR_INVALID_ARG, "frame update grid/stride mismatch");
+  }
+  const size_t need = gs_render_bwd_workspace_size(V, frame->ld);
+  if (!ws || ws_bytes < need)
+    return fail(c, GS_ERR_OOM, "render_bwd workspace %zu < %zu bytes", ws_bytes, need);
+  GS_TRY(use_device(c));
+  hipStream_t s = (hipStream_t)stream;
+  float* grad2d = static_cast<float*>(ws);
+  gs::launch_fill_f32(grad2d, 0.f, (int64_t)(need / sizeof(float)), s);
+  const float zero[3] = {0.f, 0.f, 0.f};
+  gs::launch_render_bwd(*proj, *lists, V, ch[0].width, ch[0].height, opts ? opts->bg : zero,
+                        final_T, n_contrib, dL_dimage, grad2d, s);
+  GS_LAUNCHED(c, "render_bwd");
+  gs::launch_project_bwd(*frame, cd, V, *proj, grad2d, *grad, s);
+  GS_LAUNCHED(c, "project_bwd");
+  if (upd) {
+    gs::launch_apply_bwd(frame->n, *upd, *grad, dL_ddelta, s);
+    GS_LAUNCHED(c, "apply_bwd");
+  }
+  return GS_OK;
+}
+
+gs_status gs_l1_loss_grad(gs_ctx* c, const float* image, const float* target, int64_t count,
+                          float* grad, double* loss_dev, void* stream) {
+  if (!c) return fail(nullptr, GS_ERR_INVALID_ARG, "ctx is NULL");
+  TimerGuard timer_guard(c);
+  if (count < 0) return fail(c, GS_ERR_INVALID_ARG, "count < 0");
+  if (count > 0 && (!image || !target || !grad || !loss_dev))
+    return fail(c, GS_ERR_INVALID_ARG, "NULL buffer");
+  GS_TRY(use_device(c));
+  gs::launch_l1(image, target, count, grad, loss_dev, (hipStream_t)stream);
+  GS_LAUNCHED(c, "l1");
+  return GS_OK;
+}
+
+gs_status gs_adam_step(gs_ctx* c, float* param, const float* grad, float* m, float* v,
+                       int64_t count, int step, float lr, float b1, float b2, float eps,
+                       void* stream) {
+  if (!c) return fail(nullptr, GS_ERR_INVALID_ARG, "ctx is NULL");
+  TimerGuard timer_guard(c);
+  if (count < 0 || step < 1) return fail(c, GS_ERR_INVALID_ARG, "count < 0 or step < 1");
+  if (!(b1 >= 0.f && b1 < 1.f) || !(b2 >= 0.f && b2 < 1.f) || !(eps > 0.f))
+    return fail(c, GS_ERR_INVALID_ARG, "Adam hyper-parameters out of range");
+  if (count > 0 && (!param || !grad || !m || !v))
+    return fail(c, GS_ERR_INVALID_ARG, "NULL buffer");
+  GS_TRY(use_device(c));
+  const double bc1 = 1.0 - std::pow((double)b1, (double)step);
+  const double bc2 = 1.0 - std::pow((double)b2, (double)step);
+  gs::launch_adam(param, grad, m, v, count, lr, b1, b2, eps, (float)bc1, (float)bc2,
+                  (hipStream_t)stream);
+  GS_LAUNCHED(c, "adam");
+  return GS_OK;
+}
+
+}  // extern "C"

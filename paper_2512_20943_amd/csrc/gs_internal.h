@@ -1,0 +1,100 @@
+// Internal declarations of the HIP rasterizer: constants, the projected
+// record layout, and the host-side launchers each kernel file provides.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "airgs_gs.h"
+
+namespace gs {
+
+constexpr int kTile = GS_TILE;
+constexpr double kNear = 0.2;       // cull when camera-space z <= kNear
+constexpr double kDilate = 0.3;     // screen-space low-pass, px^2
+constexpr double kGuard = 1.3;      // guard band on x/z, y/z in the Jacobian
+constexpr float kAlphaMax = 0.99f;  // opacity cap per composited entry
+constexpr float kAlphaMin = 1.0f / 255.0f;
+constexpr float kTStop = 1e-4f;     // stop before T would fall below this
+
+constexpr uint8_t kClampR = 1, kClampG = 2, kClampB = 4, kClampU = 8, kClampV = 16,
+                  kVisible = 32;
+
+constexpr int kSplatFloats = 12;    // projected record stride (3 x float4)
+constexpr int kGrad2dFloats = 12;   // screen-space gradient record stride
+
+__host__ __device__ inline int tiles_across(int px) { return (px + kTile - 1) / kTile; }
+
+// ---------------------------------------------------------------- timing
+// Stages whose device time the context can measure with HIP events.
+enum Stage {
+  kStApply = 0, kStProject, kStDepthSort, kStCountScan, kStEmit, kStSegmentSort, kStRanges,
+  kStRenderFwd, kStRenderBwd, kStProjectBwd, kStApplyBwd, kStL1, kStAdam, kStFill, kStageCount
+};
+static_assert(kStageCount == GS_STAGE_COUNT, "stage table out of sync with the header");
+
+struct StageTimer {
+  virtual void begin(int stage, hipStream_t s) = 0;
+  virtual void end(int stage, hipStream_t s) = 0;
+  virtual ~StageTimer() = default;
+};
+// Active timer of the C ABI call running on this host thread (or null).
+extern thread_local StageTimer* g_timer;
+
+struct StageScope {
+  int stage;
+  hipStream_t stream;
+  StageScope(int st, hipStream_t s) : stage(st), stream(s) {
+    if (g_timer) g_timer->begin(stage, stream);
+  }
+  ~StageScope() {
+    if (g_timer) g_timer->end(stage, stream);
+  }
+};
+
+// ---------------------------------------------------------------- launchers
+// apply
+void launch_apply(const gs_gaussians& anchor, const float* delta, const uint8_t* mask, int gw,
+                  int gh, gs_gaussians& frame, hipStream_t s);
+void launch_apply_bwd(int n, const gs_frame_update& upd, const gs_gaussians& grad,
+                      float* dL_ddelta, hipStream_t s);
+// project
+void launch_project(const gs_gaussians& g, const gs_camera* cams_dev, int n_views,
+                    const gs_projected& out, hipStream_t s);
+void launch_project_bwd(const gs_gaussians& g, const gs_camera* cams_dev, int n_views,
+                        const gs_projected& proj, const float* grad2d, gs_gaussians& grad,
+                        hipStream_t s);
+// sort / binning
+struct BinSortPlan {
+  int n_views;
+  int n;
+  int ld;
+  int64_t capacity;
+  int64_t n_segments;
+};
+size_t bin_sort_workspace_bytes(int n_views, int ld, int64_t capacity, int64_t n_segments);
+// Runs everything up to the instance count; returns the device pointer of M.
+// The second stage emits, sorts and builds ranges once M is known.
+struct BinSortState;
+hipError_t bin_sort_stage1(const BinSortPlan& p, const gs_projected& proj,
+                           const gs_camera* cams_dev, void* ws, hipStream_t s,
+                           uint32_t** d_count);
+hipError_t bin_sort_stage2(const BinSortPlan& p, const gs_projected& proj,
+                           const gs_camera* cams_dev, uint32_t M, gs_tile_lists& lists, void* ws,
+                           hipStream_t s);
+// render
+void launch_render_fwd(const gs_projected& proj, const gs_tile_lists& lists, int n_views, int W,
+                       int H, const float bg[3], float* image, float* final_T,
+                       int32_t* n_contrib, hipStream_t s);
+void launch_render_bwd(const gs_projected& proj, const gs_tile_lists& lists, int n_views, int W,
+                       int H, const float bg[3], const float* final_T, const int32_t* n_contrib,
+                       const float* dL_dimage, float* grad2d, hipStream_t s);
+// training support
+void launch_l1(const float* image, const float* target, int64_t count, float* grad,
+               double* loss, hipStream_t s);
+void launch_adam(float* p, const float* g, float* m, float* v, int64_t count, float lr, float b1,
+                 float b2, float eps, float bc1, float bc2, hipStream_t s);
+void launch_fill_u32(uint32_t* p, uint32_t value, int64_t count, hipStream_t s);
+void launch_fill_f32(float* p, float value, int64_t count, hipStream_t s);
+
+}  // namespace gs

@@ -1,0 +1,547 @@
+// Tile binning and depth ordering.
+//
+// The order the renderer needs is, per tile segment, the instances sorted by
+// (FP32 depth, Gaussian id).  It is reached in two sorts that both use the
+// same LDS-resident onesweep LSD radix sort (stable, 8-bit digits, one
+// global histogram pass, then one pass per digit with decoupled look-back
+// over dynamically numbered partitions):
+//   1. the (view, depth) keys of the V*n projected Gaussians;
+//   2. after emitting every Gaussian's tiles in that depth order, the
+//      instances by their segment id only.
+// Stability of (2) keeps the depth order of (1) inside each segment, and
+// stability of (1) keeps ascending ids for equal depths, so the result is
+// the (segment, depth, id) order -- while the per-instance sort moves only
+// ceil(log2(segments)/8) digits of 32-bit keys instead of 5-7 digits of
+// 64-bit keys.
+#include <algorithm>
+
+#include "gs_internal.h"
+
+namespace gs {
+namespace {
+
+constexpr int kBlock = 256;
+constexpr int kItems = 16;
+constexpr int kPart = kBlock * kItems;  // keys per onesweep partition
+constexpr uint32_t kFlagAgg = 1u << 30;
+constexpr uint32_t kFlagPre = 2u << 30;
+constexpr uint32_t kValMask = (1u << 30) - 1u;
+constexpr int kMaxPasses = 8;
+
+__device__ __forceinline__ uint64_t wave_ballot(bool p) { return __builtin_amdgcn_ballot_w64(p); }
+
+__device__ __forceinline__ uint32_t ld_relaxed(const uint32_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_relaxed(uint32_t* p, uint32_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+template <typename K>
+__device__ __forceinline__ uint32_t digit_of(K key, int shift) {
+  return (uint32_t)(key >> shift) & 0xFFu;
+}
+
+// Exclusive scan of one value per thread over a 256-thread block.
+__device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t x, uint32_t* s_wave,
+                                                         uint32_t* total) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  uint32_t v = x;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const uint32_t y = __shfl_up(v, off, 64);
+    if (lane >= off) v += y;
+  }
+  if (lane == 63) s_wave[wave] = v;
+  __syncthreads();
+  uint32_t pre = 0;
+  for (int k = 0; k < wave; ++k) pre += s_wave[k];
+  if (total) *total = s_wave[0] + s_wave[1] + s_wave[2] + s_wave[3];
+  __syncthreads();
+  return pre + v - x;
+}
+
+// ------------------------------------------------------------ radix sort
+template <typename K>
+__global__ __launch_bounds__(kBlock) void k_histogram(const K* __restrict__ keys, uint32_t n,
+                                                      int shift0, int passes,
+                                                      uint32_t* __restrict__ hist) {
+  __shared__ uint32_t h[kMaxPasses * 256];
+  for (int t = threadIdx.x; t < passes * 256; t += kBlock) h[t] = 0;
+  __syncthreads();
+  for (uint32_t i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
+    const K k = keys[i];
+    for (int p = 0; p < passes; ++p) atomicAdd(&h[p * 256 + digit_of(k, shift0 + 8 * p)], 1u);
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < passes * 256; t += kBlock)
+    if (h[t]) atomicAdd(&hist[t], h[t]);
+}
+
+// Exclusive scan of each pass's 256-bin histogram (one block).
+__global__ __launch_bounds__(kBlock) void k_hist_scan(const uint32_t* __restrict__ hist,
+                                                      int passes, uint32_t* __restrict__ off) {
+  __shared__ uint32_t s_wave[4];
+  for (int p = 0; p < passes; ++p) {
+    const uint32_t x = hist[p * 256 + threadIdx.x];
+    off[p * 256 + threadIdx.x] = block_exclusive_scan(x, s_wave, nullptr);
+  }
+}
+
+// One digit pass.  Each block takes the next partition id, ranks its keys
+// stably by digit in LDS (wave ballots find equal digits among the 64 lanes
+// of a wave, per-wave counters in LDS carry the rank across items and
+// waves), publishes its per-digit counts, looks back over earlier
+// partitions for the global prefix, then scatters through LDS so that the
+// global writes come out in digit-contiguous runs.
+template <typename K>
+__global__ __launch_bounds__(kBlock) void k_onesweep(
+    const K* __restrict__ kin, const uint32_t* __restrict__ vin, K* __restrict__ kout,
+    uint32_t* __restrict__ vout, uint32_t n, int shift, const uint32_t* __restrict__ dig_off,
+    uint32_t* lookback, uint32_t* counter) {
+  __shared__ uint32_t s_part;
+  __shared__ uint32_t s_wh[4][256];
+  __shared__ uint32_t s_dstart[256];
+  __shared__ uint32_t s_gbase[256];
+  __shared__ uint32_t s_wave[4];
+  __shared__ K s_k[kPart];
+  __shared__ uint32_t s_v[kPart];
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  if (tid == 0) s_part = atomicAdd(counter, 1u);
+  for (int t = tid; t < 4 * 256; t += kBlock) (&s_wh[0][0])[t] = 0;
+  __syncthreads();
+  const uint32_t part = s_part;
+  const uint32_t base = part * (uint32_t)kPart + (uint32_t)wave * 64u * kItems;
+
+  K k[kItems];
+  uint32_t val[kItems], rank[kItems], dig[kItems];
+#pragma unroll
+  for (int j = 0; j < kItems; ++j) {
+    const uint32_t idx = base + j * 64 + lane;
+    if (idx < n) {
+      k[j] = kin[idx];
+      val[j] = vin[idx];
+    } else {
+      k[j] = 0;
+      val[j] = 0;
+    }
+  }
+  const uint64_t lower = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+#pragma unroll
+  for (int j = 0; j < kItems; ++j) {
+    const bool valid = base + j * 64 + lane < n;
+    const uint32_t d = valid ? digit_of(k[j], shift) : 0u;
+    uint64_t peers = wave_ballot(valid);
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      const bool bit = (d >> b) & 1u;
+      const uint64_t bb = wave_ballot(bit);
+      peers &= bit ? bb : ~bb;
+    }
+    const uint32_t below = (uint32_t)__popcll(peers & lower);
+    const uint32_t cnt = (uint32_t)__popcll(peers);
+    uint32_t prev = 0;
+    if (valid) prev = s_wh[wave][d];
+    if (valid && below == cnt - 1) s_wh[wave][d] = prev + cnt;
+    rank[j] = prev + below;
+    dig[j] = d;
+  }
+  __syncthreads();
+  {
+    const uint32_t d = (uint32_t)tid;
+    uint32_t run = 0;
+#pragma unroll
+    for (int w = 0; w < 4; ++w) {
+      const uint32_t c = s_wh[w][d];
+      s_wh[w][d] = run;
+      run += c;
+    }
+    uint32_t* mine = lookback + (size_t)part * 256 + d;
+    st_relaxed(mine, (part == 0 ? kFlagPre : kFlagAgg) | run);
+    const uint32_t dstart = block_exclusive_scan(run, s_wave, nullptr);
+    s_dstart[d] = dstart;
+    uint32_t excl = 0;
+    if (part > 0) {
+      int64_t p = (int64_t)part - 1;
+      while (true) {
+        const uint32_t sv = ld_relaxed(lookback + (size_t)p * 256 + d);
+        if ((sv & ~kValMask) == 0u) {
+          __builtin_amdgcn_s_sleep(1);
+          continue;
+        }
+        excl += sv & kValMask;
+        if (sv & kFlagPre) break;
+        --p;
+      }
+      st_relaxed(mine, kFlagPre | (excl + run));
+    }
+    s_gbase[d] = dig_off[d] + excl - dstart;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < kItems; ++j) {
+    if (base + j * 64 + lane < n) {
+      const uint32_t lp = s_dstart[dig[j]] + s_wh[wave][dig[j]] + rank[j];
+      s_k[lp] = k[j];
+      s_v[lp] = val[j];
+    }
+  }
+  __syncthreads();
+  const uint32_t start = part * (uint32_t)kPart;
+  const uint32_t nvalid = (n - start) < (uint32_t)kPart ? (n - start) : (uint32_t)kPart;
+  for (uint32_t t = tid; t < nvalid; t += kBlock) {
+    const K kk = s_k[t];
+    const uint32_t g = s_gbase[digit_of(kk, shift)] + t;
+    kout[g] = kk;
+    vout[g] = s_v[t];
+  }
+}
+
+// ------------------------------------------------------------ binning
+// Per-view tile geometry from the device cameras: seg_base (V+1), tx (V).
+__global__ void k_view_info(const gs_camera* __restrict__ cams, int V, uint32_t* seg_base,
+                            int32_t* txv) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  uint32_t acc = 0;
+  for (int v = 0; v < V; ++v) {
+    const int tx = tiles_across(cams[v].width), ty = tiles_across(cams[v].height);
+    seg_base[v] = acc;
+    txv[v] = tx;
+    acc += (uint32_t)(tx * ty);
+  }
+  seg_base[V] = acc;
+}
+
+// (view, depth) keys of every (view, Gaussian); culled ones sort last.
+__global__ __launch_bounds__(kBlock) void k_depth_keys(int n, int ld, int V,
+                                                       const uint32_t* __restrict__ depth_bits,
+                                                       const int32_t* __restrict__ tiles,
+                                                       uint64_t* __restrict__ keys,
+                                                       uint32_t* __restrict__ vals) {
+  const uint32_t j = blockIdx.x * kBlock + threadIdx.x;
+  if (j >= (uint32_t)n * (uint32_t)V) return;
+  const uint32_t v = j / (uint32_t)n, i = j - v * (uint32_t)n;
+  const size_t r = (size_t)v * ld + i;
+  const uint32_t d = tiles[r] > 0 ? depth_bits[r] : 0xFFFFFFFFu;
+  keys[j] = ((uint64_t)v << 32) | d;
+  vals[j] = i;
+}
+
+// Instance count of each depth-sorted entry, and partial sums per chunk.
+__global__ __launch_bounds__(kBlock) void k_count_reduce(uint32_t N, int ld,
+                                                         const uint64_t* __restrict__ keys,
+                                                         const uint32_t* __restrict__ vals,
+                                                         const int32_t* __restrict__ tiles,
+                                                         uint32_t* __restrict__ cnt,
+                                                         uint32_t* __restrict__ chunk_sums) {
+  __shared__ uint32_t s_wave[4];
+  const uint32_t c0 = blockIdx.x * (uint32_t)kPart;
+  uint32_t acc = 0;
+  for (int j = 0; j < kItems; ++j) {
+    const uint32_t e = c0 + j * kBlock + threadIdx.x;
+    if (e < N) {
+      const uint32_t v = (uint32_t)(keys[e] >> 32);
+      const uint32_t c = (uint32_t)tiles[(size_t)v * ld + vals[e]];
+      cnt[e] = c;
+      acc += c;
+    }
+  }
+  uint32_t tot;
+  block_exclusive_scan(acc, s_wave, &tot);
+  if (threadIdx.x == 0) chunk_sums[blockIdx.x] = tot;
+}
+
+// Exclusive scan of the chunk sums in place (one block); total to *total.
+__global__ __launch_bounds__(kBlock) void k_chunk_scan(uint32_t* __restrict__ sums, uint32_t nb,
+                                                       uint32_t* __restrict__ total) {
+  __shared__ uint32_t s_wave[4];
+  uint32_t carry = 0;
+  for (uint32_t b0 = 0; b0 < nb; b0 += kBlock) {
+    const uint32_t b = b0 + threadIdx.x;
+    const uint32_t x = b < nb ? sums[b] : 0u;
+    uint32_t tot;
+    const uint32_t e = block_exclusive_scan(x, s_wave, &tot);
+    if (b < nb) sums[b] = carry + e;
+    carry += tot;
+  }
+  if (threadIdx.x == 0) *total = carry;
+}
+
+// Exclusive offsets of every entry: chunk offset + scan inside the chunk.
+// Thread t of a block owns entries c0 + 16t .. c0 + 16t + 15.
+__global__ __launch_bounds__(kBlock) void k_count_scan(uint32_t N, const uint32_t* __restrict__ cnt,
+                                                       const uint32_t* __restrict__ chunk_off,
+                                                       uint32_t* __restrict__ offs) {
+  __shared__ uint32_t s_wave[4];
+  const uint32_t e0 = blockIdx.x * (uint32_t)kPart + threadIdx.x * kItems;
+  uint32_t c[kItems];
+  uint32_t acc = 0;
+#pragma unroll
+  for (int j = 0; j < kItems; ++j) {
+    c[j] = (e0 + j < N) ? cnt[e0 + j] : 0u;
+    acc += c[j];
+  }
+  uint32_t run = chunk_off[blockIdx.x] + block_exclusive_scan(acc, s_wave, nullptr);
+#pragma unroll
+  for (int j = 0; j < kItems; ++j) {
+    if (e0 + j < N) offs[e0 + j] = run;
+    run += c[j];
+  }
+}
+
+// Emit (segment, Gaussian id) for each tile of each depth-sorted entry.
+__global__ __launch_bounds__(kBlock) void k_emit(uint32_t N, int ld,
+                                                 const uint64_t* __restrict__ keys,
+                                                 const uint32_t* __restrict__ vals,
+                                                 const uint32_t* __restrict__ cnt,
+                                                 const uint32_t* __restrict__ offs,
+                                                 const int4* __restrict__ rect,
+                                                 const uint32_t* __restrict__ seg_base,
+                                                 const int32_t* __restrict__ txv,
+                                                 uint32_t* __restrict__ seg_out,
+                                                 uint32_t* __restrict__ id_out) {
+  const uint32_t e = blockIdx.x * kBlock + threadIdx.x;
+  if (e >= N || cnt[e] == 0) return;
+  const uint32_t v = (uint32_t)(keys[e] >> 32), g = vals[e];
+  const int4 r = rect[(size_t)v * ld + g];
+  const uint32_t sb = seg_base[v];
+  const int tx = txv[v];
+  uint32_t o = offs[e];
+  for (int ty = r.y; ty < r.w; ++ty)
+    for (int x = r.x; x < r.z; ++x) {
+      seg_out[o] = sb + (uint32_t)(ty * tx + x);
+      id_out[o] = g;
+      ++o;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_ranges(uint32_t M, const uint32_t* __restrict__ seg,
+                                                   uint32_t* __restrict__ ranges) {
+  const uint32_t j = blockIdx.x * kBlock + threadIdx.x;
+  if (j >= M) return;
+  const uint32_t s = seg[j];
+  if (j == 0 || seg[j - 1] != s) ranges[2 * (size_t)s] = j;
+  if (j == M - 1 || seg[j + 1] != s) ranges[2 * (size_t)s + 1] = j + 1;
+}
+
+__global__ __launch_bounds__(kBlock) void k_keys64(uint32_t M, int V, int ld,
+                                                   const uint32_t* __restrict__ seg,
+                                                   const uint32_t* __restrict__ ids,
+                                                   const uint32_t* __restrict__ seg_base,
+                                                   const uint32_t* __restrict__ depth_bits,
+                                                   uint64_t* __restrict__ keys) {
+  const uint32_t j = blockIdx.x * kBlock + threadIdx.x;
+  if (j >= M) return;
+  const uint32_t s = seg[j];
+  int lo = 0, hi = V - 1;  // last view whose base <= s
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (seg_base[mid] <= s) lo = mid; else hi = mid - 1;
+  }
+  keys[j] = ((uint64_t)s << 32) | depth_bits[(size_t)lo * ld + ids[j]];
+}
+
+__global__ void k_fill_u32(uint32_t* p, uint32_t value, size_t count) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
+       i += (size_t)gridDim.x * blockDim.x)
+    p[i] = value;
+}
+
+__global__ void k_fill_f32(float* p, float value, size_t count) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
+       i += (size_t)gridDim.x * blockDim.x)
+    p[i] = value;
+}
+
+// ------------------------------------------------------------ host side
+inline int bits_for(uint64_t count) {  // bits to hold values 0 .. count-1
+  int b = 0;
+  while (b < 64 && ((uint64_t)1 << b) < count) ++b;
+  return b;
+}
+
+inline size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
+
+inline uint32_t cdiv(uint64_t a, uint64_t b) { return (uint32_t)((a + b - 1) / b); }
+
+struct Layout {
+  size_t dk0, dk1, dv0, dv1, cnt, offs, chunks, segk0, segk1, segv_alt, hist, digoff, counters,
+      lookback, seg_base, txv, total, bytes;
+};
+
+Layout make_layout(int V, int ld, int64_t cap, int64_t nseg) {
+  Layout L{};
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = o;
+    o = align_up(o + bytes);
+    return at;
+  };
+  const size_t N = (size_t)V * (size_t)ld;
+  const size_t depth_passes = (size_t)((32 + bits_for((uint64_t)V) + 7) / 8);
+  const size_t seg_passes = (size_t)((bits_for((uint64_t)nseg) + 7) / 8);
+  const size_t lb_depth = depth_passes * cdiv(N, kPart) * 256;
+  const size_t lb_seg = seg_passes * cdiv((uint64_t)cap, kPart) * 256;
+  L.dk0 = take(N * 8);
+  L.dk1 = take(N * 8);
+  L.dv0 = take(N * 4);
+  L.dv1 = take(N * 4);
+  L.cnt = take(N * 4);
+  L.offs = take(N * 4);
+  L.chunks = take(((size_t)cdiv(N, kPart) + 1) * 4);
+  L.segk0 = take((size_t)cap * 4);
+  L.segk1 = take((size_t)cap * 4);
+  L.segv_alt = take((size_t)cap * 4);
+  L.hist = take(kMaxPasses * 256 * 4);
+  L.digoff = take(kMaxPasses * 256 * 4);
+  L.counters = take(kMaxPasses * 4);
+  L.lookback = take((lb_depth > lb_seg ? lb_depth : lb_seg) * 4 + 4);
+  L.seg_base = take(((size_t)V + 1) * 4);
+  L.txv = take((size_t)V * 4);
+  L.total = take(16);
+  L.bytes = o;
+  return L;
+}
+
+template <typename T>
+T* at(void* ws, size_t off) {
+  return reinterpret_cast<T*>(static_cast<char*>(ws) + off);
+}
+
+// Stable LSD radix sort of (key, value) pairs on bits [0, bits), ping-pong
+// between buffer pair 0 and 1; returns the index (0/1) holding the result.
+template <typename K>
+int radix_sort(K* k0, K* k1, uint32_t* v0, uint32_t* v1, uint32_t n, int bits, void* ws,
+               const Layout& L, hipStream_t s) {
+  const int passes = (bits + 7) / 8;
+  if (n == 0 || passes == 0) return 0;
+  uint32_t* hist = at<uint32_t>(ws, L.hist);
+  uint32_t* off = at<uint32_t>(ws, L.digoff);
+  uint32_t* counters = at<uint32_t>(ws, L.counters);
+  uint32_t* lb = at<uint32_t>(ws, L.lookback);
+  const uint32_t parts = cdiv(n, kPart);
+  const size_t lb_words = (size_t)passes * parts * 256;
+  launch_fill_u32(hist, 0u, (int64_t)passes * 256, s);
+  launch_fill_u32(counters, 0u, kMaxPasses, s);
+  launch_fill_u32(lb, 0u, (int64_t)lb_words, s);
+  const uint32_t hblocks = std::min<uint32_t>(cdiv(n, kBlock * 8), 2048u);
+  hipLaunchKernelGGL(k_histogram<K>, dim3(hblocks), dim3(kBlock), 0, s, k0, n, 0, passes, hist);
+  hipLaunchKernelGGL(k_hist_scan, dim3(1), dim3(kBlock), 0, s, hist, passes, off);
+  K* kb[2] = {k0, k1};
+  uint32_t* vb[2] = {v0, v1};
+  for (int p = 0; p < passes; ++p) {
+    const int src = p & 1;
+    hipLaunchKernelGGL(k_onesweep<K>, dim3(parts), dim3(kBlock), 0, s, kb[src], vb[src],
+                       kb[src ^ 1], vb[src ^ 1], n, 8 * p, off + p * 256,
+                       lb + (size_t)p * parts * 256, counters + p);
+  }
+  return passes & 1;
+}
+
+}  // namespace
+
+void launch_fill_u32(uint32_t* p, uint32_t value, int64_t count, hipStream_t s) {
+  if (count <= 0) return;
+  const int64_t want = (count + 255) / 256;
+  const int blocks = (int)std::min<int64_t>(want, 4096);
+  StageScope scope(kStFill, s);
+  hipLaunchKernelGGL(k_fill_u32, dim3(blocks), dim3(256), 0, s, p, value, (size_t)count);
+}
+
+void launch_fill_f32(float* p, float value, int64_t count, hipStream_t s) {
+  if (count <= 0) return;
+  const int64_t want = (count + 255) / 256;
+  const int blocks = (int)std::min<int64_t>(want, 4096);
+  StageScope scope(kStFill, s);
+  hipLaunchKernelGGL(k_fill_f32, dim3(blocks), dim3(256), 0, s, p, value, (size_t)count);
+}
+
+size_t bin_sort_workspace_bytes(int V, int ld, int64_t cap, int64_t nseg) {
+  return make_layout(V, ld, cap, nseg).bytes;
+}
+
+hipError_t bin_sort_stage1(const BinSortPlan& p, const gs_projected& proj,
+                           const gs_camera* cams_dev, void* ws, hipStream_t s,
+                           uint32_t** d_count) {
+  const Layout L = make_layout(p.n_views, p.ld, p.capacity, p.n_segments);
+  const uint32_t N = (uint32_t)p.n_views * (uint32_t)p.n;
+  uint32_t* total = at<uint32_t>(ws, L.total);
+  *d_count = total;
+  hipLaunchKernelGGL(k_view_info, dim3(1), dim3(64), 0, s, cams_dev, p.n_views,
+                     at<uint32_t>(ws, L.seg_base), at<int32_t>(ws, L.txv));
+  if (N == 0) {
+    launch_fill_u32(total, 0u, 1, s);
+    return hipGetLastError();
+  }
+  uint64_t* dk0 = at<uint64_t>(ws, L.dk0);
+  uint64_t* dk1 = at<uint64_t>(ws, L.dk1);
+  uint32_t* dv0 = at<uint32_t>(ws, L.dv0);
+  uint32_t* dv1 = at<uint32_t>(ws, L.dv1);
+  const int dbits = 32 + bits_for((uint64_t)p.n_views);
+  int which;
+  {
+    StageScope scope(kStDepthSort, s);
+    hipLaunchKernelGGL(k_depth_keys, dim3(cdiv(N, kBlock)), dim3(kBlock), 0, s, p.n, p.ld,
+                       p.n_views, proj.depth_bits, proj.tiles_touched, dk0, dv0);
+    which = radix_sort<uint64_t>(dk0, dk1, dv0, dv1, N, dbits, ws, L, s);
+  }
+  const uint64_t* sk = which ? dk1 : dk0;
+  const uint32_t* sv = which ? dv1 : dv0;
+  uint32_t* cnt = at<uint32_t>(ws, L.cnt);
+  uint32_t* chunks = at<uint32_t>(ws, L.chunks);
+  const uint32_t nch = cdiv(N, kPart);
+  StageScope scope(kStCountScan, s);
+  hipLaunchKernelGGL(k_count_reduce, dim3(nch), dim3(kBlock), 0, s, N, p.ld, sk, sv,
+                     proj.tiles_touched, cnt, chunks);
+  hipLaunchKernelGGL(k_chunk_scan, dim3(1), dim3(kBlock), 0, s, chunks, nch, total);
+  hipLaunchKernelGGL(k_count_scan, dim3(nch), dim3(kBlock), 0, s, N, cnt, chunks,
+                     at<uint32_t>(ws, L.offs));
+  return hipGetLastError();
+}
+
+hipError_t bin_sort_stage2(const BinSortPlan& p, const gs_projected& proj,
+                           const gs_camera* cams_dev, uint32_t M, gs_tile_lists& lists, void* ws,
+                           hipStream_t s) {
+  (void)cams_dev;
+  const Layout L = make_layout(p.n_views, p.ld, p.capacity, p.n_segments);
+  const uint32_t N = (uint32_t)p.n_views * (uint32_t)p.n;
+  launch_fill_u32(lists.ranges, 0u, 2 * p.n_segments, s);
+  if (M == 0) return hipGetLastError();
+  // The depth sort's pass count is known on the host, so is its result buffer.
+  const int dbits = 32 + bits_for((uint64_t)p.n_views);
+  const int which = ((dbits + 7) / 8) & 1;
+  const uint64_t* sk = which ? at<uint64_t>(ws, L.dk1) : at<uint64_t>(ws, L.dk0);
+  const uint32_t* sv = which ? at<uint32_t>(ws, L.dv1) : at<uint32_t>(ws, L.dv0);
+  const int sbits = bits_for((uint64_t)p.n_segments);
+  const int spasses = (sbits + 7) / 8;
+  uint32_t* segk0 = at<uint32_t>(ws, L.segk0);
+  uint32_t* segk1 = at<uint32_t>(ws, L.segk1);
+  uint32_t* alt = at<uint32_t>(ws, L.segv_alt);
+  // emit into the buffer that makes the sorted ids land in lists.vals
+  uint32_t* v0 = (spasses & 1) ? alt : lists.vals;
+  uint32_t* v1 = (spasses & 1) ? lists.vals : alt;
+  {
+    StageScope scope(kStEmit, s);
+    hipLaunchKernelGGL(k_emit, dim3(cdiv(N, kBlock)), dim3(kBlock), 0, s, N, p.ld, sk, sv,
+                       at<uint32_t>(ws, L.cnt), at<uint32_t>(ws, L.offs),
+                       reinterpret_cast<const int4*>(proj.rect), at<uint32_t>(ws, L.seg_base),
+                       at<int32_t>(ws, L.txv), segk0, v0);
+  }
+  int which2;
+  {
+    StageScope scope(kStSegmentSort, s);
+    which2 = radix_sort<uint32_t>(segk0, segk1, v0, v1, M, sbits, ws, L, s);
+  }
+  const uint32_t* seg_sorted = which2 ? segk1 : segk0;
+  StageScope scope(kStRanges, s);
+  hipLaunchKernelGGL(k_ranges, dim3(cdiv(M, kBlock)), dim3(kBlock), 0, s, M, seg_sorted,
+                     lists.ranges);
+  if (lists.keys)
+    hipLaunchKernelGGL(k_keys64, dim3(cdiv(M, kBlock)), dim3(kBlock), 0, s, M, p.n_views, p.ld,
+                       seg_sorted, lists.vals, at<uint32_t>(ws, L.seg_base), proj.depth_bits,
+                       lists.keys);
+  return hipGetLastError();
+}
+
+}  // namespace gs

@@ -1,0 +1,67 @@
+// Training support: the L1 photometric term (AirGS Eq. (1)) and the Adam
+// update (Kingma & Ba 2015).  Both are elementwise and HBM-bound.
+#include "gs_internal.h"
+
+namespace gs {
+namespace {
+
+// grad = sign(I - I*) / count; per-block FP64 partial sums of |I - I*| are
+// reduced across the wave with shuffles and added to *loss once per block.
+__global__ __launch_bounds__(256) void k_l1(const float* __restrict__ img,
+                                            const float* __restrict__ tgt, int64_t count,
+                                            float inv_count, float* __restrict__ grad,
+                                            double* __restrict__ loss) {
+  __shared__ double s_w[4];
+  double acc = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < count;
+       i += (int64_t)gridDim.x * 256) {
+    const float d = img[i] - tgt[i];
+    acc += (double)fabsf(d);
+    grad[i] = d > 0.f ? inv_count : (d < 0.f ? -inv_count : 0.f);
+  }
+  for (int off = 32; off >= 1; off >>= 1) acc += __shfl_xor(acc, off, 64);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0) s_w[wave] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) atomicAdd(loss, ((s_w[0] + s_w[1]) + (s_w[2] + s_w[3])) / (double)count);
+}
+
+__global__ __launch_bounds__(256) void k_adam(float* __restrict__ p, const float* __restrict__ g,
+                                              float* __restrict__ m, float* __restrict__ v,
+                                              int64_t count, float lr, float b1, float b2,
+                                              float eps, float ibc1, float ibc2) {
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < count;
+       i += (int64_t)gridDim.x * 256) {
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.f - b1) * gi;
+    const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    p[i] -= lr * (mi * ibc1) / (sqrtf(vi * ibc2) + eps);
+  }
+}
+
+inline int grid_for(int64_t count) {
+  const int64_t want = (count + 255) / 256;
+  return (int)(want < 8192 ? want : 8192);
+}
+
+}  // namespace
+
+void launch_l1(const float* image, const float* target, int64_t count, float* grad, double* loss,
+               hipStream_t s) {
+  if (count <= 0) return;
+  StageScope scope(kStL1, s);
+  hipLaunchKernelGGL(k_l1, dim3(grid_for(count)), dim3(256), 0, s, image, target, count,
+                     (float)(1.0 / (double)count), grad, loss);
+}
+
+void launch_adam(float* p, const float* g, float* m, float* v, int64_t count, float lr, float b1,
+                 float b2, float eps, float bc1, float bc2, hipStream_t s) {
+  if (count <= 0) return;
+  StageScope scope(kStAdam, s);
+  hipLaunchKernelGGL(k_adam, dim3(grid_for(count)), dim3(256), 0, s, p, g, m, v, count, lr, b1,
+                     b2, eps, 1.f / bc1, 1.f / bc2);
+}
+
+}  // namespace gs

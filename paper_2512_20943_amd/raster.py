@@ -1,0 +1,141 @@
+"""Pipeline around the C ABI: workspaces, capacity growth and autograd.
+
+``Rasterizer`` owns the per-call buffers of one (scene size, camera set)
+shape and chains gs_project -> gs_bin_sort -> gs_render_fwd, and
+gs_render_bwd for the backward.  ``GSRender`` and ``GSFrameRender`` are the
+``torch.autograd.Function`` front ends: the first differentiates the images
+w.r.t. means, log-scales, quaternions, opacity logits and SH coefficients;
+the second w.r.t. the per-frame delta images applied to a frozen anchor
+(frame = anchor + pruned delta, AirGS Eq. (12)).
+"""
+from __future__ import annotations
+
+import torch
+
+from . import gs
+
+
+class Rasterizer:
+    def __init__(self, ctx: gs.Context | None = None, capacity: int = 1 << 20,
+                 with_keys: bool = False, growth: float = 1.25):
+        self.ctx = ctx or gs.default_context()
+        self.capacity = int(capacity)
+        self.with_keys = with_keys
+        self.growth = growth
+        self._lists = None
+        self._ws_sort = None
+        self._proj = None
+        self._ws_bwd = None
+
+    # -- buffers ------------------------------------------------------------
+    def _projected(self, V, n, ld, device):
+        p = self._proj
+        if p is None or p.V != V or p.n != n or p.ld != ld:
+            self._proj = gs.Projected.empty(V, n, ld, device)
+        return self._proj
+
+    def _sort_buffers(self, V, ld, nseg, device):
+        L = self._lists
+        if L is None or L.capacity < self.capacity or L.n_segments != nseg:
+            self._lists = gs.TileLists(self.capacity, nseg, self.with_keys, device)
+        need = gs.bin_sort_workspace_size(V, ld, self._lists.capacity, nseg)
+        if self._ws_sort is None or self._ws_sort.numel() < need:
+            self._ws_sort = torch.empty(need, dtype=torch.uint8, device=device)
+        return self._lists, self._ws_sort
+
+    def bwd_workspace(self, V, ld, device):
+        need = gs.render_bwd_workspace_size(V, ld)
+        if self._ws_bwd is None or self._ws_bwd.numel() < need:
+            self._ws_bwd = torch.empty(need, dtype=torch.uint8, device=device)
+        return self._ws_bwd
+
+    # -- passes -------------------------------------------------------------
+    def project(self, g: gs.Gaussians, cams: gs.Cameras, stream=None) -> gs.Projected:
+        proj = self._projected(cams.V, g.n, g.ld, g.mean.device)
+        gs.gs_project(self.ctx, g, cams, proj, stream)
+        return proj
+
+    def bin_sort(self, proj: gs.Projected, cams: gs.Cameras, stream=None) -> gs.TileLists:
+        device = proj.splat.device
+        nseg = cams.n_segments()
+        while True:
+            lists, ws = self._sort_buffers(cams.V, proj.ld, nseg, device)
+            try:
+                gs.gs_bin_sort(self.ctx, proj, cams, lists, ws, stream)
+                return lists
+            except gs.GsError as e:
+                if e.code != gs.GS_ERR_CAPACITY:
+                    raise
+                self.capacity = max(int(lists.count * self.growth) + 1024, self.capacity * 2)
+
+    def forward(self, g: gs.Gaussians, cams: gs.Cameras, bg=(0.0, 0.0, 0.0), stream=None):
+        W, H = cams.wh[0]
+        device = g.mean.device
+        proj = self.project(g, cams, stream)
+        lists = self.bin_sort(proj, cams, stream)
+        image = torch.empty(cams.V, 3, H, W, device=device)
+        final_T = torch.empty(cams.V, H, W, device=device)
+        n_contrib = torch.empty(cams.V, H, W, dtype=torch.int32, device=device)
+        gs.gs_render_fwd(self.ctx, proj, lists, cams, bg, image, final_T, n_contrib, stream)
+        return dict(image=image, final_T=final_T, n_contrib=n_contrib, proj=proj, lists=lists)
+
+    def backward(self, g: gs.Gaussians, cams: gs.Cameras, state: dict, dL_dimage: torch.Tensor,
+                 grad: gs.Gaussians, bg=(0.0, 0.0, 0.0), upd=None, dL_ddelta=None, stream=None):
+        ws = self.bwd_workspace(cams.V, g.ld, g.mean.device)
+        gs.gs_render_bwd(self.ctx, g, state["proj"], state["lists"], cams, bg, state["final_T"],
+                         state["n_contrib"], dL_dimage.contiguous(), grad, ws, upd, dL_ddelta,
+                         stream)
+        return ws
+
+
+class GSRender(torch.autograd.Function):
+    """images = render(mean, log_scale, quat, opacity, sh) for the cameras."""
+
+    @staticmethod
+    def forward(ctx, mean, log_scale, quat, opacity, sh, meta):
+        raster, cams, n, deg, bg = meta
+        g = gs.Gaussians(n, deg, mean.shape[-1], mean.contiguous(), log_scale.contiguous(),
+                         quat.contiguous(), opacity.contiguous(), sh.contiguous())
+        out = raster.forward(g, cams, bg)
+        ctx.meta = meta
+        ctx.g = g
+        ctx.state = out
+        return out["image"]
+
+    @staticmethod
+    def backward(ctx, dimage):
+        raster, cams, n, deg, bg = ctx.meta
+        grad = gs.Gaussians.zeros_like(ctx.g)
+        raster.backward(ctx.g, cams, ctx.state, dimage, grad, bg)
+        return grad.mean, grad.log_scale, grad.quat, grad.opacity, grad.sh, None
+
+
+class GSFrameRender(torch.autograd.Function):
+    """images = render(apply(anchor, delta, mask)); gradient to the (8, gh, gw)
+    delta images, anchor frozen."""
+
+    @staticmethod
+    def forward(ctx, delta, meta):
+        raster, cams, anchor, mask, gw, gh, bg, frame = meta
+        gs.gs_apply_frame_update(raster.ctx, anchor, delta.contiguous(), mask, gw, gh, frame)
+        out = raster.forward(frame, cams, bg)
+        ctx.meta = meta
+        ctx.state = out
+        return out["image"]
+
+    @staticmethod
+    def backward(ctx, dimage):
+        raster, cams, anchor, mask, gw, gh, bg, frame = ctx.meta
+        grad = gs.Gaussians.zeros_like(frame)
+        dd = torch.empty(8, gh, gw, device=dimage.device)
+        raster.backward(frame, cams, ctx.state, dimage, grad, bg,
+                        upd=(anchor.quat, mask, gw, gh), dL_ddelta=dd)
+        return dd, None
+
+
+def frame_of(anchor: gs.Gaussians) -> gs.Gaussians:
+    """Frame buffers for an anchor: new mean/quat/opacity planes, log-scale
+    and SH shared with the anchor."""
+    return gs.Gaussians(anchor.n, anchor.deg, anchor.ld, torch.empty_like(anchor.mean),
+                        anchor.log_scale, torch.empty_like(anchor.quat),
+                        torch.empty_like(anchor.opacity), anchor.sh)

@@ -1,0 +1,382 @@
+"""HIP path vs the FP64 oracle, through the C ABI, on seeded inputs.
+
+Bars: apply results bit-exact; projection within 1e-3 px (screen mean) and
+1e-4 relative (conic, colour, opacity); tile lists, keys and ranges
+bit-exact; images and final transmittance within 1e-4 absolute with equal
+n_contrib, except at pixels where the oracle finds a skip/stop decision
+within a small relative margin of its threshold (counted, must be rare);
+gradients within 1e-3 relative.
+"""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2512_20943_amd import gs, scenes
+from paper_2512_20943_amd.raster import GSFrameRender, GSRender, Rasterizer, frame_of
+from tests.gpu_helpers import (IMG_ATOL, MEAN2D_ATOL, assert_close_rel, assert_grad_close,
+                               gpu_forward, lists_to_numpy, projected_to_oracle, require_gpu)
+
+pytestmark = pytest.mark.gpu
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def small_frame_workload(seed=0):
+    """20,000 Gaussians of the 300k-frame distribution (SH 3) seen by 4 arc
+    cameras at 200x150 (ragged in both directions: 12.5 x 9.4 tiles)."""
+    scene = scenes.make_scene(20_000, seed, -3.0, 3.0, -4.0, 0.5, 3)
+    cams = scenes.arc_cameras(4, 5.0, 200, 150)
+    return scene, cams
+
+
+def compare_projection(P_gpu, P_or, vis_only=True):
+    fl_g, fl_o = P_gpu["flags"], P_or["flags"]
+    np.testing.assert_array_equal(fl_g & 0x38, fl_o & 0x38)  # visible + guard-band bits
+    vis = (fl_o & 32) > 0
+    np.testing.assert_array_equal(P_gpu["rect"][vis], P_or["rect"][vis])
+    np.testing.assert_array_equal(P_gpu["tiles"], P_or["tiles"])
+    np.testing.assert_array_equal(P_gpu["depth_bits"][vis], P_or["depth_bits"][vis])
+    d = np.abs(P_gpu["mean2d"][vis] - P_or["mean2d"][vis]).max(initial=0.0)
+    assert d <= MEAN2D_ATOL, f"mean2d error {d}"
+    assert_close_rel(P_gpu["conic"][vis], P_or["conic"][vis], what="conic")
+    assert_close_rel(P_gpu["rgb"][vis], P_or["rgb"][vis], what="rgb")
+    assert_close_rel(P_gpu["alpha_hat"][vis], P_or["alpha_hat"][vis], what="opacity")
+    # colour clamp bits may differ only where the oracle colour is ~0
+    cg, co = fl_g & 7, fl_o & 7
+    diff = (cg != co) & vis
+    if diff.any():
+        assert P_or["rgb"][diff].max() < 1e-5
+    return int(vis.sum())
+
+
+def compare_images(img_gpu, img_or, max_frac=5e-3):
+    near = img_or["near_threshold"]
+    keep = ~near
+    frac = near.mean()
+    assert frac <= max_frac, f"{frac:.4%} pixels near a threshold"
+    im_g = img_gpu["image"].cpu().numpy()
+    T_g = img_gpu["final_T"].cpu().numpy()
+    n_g = img_gpu["n_contrib"].cpu().numpy()
+    err = np.abs(im_g - img_or["image"]).max(axis=1)[keep]
+    assert err.max(initial=0.0) <= IMG_ATOL, f"image error {err.max():.3e}"
+    errT = np.abs(T_g - img_or["final_T"])[keep]
+    assert errT.max(initial=0.0) <= IMG_ATOL, f"final_T error {errT.max():.3e}"
+    np.testing.assert_array_equal(n_g[keep], img_or["n_contrib"][keep])
+    return float(err.max(initial=0.0)), int(near.sum())
+
+
+# ---------------------------------------------------------------------------
+
+def test_context_and_version():
+    require_gpu()
+    ctx = gs.default_context()
+    assert ctx.lib.gs_version() >= 100
+
+
+@pytest.mark.parametrize("n,level", [(5_000, 0.3), (300_000, 0.1)])
+def test_apply_bit_exact(n, level):
+    require_gpu()
+    say(f"apply n={n} level={level}")
+    gw = gh = scenes.grid_side(n)
+    sc = scenes.make_scene(n, 3, -3, 3, -4, 0.5, 0)
+    d = scenes.make_delta(n, gw, gh, 4)
+    mask = scenes.prune_mask(d, n, level)
+    ref = oracle.apply(sc, d, mask, gw, gh)
+    g = gs.Gaussians.from_scene(sc)
+    f = frame_of(g)
+    gs.gs_apply_frame_update(gs.default_context(), g, torch.from_numpy(d).cuda(),
+                             torch.from_numpy(mask).cuda(), gw, gh, f)
+    torch.cuda.synchronize()
+    for k, t in (("mean", f.mean), ("quat", f.quat), ("opacity", f.opacity)):
+        np.testing.assert_array_equal(t.cpu().numpy()[..., :n], ref[k][..., :n])
+
+
+@pytest.mark.parametrize("which", ["plain_10k", "frame_20k_4v"])
+def test_projection_and_lists_bit_exact(which):
+    require_gpu()
+    say(f"projection+lists {which}")
+    if which == "plain_10k":
+        scene, cams, _ = scenes.workload_plain_10k(0)
+    else:
+        scene, cams = small_frame_workload(1)
+    g, gc, r, out = gpu_forward(scene, cams)
+    P_or = oracle.project(scene, cams)
+    P_g = projected_to_oracle(out["proj"])
+    nvis = compare_projection(P_g, P_or)
+    assert nvis > 0
+    L_or = oracle.bin_sort(P_or, cams)
+    L_g = lists_to_numpy(out["lists"])
+    assert L_g["count"] == L_or["count"] > 0
+    np.testing.assert_array_equal(L_g["keys"], L_or["keys"])
+    np.testing.assert_array_equal(L_g["vals"], L_or["vals"])
+    np.testing.assert_array_equal(L_g["ranges"], L_or["ranges"])
+    # stage-B replay: the oracle's ordering of the GPU's own binning inputs
+    L_rep = oracle.bin_sort(P_or, cams, depth_bits=P_g["depth_bits"], rect=P_g["rect"],
+                            tiles=P_g["tiles"])
+    np.testing.assert_array_equal(L_g["vals"], L_rep["vals"])
+
+
+@pytest.mark.parametrize("which", ["plain_10k", "frame_20k_4v"])
+def test_render_forward_parity(which):
+    require_gpu()
+    say(f"render fwd {which}")
+    if which == "plain_10k":
+        scene, cams, _ = scenes.workload_plain_10k(0)
+        bg = (0.0, 0.0, 0.0)
+    else:
+        scene, cams = small_frame_workload(2)
+        bg = (0.25, 0.5, 0.75)
+    g, gc, r, out = gpu_forward(scene, cams, bg)
+    P_or, L_or, img_or = oracle.forward(scene, cams, bg)
+    err, near = compare_images(out, img_or)
+    say(f"  max image error {err:.2e}, {near} pixels near a threshold")
+
+
+def test_render_forward_is_deterministic():
+    require_gpu()
+    scene, cams = small_frame_workload(3)
+    _, _, _, a = gpu_forward(scene, cams)
+    _, _, _, b = gpu_forward(scene, cams)
+    assert torch.equal(a["image"], b["image"])
+    assert torch.equal(a["n_contrib"], b["n_contrib"])
+
+
+def _oracle_grads(scene, cams, P_or, L_or, img_or, seed):
+    rng = np.random.default_rng(seed)
+    target = rng.uniform(0, 1, size=img_or["image"].shape)
+    _, gI = oracle.l1(img_or["image"], target)
+    gI[np.broadcast_to(img_or["near_threshold"][:, None], gI.shape)] = 0.0
+    g2d, grads = oracle.backward(scene, cams, P_or, L_or, gI)
+    return gI, g2d, grads
+
+
+@pytest.mark.parametrize("which", ["plain_10k", "frame_20k_4v"])
+def test_render_backward_parity(which):
+    require_gpu()
+    say(f"render bwd {which}")
+    if which == "plain_10k":
+        scene, cams, _ = scenes.workload_plain_10k(0)
+    else:
+        scene, cams = small_frame_workload(4)
+    g, gc, r, out = gpu_forward(scene, cams)
+    P_or, L_or, img_or = oracle.forward(scene, cams)
+    gI, g2d_or, gr_or = _oracle_grads(scene, cams, P_or, L_or, img_or, 5)
+    grad = gs.Gaussians.zeros_like(g)
+    ws = r.backward(g, gc, out, torch.from_numpy(gI.astype(np.float32)).cuda(), grad)
+    torch.cuda.synchronize()
+    n = scene["n"]
+    g2d = ws.view(torch.float32)[: gc.V * g.ld * 12].view(gc.V, g.ld, 12)[:, :n, :9].cpu().numpy()
+    assert_grad_close(g2d, g2d_or, "screen-space gradients")
+    for name in ("mean", "log_scale", "quat", "opacity", "sh"):
+        got = getattr(grad, name).cpu().numpy()[..., :n]
+        assert_grad_close(got, gr_or[name][..., :n], name)
+
+
+def test_frame_update_gradient_parity():
+    """Backward to the (8, gh, gw) delta images on the 2,000-Gaussian, 64x64
+    subset of the temporal frame-update workload."""
+    require_gpu()
+    full = scenes.make_scene(300_000, 0, -3.0, 3.0, -4.0, 0.5, 3)
+    sc = scenes.subset(full, 2000)
+    n = 2000
+    gw = gh = scenes.grid_side(n)
+    d = scenes.make_delta(n, gw, gh, 7)
+    mask = scenes.prune_mask(d, n, 0.3)
+    cams = scenes.arc_cameras(1, 5.0, 64, 64)
+    frame = oracle.apply(sc, d, mask, gw, gh)
+    P_or, L_or, img_or = oracle.forward(frame, cams)
+    gI, _, gr_or = _oracle_grads(frame, cams, P_or, L_or, img_or, 8)
+    gd_or = oracle.apply_bwd(sc, mask, gw, gh, gr_or)
+    anchor = gs.Gaussians.from_scene(sc)
+    r = Rasterizer(capacity=1 << 16)
+    gc = gs.Cameras(cams)
+    fr = frame_of(anchor)
+    delta = torch.from_numpy(d).cuda().requires_grad_(True)
+    mask_t = torch.from_numpy(mask).cuda()
+    img = GSFrameRender.apply(delta, (r, gc, anchor, mask_t, gw, gh, (0.0, 0.0, 0.0), fr))
+    img.backward(torch.from_numpy(gI.astype(np.float32)).cuda())
+    torch.cuda.synchronize()
+    got = delta.grad.cpu().numpy()
+    assert np.all(got.reshape(8, -1)[:, n:] == 0)
+    assert np.all(got.reshape(8, -1)[:, :n][:, mask.reshape(-1)[:n] == 0] == 0)
+    assert_grad_close(got, gd_or, "delta images")
+
+
+def test_autograd_function_returns_all_parameter_grads():
+    require_gpu()
+    scene, cams, _ = scenes.workload_plain_10k(1)
+    g = gs.Gaussians.from_scene(scene)
+    gc = gs.Cameras(cams)
+    r = Rasterizer(capacity=1 << 16)
+    leaves = [t.clone().requires_grad_(True) for t in g.planes()]
+    img = GSRender.apply(*leaves, (r, gc, g.n, g.deg, (0.0, 0.0, 0.0)))
+    (img.abs().sum()).backward()
+    for t in leaves:
+        assert t.grad is not None and torch.isfinite(t.grad).all()
+    assert leaves[0].grad.abs().sum() > 0
+
+
+def test_l1_and_adam_match_closed_forms():
+    require_gpu()
+    ctx = gs.default_context()
+    rng = np.random.default_rng(9)
+    img = rng.uniform(0, 1, 5000).astype(np.float32)
+    tgt = img.copy()
+    tgt[::3] = rng.uniform(0, 1, tgt[::3].shape)
+    loss_or, g_or = oracle.l1(img, tgt)
+    grad = torch.empty(5000, device="cuda")
+    loss = torch.zeros(1, dtype=torch.float64, device="cuda")
+    gs.gs_l1_loss_grad(ctx, torch.from_numpy(img).cuda(), torch.from_numpy(tgt).cuda(), grad, loss)
+    torch.cuda.synchronize()
+    assert abs(loss.item() - loss_or) <= 1e-9
+    np.testing.assert_allclose(grad.cpu().numpy(), g_or, rtol=1e-6, atol=0)
+    th = rng.normal(size=4096).astype(np.float32)
+    gg = rng.normal(size=4096).astype(np.float32)
+    m = np.zeros(4096)
+    v = np.zeros(4096)
+    p_t, g_t = torch.from_numpy(th.copy()).cuda(), torch.from_numpy(gg).cuda()
+    m_t, v_t = torch.zeros(4096, device="cuda"), torch.zeros(4096, device="cuda")
+    ref = th.astype(np.float64)
+    for step in range(1, 4):
+        ref, m, v = oracle.adam(ref, gg, m, v, step)
+        gs.gs_adam_step(ctx, p_t, g_t, m_t, v_t, step)
+    torch.cuda.synchronize()
+    np.testing.assert_allclose(p_t.cpu().numpy(), ref, rtol=0, atol=1e-6)
+
+
+# ---------------------------------------------------------------------------
+# edge cases
+# ---------------------------------------------------------------------------
+
+def test_empty_scene_renders_background():
+    require_gpu()
+    sc = scenes.make_scene(0, 0, sh_degree=1)
+    cams = scenes.axis_camera(33, 17)
+    g, gc, r, out = gpu_forward(sc, cams, bg=(0.1, 0.2, 0.3))
+    assert out["lists"].count == 0
+    im = out["image"].cpu().numpy()
+    np.testing.assert_allclose(im[0, :, :, :], np.array([0.1, 0.2, 0.3])[:, None, None] *
+                               np.ones((3, 17, 33)), atol=1e-7)
+    assert (out["n_contrib"] == 0).all() and (out["final_T"] == 1).all()
+
+
+def test_all_culled_and_tiny_images():
+    require_gpu()
+    sc = scenes.make_scene(500, 1, -1, 1, -3, 0.5, 0)
+    behind = scenes.stack_cams([(np.eye(3), np.array([0.0, 0.0, -10.0]),
+                                 np.array([50.0, 50.0, 0.5, 0.5]), (1, 1))])
+    _, _, _, out = gpu_forward(sc, behind)
+    assert out["lists"].count == 0
+    for W, H in ((1, 1), (17, 33), (16, 16)):
+        cams = scenes.axis_camera(W, H)
+        _, _, _, out = gpu_forward(sc, cams)
+        _, L_or, img_or = oracle.forward(sc, cams)
+        assert out["lists"].count == L_or["count"]
+        compare_images(out, img_or, max_frac=0.05)
+
+
+def test_single_centred_gaussian_and_huge_gaussian():
+    require_gpu()
+    sc = scenes.make_scene(2, 0, 0, 0, -3, 0.0, 0)
+    sc["mean"][:, :2] = 0.0
+    sc["mean"][2, 1] = 0.5
+    sc["log_scale"][:, 1] = 0.3  # sigma ~ 1.35 -> covers every tile
+    sc["opacity"][:2] = [0.2, -1.0]
+    cams = scenes.axis_camera(96, 80)
+    g, gc, r, out = gpu_forward(sc, cams)
+    _, L_or, img_or = oracle.forward(sc, cams)
+    assert out["lists"].count == L_or["count"]
+    compare_images(out, img_or)
+    TX, TY = 6, 5
+    assert (out["lists"].ranges[:TX * TY, 1] - out["lists"].ranges[:TX * TY, 0] >= 1).all()
+
+
+def test_capacity_error_reports_the_need_and_retry_succeeds():
+    require_gpu()
+    scene, cams, _ = scenes.workload_plain_10k(0)
+    g = gs.Gaussians.from_scene(scene)
+    gc = gs.Cameras(cams)
+    ctx = gs.default_context()
+    proj = gs.Projected.empty(gc.V, g.n, g.ld)
+    gs.gs_project(ctx, g, gc, proj)
+    small = gs.TileLists(100, gc.n_segments())
+    ws = torch.empty(gs.bin_sort_workspace_size(gc.V, g.ld, 100, gc.n_segments()),
+                     dtype=torch.uint8, device="cuda")
+    with pytest.raises(gs.GsError) as ei:
+        gs.gs_bin_sort(ctx, proj, gc, small, ws)
+    assert ei.value.code == gs.GS_ERR_CAPACITY
+    need = small.count
+    assert need > 100
+    r = Rasterizer(capacity=100)
+    lists = r.bin_sort(proj, gc)
+    assert lists.count == need
+
+
+def test_invalid_arguments_are_rejected():
+    require_gpu()
+    scene, cams, _ = scenes.workload_plain_10k(0)
+    g = gs.Gaussians.from_scene(scene)
+    gc = gs.Cameras(cams)
+    ctx = gs.default_context()
+    proj = gs.Projected.empty(gc.V, g.n, g.ld)
+    bad = gs.Gaussians(g.n, 4, g.ld, *g.planes())
+    with pytest.raises(gs.GsError) as ei:
+        gs.gs_project(ctx, bad, gc, proj)
+    assert ei.value.code == gs.GS_ERR_INVALID_ARG
+    bad = gs.Gaussians(g.n, g.deg, g.ld + 1, *g.planes())
+    with pytest.raises(gs.GsError):
+        gs.gs_project(ctx, bad, gc, proj)
+    two = gs.Cameras(scenes.stack_cams([
+        (np.eye(3), np.array([0, 0, 4.0]), np.array([100.0, 100, 64, 64]), (128, 128)),
+        (np.eye(3), np.array([0, 0, 4.0]), np.array([100.0, 100, 32, 32]), (64, 64))]))
+    p2 = gs.Projected.empty(2, g.n, g.ld)
+    gs.gs_project(ctx, g, two, p2)
+    r = Rasterizer(capacity=1 << 16)
+    lists = r.bin_sort(p2, two)
+    with pytest.raises(gs.GsError):
+        gs.gs_render_fwd(ctx, p2, lists, two, (0, 0, 0), torch.empty(2, 3, 128, 128, device="cuda"),
+                         torch.empty(2, 128, 128, device="cuda"),
+                         torch.empty(2, 128, 128, dtype=torch.int32, device="cuda"))
+    ws = torch.empty(16, dtype=torch.uint8, device="cuda")
+    with pytest.raises(gs.GsError) as ei:
+        gs.gs_bin_sort(ctx, proj, gc, gs.TileLists(1000, gc.n_segments()), ws)
+    assert ei.value.code == gs.GS_ERR_OOM
+
+
+# ---------------------------------------------------------------------------
+# full-size frame workload: sampled checks
+# ---------------------------------------------------------------------------
+
+def test_full_frame_300k_20_views_sampled():
+    """300,000 Gaussians, SH 3, 20 views at 1352x1014, in the launch
+    configuration the benchmark times: every projection record is compared,
+    view 0's tile lists bit for bit, and view 0's image in full."""
+    require_gpu()
+    say("full frame 300k x 20 views")
+    scene, cams, _ = scenes.workload_frame_300k(0)
+    g, gc, r, out = gpu_forward(scene, cams, capacity=1 << 26)
+    say(f"  instances {out['lists'].count}")
+    P_or = oracle.project(scene, cams)
+    P_g = projected_to_oracle(out["proj"])
+    compare_projection(P_g, P_or)
+    cam0 = {k: v[:1] for k, v in cams.items()}
+    P0 = {k: (v[:1] if isinstance(v, np.ndarray) else v) for k, v in P_or.items()}
+    P0["V"] = 1
+    L0 = oracle.bin_sort(P0, cam0)
+    L_g = lists_to_numpy(out["lists"])
+    nseg0 = L0["n_segments"]
+    rg = L_g["ranges"][:nseg0]
+    np.testing.assert_array_equal(rg, L0["ranges"])
+    M0 = int(rg[:, 1].max())
+    np.testing.assert_array_equal(L_g["vals"][:M0], L0["vals"])
+    np.testing.assert_array_equal(L_g["keys"][:M0], L0["keys"])
+    img0 = oracle.render_fwd(P0, L0, cam0)
+    out0 = {k: out[k][:1] for k in ("image", "final_T", "n_contrib")}
+    err, near = compare_images(out0, img0)
+    say(f"  view 0 max image error {err:.2e}, {near} near-threshold pixels")
