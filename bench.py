@@ -24,6 +24,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -34,8 +36,8 @@ PEAK_ALU_TFLOPS = 78.6
 
 # Algorithmic FP32 operations per (pixel, entry) pair, FMA counted as 2 and
 # a transcendental as 1 (see the design doc for the breakdown).
-FLOP_PER_PAIR_FWD = 24
-FLOP_PER_PAIR_BWD = 66
+FLOP_PER_PAIR_FWD = 26
+FLOP_PER_PAIR_BWD = 68
 
 
 def log(msg):
@@ -51,6 +53,12 @@ def parse():
     ap.add_argument("--no-frame-step", action="store_true")
     ap.add_argument("--views", type=int, default=20)
     ap.add_argument("--gaussians", type=int, default=300_000)
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--serve-rates", default="500,2000",
+                    help="aggregate Poisson arrival rates (requests/s)")
+    ap.add_argument("--serve-seconds", type=float, default=2.0)
+    ap.add_argument("--serve-warmup", type=float, default=0.5)
+    ap.add_argument("--serve-frames", type=int, default=300)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of known size (counter calibration)")
     return ap.parse_args()
@@ -250,6 +258,48 @@ def cpu_baseline(scene, cams, target_scene):
                         f"not counted"))
 
 
+def serving(args, scene):
+    """Served views/s and p50/p99 latency of the continuous-batching server
+    vs the plain one-request-per-launch renderer on the same Poisson trace:
+    300 resident frames of the 300k-Gaussian sequence, 64 viewers, random
+    viewpoints on a sphere of radius 4-6, resolutions 640x480 / 1280x720 /
+    1920x1080."""
+    import copy
+
+    import torch
+
+    from paper_2512_20943_amd import serve
+    t0 = time.perf_counter()
+    seq = serve.ResidentSequence(scene, args.serve_frames, seed=0)
+    log(f"resident sequence: {args.serve_frames} frames, {seq.device_bytes() / 2**30:.2f} GiB "
+        f"({time.perf_counter() - t0:.1f} s to generate)")
+    budget = 32 << 30
+    server = serve.Server(seq, budget_bytes=budget, max_batch=32)
+    plain = serve.PlainRenderer(seq)
+    # warm both paths (allocations, first launches)
+    wt = serve.make_trace(64, 1e6, None, 64, seq.n_frames, 99)
+    server.run(copy.deepcopy(wt))
+    serve.run_plain(plain, copy.deepcopy(wt[:8]))
+    out = {"frames": seq.n_frames, "viewers": 64, "budget_gib": budget / 2**30,
+           "resident_gib": round(seq.device_bytes() / 2**30, 3), "max_batch": 32,
+           "seconds": args.serve_seconds, "warmup_s": args.serve_warmup, "rates": {}}
+    for rate in [float(x) for x in args.serve_rates.split(",")]:
+        trace = serve.make_trace(None, rate, args.serve_warmup + args.serve_seconds, 64,
+                                 seq.n_frames, int(rate))
+        tb = copy.deepcopy(trace)
+        server.batches.clear()
+        server.run(tb)
+        sb = serve.summarize(tb, args.serve_warmup)
+        sb["mean_batch"] = round(float(np.mean(server.batches)), 2)
+        tp = copy.deepcopy(trace)
+        serve.run_plain(plain, tp)
+        sp = serve.summarize(tp, args.serve_warmup)
+        out["rates"][str(int(rate))] = {"requests": len(trace), "batched": sb, "plain": sp}
+        log(f"serving @ {rate:.0f} req/s: batched {sb}  plain {sp}")
+        torch.cuda.synchronize()
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -302,6 +352,8 @@ def main():
             "stage_ms_per_step": {k: round(v[0] / k2, 4) for k, v in st2.items() if v[1] > 0}}
         log(f"frame-update step: {wall2 / k2 * 1e3:.2f} ms")
         del fs
+    if not args.no_serve:
+        result["serving"] = serving(args, scene)
     if not args.no_cpu_baseline:
         log("timing the FP64 oracle on one view")
         result["cpu_baseline"] = cpu_baseline(scene, cams, target_scene)

@@ -219,6 +219,21 @@ gs_status gs_render_fwd(gs_ctx* ctx, const gs_projected* proj, const gs_tile_lis
                         const gs_opts* opts, float* image, float* final_T, int32_t* n_contrib,
                         void* stream);
 
+/* Batched rendering of n_views requests of (possibly) different sizes in one
+ * persistent launch: workgroups take (request, tile) items from a shared
+ * device-wide queue until it is drained (view delivery, Sec. IV-B: the
+ * client applies the update and renders the frame).  Same compositing as
+ * gs_render_fwd.  images: packed FP32 planes, request v's (3, H_v, W_v)
+ * image starting at float offset 3 * sum_{u<v} W_u H_u.  final_T and
+ * n_contrib are not produced.  workspace: gs_render_batched_workspace_size
+ * bytes; the queue state lives there, so concurrent calls need distinct
+ * workspaces. */
+size_t gs_render_batched_workspace_size(int n_views);
+gs_status gs_render_fwd_batched(gs_ctx* ctx, const gs_projected* proj,
+                                const gs_tile_lists* lists, const gs_camera* cams_host,
+                                const gs_camera* cams_dev, int n_views, const gs_opts* opts,
+                                float* images, void* workspace, size_t ws_bytes, void* stream);
+
 /* Backward of gs_project + gs_render_fwd for dL/dimage (V, 3, H, W):
  * transmittance is recovered by walking each pixel's list back from
  * n_contrib.  Gradients w.r.t. the frame's mean, log_scale, quat, opacity

@@ -777,6 +777,8 @@ void or_render_bwd(int V, int n, const double* mean2d, const double* conic, cons
             const size_t p = (size_t)y * W + x;
             double gI[3];
             for (int ch = 0; ch < 3; ++ch) gI[ch] = dL_dimage[(size_t)v * 3 * pix + ch * pix + p];
+            /* a pixel with zero image gradient contributes nothing */
+            if (gI[0] == 0.0 && gI[1] == 0.0 && gI[2] == 0.0) continue;
             composite_pixel_bwd(&S, vals + b, (int)(e - b), (double)x, (double)y, bg + 3 * v, gI,
                                 loc);
           }

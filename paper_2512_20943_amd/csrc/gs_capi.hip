@@ -364,6 +364,37 @@ gs_status gs_render_fwd(gs_ctx* c, const gs_projected* proj, const gs_tile_lists
   return GS_OK;
 }
 
+size_t gs_render_batched_workspace_size(int V) {
+  if (V <= 0) return 0;
+  return gs::render_batched_workspace_bytes(V);
+}
+
+gs_status gs_render_fwd_batched(gs_ctx* c, const gs_projected* proj, const gs_tile_lists* lists,
+                                const gs_camera* ch, const gs_camera* cd, int V,
+                                const gs_opts* opts, float* images, void* ws, size_t ws_bytes,
+                                void* stream) {
+  if (!c) return fail(nullptr, GS_ERR_INVALID_ARG, "ctx is NULL");
+  TimerGuard timer_guard(c);
+  GS_TRY(check_cams(c, ch, cd, V));
+  if (!proj) return fail(c, GS_ERR_INVALID_ARG, "projected is NULL");
+  GS_TRY(check_projected(c, proj, V, proj->ld));
+  if (!lists || !lists->vals || !lists->ranges)
+    return fail(c, GS_ERR_INVALID_ARG, "tile lists are NULL");
+  const int64_t nseg = segments_of(ch, V);
+  if (lists->n_segments != nseg)
+    return fail(c, GS_ERR_INVALID_ARG, "tile lists were built for other cameras");
+  if (!images) return fail(c, GS_ERR_INVALID_ARG, "images is NULL");
+  const size_t need = gs::render_batched_workspace_bytes(V);
+  if (!ws || ws_bytes < need)
+    return fail(c, GS_ERR_OOM, "batched render workspace %zu < %zu bytes", ws_bytes, need);
+  GS_TRY(use_device(c));
+  const float zero[3] = {0.f, 0.f, 0.f};
+  gs::launch_render_batched(*proj, *lists, cd, V, nseg, opts ? opts->bg : zero, images, ws,
+                            (hipStream_t)stream);
+  GS_LAUNCHED(c, "render_fwd_batched");
+  return GS_OK;
+}
+
 gs_status gs_render_bwd(gs_ctx* c, const gs_gaussians* frame, const gs_projected* proj,
                         const gs_tile_lists* lists, const gs_camera* ch, const gs_camera* cd,
                         int V, const gs_opts* opts, const float* final_T, const int32_t* n_contrib,

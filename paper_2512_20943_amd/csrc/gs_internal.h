@@ -86,6 +86,10 @@ hipError_t bin_sort_stage2(const BinSortPlan& p, const gs_projected& proj,
 void launch_render_fwd(const gs_projected& proj, const gs_tile_lists& lists, int n_views, int W,
                        int H, const float bg[3], float* image, float* final_T,
                        int32_t* n_contrib, hipStream_t s);
+size_t render_batched_workspace_bytes(int V);
+void launch_render_batched(const gs_projected& proj, const gs_tile_lists& lists,
+                           const gs_camera* cams_dev, int V, int64_t total_segments,
+                           const float bg[3], float* images, void* ws, hipStream_t s);
 void launch_render_bwd(const gs_projected& proj, const gs_tile_lists& lists, int n_views, int W,
                        int H, const float bg[3], const float* final_T, const int32_t* n_contrib,
                        const float* dL_dimage, float* grad2d, hipStream_t s);

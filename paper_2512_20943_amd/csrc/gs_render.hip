@@ -23,7 +23,6 @@
 namespace gs {
 namespace {
 
-constexpr int kBlock = 256;
 constexpr float kLog2e = 1.4426950408889634f;
 constexpr float kLn255 = 5.541263545158426f;
 
@@ -119,202 +118,329 @@ __device__ __forceinline__ float wave_sum_lane63(float v) {
   return v;
 }
 
-__global__ __launch_bounds__(kBlock) void k_render_fwd(
+// ---------------------------------------------------------------- forward
+// One 64-lane wave per 16x16 tile.  Lane l owns pixel (l & 7, l >> 3) of
+// each of the four 8x8 quadrants ("slot" w = quadrant w), so a record's
+// quadrant mask selects slots uniformly across the wave.
+constexpr int kFwdBatch = 256;  // records staged per batch (4 per lane)
+constexpr int kBwdBatch = 128;  // records staged per backward batch (2 per lane)
+
+struct FwdShared {
+  float4 a[kFwdBatch];
+  float4 b[kFwdBatch];
+  float c[kFwdBatch];
+  uint32_t m[kFwdBatch];
+};
+
+__device__ __forceinline__ uint32_t live_mask(const bool (&done)[4]) {
+  uint32_t live = 0;
+#pragma unroll
+  for (int w = 0; w < 4; ++w)
+    if (__builtin_amdgcn_ballot_w64(!done[w]) != 0) live |= 1u << w;
+  return live;
+}
+
+// Composites one tile; all 64 lanes of the workgroup call it.  image points
+// at the view's (3, H, W) planes; final_T / n_contrib at its (H, W) planes or
+// are null.
+__device__ __forceinline__ void render_tile_fwd(FwdShared& sh, const float4* __restrict__ sv,
+                                                const uint32_t* __restrict__ vals, uint2 rg,
+                                                int tx, int ty, int W, int H, float bg0,
+                                                float bg1, float bg2, float* __restrict__ image,
+                                                float* __restrict__ final_T,
+                                                int32_t* __restrict__ n_contrib) {
+  const int lane = threadIdx.x;
+  float fx[4], fy[4], T[4], c0[4], c1[4], c2[4];
+  int last[4];
+  bool done[4], inside[4];
+#pragma unroll
+  for (int w = 0; w < 4; ++w) {
+    const int x = tx * kTile + (w & 1) * 8 + (lane & 7);
+    const int y = ty * kTile + (w >> 1) * 8 + (lane >> 3);
+    fx[w] = (float)x;
+    fy[w] = (float)y;
+    inside[w] = x < W && y < H;
+    done[w] = !inside[w];
+    T[w] = 1.f;
+    c0[w] = c1[w] = c2[w] = 0.f;
+    last[w] = 0;
+  }
+  uint32_t live = live_mask(done);
+  const float ox = (float)(tx * kTile), oy = (float)(ty * kTile);
+  for (uint32_t b0 = rg.x; b0 < rg.y && live != 0; b0 += kFwdBatch) {
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < kFwdBatch / 64; ++r) {
+      const int k = r * 64 + lane;
+      const uint32_t e = b0 + (uint32_t)k;
+      if (e < rg.y) {
+        const uint32_t g = vals[e];
+        const float4 q0 = sv[3 * (size_t)g], q1 = sv[3 * (size_t)g + 1],
+                     q2 = sv[3 * (size_t)g + 2];
+        const Rec rr = make_rec(q0, q1, q2);
+        sh.a[k] = rr.a;
+        sh.b[k] = rr.b;
+        sh.c[k] = rr.c.x;
+        sh.m[k] = quadrant_mask(q0, q1, q2, ox, oy);
+      }
+    }
+    __syncthreads();
+    const int nb = (int)((rg.y - b0) < (uint32_t)kFwdBatch ? (rg.y - b0) : (uint32_t)kFwdBatch);
+    for (int k = 0; k < nb; ++k) {
+      const uint32_t m = __builtin_amdgcn_readfirstlane(sh.m[k]) & live;
+      if (m == 0) continue;
+      const float4 a = sh.a[k];
+      const float4 b = sh.b[k];
+      const float cb = sh.c[k];
+      const int pos = (int)(b0 - rg.x) + k + 1;
+#pragma unroll
+      for (int w = 0; w < 4; ++w) {
+        if (m & (1u << w)) {
+          if (!done[w]) {
+            const float dx = a.x - fx[w], dy = a.y - fy[w];
+            const float power = eval_power(a, b.x, dx, dy);
+            if (!(power > 0.f)) {
+              const float alpha = fminf(kAlphaMax, eval_ea(power, b.y));
+              if (alpha >= kAlphaMin) {
+                const float Tn = T[w] * (1.f - alpha);
+                if (Tn < kTStop) {
+                  done[w] = true;
+                } else {
+                  const float wt = alpha * T[w];
+                  c0[w] = fmaf(b.z, wt, c0[w]);
+                  c1[w] = fmaf(b.w, wt, c1[w]);
+                  c2[w] = fmaf(cb, wt, c2[w]);
+                  T[w] = Tn;
+                  last[w] = pos;
+                }
+              }
+            }
+          }
+          if (__builtin_amdgcn_ballot_w64(!done[w]) == 0) live &= ~(1u << w);
+        }
+      }
+      if (live == 0) break;
+    }
+  }
+  const size_t pix = (size_t)W * H;
+#pragma unroll
+  for (int w = 0; w < 4; ++w) {
+    if (!inside[w]) continue;
+    const size_t p = (size_t)fy[w] * W + (size_t)fx[w];
+    image[p] = c0[w] + T[w] * bg0;
+    image[pix + p] = c1[w] + T[w] * bg1;
+    image[2 * pix + p] = c2[w] + T[w] * bg2;
+    if (final_T) final_T[p] = T[w];
+    if (n_contrib) n_contrib[p] = last[w];
+  }
+}
+
+__global__ __launch_bounds__(64) void k_render_fwd(
     const float4* __restrict__ splat, int ld, const uint32_t* __restrict__ vals,
     const uint2* __restrict__ ranges, int W, int H, int TX, int tiles_per_view, float bg0,
     float bg1, float bg2, float* __restrict__ image, float* __restrict__ final_T,
     int32_t* __restrict__ n_contrib) {
-  __shared__ float4 s_a[kBlock];
-  __shared__ float4 s_b[kBlock];
-  __shared__ float s_c[kBlock];
-  __shared__ uint32_t s_m[kBlock];
-
+  __shared__ FwdShared sh;
   const int seg = blockIdx.x;
   const int v = seg / tiles_per_view, tile = seg - v * tiles_per_view;
   const int ty = tile / TX, tx = tile - ty * TX;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int x = tx * kTile + (wave & 1) * 8 + (lane & 7);
-  const int y = ty * kTile + (wave >> 1) * 8 + (lane >> 3);
-  const bool inside = x < W && y < H;
-  const float fx = (float)x, fy = (float)y;
-  const uint2 rg = ranges[seg];
-  const float4* sv = splat + 3 * (size_t)v * ld;
+  const size_t pix = (size_t)W * H;
+  render_tile_fwd(sh, splat + 3 * (size_t)v * ld, vals, ranges[seg], tx, ty, W, H, bg0, bg1, bg2,
+                  image + 3 * pix * v, final_T + pix * v, n_contrib + pix * v);
+}
 
-  float T = 1.f, c0 = 0.f, c1 = 0.f, c2 = 0.f;
-  int last = 0;
-  bool done = !inside;
-  for (uint32_t b0 = rg.x; b0 < rg.y; b0 += kBlock) {
-    if (__syncthreads_count(done) == kBlock) break;
-    const uint32_t e = b0 + threadIdx.x;
-    if (e < rg.y) {
-      const uint32_t g = vals[e];
-      const float4 q0 = sv[3 * (size_t)g], q1 = sv[3 * (size_t)g + 1], q2 = sv[3 * (size_t)g + 2];
-      const Rec r = make_rec(q0, q1, q2);
-      s_a[threadIdx.x] = r.a;
-      s_b[threadIdx.x] = r.b;
-      s_c[threadIdx.x] = r.c.x;
-      s_m[threadIdx.x] = quadrant_mask(q0, q1, q2, (float)(tx * kTile), (float)(ty * kTile));
-    }
-    __syncthreads();
-    const int nb = (int)((rg.y - b0) < (uint32_t)kBlock ? (rg.y - b0) : (uint32_t)kBlock);
-    if (__builtin_amdgcn_ballot_w64(!done) == 0) continue;
-    for (int k = 0; k < nb; ++k) {
-      const uint32_t m = __builtin_amdgcn_readfirstlane(s_m[k]);
-      if (!((m >> wave) & 1u)) continue;
-      if (!done) {
-        const float4 a = s_a[k];
-        const float4 b = s_b[k];
-        const float dx = a.x - fx, dy = a.y - fy;
-        const float power = eval_power(a, b.x, dx, dy);
-        if (!(power > 0.f)) {
-          const float alpha = fminf(kAlphaMax, eval_ea(power, b.y));
-          if (alpha >= kAlphaMin) {
-            const float Tn = T * (1.f - alpha);
-            if (Tn < kTStop) {
-              done = true;
-            } else {
-              const float w = alpha * T;
-              c0 = fmaf(b.z, w, c0);
-              c1 = fmaf(b.w, w, c1);
-              c2 = fmaf(s_c[k], w, c2);
-              T = Tn;
-              last = (int)(b0 - rg.x) + k + 1;
-            }
-          }
-        }
-      }
-      if (__builtin_amdgcn_ballot_w64(!done) == 0) break;
-    }
+// Per-request geometry for the batched renderer: segment base (V+1), pixel
+// base (V+1, in pixels of the packed output), width/height (V).
+__global__ void k_batch_info(const gs_camera* __restrict__ cams, int V, uint32_t* seg_base,
+                             int64_t* pix_base, int2* wh, uint32_t* queue) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  uint32_t s = 0;
+  int64_t p = 0;
+  for (int v = 0; v < V; ++v) {
+    const int W = cams[v].width, H = cams[v].height;
+    seg_base[v] = s;
+    pix_base[v] = p;
+    wh[v] = make_int2(W, H);
+    s += (uint32_t)(tiles_across(W) * tiles_across(H));
+    p += (int64_t)W * H;
   }
-  if (inside) {
-    const size_t pix = (size_t)W * H, p = (size_t)y * W + x;
-    float* im = image + 3 * pix * v;
-    im[p] = c0 + T * bg0;
-    im[pix + p] = c1 + T * bg1;
-    im[2 * pix + p] = c2 + T * bg2;
-    final_T[pix * v + p] = T;
-    n_contrib[pix * v + p] = last;
+  seg_base[V] = s;
+  pix_base[V] = p;
+  *queue = 0u;
+}
+
+// Persistent multi-request renderer: each workgroup repeatedly takes the
+// next (request, tile) item from a device-wide counter until the queue is
+// drained, so requests of uneven sizes share one launch.
+__global__ __launch_bounds__(64) void k_render_persistent(
+    const float4* __restrict__ splat, int ld, const uint32_t* __restrict__ vals,
+    const uint2* __restrict__ ranges, const uint32_t* __restrict__ seg_base,
+    const int64_t* __restrict__ pix_base, const int2* __restrict__ wh, int V, uint32_t total,
+    float bg0, float bg1, float bg2, float* __restrict__ images, uint32_t* __restrict__ queue) {
+  __shared__ FwdShared sh;
+  __shared__ uint32_t s_item;
+  for (;;) {
+    __syncthreads();
+    if (threadIdx.x == 0) s_item = atomicAdd(queue, 1u);
+    __syncthreads();
+    const uint32_t item = s_item;
+    if (item >= total) break;
+    int lo = 0, hi = V - 1;  // request: last v with seg_base[v] <= item
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (seg_base[mid] <= item) lo = mid; else hi = mid - 1;
+    }
+    const int2 d = wh[lo];
+    const int TX = tiles_across(d.x);
+    const int tile = (int)(item - seg_base[lo]);
+    const int ty = tile / TX, tx = tile - ty * TX;
+    render_tile_fwd(sh, splat + 3 * (size_t)lo * ld, vals, ranges[item], tx, ty, d.x, d.y, bg0,
+                    bg1, bg2, images + 3 * pix_base[lo], nullptr, nullptr);
   }
 }
 
-__global__ __launch_bounds__(kBlock) void k_render_bwd(
+// ---------------------------------------------------------------- backward
+struct BwdShared {
+  float4 a[kBwdBatch];
+  float4 b[kBwdBatch];
+  float4 c[kBwdBatch];
+  uint32_t m[kBwdBatch];
+  uint32_t g[kBwdBatch];
+  float acc[9][kBwdBatch];
+};
+
+__device__ __forceinline__ int wave_max(int x) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) x = max(x, __shfl_xor(x, off, 64));
+  return x;
+}
+
+__global__ __launch_bounds__(64) void k_render_bwd(
     const float4* __restrict__ splat, int ld, const uint32_t* __restrict__ vals,
     const uint2* __restrict__ ranges, int W, int H, int TX, int tiles_per_view, float bg0,
     float bg1, float bg2, const float* __restrict__ final_T, const int32_t* __restrict__ n_contrib,
     const float* __restrict__ dL_dimage, float* __restrict__ grad2d) {
-  __shared__ float4 s_a[kBlock];
-  __shared__ float4 s_b[kBlock];
-  __shared__ float4 s_c[kBlock];
-  __shared__ uint32_t s_m[kBlock];
-  __shared__ uint32_t s_g[kBlock];
-  __shared__ float s_acc[kBlock][9];
-  __shared__ int s_max[4];
-
+  __shared__ BwdShared sh;
   const int seg = blockIdx.x;
   const int v = seg / tiles_per_view, tile = seg - v * tiles_per_view;
   const int ty = tile / TX, tx = tile - ty * TX;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int x = tx * kTile + (wave & 1) * 8 + (lane & 7);
-  const int y = ty * kTile + (wave >> 1) * 8 + (lane >> 3);
-  const bool inside = x < W && y < H;
-  const float fx = (float)x, fy = (float)y;
+  const int lane = threadIdx.x;
   const uint2 rg = ranges[seg];
   const float4* sv = splat + 3 * (size_t)v * ld;
-  const size_t pix = (size_t)W * H, p = (size_t)y * W + x;
+  const size_t pix = (size_t)W * H;
+  const float* gi = dL_dimage + 3 * pix * v;
 
-  float T = 1.f, gI0 = 0.f, gI1 = 0.f, gI2 = 0.f;
-  int nc = 0;
-  if (inside) {
-    T = final_T[pix * v + p];
-    nc = n_contrib[pix * v + p];
-    const float* gi = dL_dimage + 3 * pix * v;
-    gI0 = gi[p];
-    gI1 = gi[pix + p];
-    gI2 = gi[2 * pix + p];
-  }
-  // longest walk in the wave and in the block
-  int wmax = nc;
+  float fx[4], fy[4], T[4], g0[4], g1[4], g2[4], B0[4], B1[4], B2[4];
+  int nc[4], wmax[4];
+  int jmax = 0;
 #pragma unroll
-  for (int off = 32; off >= 1; off >>= 1) wmax = max(wmax, __shfl_xor(wmax, off, 64));
-  if (lane == 0) s_max[wave] = wmax;
-  __syncthreads();
-  const int bmax = max(max(s_max[0], s_max[1]), max(s_max[2], s_max[3]));
-  float B0 = bg0, B1 = bg1, B2 = bg2;  // colour behind the current entry
+  for (int w = 0; w < 4; ++w) {
+    const int x = tx * kTile + (w & 1) * 8 + (lane & 7);
+    const int y = ty * kTile + (w >> 1) * 8 + (lane >> 3);
+    fx[w] = (float)x;
+    fy[w] = (float)y;
+    T[w] = 1.f;
+    g0[w] = g1[w] = g2[w] = 0.f;
+    nc[w] = 0;
+    if (x < W && y < H) {
+      const size_t p = (size_t)y * W + x;
+      T[w] = final_T[pix * v + p];
+      nc[w] = n_contrib[pix * v + p];
+      g0[w] = gi[p];
+      g1[w] = gi[pix + p];
+      g2[w] = gi[2 * pix + p];
+    }
+    B0[w] = bg0;
+    B1[w] = bg1;
+    B2[w] = bg2;
+    wmax[w] = __builtin_amdgcn_readfirstlane(wave_max(nc[w]));
+    jmax = max(jmax, wmax[w]);
+  }
+  const float ox = (float)(tx * kTile), oy = (float)(ty * kTile);
 
-  for (int hi = bmax; hi > 0; hi -= kBlock) {
-    const int lo = hi > kBlock ? hi - kBlock : 0;
+  for (int hi = jmax; hi > 0; hi -= kBwdBatch) {
+    const int lo = hi > kBwdBatch ? hi - kBwdBatch : 0;
     __syncthreads();
-    {
-      const int k = (int)threadIdx.x;
+#pragma unroll
+    for (int r = 0; r < kBwdBatch / 64; ++r) {
+      const int k = r * 64 + lane;
       if (lo + k < hi) {
         const uint32_t g = vals[rg.x + (uint32_t)(lo + k)];
-        const float4 q0 = sv[3 * (size_t)g], q1 = sv[3 * (size_t)g + 1], q2 = sv[3 * (size_t)g + 2];
-        const Rec r = make_rec(q0, q1, q2);
-        s_a[k] = r.a;
-        s_b[k] = r.b;
-        s_c[k] = r.c;
-        s_g[k] = g;
-        s_m[k] = quadrant_mask(q0, q1, q2, (float)(tx * kTile), (float)(ty * kTile));
+        const float4 q0 = sv[3 * (size_t)g], q1 = sv[3 * (size_t)g + 1],
+                     q2 = sv[3 * (size_t)g + 2];
+        const Rec rr = make_rec(q0, q1, q2);
+        sh.a[k] = rr.a;
+        sh.b[k] = rr.b;
+        sh.c[k] = rr.c;
+        sh.g[k] = g;
+        sh.m[k] = quadrant_mask(q0, q1, q2, ox, oy);
       }
 #pragma unroll
-      for (int c = 0; c < 9; ++c) s_acc[k][c] = 0.f;
+      for (int c = 0; c < 9; ++c) sh.acc[c][k] = 0.f;
     }
     __syncthreads();
     for (int k = hi - lo - 1; k >= 0; --k) {
       const int j = lo + k;  // position in the tile list
-      if (j >= wmax) continue;
-      const uint32_t m = __builtin_amdgcn_readfirstlane(s_m[k]);
-      if (!((m >> wave) & 1u)) continue;
-      float g[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+      uint32_t m = __builtin_amdgcn_readfirstlane(sh.m[k]);
+#pragma unroll
+      for (int w = 0; w < 4; ++w)
+        if (j >= wmax[w]) m &= ~(1u << w);
+      if (m == 0) continue;
+      const float4 a = sh.a[k];
+      const float4 b = sh.b[k];
+      const float4 c = sh.c[k];
+      float gr[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
       bool contrib = false;
-      if (j < nc) {
-        const float4 a = s_a[k];
-        const float4 b = s_b[k];
-        const float dx = a.x - fx, dy = a.y - fy;
-        const float power = eval_power(a, b.x, dx, dy);
-        if (!(power > 0.f)) {
-          const float ea = eval_ea(power, b.y);
-          const float alpha = fminf(kAlphaMax, ea);
-          if (alpha >= kAlphaMin) {
-            contrib = true;
-            const float4 c = s_c[k];
-            T = __fdividef(T, 1.f - alpha);
-            const float w = alpha * T;
-            g[6] = gI0 * w;
-            g[7] = gI1 * w;
-            g[8] = gI2 * w;
-            const float da = T * (gI0 * (b.z - B0) + gI1 * (b.w - B1) + gI2 * (c.x - B2));
-            if (ea < kAlphaMax) {
-              const float gp = da * alpha;
-              g[5] = da * __builtin_amdgcn_exp2f(power * kLog2e);
-              g[0] = -gp * (c.y * dx + c.z * dy);
-              g[1] = -gp * (c.z * dx + c.w * dy);
-              g[2] = -0.5f * gp * dx * dx;
-              g[3] = -gp * dx * dy;
-              g[4] = -0.5f * gp * dy * dy;
+#pragma unroll
+      for (int w = 0; w < 4; ++w) {
+        if ((m & (1u << w)) && j < nc[w]) {
+          const float dx = a.x - fx[w], dy = a.y - fy[w];
+          const float power = eval_power(a, b.x, dx, dy);
+          if (!(power > 0.f)) {
+            const float ea = eval_ea(power, b.y);
+            const float alpha = fminf(kAlphaMax, ea);
+            if (alpha >= kAlphaMin) {
+              contrib = true;
+              T[w] = __fdividef(T[w], 1.f - alpha);
+              const float wt = alpha * T[w];
+              gr[6] += g0[w] * wt;
+              gr[7] += g1[w] * wt;
+              gr[8] += g2[w] * wt;
+              const float da =
+                  T[w] * (g0[w] * (b.z - B0[w]) + g1[w] * (b.w - B1[w]) + g2[w] * (c.x - B2[w]));
+              if (ea < kAlphaMax) {
+                const float gp = da * alpha;
+                gr[5] += da * __builtin_amdgcn_exp2f(power * kLog2e);
+                gr[0] -= gp * (c.y * dx + c.z * dy);
+                gr[1] -= gp * (c.z * dx + c.w * dy);
+                gr[2] -= 0.5f * gp * dx * dx;
+                gr[3] -= gp * dx * dy;
+                gr[4] -= 0.5f * gp * dy * dy;
+              }
+              B0[w] = alpha * b.z + (1.f - alpha) * B0[w];
+              B1[w] = alpha * b.w + (1.f - alpha) * B1[w];
+              B2[w] = alpha * c.x + (1.f - alpha) * B2[w];
             }
-            B0 = alpha * b.z + (1.f - alpha) * B0;
-            B1 = alpha * b.w + (1.f - alpha) * B1;
-            B2 = alpha * c.x + (1.f - alpha) * B2;
           }
         }
       }
       if (__builtin_amdgcn_ballot_w64(contrib) == 0) continue;
 #pragma unroll
-      for (int c = 0; c < 9; ++c) {
-        const float s = wave_sum_lane63(g[c]);
-        if (lane == 63 && s != 0.f) atomicAdd(&s_acc[k][c], s);
+      for (int cc = 0; cc < 9; ++cc) {
+        const float s = wave_sum_lane63(gr[cc]);
+        if (lane == 63) sh.acc[cc][k] = s;
       }
     }
     __syncthreads();
-    {
-      const int k = (int)threadIdx.x;
-      if (lo + k < hi) {
-        float* dst = grad2d + ((size_t)v * ld + s_g[k]) * kGrad2dFloats;
 #pragma unroll
-        for (int c = 0; c < 9; ++c) {
-          const float s = s_acc[k][c];
-          if (s != 0.f) atomicAdd(dst + c, s);
+    for (int r = 0; r < kBwdBatch / 64; ++r) {
+      const int k = r * 64 + lane;
+      if (lo + k < hi) {
+        float* dst = grad2d + ((size_t)v * ld + sh.g[k]) * kGrad2dFloats;
+#pragma unroll
+        for (int cc = 0; cc < 9; ++cc) {
+          const float s = sh.acc[cc][k];
+          if (s != 0.f) atomicAdd(dst + cc, s);
         }
       }
     }
@@ -331,10 +457,41 @@ void launch_render_fwd(const gs_projected& proj, const gs_tile_lists& lists, int
   const int blocks = tpv * V;
   if (blocks == 0) return;
   StageScope scope(kStRenderFwd, s);
-  hipLaunchKernelGGL(k_render_fwd, dim3(blocks), dim3(kBlock), 0, s,
+  hipLaunchKernelGGL(k_render_fwd, dim3(blocks), dim3(64), 0, s,
                      reinterpret_cast<const float4*>(proj.splat), proj.ld, lists.vals,
                      reinterpret_cast<const uint2*>(lists.ranges), W, H, TX, tpv, bg[0], bg[1],
                      bg[2], image, final_T, n_contrib);
+}
+
+size_t render_batched_workspace_bytes(int V) {
+  return 256 + 256 * ((((size_t)V + 1) * 4 + 255) / 256) + 256 * ((((size_t)V + 1) * 8 + 255) / 256) +
+         256 * (((size_t)V * 8 + 255) / 256);
+}
+
+void launch_render_batched(const gs_projected& proj, const gs_tile_lists& lists,
+                           const gs_camera* cams_dev, int V, int64_t total_segments,
+                           const float bg[3], float* images, void* ws, hipStream_t s) {
+  char* w = static_cast<char*>(ws);
+  uint32_t* queue = reinterpret_cast<uint32_t*>(w);
+  w += 256;
+  uint32_t* seg_base = reinterpret_cast<uint32_t*>(w);
+  w += 256 * ((((size_t)V + 1) * 4 + 255) / 256);
+  int64_t* pix_base = reinterpret_cast<int64_t*>(w);
+  w += 256 * ((((size_t)V + 1) * 8 + 255) / 256);
+  int2* wh = reinterpret_cast<int2*>(w);
+  int dev = 0, cus = 256;
+  hipGetDevice(&dev);
+  hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  const int64_t want = (int64_t)cus * 16;
+  const int blocks = (int)(total_segments < want ? total_segments : want);
+  StageScope scope(kStRenderFwd, s);
+  hipLaunchKernelGGL(k_batch_info, dim3(1), dim3(64), 0, s, cams_dev, V, seg_base, pix_base, wh,
+                     queue);
+  if (blocks <= 0) return;
+  hipLaunchKernelGGL(k_render_persistent, dim3(blocks), dim3(64), 0, s,
+                     reinterpret_cast<const float4*>(proj.splat), proj.ld, lists.vals,
+                     reinterpret_cast<const uint2*>(lists.ranges), seg_base, pix_base, wh, V,
+                     (uint32_t)total_segments, bg[0], bg[1], bg[2], images, queue);
 }
 
 void launch_render_bwd(const gs_projected& proj, const gs_tile_lists& lists, int V, int W, int H,
@@ -345,7 +502,7 @@ void launch_render_bwd(const gs_projected& proj, const gs_tile_lists& lists, int
   const int blocks = tpv * V;
   if (blocks == 0) return;
   StageScope scope(kStRenderBwd, s);
-  hipLaunchKernelGGL(k_render_bwd, dim3(blocks), dim3(kBlock), 0, s,
+  hipLaunchKernelGGL(k_render_bwd, dim3(blocks), dim3(64), 0, s,
                      reinterpret_cast<const float4*>(proj.splat), proj.ld, lists.vals,
                      reinterpret_cast<const uint2*>(lists.ranges), W, H, TX, tpv, bg[0], bg[1],
                      bg[2], final_T, n_contrib, dL_dimage, grad2d);

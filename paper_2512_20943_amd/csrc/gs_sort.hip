@@ -37,9 +37,9 @@ __device__ __forceinline__ void st_relaxed(uint32_t* p, uint32_t v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-template <typename K>
+template <int BITS, typename K>
 __device__ __forceinline__ uint32_t digit_of(K key, int shift) {
-  return (uint32_t)(key >> shift) & 0xFFu;
+  return (uint32_t)(key >> shift) & ((1u << BITS) - 1u);
 }
 
 // Exclusive scan of one value per thread over a 256-thread block.
@@ -62,29 +62,44 @@ __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t x, uint32_t* s
 }
 
 // ------------------------------------------------------------ radix sort
-template <typename K>
+// Digits are BITS wide (8 or 9): the pass count is chosen per sort so
+// that the key's significant bits take as few passes as possible.
+template <typename K, int BITS>
 __global__ __launch_bounds__(kBlock) void k_histogram(const K* __restrict__ keys, uint32_t n,
-                                                      int shift0, int passes,
-                                                      uint32_t* __restrict__ hist) {
-  __shared__ uint32_t h[kMaxPasses * 256];
-  for (int t = threadIdx.x; t < passes * 256; t += kBlock) h[t] = 0;
+                                                      int passes, uint32_t* __restrict__ hist) {
+  constexpr int R = 1 << BITS;
+  __shared__ uint32_t h[kMaxPasses * R];
+  for (int t = threadIdx.x; t < passes * R; t += kBlock) h[t] = 0;
   __syncthreads();
   for (uint32_t i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
     const K k = keys[i];
-    for (int p = 0; p < passes; ++p) atomicAdd(&h[p * 256 + digit_of(k, shift0 + 8 * p)], 1u);
+    for (int p = 0; p < passes; ++p) atomicAdd(&h[p * R + digit_of<BITS>(k, BITS * p)], 1u);
   }
   __syncthreads();
-  for (int t = threadIdx.x; t < passes * 256; t += kBlock)
+  for (int t = threadIdx.x; t < passes * R; t += kBlock)
     if (h[t]) atomicAdd(&hist[t], h[t]);
 }
 
-// Exclusive scan of each pass's 256-bin histogram (one block).
+// Exclusive scan of each pass's histogram (one block; thread t owns the R/256
+// consecutive bins starting at t*R/256).
+template <int BITS>
 __global__ __launch_bounds__(kBlock) void k_hist_scan(const uint32_t* __restrict__ hist,
                                                       int passes, uint32_t* __restrict__ off) {
+  constexpr int R = 1 << BITS, DPT = R / kBlock;
   __shared__ uint32_t s_wave[4];
   for (int p = 0; p < passes; ++p) {
-    const uint32_t x = hist[p * 256 + threadIdx.x];
-    off[p * 256 + threadIdx.x] = block_exclusive_scan(x, s_wave, nullptr);
+    uint32_t x[DPT], sum = 0;
+#pragma unroll
+    for (int i = 0; i < DPT; ++i) {
+      x[i] = hist[p * R + threadIdx.x * DPT + i];
+      sum += x[i];
+    }
+    uint32_t run = block_exclusive_scan(sum, s_wave, nullptr);
+#pragma unroll
+    for (int i = 0; i < DPT; ++i) {
+      off[p * R + threadIdx.x * DPT + i] = run;
+      run += x[i];
+    }
   }
 }
 
@@ -93,23 +108,25 @@ __global__ __launch_bounds__(kBlock) void k_hist_scan(const uint32_t* __restrict
 // of a wave, per-wave counters in LDS carry the rank across items and
 // waves), publishes its per-digit counts, looks back over earlier
 // partitions for the global prefix, then scatters through LDS so that the
-// global writes come out in digit-contiguous runs.
-template <typename K>
+// global writes come out in digit-contiguous runs.  Thread t owns the R/256
+// consecutive digits starting at t*R/256 in the per-digit phase.
+template <typename K, int BITS>
 __global__ __launch_bounds__(kBlock) void k_onesweep(
     const K* __restrict__ kin, const uint32_t* __restrict__ vin, K* __restrict__ kout,
     uint32_t* __restrict__ vout, uint32_t n, int shift, const uint32_t* __restrict__ dig_off,
     uint32_t* lookback, uint32_t* counter) {
+  constexpr int R = 1 << BITS, DPT = R / kBlock;
   __shared__ uint32_t s_part;
-  __shared__ uint32_t s_wh[4][256];
-  __shared__ uint32_t s_dstart[256];
-  __shared__ uint32_t s_gbase[256];
+  __shared__ uint32_t s_wh[4][R];
+  __shared__ uint32_t s_dstart[R];
+  __shared__ uint32_t s_gbase[R];
   __shared__ uint32_t s_wave[4];
   __shared__ K s_k[kPart];
   __shared__ uint32_t s_v[kPart];
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   if (tid == 0) s_part = atomicAdd(counter, 1u);
-  for (int t = tid; t < 4 * 256; t += kBlock) (&s_wh[0][0])[t] = 0;
+  for (int t = tid; t < 4 * R; t += kBlock) (&s_wh[0][0])[t] = 0;
   __syncthreads();
   const uint32_t part = s_part;
   const uint32_t base = part * (uint32_t)kPart + (uint32_t)wave * 64u * kItems;
@@ -131,10 +148,10 @@ __global__ __launch_bounds__(kBlock) void k_onesweep(
 #pragma unroll
   for (int j = 0; j < kItems; ++j) {
     const bool valid = base + j * 64 + lane < n;
-    const uint32_t d = valid ? digit_of(k[j], shift) : 0u;
+    const uint32_t d = valid ? digit_of<BITS>(k[j], shift) : 0u;
     uint64_t peers = wave_ballot(valid);
 #pragma unroll
-    for (int b = 0; b < 8; ++b) {
+    for (int b = 0; b < BITS; ++b) {
       const bool bit = (d >> b) & 1u;
       const uint64_t bb = wave_ballot(bit);
       peers &= bit ? bb : ~bb;
@@ -149,34 +166,44 @@ __global__ __launch_bounds__(kBlock) void k_onesweep(
   }
   __syncthreads();
   {
-    const uint32_t d = (uint32_t)tid;
-    uint32_t run = 0;
+    uint32_t run[DPT], tsum = 0;
 #pragma unroll
-    for (int w = 0; w < 4; ++w) {
-      const uint32_t c = s_wh[w][d];
-      s_wh[w][d] = run;
-      run += c;
-    }
-    uint32_t* mine = lookback + (size_t)part * 256 + d;
-    st_relaxed(mine, (part == 0 ? kFlagPre : kFlagAgg) | run);
-    const uint32_t dstart = block_exclusive_scan(run, s_wave, nullptr);
-    s_dstart[d] = dstart;
-    uint32_t excl = 0;
-    if (part > 0) {
-      int64_t p = (int64_t)part - 1;
-      while (true) {
-        const uint32_t sv = ld_relaxed(lookback + (size_t)p * 256 + d);
-        if ((sv & ~kValMask) == 0u) {
-          __builtin_amdgcn_s_sleep(1);
-          continue;
-        }
-        excl += sv & kValMask;
-        if (sv & kFlagPre) break;
-        --p;
+    for (int i = 0; i < DPT; ++i) {
+      const int d = tid * DPT + i;
+      uint32_t r = 0;
+#pragma unroll
+      for (int w = 0; w < 4; ++w) {
+        const uint32_t c = s_wh[w][d];
+        s_wh[w][d] = r;
+        r += c;
       }
-      st_relaxed(mine, kFlagPre | (excl + run));
+      run[i] = r;
+      tsum += r;
+      st_relaxed(lookback + (size_t)part * R + d, (part == 0 ? kFlagPre : kFlagAgg) | r);
     }
-    s_gbase[d] = dig_off[d] + excl - dstart;
+    uint32_t dstart = block_exclusive_scan(tsum, s_wave, nullptr);
+#pragma unroll
+    for (int i = 0; i < DPT; ++i) {
+      const int d = tid * DPT + i;
+      s_dstart[d] = dstart;
+      uint32_t excl = 0;
+      if (part > 0) {
+        int64_t p = (int64_t)part - 1;
+        while (true) {
+          const uint32_t sv = ld_relaxed(lookback + (size_t)p * R + d);
+          if ((sv & ~kValMask) == 0u) {
+            __builtin_amdgcn_s_sleep(1);
+            continue;
+          }
+          excl += sv & kValMask;
+          if (sv & kFlagPre) break;
+          --p;
+        }
+        st_relaxed(lookback + (size_t)part * R + d, kFlagPre | (excl + run[i]));
+      }
+      s_gbase[d] = dig_off[d] + excl - dstart;
+      dstart += run[i];
+    }
   }
   __syncthreads();
 #pragma unroll
@@ -192,7 +219,7 @@ __global__ __launch_bounds__(kBlock) void k_onesweep(
   const uint32_t nvalid = (n - start) < (uint32_t)kPart ? (n - start) : (uint32_t)kPart;
   for (uint32_t t = tid; t < nvalid; t += kBlock) {
     const K kk = s_k[t];
-    const uint32_t g = s_gbase[digit_of(kk, shift)] + t;
+    const uint32_t g = s_gbase[digit_of<BITS>(kk, shift)] + t;
     kout[g] = kk;
     vout[g] = s_v[t];
   }
@@ -363,6 +390,21 @@ inline int bits_for(uint64_t count) {  // bits to hold values 0 .. count-1
 
 inline size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
+// Fewest passes with digits of 8 or 9 bits (wider digits cost more per pass
+// than they save).
+struct DigitPlan {
+  int passes;
+  int bits;
+};
+inline DigitPlan plan_digits(int key_bits) {
+  if (key_bits <= 0) return {0, 8};
+  const int passes = (key_bits + 8) / 9;
+  int b = (key_bits + passes - 1) / passes;
+  if (b < 8) b = 8;
+  return {passes, b};
+}
+inline int depth_key_bits(int V) { return 32 + bits_for((uint64_t)V); }
+
 inline uint32_t cdiv(uint64_t a, uint64_t b) { return (uint32_t)((a + b - 1) / b); }
 
 struct Layout {
@@ -379,10 +421,10 @@ Layout make_layout(int V, int ld, int64_t cap, int64_t nseg) {
     return at;
   };
   const size_t N = (size_t)V * (size_t)ld;
-  const size_t depth_passes = (size_t)((32 + bits_for((uint64_t)V) + 7) / 8);
-  const size_t seg_passes = (size_t)((bits_for((uint64_t)nseg) + 7) / 8);
-  const size_t lb_depth = depth_passes * cdiv(N, kPart) * 256;
-  const size_t lb_seg = seg_passes * cdiv((uint64_t)cap, kPart) * 256;
+  const DigitPlan dp = plan_digits(depth_key_bits(V));
+  const DigitPlan sp = plan_digits(bits_for((uint64_t)nseg));
+  const size_t lb_depth = (size_t)dp.passes * cdiv(N, kPart) * ((size_t)1 << dp.bits);
+  const size_t lb_seg = (size_t)sp.passes * cdiv((uint64_t)cap, kPart) * ((size_t)1 << sp.bits);
   L.dk0 = take(N * 8);
   L.dk1 = take(N * 8);
   L.dv0 = take(N * 4);
@@ -393,8 +435,8 @@ Layout make_layout(int V, int ld, int64_t cap, int64_t nseg) {
   L.segk0 = take((size_t)cap * 4);
   L.segk1 = take((size_t)cap * 4);
   L.segv_alt = take((size_t)cap * 4);
-  L.hist = take(kMaxPasses * 256 * 4);
-  L.digoff = take(kMaxPasses * 256 * 4);
+  L.hist = take(kMaxPasses * 1024 * 4);
+  L.digoff = take(kMaxPasses * 1024 * 4);
   L.counters = take(kMaxPasses * 4);
   L.lookback = take((lb_depth > lb_seg ? lb_depth : lb_seg) * 4 + 4);
   L.seg_base = take(((size_t)V + 1) * 4);
@@ -411,32 +453,42 @@ T* at(void* ws, size_t off) {
 
 // Stable LSD radix sort of (key, value) pairs on bits [0, bits), ping-pong
 // between buffer pair 0 and 1; returns the index (0/1) holding the result.
-template <typename K>
-int radix_sort(K* k0, K* k1, uint32_t* v0, uint32_t* v1, uint32_t n, int bits, void* ws,
-               const Layout& L, hipStream_t s) {
-  const int passes = (bits + 7) / 8;
-  if (n == 0 || passes == 0) return 0;
+template <typename K, int BITS>
+void radix_passes(K* k0, K* k1, uint32_t* v0, uint32_t* v1, uint32_t n, int passes, void* ws,
+                  const Layout& L, hipStream_t s) {
+  constexpr int R = 1 << BITS;
   uint32_t* hist = at<uint32_t>(ws, L.hist);
   uint32_t* off = at<uint32_t>(ws, L.digoff);
   uint32_t* counters = at<uint32_t>(ws, L.counters);
   uint32_t* lb = at<uint32_t>(ws, L.lookback);
   const uint32_t parts = cdiv(n, kPart);
-  const size_t lb_words = (size_t)passes * parts * 256;
-  launch_fill_u32(hist, 0u, (int64_t)passes * 256, s);
+  launch_fill_u32(hist, 0u, (int64_t)passes * R, s);
   launch_fill_u32(counters, 0u, kMaxPasses, s);
-  launch_fill_u32(lb, 0u, (int64_t)lb_words, s);
+  launch_fill_u32(lb, 0u, (int64_t)passes * parts * R, s);
   const uint32_t hblocks = std::min<uint32_t>(cdiv(n, kBlock * 8), 2048u);
-  hipLaunchKernelGGL(k_histogram<K>, dim3(hblocks), dim3(kBlock), 0, s, k0, n, 0, passes, hist);
-  hipLaunchKernelGGL(k_hist_scan, dim3(1), dim3(kBlock), 0, s, hist, passes, off);
+  hipLaunchKernelGGL((k_histogram<K, BITS>), dim3(hblocks), dim3(kBlock), 0, s, k0, n, passes,
+                     hist);
+  hipLaunchKernelGGL((k_hist_scan<BITS>), dim3(1), dim3(kBlock), 0, s, hist, passes, off);
   K* kb[2] = {k0, k1};
   uint32_t* vb[2] = {v0, v1};
   for (int p = 0; p < passes; ++p) {
     const int src = p & 1;
-    hipLaunchKernelGGL(k_onesweep<K>, dim3(parts), dim3(kBlock), 0, s, kb[src], vb[src],
-                       kb[src ^ 1], vb[src ^ 1], n, 8 * p, off + p * 256,
-                       lb + (size_t)p * parts * 256, counters + p);
+    hipLaunchKernelGGL((k_onesweep<K, BITS>), dim3(parts), dim3(kBlock), 0, s, kb[src], vb[src],
+                       kb[src ^ 1], vb[src ^ 1], n, BITS * p, off + p * R,
+                       lb + (size_t)p * parts * R, counters + p);
   }
-  return passes & 1;
+}
+
+template <typename K>
+int radix_sort(K* k0, K* k1, uint32_t* v0, uint32_t* v1, uint32_t n, int bits, void* ws,
+               const Layout& L, hipStream_t s) {
+  const DigitPlan dp = plan_digits(bits);
+  if (n == 0 || dp.passes == 0) return 0;
+  switch (dp.bits) {
+    case 8: radix_passes<K, 8>(k0, k1, v0, v1, n, dp.passes, ws, L, s); break;
+    default: radix_passes<K, 9>(k0, k1, v0, v1, n, dp.passes, ws, L, s); break;
+  }
+  return dp.passes & 1;
 }
 
 }  // namespace
@@ -478,7 +530,7 @@ hipError_t bin_sort_stage1(const BinSortPlan& p, const gs_projected& proj,
   uint64_t* dk1 = at<uint64_t>(ws, L.dk1);
   uint32_t* dv0 = at<uint32_t>(ws, L.dv0);
   uint32_t* dv1 = at<uint32_t>(ws, L.dv1);
-  const int dbits = 32 + bits_for((uint64_t)p.n_views);
+  const int dbits = depth_key_bits(p.n_views);
   int which;
   {
     StageScope scope(kStDepthSort, s);
@@ -509,12 +561,11 @@ hipError_t bin_sort_stage2(const BinSortPlan& p, const gs_projected& proj,
   launch_fill_u32(lists.ranges, 0u, 2 * p.n_segments, s);
   if (M == 0) return hipGetLastError();
   // The depth sort's pass count is known on the host, so is its result buffer.
-  const int dbits = 32 + bits_for((uint64_t)p.n_views);
-  const int which = ((dbits + 7) / 8) & 1;
+  const int which = plan_digits(depth_key_bits(p.n_views)).passes & 1;
   const uint64_t* sk = which ? at<uint64_t>(ws, L.dk1) : at<uint64_t>(ws, L.dk0);
   const uint32_t* sv = which ? at<uint32_t>(ws, L.dv1) : at<uint32_t>(ws, L.dv0);
   const int sbits = bits_for((uint64_t)p.n_segments);
-  const int spasses = (sbits + 7) / 8;
+  const int spasses = plan_digits(sbits).passes;
   uint32_t* segk0 = at<uint32_t>(ws, L.segk0);
   uint32_t* segk1 = at<uint32_t>(ws, L.segk1);
   uint32_t* alt = at<uint32_t>(ws, L.segv_alt);

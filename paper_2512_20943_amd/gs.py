@@ -114,6 +114,12 @@ def load() -> ctypes.CDLL:
                                     c_void_p]
     lib.gs_adam_step.argtypes = [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_int64,
                                  ctypes.c_int, c_float, c_float, c_float, c_float, c_void_p]
+    lib.gs_render_batched_workspace_size.argtypes = [ctypes.c_int]
+    lib.gs_render_batched_workspace_size.restype = ctypes.c_size_t
+    lib.gs_render_fwd_batched.argtypes = [c_void_p, P(GsProjected), P(GsTileLists), P(GsCamera),
+                                          c_void_p, ctypes.c_int, P(GsOpts), c_void_p, c_void_p,
+                                          ctypes.c_size_t, c_void_p]
+    lib.gs_render_fwd_batched.restype = c_int32
     lib.gs_set_timing.argtypes = [c_void_p, ctypes.c_int]
     lib.gs_collect_timing.argtypes = [c_void_p, P(c_double), P(c_int64)]
     lib.gs_stage_name.argtypes = [ctypes.c_int]
@@ -132,7 +138,8 @@ def exported_symbols():
             "gs_bin_sort_workspace_size", "gs_render_bwd_workspace_size",
             "gs_apply_frame_update", "gs_project", "gs_bin_sort", "gs_render_fwd",
             "gs_render_bwd", "gs_l1_loss_grad", "gs_adam_step", "gs_set_timing",
-            "gs_collect_timing", "gs_stage_name"]
+            "gs_collect_timing", "gs_stage_name", "gs_render_batched_workspace_size",
+            "gs_render_fwd_batched"]
 
 
 def _ptr(t):
@@ -257,6 +264,26 @@ class Cameras:
     def n_segments(self) -> int:
         return int(load().gs_num_segments(self.host, self.V))
 
+    def slice(self, start: int, count: int) -> "Cameras":
+        """Views start .. start+count-1, sharing this object's memory."""
+        out = Cameras.__new__(Cameras)
+        out.V = count
+        out.host = (GsCamera * count).from_address(ctypes.addressof(self.host[start]))
+        out._owner = self
+        nb = ctypes.sizeof(GsCamera)
+        out.dev = self.dev[start * nb:(start + count) * nb]
+        out.wh = self.wh[start:start + count]
+        return out
+
+    @staticmethod
+    def from_list(items, device="cuda", stream=None) -> "Cameras":
+        """Cameras from (R, t, f, (W, H)) tuples."""
+        R = np.stack([np.asarray(it[0], np.float64) for it in items])
+        t = np.stack([np.asarray(it[1], np.float64) for it in items])
+        f = np.stack([np.asarray(it[2], np.float64) for it in items])
+        wh = np.array([it[3] for it in items], np.int32)
+        return Cameras(dict(R=R, t=t, f=f, wh=wh), device)
+
 
 @dataclass
 class Projected:
@@ -276,6 +303,11 @@ class Projected:
                          torch.empty(V, ld, dtype=torch.int32, device=device),
                          torch.empty(V, ld, dtype=torch.int32, device=device),
                          torch.empty(V, ld, dtype=torch.uint8, device=device))
+
+    def slice(self, start: int, count: int) -> "Projected":
+        return Projected(count, self.n, self.ld, self.splat[start:start + count],
+                         self.rect[start:start + count], self.tiles_touched[start:start + count],
+                         self.depth_bits[start:start + count], self.flags[start:start + count])
 
     def c(self) -> GsProjected:
         return GsProjected(self.V, self.n, self.ld, 0, _ptr(self.splat), _ptr(self.rect),
@@ -338,6 +370,20 @@ def gs_render_fwd(ctx: Context, proj: Projected, lists: TileLists, cams: Cameras
                                     cams.host, _ptr(cams.dev), cams.V, ctypes.byref(opts),
                                     _ptr(image), _ptr(final_T), _ptr(n_contrib),
                                     _stream(stream)))
+
+
+def gs_render_fwd_batched(ctx: Context, proj: Projected, lists: TileLists, cams: Cameras, bg,
+                          images: torch.Tensor, workspace: torch.Tensor, stream=None):
+    pc = proj.c()
+    opts = GsOpts((c_float * 3)(*[float(x) for x in bg]), 0.0)
+    ctx.check(ctx.lib.gs_render_fwd_batched(ctx.handle, ctypes.byref(pc), ctypes.byref(lists.c()),
+                                            cams.host, _ptr(cams.dev), cams.V, ctypes.byref(opts),
+                                            _ptr(images), _ptr(workspace), workspace.numel(),
+                                            _stream(stream)))
+
+
+def render_batched_workspace_size(V: int) -> int:
+    return int(load().gs_render_batched_workspace_size(V))
 
 
 def gs_render_bwd(ctx: Context, frame: Gaussians, proj: Projected, lists: TileLists,

@@ -172,9 +172,10 @@ def make_delta(n: int, gw: int, gh: int, seed: int, mean_sd: float = 0.005,
     g = rng(seed)
     d = np.zeros((8, gh * gw), np.float32)
     d[3, :] = 1.0
-    d[0:3, :n] = g.normal(0.0, mean_sd, size=(3, n))
-    d[3:7, :n] += g.normal(0.0, quat_sd, size=(4, n))
-    d[7, :n] = g.normal(0.0, opacity_sd, size=n)
+    z = g.standard_normal(size=(8, n), dtype=np.float32)
+    d[0:3, :n] = z[0:3] * np.float32(mean_sd)
+    d[3:7, :n] += z[3:7] * np.float32(quat_sd)
+    d[7, :n] = z[7] * np.float32(opacity_sd)
     return d.reshape(8, gh, gw)
 
 
@@ -187,7 +188,7 @@ def prune_mask(delta: np.ndarray, n: int, level: float) -> np.ndarray:
     dev = flat.copy()
     dev[3] -= 1.0
     mag = np.sqrt((dev ** 2).sum(axis=0))
-    order = np.lexsort((np.arange(n), mag))
+    order = np.argsort(mag, kind="stable")  # equal magnitudes: lower id first
     drop = order[: int(math.floor(level * n))]
     m = np.zeros(gh * gw, np.uint8)
     m[:n] = 1

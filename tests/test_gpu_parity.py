@@ -55,19 +55,29 @@ def compare_projection(P_gpu, P_or, vis_only=True):
     return int(vis.sum())
 
 
-def compare_images(img_gpu, img_or, max_frac=5e-3):
+# At a pixel whose skip/stop decision the oracle reports within the FP32
+# error bound of its threshold, the two sides may composite one entry more or
+# less; that entry's share of the pixel is bounded by (1/255 or alpha) * T,
+# at most a few 1e-3.
+NEAR_ATOL = 5e-3
+
+
+def compare_images(img_gpu, img_or, max_frac=0.03):
     near = img_or["near_threshold"]
     keep = ~near
     frac = near.mean()
-    assert frac <= max_frac, f"{frac:.4%} pixels near a threshold"
     im_g = img_gpu["image"].cpu().numpy()
     T_g = img_gpu["final_T"].cpu().numpy()
     n_g = img_gpu["n_contrib"].cpu().numpy()
-    err = np.abs(im_g - img_or["image"]).max(axis=1)[keep]
+    diff = np.abs(im_g - img_or["image"]).max(axis=1)
+    err = diff[keep]
     assert err.max(initial=0.0) <= IMG_ATOL, f"image error {err.max():.3e}"
-    errT = np.abs(T_g - img_or["final_T"])[keep]
-    assert errT.max(initial=0.0) <= IMG_ATOL, f"final_T error {errT.max():.3e}"
+    errT = np.abs(T_g - img_or["final_T"])
+    assert errT[keep].max(initial=0.0) <= IMG_ATOL, f"final_T error {errT[keep].max():.3e}"
     np.testing.assert_array_equal(n_g[keep], img_or["n_contrib"][keep])
+    assert diff[near].max(initial=0.0) <= NEAR_ATOL, "near-threshold pixel off by more than one entry"
+    assert errT[near].max(initial=0.0) <= NEAR_ATOL
+    assert frac <= max_frac, f"{frac:.4%} pixels near a threshold"
     return float(err.max(initial=0.0)), int(near.sum())
 
 
@@ -376,6 +386,98 @@ def test_full_frame_300k_20_views_sampled():
     M0 = int(rg[:, 1].max())
     np.testing.assert_array_equal(L_g["vals"][:M0], L0["vals"])
     np.testing.assert_array_equal(L_g["keys"][:M0], L0["keys"])
+    img0 = oracle.render_fwd(P0, L0, cam0)
+    out0 = {k: out[k][:1] for k in ("image", "final_T", "n_contrib")}
+    err, near = compare_images(out0, img0)
+    say(f"  view 0 max image error {err:.2e}, {near} near-threshold pixels")
+
+
+def _sparse_tile_gradient(img_shape, n_tiles, seed, W, H):
+    """dL/dimage that is nonzero (random signs / count) only on n_tiles random
+    16x16 tiles per view, so the oracle backward only walks those tiles."""
+    rng = np.random.default_rng(seed)
+    V = img_shape[0]
+    g = np.zeros(img_shape)
+    TX, TY = (W + 15) // 16, (H + 15) // 16
+    count = float(np.prod(img_shape))
+    for v in range(V):
+        for t in rng.choice(TX * TY, size=min(n_tiles, TX * TY), replace=False):
+            ty, tx = divmod(int(t), TX)
+            blk = g[v, :, ty * 16:(ty + 1) * 16, tx * 16:(tx + 1) * 16]
+            blk[...] = rng.choice([-1.0, 1.0], size=blk.shape) / count
+    return g
+
+
+def test_full_frame_backward_sparse_tiles():
+    """Backward at the full 300k-Gaussian / 20-view / 1352x1014 size and in the
+    benchmark's launch configuration, with the image gradient restricted to
+    30 random tiles per view (the oracle walks only those)."""
+    require_gpu()
+    say("full frame backward, sparse tiles")
+    scene, cams, _ = scenes.workload_frame_300k(0)
+    g, gc, r, out = gpu_forward(scene, cams, with_keys=False, capacity=1 << 26)
+    P_or, L_or, img_or = oracle.forward(scene, cams)
+    gI = _sparse_tile_gradient(img_or["image"].shape, 30, 21, 1352, 1014)
+    gI[np.broadcast_to(img_or["near_threshold"][:, None], gI.shape)] = 0.0
+    g2d_or, gr_or = oracle.backward(scene, cams, P_or, L_or, gI)
+    grad = gs.Gaussians.zeros_like(g)
+    ws = r.backward(g, gc, out, torch.from_numpy(gI.astype(np.float32)).cuda(), grad)
+    torch.cuda.synchronize()
+    n = scene["n"]
+    g2d = ws.view(torch.float32)[: gc.V * g.ld * 12].view(gc.V, g.ld, 12)[:, :n, :9].cpu().numpy()
+    assert_grad_close(g2d, g2d_or, "screen-space gradients")
+    for name in ("mean", "log_scale", "quat", "opacity", "sh"):
+        assert_grad_close(getattr(grad, name).cpu().numpy()[..., :n], gr_or[name][..., :n], name)
+
+
+def test_full_frame_update_delta_gradient_sparse_tiles():
+    """Apply + render + backward to the (8, 548, 548) delta images at the full
+    300k / 20-view size, pruning level 0.5, sparse-tile image gradient."""
+    require_gpu()
+    say("full frame update backward, sparse tiles")
+    scene, cams, _ = scenes.workload_frame_300k(0)
+    n = scene["n"]
+    gw = gh = scenes.grid_side(n)
+    d = scenes.make_delta(n, gw, gh, 12)
+    mask = scenes.prune_mask(d, n, 0.5)
+    frame = oracle.apply(scene, d, mask, gw, gh)
+    P_or, L_or, img_or = oracle.forward(frame, cams)
+    gI = _sparse_tile_gradient(img_or["image"].shape, 20, 22, 1352, 1014)
+    gI[np.broadcast_to(img_or["near_threshold"][:, None], gI.shape)] = 0.0
+    _, gr_or = oracle.backward(frame, cams, P_or, L_or, gI)
+    gd_or = oracle.apply_bwd(scene, mask, gw, gh, gr_or)
+    anchor = gs.Gaussians.from_scene(scene)
+    r = Rasterizer(capacity=1 << 26)
+    fr = frame_of(anchor)
+    delta = torch.from_numpy(d).cuda().requires_grad_(True)
+    img = GSFrameRender.apply(delta, (r, gs.Cameras(cams), anchor, torch.from_numpy(mask).cuda(),
+                                      gw, gh, (0.0, 0.0, 0.0), fr))
+    img.backward(torch.from_numpy(gI.astype(np.float32)).cuda())
+    torch.cuda.synchronize()
+    assert_grad_close(delta.grad.cpu().numpy(), gd_or, "delta images")
+
+
+def test_large_2m_8_views_sampled():
+    """2,000,000 Gaussians (means U[-6,6]^3, log-scales N(-4.5,0.7), SH 3), 8
+    views at 1920x1080 from inside the cloud: every projection record, view 0's
+    tile lists bit for bit and view 0's image."""
+    require_gpu()
+    say("large 2M x 8 views")
+    scene, cams, _ = scenes.workload_large_2m(0)
+    g, gc, r, out = gpu_forward(scene, cams, capacity=1 << 26)
+    say(f"  instances {out['lists'].count}")
+    P_or = oracle.project(scene, cams)
+    compare_projection(projected_to_oracle(out["proj"]), P_or)
+    cam0 = {k: v[:1] for k, v in cams.items()}
+    P0 = {k: (v[:1] if isinstance(v, np.ndarray) else v) for k, v in P_or.items()}
+    P0["V"] = 1
+    del P_or
+    L0 = oracle.bin_sort(P0, cam0)
+    L_g = lists_to_numpy(out["lists"])
+    rg = L_g["ranges"][:L0["n_segments"]]
+    np.testing.assert_array_equal(rg, L0["ranges"])
+    M0 = int(rg[:, 1].max())
+    np.testing.assert_array_equal(L_g["vals"][:M0], L0["vals"])
     img0 = oracle.render_fwd(P0, L0, cam0)
     out0 = {k: out[k][:1] for k in ("image", "final_T", "n_contrib")}
     err, near = compare_images(out0, img0)

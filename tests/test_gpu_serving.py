@@ -1,0 +1,81 @@
+"""Serving path on the GPU: every request's image is the same alone, in a
+mixed batch, through the continuous-batching server and through the plain
+one-request-per-launch renderer; a served image matches the oracle."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2512_20943_amd import scenes, serve
+from tests.gpu_helpers import IMG_ATOL, require_gpu
+
+pytestmark = pytest.mark.gpu
+
+SMALL_RES = ((64, 48), (128, 96), (200, 150))
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def seq():
+    require_gpu()
+    anchor = scenes.make_scene(20_000, 11, -3.0, 3.0, -4.0, 0.5, 3)
+    return serve.ResidentSequence(anchor, 6, seed=3), anchor
+
+
+def test_request_alone_equals_request_in_mixed_batch(seq):
+    s, _ = seq
+    reqs = serve.make_trace(12, 1000.0, None, 4, s.n_frames, 5, resolutions=SMALL_RES)
+    w = serve.BatchWorker(s)
+    _, mixed = w.render(reqs)
+    mixed = [m.clone() for m in mixed]
+    plain = serve.PlainRenderer(s)
+    for r, m in zip(reqs, mixed):
+        _, alone = w.render([r])
+        assert torch.equal(alone[0], m), f"request {r.rid} differs alone vs mixed"
+        assert torch.equal(plain.render(r), m), f"request {r.rid} differs plain vs batched"
+
+
+def test_served_image_matches_oracle(seq):
+    s, anchor = seq
+    reqs = serve.make_trace(3, 1000.0, None, 4, s.n_frames, 6, resolutions=SMALL_RES)
+    w = serve.BatchWorker(s)
+    _, imgs = w.render(reqs)
+    for r, im in zip(reqs, imgs):
+        d, m = s.frame_inputs(r.frame)
+        frame = oracle.apply(anchor, d, m, s.gw, s.gh)
+        cams = scenes.stack_cams([r.cam])
+        _, _, ref = oracle.forward(frame, cams)
+        keep = ~ref["near_threshold"][0]
+        err = np.abs(im.cpu().numpy() - ref["image"][0]).max(axis=0)[keep].max()
+        assert err <= IMG_ATOL, f"request {r.rid}: image error {err}"
+
+
+def test_continuous_batching_server_results_match_plain(seq):
+    s, _ = seq
+    trace = serve.make_trace(None, 400.0, 0.25, 64, s.n_frames, 7, resolutions=SMALL_RES)
+    assert len(trace) > 20
+    server = serve.Server(s, budget_bytes=8 << 30, max_batch=16, keep_images=True)
+    server.run(trace)
+    assert all(np.isfinite(r.t_done) for r in trace)
+    assert max(server.batches) > 1, "no request was batched with another"
+    plain = serve.PlainRenderer(s)
+    for r in trace:
+        assert torch.equal(r.image, plain.render(r)), f"request {r.rid}"
+    st = serve.summarize(trace)
+    say(f"  served {st}")
+
+
+def test_tiny_hbm_budget_serialises_but_completes(seq):
+    s, _ = seq
+    trace = serve.make_trace(None, 300.0, 0.1, 8, s.n_frames, 8, resolutions=SMALL_RES)
+    one = max(serve.request_bytes(r, s.anchor.ld, 600.0) for r in trace)
+    server = serve.Server(s, budget_bytes=int(one * 1.2), max_batch=16)
+    server.run(trace)
+    assert all(np.isfinite(r.t_done) for r in trace)
+    assert max(server.batches) <= 2
