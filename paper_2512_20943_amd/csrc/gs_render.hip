@@ -196,26 +196,21 @@ __device__ __forceinline__ void render_tile_fwd(FwdShared& sh, const float4* __r
 #pragma unroll
       for (int w = 0; w < 4; ++w) {
         if (m & (1u << w)) {
-          if (!done[w]) {
-            const float dx = a.x - fx[w], dy = a.y - fy[w];
-            const float power = eval_power(a, b.x, dx, dy);
-            if (!(power > 0.f)) {
-              const float alpha = fminf(kAlphaMax, eval_ea(power, b.y));
-              if (alpha >= kAlphaMin) {
-                const float Tn = T[w] * (1.f - alpha);
-                if (Tn < kTStop) {
-                  done[w] = true;
-                } else {
-                  const float wt = alpha * T[w];
-                  c0[w] = fmaf(b.z, wt, c0[w]);
-                  c1[w] = fmaf(b.w, wt, c1[w]);
-                  c2[w] = fmaf(cb, wt, c2[w]);
-                  T[w] = Tn;
-                  last[w] = pos;
-                }
-              }
-            }
-          }
+          // per-lane decisions as selects: no divergent branches in the slot
+          const float dx = a.x - fx[w], dy = a.y - fy[w];
+          const float power = eval_power(a, b.x, dx, dy);
+          const float alpha = fminf(kAlphaMax, eval_ea(power, b.y));
+          const bool use = !done[w] && !(power > 0.f) && alpha >= kAlphaMin;
+          const float Tn = T[w] * (1.f - alpha);
+          const bool stop = use && Tn < kTStop;
+          const bool comp = use && !stop;
+          const float wt = comp ? alpha * T[w] : 0.f;
+          c0[w] = fmaf(b.z, wt, c0[w]);
+          c1[w] = fmaf(b.w, wt, c1[w]);
+          c2[w] = fmaf(cb, wt, c2[w]);
+          T[w] = comp ? Tn : T[w];
+          last[w] = comp ? pos : last[w];
+          done[w] = done[w] || stop;
           if (__builtin_amdgcn_ballot_w64(!done[w]) == 0) live &= ~(1u << w);
         }
       }
@@ -393,35 +388,36 @@ __global__ __launch_bounds__(64) void k_render_bwd(
       bool contrib = false;
 #pragma unroll
       for (int w = 0; w < 4; ++w) {
-        if ((m & (1u << w)) && j < nc[w]) {
+        if (m & (1u << w)) {
+          // per-lane decisions as selects; an unused pair gets alpha 0, which
+          // leaves T and B unchanged and contributes nothing
           const float dx = a.x - fx[w], dy = a.y - fy[w];
           const float power = eval_power(a, b.x, dx, dy);
-          if (!(power > 0.f)) {
-            const float ea = eval_ea(power, b.y);
-            const float alpha = fminf(kAlphaMax, ea);
-            if (alpha >= kAlphaMin) {
-              contrib = true;
-              T[w] = __fdividef(T[w], 1.f - alpha);
-              const float wt = alpha * T[w];
-              gr[6] += g0[w] * wt;
-              gr[7] += g1[w] * wt;
-              gr[8] += g2[w] * wt;
-              const float da =
-                  T[w] * (g0[w] * (b.z - B0[w]) + g1[w] * (b.w - B1[w]) + g2[w] * (c.x - B2[w]));
-              if (ea < kAlphaMax) {
-                const float gp = da * alpha;
-                gr[5] += da * __builtin_amdgcn_exp2f(power * kLog2e);
-                gr[0] -= gp * (c.y * dx + c.z * dy);
-                gr[1] -= gp * (c.z * dx + c.w * dy);
-                gr[2] -= 0.5f * gp * dx * dx;
-                gr[3] -= gp * dx * dy;
-                gr[4] -= 0.5f * gp * dy * dy;
-              }
-              B0[w] = alpha * b.z + (1.f - alpha) * B0[w];
-              B1[w] = alpha * b.w + (1.f - alpha) * B1[w];
-              B2[w] = alpha * c.x + (1.f - alpha) * B2[w];
-            }
-          }
+          const float ea = eval_ea(power, b.y);
+          const float alpha = fminf(kAlphaMax, ea);
+          const bool use = j < nc[w] && !(power > 0.f) && alpha >= kAlphaMin;
+          const float au = use ? alpha : 0.f;
+          const float Tk = T[w] * __builtin_amdgcn_rcpf(1.f - au);
+          const float wt = au * Tk;
+          gr[6] = fmaf(g0[w], wt, gr[6]);
+          gr[7] = fmaf(g1[w], wt, gr[7]);
+          gr[8] = fmaf(g2[w], wt, gr[8]);
+          const float dc0 = b.z - B0[w], dc1 = b.w - B1[w], dc2 = c.x - B2[w];
+          const float da = (use && ea < kAlphaMax)
+                               ? Tk * (g0[w] * dc0 + g1[w] * dc1 + g2[w] * dc2)
+                               : 0.f;
+          const float gp = da * alpha;
+          gr[5] = fmaf(da, __builtin_amdgcn_exp2f(power * kLog2e), gr[5]);
+          gr[0] = fmaf(-gp, c.y * dx + c.z * dy, gr[0]);
+          gr[1] = fmaf(-gp, c.z * dx + c.w * dy, gr[1]);
+          gr[2] = fmaf(-0.5f * gp, dx * dx, gr[2]);
+          gr[3] = fmaf(-gp, dx * dy, gr[3]);
+          gr[4] = fmaf(-0.5f * gp, dy * dy, gr[4]);
+          B0[w] = fmaf(au, dc0, B0[w]);
+          B1[w] = fmaf(au, dc1, B1[w]);
+          B2[w] = fmaf(au, dc2, B2[w]);
+          T[w] = Tk;
+          contrib = contrib || use;
         }
       }
       if (__builtin_amdgcn_ballot_w64(contrib) == 0) continue;

@@ -71,9 +71,23 @@ __global__ __launch_bounds__(kBlock) void k_histogram(const K* __restrict__ keys
   __shared__ uint32_t h[kMaxPasses * R];
   for (int t = threadIdx.x; t < passes * R; t += kBlock) h[t] = 0;
   __syncthreads();
-  for (uint32_t i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
-    const K k = keys[i];
-    for (int p = 0; p < passes; ++p) atomicAdd(&h[p * R + digit_of<BITS>(k, BITS * p)], 1u);
+  // 8 keys per thread per round, loaded before they are counted, so that
+  // each wave keeps several loads in flight
+  constexpr int U = 8;
+  const uint32_t stride = gridDim.x * kBlock;
+  for (uint32_t i0 = blockIdx.x * kBlock + threadIdx.x; i0 < n; i0 += U * stride) {
+    K kk[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const uint32_t i = i0 + u * stride;
+      kk[u] = i < n ? keys[i] : K(0);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if (i0 + u * stride >= n) break;
+      for (int p = 0; p < passes; ++p)
+        atomicAdd(&h[p * R + digit_of<BITS>(kk[u], BITS * p)], 1u);
+    }
   }
   __syncthreads();
   for (int t = threadIdx.x; t < passes * R; t += kBlock)
