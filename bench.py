@@ -198,6 +198,34 @@ def algorithmic_work(stage, ts, steps):
     return None
 
 
+STAGE_SOURCE = {"render_fwd": "gs_render.hip", "render_bwd": "gs_render.hip",
+                "project": "gs_project.hip", "project_bwd": "gs_project.hip",
+                "depth_sort": "gs_sort.hip", "segment_sort": "gs_sort.hip", "emit": "gs_sort.hip",
+                "adam": "gs_train.hip", "l1": "gs_train.hip"}
+
+
+def counted_traffic(stage):
+    """HBM bytes per launch of a stage's kernel from the committed rocprofv3
+    FETCH_SIZE / WRITE_SIZE summary (profiles/*.md, line 'traffic: ...'),
+    scaled by the copy-kernel calibration recorded there; None when no
+    summary exists or the kernel's source changed since it was taken."""
+    import glob
+    import hashlib
+    src = STAGE_SOURCE.get(stage)
+    if src is None:
+        return None
+    path = os.path.join(ROOT, "paper_2512_20943_amd", "csrc", src)
+    digest = hashlib.sha256(open(path, "rb").read()).hexdigest()[:16]
+    for md in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.md"))):
+        for line in open(md):
+            if not line.startswith("traffic:"):
+                continue
+            kv = dict(tok.split("=", 1) for tok in line.split()[1:])
+            if kv.get("stage") == stage and kv.get("source_sha256") == digest:
+                return float(kv["bytes_per_launch"])
+    return None
+
+
 def roofline(stages, ts, steps):
     busy = {k: v for k, v in stages.items() if v[1] > 0}
     dom = max(busy, key=lambda k: busy[k][0])
@@ -212,11 +240,11 @@ def roofline(stages, ts, steps):
     if unit == "byte":
         achieved = amount_per_launch / per_launch_s / 1e9
         rf = dict(bound=bound, achieved=round(achieved, 2), peak=PEAK_HBM_GBS, unit="GB/s",
-                  frac=round(achieved / PEAK_HBM_GBS, 4), traffic=None)
+                  frac=round(achieved / PEAK_HBM_GBS, 4), traffic=counted_traffic(dom))
     else:
         achieved = amount_per_launch / per_launch_s / 1e12
         rf = dict(bound=bound, achieved=round(achieved, 3), peak=PEAK_ALU_TFLOPS, unit="TFLOP/s",
-                  frac=round(achieved / PEAK_ALU_TFLOPS, 4), traffic=None)
+                  frac=round(achieved / PEAK_ALU_TFLOPS, 4), traffic=counted_traffic(dom))
     rf["kernel"] = dom
     rf["launch_ms"] = round(per_launch_s * 1e3, 4)
     if pairs is not None:

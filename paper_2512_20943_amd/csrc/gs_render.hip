@@ -27,7 +27,7 @@ constexpr float kLog2e = 1.4426950408889634f;
 constexpr float kLn255 = 5.541263545158426f;
 
 // Screen-space record as staged in LDS:
-//   a = (px, py, nA, r1), b = (n2, log2 opacity, r, g), c = (b, A, B, C)
+//   a = (px, py, nA, r1), b = (n2, log2 opacity, r, g), c = (b, 1/opacity, B, C)
 // with power = nA (dx + r1 dy)^2 + n2 dy^2, nA = -A/2, r1 = B/A,
 // n2 = -(AC - B^2) / (2A): the conic quadratic form written as a sum of two
 // non-positive squares, so FP32 evaluation has no cancellation.
@@ -42,7 +42,7 @@ __device__ __forceinline__ Rec make_rec(float4 s0, float4 s1, float4 s2) {
   const float iA = 1.f / A;
   r.a = make_float4(s0.x, s0.y, -0.5f * A, B * iA);
   r.b = make_float4(-0.5f * dq * iA, __log2f(s1.y), s1.z, s1.w);
-  r.c = make_float4(s2.x, A, B, C);
+  r.c = make_float4(s2.x, 1.f / s1.y, B, C);
   return r;
 }
 
@@ -122,8 +122,8 @@ __device__ __forceinline__ float wave_sum_lane63(float v) {
 // One 64-lane wave per 16x16 tile.  Lane l owns pixel (l & 7, l >> 3) of
 // each of the four 8x8 quadrants ("slot" w = quadrant w), so a record's
 // quadrant mask selects slots uniformly across the wave.
-constexpr int kFwdBatch = 256;  // records staged per batch (4 per lane)
-constexpr int kBwdBatch = 128;  // records staged per backward batch (2 per lane)
+constexpr int kFwdBatch = 128;  // records staged per batch (2 per lane)
+constexpr int kBwdBatch = 64;   // records staged per backward batch (1 per lane)
 
 struct FwdShared {
   float4 a[kFwdBatch];
@@ -407,8 +407,9 @@ __global__ __launch_bounds__(64) void k_render_bwd(
                                ? Tk * (g0[w] * dc0 + g1[w] * dc1 + g2[w] * dc2)
                                : 0.f;
           const float gp = da * alpha;
-          gr[5] = fmaf(da, __builtin_amdgcn_exp2f(power * kLog2e), gr[5]);
-          gr[0] = fmaf(-gp, c.y * dx + c.z * dy, gr[0]);
+          const float A = -2.f * a.z;
+          gr[5] = fmaf(da, ea * c.y, gr[5]);  // d alpha / d opacity = exp(power)
+          gr[0] = fmaf(-gp, A * dx + c.z * dy, gr[0]);
           gr[1] = fmaf(-gp, c.z * dx + c.w * dy, gr[1]);
           gr[2] = fmaf(-0.5f * gp, dx * dx, gr[2]);
           gr[3] = fmaf(-gp, dx * dy, gr[3]);
