@@ -78,10 +78,15 @@ typedef struct gs_camera {
   int32_t reserved[2];
 } gs_camera;
 
-/* Render options: background colour added with the final transmittance. */
+/* Render options: background colour added with the final transmittance;
+ * usage (device, n uint32, nullable): when set, gs_render_fwd ADDS to
+ * usage[i] the number of (view, pixel) pairs that composite Gaussian i --
+ * the rendering usage frequency by which the paper prunes updates
+ * (Sec. III-C).  Ignored by gs_render_fwd_batched and gs_render_bwd. */
 typedef struct gs_opts {
   float bg[3];
   float reserved;
+  uint32_t* usage;
 } gs_opts;
 
 /* Per (view, Gaussian) projection records, index v*ld + i:
@@ -254,6 +259,12 @@ gs_status gs_render_bwd(gs_ctx* ctx, const gs_gaussians* frame, const gs_project
  * grad = sign(image - target) / count (sign(0) = 0) WRITTEN. */
 gs_status gs_l1_loss_grad(gs_ctx* ctx, const float* image, const float* target, int64_t count,
                           float* grad, double* loss_dev, void* stream);
+
+/* Sum of squared differences over count values, ACCUMULATED in FP64 into
+ * *sum_dev (device; caller zeroes).  mean = sum / count gives the MSE behind
+ * the PSNR quality measure of the pruning-level sweep (Sec. III-C, Alg. 1). */
+gs_status gs_sq_error(gs_ctx* ctx, const float* a, const float* b, int64_t count,
+                      double* sum_dev, void* stream);
 
 /* One Adam step (Kingma & Ba 2015, Alg. 1) over count FP32 values, in
  * place, bias-corrected for step number `step` >= 1. */

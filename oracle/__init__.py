@@ -165,9 +165,12 @@ def bin_sort(proj, cams, depth_bits=None, rect=None, tiles=None):
 
 def render_fwd(proj, lists, cams, bg=None):
     """Step 8: per-pixel front-to-back compositing over each tile's list.
-    Returns image (V,3,H,W), final_T (V,H,W), n_contrib (V,H,W) and
+    Returns image (V,3,H,W), final_T (V,H,W), n_contrib (V,H,W),
     near_threshold (V,H,W) marking pixels where a decision sits within a
-    small relative margin of a threshold."""
+    small relative margin of a threshold, usage (n,) = number of (view,
+    pixel) pairs compositing each Gaussian (the usage frequency the paper
+    prunes by, Sec. III-C), and near_involved (n,) = near-threshold pixels
+    whose list holds each Gaussian."""
     lib = _load()
     V, n = proj["V"], proj["n"]
     R, t, f, wh, _ = _cam_arrays(cams)
@@ -178,6 +181,8 @@ def render_fwd(proj, lists, cams, bg=None):
     T = np.zeros((V, H, W))
     nc = np.zeros((V, H, W), np.int32)
     near = np.zeros((V, H, W), np.uint8)
+    usage = np.zeros(max(n, 1), np.int64)
+    near_inv = np.zeros(max(n, 1), np.int64)
     vals = np.ascontiguousarray(lists["vals"], dtype=np.uint32)
     if vals.size == 0:
         vals = np.zeros(1, np.uint32)
@@ -185,8 +190,9 @@ def render_fwd(proj, lists, cams, bg=None):
                       _p(_f64(proj["conic"])), _p(_f64(proj["rgb"])), _p(_f64(proj["alpha_hat"])),
                       _p(np.ascontiguousarray(lists["seg_base"], np.int64)), _p(wh), _p(vals),
                       _p(np.ascontiguousarray(lists["ranges"], np.uint32)), _p(bgv), _p(image),
-                      _p(T), _p(nc), _p(near))
-    return dict(image=image, final_T=T, n_contrib=nc, near_threshold=near.astype(bool))
+                      _p(T), _p(nc), _p(near), _p(usage), _p(near_inv))
+    return dict(image=image, final_T=T, n_contrib=nc, near_threshold=near.astype(bool),
+                usage=usage[:n], near_involved=near_inv[:n])
 
 
 def render_brute(proj, cams, view=0, bg=None):

@@ -549,7 +549,7 @@ typedef struct {
 
 static void composite_pixel(const or_splats* S, const uint32_t* list, int len, double px,
                             double py, const double bg[3], double out_c[3], double* out_T,
-                            int* out_n, int* near_thr) {
+                            int* out_n, int* near_thr, int64_t* usage) {
   double T = 1.0, C[3] = {0.0, 0.0, 0.0};
   double cond = 0.0; /* sum of alpha/(1-alpha) over composited entries */
   int last = 0;
@@ -574,6 +574,10 @@ static void composite_pixel(const or_splats* S, const uint32_t* list, int len, d
     T = Tn;
     cond += a_cond;
     last = j + 1;
+    if (usage) {
+#pragma omp atomic
+      usage[g] += 1;
+    }
   }
   for (int ch = 0; ch < 3; ++ch) out_c[ch] = C[ch] + T * bg[ch];
   *out_T = T;
@@ -589,7 +593,8 @@ static void composite_pixel(const or_splats* S, const uint32_t* list, int len, d
 void or_render_fwd(int V, int n, const double* mean2d, const double* conic, const double* rgb,
                    const double* alpha_hat, const int64_t* seg_base, const int* camwh,
                    const uint32_t* vals, const uint32_t* ranges, const double* bg,
-                   double* image, double* final_T, int* n_contrib, uint8_t* near_thr) {
+                   double* image, double* final_T, int* n_contrib, uint8_t* near_thr,
+                   int64_t* usage, int64_t* near_involved) {
   for (int v = 0; v < V; ++v) {
     const int W = camwh[2 * v], H = camwh[2 * v + 1];
     const int TX = tiles_x(W), TY = tiles_x(H);
@@ -608,7 +613,15 @@ void or_render_fwd(int V, int n, const double* mean2d, const double* conic, cons
           double c[3], T;
           int nc, nt = 0;
           composite_pixel(&S, vals + b, (int)(e - b), (double)x, (double)y, bg + 3 * v, c, &T,
-                          &nc, &nt);
+                          &nc, &nt, usage);
+          /* usage: per Gaussian, the number of (view, pixel) pairs that
+           * composite it; near_involved: pixels near a threshold whose list
+           * holds it (where an FP32 walk may composite it or not) */
+          if (nt && near_involved)
+            for (uint32_t k = b; k < e; ++k) {
+#pragma omp atomic
+              near_involved[vals[k]] += 1;
+            }
           const size_t p = (size_t)y * W + x;
           for (int ch = 0; ch < 3; ++ch) image[(size_t)v * 3 * pix + ch * pix + p] = c[ch];
           final_T[(size_t)v * pix + p] = T;
@@ -659,7 +672,7 @@ void or_render_brute(int n, const double* mean2d, const double* conic, const dou
       for (int k = 0; k < len; ++k) ids[k] = lst[k].id;
       double c[3], T;
       int nc, nt = 0;
-      composite_pixel(&S, ids, len, (double)x, (double)y, bg, c, &T, &nc, &nt);
+      composite_pixel(&S, ids, len, (double)x, (double)y, bg, c, &T, &nc, &nt, NULL);
       const size_t p = (size_t)y * W + x;
       for (int ch = 0; ch < 3; ++ch) image[ch * pix + p] = c[ch];
       final_T[p] = T;

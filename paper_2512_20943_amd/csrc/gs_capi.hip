@@ -359,7 +359,7 @@ gs_status gs_render_fwd(gs_ctx* c, const gs_projected* proj, const gs_tile_lists
   GS_TRY(use_device(c));
   const float zero[3] = {0.f, 0.f, 0.f};
   gs::launch_render_fwd(*proj, *lists, V, ch[0].width, ch[0].height, opts ? opts->bg : zero, image,
-                        final_T, n_contrib, (hipStream_t)stream);
+                        final_T, n_contrib, opts ? opts->usage : nullptr, (hipStream_t)stream);
   GS_LAUNCHED(c, "render_fwd");
   return GS_OK;
 }
@@ -455,6 +455,18 @@ gs_status gs_l1_loss_grad(gs_ctx* c, const float* image, const float* target, in
   GS_TRY(use_device(c));
   gs::launch_l1(image, target, count, grad, loss_dev, (hipStream_t)stream);
   GS_LAUNCHED(c, "l1");
+  return GS_OK;
+}
+
+gs_status gs_sq_error(gs_ctx* c, const float* a, const float* b, int64_t count, double* sum_dev,
+                      void* stream) {
+  if (!c) return fail(nullptr, GS_ERR_INVALID_ARG, "ctx is NULL");
+  TimerGuard timer_guard(c);
+  if (count < 0) return fail(c, GS_ERR_INVALID_ARG, "count < 0");
+  if (count > 0 && (!a || !b || !sum_dev)) return fail(c, GS_ERR_INVALID_ARG, "NULL buffer");
+  GS_TRY(use_device(c));
+  gs::launch_sq_error(a, b, count, sum_dev, (hipStream_t)stream);
+  GS_LAUNCHED(c, "sq_error");
   return GS_OK;
 }
 

@@ -85,7 +85,7 @@ hipError_t bin_sort_stage2(const BinSortPlan& p, const gs_projected& proj,
 // render
 void launch_render_fwd(const gs_projected& proj, const gs_tile_lists& lists, int n_views, int W,
                        int H, const float bg[3], float* image, float* final_T,
-                       int32_t* n_contrib, hipStream_t s);
+                       int32_t* n_contrib, uint32_t* usage, hipStream_t s);
 size_t render_batched_workspace_bytes(int V);
 void launch_render_batched(const gs_projected& proj, const gs_tile_lists& lists,
                            const gs_camera* cams_dev, int V, int64_t total_segments,
@@ -96,6 +96,7 @@ void launch_render_bwd(const gs_projected& proj, const gs_tile_lists& lists, int
 // training support
 void launch_l1(const float* image, const float* target, int64_t count, float* grad,
                double* loss, hipStream_t s);
+void launch_sq_error(const float* a, const float* b, int64_t count, double* sum, hipStream_t s);
 void launch_adam(float* p, const float* g, float* m, float* v, int64_t count, float lr, float b1,
                  float b2, float eps, float bc1, float bc2, hipStream_t s);
 void launch_fill_u32(uint32_t* p, uint32_t value, int64_t count, hipStream_t s);

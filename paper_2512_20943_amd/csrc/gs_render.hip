@@ -132,6 +132,12 @@ struct FwdShared {
   uint32_t m[kFwdBatch];
 };
 
+// Extra staging for per-Gaussian usage counts (composited pixels).
+struct UsageShared {
+  uint32_t g[kFwdBatch];
+  uint32_t u[kFwdBatch];
+};
+
 __device__ __forceinline__ uint32_t live_mask(const bool (&done)[4]) {
   uint32_t live = 0;
 #pragma unroll
@@ -143,24 +149,27 @@ __device__ __forceinline__ uint32_t live_mask(const bool (&done)[4]) {
 // Composites one tile; all 64 lanes of the workgroup call it.  image points
 // at the view's (3, H, W) planes; final_T / n_contrib at its (H, W) planes or
 // are null.
-__device__ __forceinline__ void render_tile_fwd(FwdShared& sh, const float4* __restrict__ sv,
+// With USAGE, the number of the tile's pixels that composite each entry is
+// added to usage[Gaussian id].
+template <bool USAGE>
+__device__ __forceinline__ void render_tile_fwd(FwdShared& sh, UsageShared* us,
+                                                const float4* __restrict__ sv,
                                                 const uint32_t* __restrict__ vals, uint2 rg,
                                                 int tx, int ty, int W, int H, float bg0,
                                                 float bg1, float bg2, float* __restrict__ image,
                                                 float* __restrict__ final_T,
-                                                int32_t* __restrict__ n_contrib) {
+                                                int32_t* __restrict__ n_contrib,
+                                                uint32_t* __restrict__ usage) {
   const int lane = threadIdx.x;
-  float fx[4], fy[4], T[4], c0[4], c1[4], c2[4];
+  // slot w's pixel is (x0 + 8 (w & 1), y0 + 8 (w >> 1))
+  const int x0 = tx * kTile + (lane & 7), y0 = ty * kTile + (lane >> 3);
+  const float fx0 = (float)x0, fy0 = (float)y0;
+  float T[4], c0[4], c1[4], c2[4];
   int last[4];
-  bool done[4], inside[4];
+  bool done[4];
 #pragma unroll
   for (int w = 0; w < 4; ++w) {
-    const int x = tx * kTile + (w & 1) * 8 + (lane & 7);
-    const int y = ty * kTile + (w >> 1) * 8 + (lane >> 3);
-    fx[w] = (float)x;
-    fy[w] = (float)y;
-    inside[w] = x < W && y < H;
-    done[w] = !inside[w];
+    done[w] = !(x0 + 8 * (w & 1) < W && y0 + 8 * (w >> 1) < H);
     T[w] = 1.f;
     c0[w] = c1[w] = c2[w] = 0.f;
     last[w] = 0;
@@ -182,6 +191,10 @@ __device__ __forceinline__ void render_tile_fwd(FwdShared& sh, const float4* __r
         sh.b[k] = rr.b;
         sh.c[k] = rr.c.x;
         sh.m[k] = quadrant_mask(q0, q1, q2, ox, oy);
+        if constexpr (USAGE) {
+          us->g[k] = g;
+          us->u[k] = 0u;
+        }
       }
     }
     __syncthreads();
@@ -189,15 +202,18 @@ __device__ __forceinline__ void render_tile_fwd(FwdShared& sh, const float4* __r
     for (int k = 0; k < nb; ++k) {
       const uint32_t m = __builtin_amdgcn_readfirstlane(sh.m[k]) & live;
       if (m == 0) continue;
+      uint32_t used = 0;
       const float4 a = sh.a[k];
       const float4 b = sh.b[k];
       const float cb = sh.c[k];
       const int pos = (int)(b0 - rg.x) + k + 1;
+      const float dxl = a.x - fx0, dyt = a.y - fy0;
 #pragma unroll
       for (int w = 0; w < 4; ++w) {
         if (m & (1u << w)) {
           // per-lane decisions as selects: no divergent branches in the slot
-          const float dx = a.x - fx[w], dy = a.y - fy[w];
+          const float dx = (w & 1) ? dxl - 8.f : dxl;
+          const float dy = (w >> 1) ? dyt - 8.f : dyt;
           const float power = eval_power(a, b.x, dx, dy);
           const float alpha = fminf(kAlphaMax, eval_ea(power, b.y));
           const bool use = !done[w] && !(power > 0.f) && alpha >= kAlphaMin;
@@ -211,17 +227,30 @@ __device__ __forceinline__ void render_tile_fwd(FwdShared& sh, const float4* __r
           T[w] = comp ? Tn : T[w];
           last[w] = comp ? pos : last[w];
           done[w] = done[w] || stop;
+          if constexpr (USAGE) used += (uint32_t)__popcll(__builtin_amdgcn_ballot_w64(comp));
           if (__builtin_amdgcn_ballot_w64(!done[w]) == 0) live &= ~(1u << w);
         }
       }
+      if constexpr (USAGE) {
+        if (lane == 0 && used) us->u[k] = used;
+      }
       if (live == 0) break;
+    }
+    if constexpr (USAGE) {
+      __syncthreads();
+#pragma unroll
+      for (int r = 0; r < kFwdBatch / 64; ++r) {
+        const int k = r * 64 + lane;
+        if (b0 + (uint32_t)k < rg.y && us->u[k]) atomicAdd(usage + us->g[k], us->u[k]);
+      }
     }
   }
   const size_t pix = (size_t)W * H;
 #pragma unroll
   for (int w = 0; w < 4; ++w) {
-    if (!inside[w]) continue;
-    const size_t p = (size_t)fy[w] * W + (size_t)fx[w];
+    const int x = x0 + 8 * (w & 1), y = y0 + 8 * (w >> 1);
+    if (!(x < W && y < H)) continue;
+    const size_t p = (size_t)y * W + x;
     image[p] = c0[w] + T[w] * bg0;
     image[pix + p] = c1[w] + T[w] * bg1;
     image[2 * pix + p] = c2[w] + T[w] * bg2;
@@ -240,8 +269,25 @@ __global__ __launch_bounds__(64) void k_render_fwd(
   const int v = seg / tiles_per_view, tile = seg - v * tiles_per_view;
   const int ty = tile / TX, tx = tile - ty * TX;
   const size_t pix = (size_t)W * H;
-  render_tile_fwd(sh, splat + 3 * (size_t)v * ld, vals, ranges[seg], tx, ty, W, H, bg0, bg1, bg2,
-                  image + 3 * pix * v, final_T + pix * v, n_contrib + pix * v);
+  render_tile_fwd<false>(sh, nullptr, splat + 3 * (size_t)v * ld, vals, ranges[seg], tx, ty, W,
+                         H, bg0, bg1, bg2, image + 3 * pix * v, final_T + pix * v,
+                         n_contrib + pix * v, nullptr);
+}
+
+__global__ __launch_bounds__(64) void k_render_fwd_usage(
+    const float4* __restrict__ splat, int ld, const uint32_t* __restrict__ vals,
+    const uint2* __restrict__ ranges, int W, int H, int TX, int tiles_per_view, float bg0,
+    float bg1, float bg2, float* __restrict__ image, float* __restrict__ final_T,
+    int32_t* __restrict__ n_contrib, uint32_t* __restrict__ usage) {
+  __shared__ FwdShared sh;
+  __shared__ UsageShared us;
+  const int seg = blockIdx.x;
+  const int v = seg / tiles_per_view, tile = seg - v * tiles_per_view;
+  const int ty = tile / TX, tx = tile - ty * TX;
+  const size_t pix = (size_t)W * H;
+  render_tile_fwd<true>(sh, &us, splat + 3 * (size_t)v * ld, vals, ranges[seg], tx, ty, W, H, bg0,
+                        bg1, bg2, image + 3 * pix * v, final_T + pix * v, n_contrib + pix * v,
+                        usage);
 }
 
 // Per-request geometry for the batched renderer: segment base (V+1), pixel
@@ -289,8 +335,9 @@ __global__ __launch_bounds__(64) void k_render_persistent(
     const int TX = tiles_across(d.x);
     const int tile = (int)(item - seg_base[lo]);
     const int ty = tile / TX, tx = tile - ty * TX;
-    render_tile_fwd(sh, splat + 3 * (size_t)lo * ld, vals, ranges[item], tx, ty, d.x, d.y, bg0,
-                    bg1, bg2, images + 3 * pix_base[lo], nullptr, nullptr);
+    render_tile_fwd<false>(sh, nullptr, splat + 3 * (size_t)lo * ld, vals, ranges[item], tx, ty,
+                           d.x, d.y, bg0, bg1, bg2, images + 3 * pix_base[lo], nullptr, nullptr,
+                           nullptr);
   }
 }
 
@@ -325,15 +372,14 @@ __global__ __launch_bounds__(64) void k_render_bwd(
   const size_t pix = (size_t)W * H;
   const float* gi = dL_dimage + 3 * pix * v;
 
-  float fx[4], fy[4], T[4], g0[4], g1[4], g2[4], B0[4], B1[4], B2[4];
+  const int x0 = tx * kTile + (lane & 7), y0 = ty * kTile + (lane >> 3);
+  const float fx0 = (float)x0, fy0 = (float)y0;
+  float T[4], g0[4], g1[4], g2[4], B0[4], B1[4], B2[4];
   int nc[4], wmax[4];
   int jmax = 0;
 #pragma unroll
   for (int w = 0; w < 4; ++w) {
-    const int x = tx * kTile + (w & 1) * 8 + (lane & 7);
-    const int y = ty * kTile + (w >> 1) * 8 + (lane >> 3);
-    fx[w] = (float)x;
-    fy[w] = (float)y;
+    const int x = x0 + 8 * (w & 1), y = y0 + 8 * (w >> 1);
     T[w] = 1.f;
     g0[w] = g1[w] = g2[w] = 0.f;
     nc[w] = 0;
@@ -384,6 +430,7 @@ __global__ __launch_bounds__(64) void k_render_bwd(
       const float4 a = sh.a[k];
       const float4 b = sh.b[k];
       const float4 c = sh.c[k];
+      const float dxl = a.x - fx0, dyt = a.y - fy0;
       float gr[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
       bool contrib = false;
 #pragma unroll
@@ -391,7 +438,8 @@ __global__ __launch_bounds__(64) void k_render_bwd(
         if (m & (1u << w)) {
           // per-lane decisions as selects; an unused pair gets alpha 0, which
           // leaves T and B unchanged and contributes nothing
-          const float dx = a.x - fx[w], dy = a.y - fy[w];
+          const float dx = (w & 1) ? dxl - 8.f : dxl;
+          const float dy = (w >> 1) ? dyt - 8.f : dyt;
           const float power = eval_power(a, b.x, dx, dy);
           const float ea = eval_ea(power, b.y);
           const float alpha = fminf(kAlphaMax, ea);
@@ -448,16 +496,22 @@ __global__ __launch_bounds__(64) void k_render_bwd(
 
 void launch_render_fwd(const gs_projected& proj, const gs_tile_lists& lists, int V, int W, int H,
                        const float bg[3], float* image, float* final_T, int32_t* n_contrib,
-                       hipStream_t s) {
+                       uint32_t* usage, hipStream_t s) {
   const int TX = tiles_across(W), TY = tiles_across(H);
   const int tpv = TX * TY;
   const int blocks = tpv * V;
   if (blocks == 0) return;
   StageScope scope(kStRenderFwd, s);
-  hipLaunchKernelGGL(k_render_fwd, dim3(blocks), dim3(64), 0, s,
-                     reinterpret_cast<const float4*>(proj.splat), proj.ld, lists.vals,
-                     reinterpret_cast<const uint2*>(lists.ranges), W, H, TX, tpv, bg[0], bg[1],
-                     bg[2], image, final_T, n_contrib);
+  if (usage)
+    hipLaunchKernelGGL(k_render_fwd_usage, dim3(blocks), dim3(64), 0, s,
+                       reinterpret_cast<const float4*>(proj.splat), proj.ld, lists.vals,
+                       reinterpret_cast<const uint2*>(lists.ranges), W, H, TX, tpv, bg[0], bg[1],
+                       bg[2], image, final_T, n_contrib, usage);
+  else
+    hipLaunchKernelGGL(k_render_fwd, dim3(blocks), dim3(64), 0, s,
+                       reinterpret_cast<const float4*>(proj.splat), proj.ld, lists.vals,
+                       reinterpret_cast<const uint2*>(lists.ranges), W, H, TX, tpv, bg[0], bg[1],
+                       bg[2], image, final_T, n_contrib);
 }
 
 size_t render_batched_workspace_bytes(int V) {

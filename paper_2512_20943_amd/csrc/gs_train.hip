@@ -26,6 +26,24 @@ __global__ __launch_bounds__(256) void k_l1(const float* __restrict__ img,
   if (threadIdx.x == 0) atomicAdd(loss, ((s_w[0] + s_w[1]) + (s_w[2] + s_w[3])) / (double)count);
 }
 
+// Sum of squared differences: per-block FP64 partials, one atomic per block.
+__global__ __launch_bounds__(256) void k_sq_error(const float* __restrict__ a,
+                                                  const float* __restrict__ b, int64_t count,
+                                                  double* __restrict__ sum) {
+  __shared__ double s_w[4];
+  double acc = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < count;
+       i += (int64_t)gridDim.x * 256) {
+    const double d = (double)a[i] - (double)b[i];
+    acc += d * d;
+  }
+  for (int off = 32; off >= 1; off >>= 1) acc += __shfl_xor(acc, off, 64);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0) s_w[wave] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) atomicAdd(sum, (s_w[0] + s_w[1]) + (s_w[2] + s_w[3]));
+}
+
 __global__ __launch_bounds__(256) void k_adam(float* __restrict__ p, const float* __restrict__ g,
                                               float* __restrict__ m, float* __restrict__ v,
                                               int64_t count, float lr, float b1, float b2,
@@ -54,6 +72,12 @@ void launch_l1(const float* image, const float* target, int64_t count, float* gr
   StageScope scope(kStL1, s);
   hipLaunchKernelGGL(k_l1, dim3(grid_for(count)), dim3(256), 0, s, image, target, count,
                      (float)(1.0 / (double)count), grad, loss);
+}
+
+void launch_sq_error(const float* a, const float* b, int64_t count, double* sum, hipStream_t s) {
+  if (count <= 0) return;
+  StageScope scope(kStL1, s);
+  hipLaunchKernelGGL(k_sq_error, dim3(grid_for(count)), dim3(256), 0, s, a, b, count, sum);
 }
 
 void launch_adam(float* p, const float* g, float* m, float* v, int64_t count, float lr, float b1,

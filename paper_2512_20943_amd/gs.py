@@ -46,7 +46,7 @@ class GsCamera(ctypes.Structure):
 
 
 class GsOpts(ctypes.Structure):
-    _fields_ = [("bg", c_float * 3), ("reserved", c_float)]
+    _fields_ = [("bg", c_float * 3), ("reserved", c_float), ("usage", c_void_p)]
 
 
 class GsProjected(ctypes.Structure):
@@ -112,6 +112,8 @@ def load() -> ctypes.CDLL:
                                   c_void_p, ctypes.c_size_t, c_void_p]
     lib.gs_l1_loss_grad.argtypes = [c_void_p, c_void_p, c_void_p, c_int64, c_void_p, c_void_p,
                                     c_void_p]
+    lib.gs_sq_error.argtypes = [c_void_p, c_void_p, c_void_p, c_int64, c_void_p, c_void_p]
+    lib.gs_sq_error.restype = c_int32
     lib.gs_adam_step.argtypes = [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_int64,
                                  ctypes.c_int, c_float, c_float, c_float, c_float, c_void_p]
     lib.gs_render_batched_workspace_size.argtypes = [ctypes.c_int]
@@ -139,7 +141,7 @@ def exported_symbols():
             "gs_apply_frame_update", "gs_project", "gs_bin_sort", "gs_render_fwd",
             "gs_render_bwd", "gs_l1_loss_grad", "gs_adam_step", "gs_set_timing",
             "gs_collect_timing", "gs_stage_name", "gs_render_batched_workspace_size",
-            "gs_render_fwd_batched"]
+            "gs_render_fwd_batched", "gs_sq_error"]
 
 
 def _ptr(t):
@@ -363,9 +365,11 @@ def gs_bin_sort(ctx: Context, proj: Projected, cams: Cameras, lists: TileLists,
 
 def gs_render_fwd(ctx: Context, proj: Projected, lists: TileLists, cams: Cameras, bg,
                   image: torch.Tensor, final_T: torch.Tensor, n_contrib: torch.Tensor,
-                  stream=None):
+                  stream=None, usage: torch.Tensor | None = None):
+    """``usage`` (int32 tensor of n, nullable) accumulates composited-pixel
+    counts per Gaussian."""
     pc = proj.c()
-    opts = GsOpts((c_float * 3)(*[float(x) for x in bg]), 0.0)
+    opts = GsOpts((c_float * 3)(*[float(x) for x in bg]), 0.0, _ptr(usage))
     ctx.check(ctx.lib.gs_render_fwd(ctx.handle, ctypes.byref(pc), ctypes.byref(lists.c()),
                                     cams.host, _ptr(cams.dev), cams.V, ctypes.byref(opts),
                                     _ptr(image), _ptr(final_T), _ptr(n_contrib),
@@ -375,7 +379,7 @@ def gs_render_fwd(ctx: Context, proj: Projected, lists: TileLists, cams: Cameras
 def gs_render_fwd_batched(ctx: Context, proj: Projected, lists: TileLists, cams: Cameras, bg,
                           images: torch.Tensor, workspace: torch.Tensor, stream=None):
     pc = proj.c()
-    opts = GsOpts((c_float * 3)(*[float(x) for x in bg]), 0.0)
+    opts = GsOpts((c_float * 3)(*[float(x) for x in bg]), 0.0, None)
     ctx.check(ctx.lib.gs_render_fwd_batched(ctx.handle, ctypes.byref(pc), ctypes.byref(lists.c()),
                                             cams.host, _ptr(cams.dev), cams.V, ctypes.byref(opts),
                                             _ptr(images), _ptr(workspace), workspace.numel(),
@@ -391,7 +395,7 @@ def gs_render_bwd(ctx: Context, frame: Gaussians, proj: Projected, lists: TileLi
                   workspace: torch.Tensor, upd=None, dL_ddelta=None, stream=None):
     """``upd`` = (anchor_quat tensor, mask tensor, gw, gh) or None."""
     fc, pc, gc = frame.c(), proj.c(), grad.c()
-    opts = GsOpts((c_float * 3)(*[float(x) for x in bg]), 0.0)
+    opts = GsOpts((c_float * 3)(*[float(x) for x in bg]), 0.0, None)
     uc = None
     if upd is not None:
         aq, mask, gw, gh = upd
@@ -406,6 +410,11 @@ def gs_render_bwd(ctx: Context, frame: Gaussians, proj: Projected, lists: TileLi
 def gs_l1_loss_grad(ctx: Context, image, target, grad, loss_dev, stream=None):
     ctx.check(ctx.lib.gs_l1_loss_grad(ctx.handle, _ptr(image), _ptr(target), image.numel(),
                                       _ptr(grad), _ptr(loss_dev), _stream(stream)))
+
+
+def gs_sq_error(ctx: Context, a, b, sum_dev, stream=None):
+    ctx.check(ctx.lib.gs_sq_error(ctx.handle, _ptr(a), _ptr(b), a.numel(), _ptr(sum_dev),
+                                  _stream(stream)))
 
 
 def gs_adam_step(ctx: Context, param, grad, m, v, step: int, lr=1e-3, beta1=0.9, beta2=0.999,

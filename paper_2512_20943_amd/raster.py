@@ -68,7 +68,8 @@ class Rasterizer:
                     raise
                 self.capacity = max(int(lists.count * self.growth) + 1024, self.capacity * 2)
 
-    def forward(self, g: gs.Gaussians, cams: gs.Cameras, bg=(0.0, 0.0, 0.0), stream=None):
+    def forward(self, g: gs.Gaussians, cams: gs.Cameras, bg=(0.0, 0.0, 0.0), stream=None,
+                usage=None):
         W, H = cams.wh[0]
         device = g.mean.device
         proj = self.project(g, cams, stream)
@@ -76,7 +77,8 @@ class Rasterizer:
         image = torch.empty(cams.V, 3, H, W, device=device)
         final_T = torch.empty(cams.V, H, W, device=device)
         n_contrib = torch.empty(cams.V, H, W, dtype=torch.int32, device=device)
-        gs.gs_render_fwd(self.ctx, proj, lists, cams, bg, image, final_T, n_contrib, stream)
+        gs.gs_render_fwd(self.ctx, proj, lists, cams, bg, image, final_T, n_contrib, stream,
+                         usage=usage)
         return dict(image=image, final_T=final_T, n_contrib=n_contrib, proj=proj, lists=lists)
 
     def backward(self, g: gs.Gaussians, cams: gs.Cameras, state: dict, dL_dimage: torch.Tensor,

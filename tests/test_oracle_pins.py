@@ -535,3 +535,44 @@ def test_apply_backward_matches_central_differences(oracle_mod):
         assert abs(fd - an) <= 1e-5 * abs(an) + 1e-7 * gmax, (c, i, fd, an)
         checked += 1
     assert checked >= 30
+
+
+def test_usage_of_an_isotropic_gaussian_is_its_alpha_disk(oracle_mod):
+    """An on-axis isotropic Gaussian composites exactly the pixels of its tile
+    rectangle where opacity * exp(-r^2 / (2 a)) >= 1/255, a the dilated
+    variance: a disk of radius^2 = 2 a ln(255 opacity)."""
+    W = H = 64
+    cams = axis_cam(W, H)
+    f = cams["f"][0, 0]
+    for ls, logit in ((-2.5, 0.5), (-3.0, 2.0), (-2.2, -1.0)):
+        sc = hand_scene([(0, 0, 0)], [(ls, ls, ls)], [(1, 0, 0, 0)], [logit], [(0.5, 0.5, 0.5)])
+        P, L, img = oracle_mod.forward(sc, cams)
+        a = (f * math.exp(float(np.float32(ls))) / 4.0) ** 2 + 0.3
+        op = 1 / (1 + math.exp(-float(np.float32(logit))))
+        r2 = 2 * a * math.log(255 * op)
+        x0, y0, x1, y1 = P["rect"][0, 0]
+        ys, xs = np.mgrid[y0 * 16:y1 * 16, x0 * 16:x1 * 16]
+        inside = ((xs - W / 2) ** 2 + (ys - H / 2) ** 2) <= r2
+        assert img["usage"][0] == int(inside.sum())
+        assert img["usage"][0] == int((img["n_contrib"][0] > 0).sum())
+
+
+def test_usage_total_counts_every_composited_pair(oracle_mod):
+    sc = scenes.make_scene(300, 17, -1, 1, -3.2, 0.5, 1)
+    cams = scenes.arc_cameras(2, 3.5, 48, 40)
+    P, L, img = oracle_mod.forward(sc, cams)
+    base, txv, _ = oracle_mod.segment_bases(cams)
+    total = 0
+    for v in range(2):
+        for y in range(40):
+            for x in range(48):
+                s = int(base[v] + (y // 16) * txv[v] + x // 16)
+                b, e = L["ranges"][s]
+                for j in range(b, b + img["n_contrib"][v, y, x]):
+                    gid = L["vals"][j]
+                    dx, dy = P["mean2d"][v, gid] - (x, y)
+                    A, B, C = P["conic"][v, gid]
+                    pw = -0.5 * (A * dx * dx + C * dy * dy) - B * dx * dy
+                    al = min(0.99, P["alpha_hat"][v, gid] * math.exp(pw))
+                    total += int(pw <= 0 and al >= 1 / 255)
+    assert img["usage"].sum() == total
