@@ -30,9 +30,10 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
-# FP32 vector rate without packed FP32 instructions (they are not emitted by
-# this build): 256 CUs x 4 SIMDs x 16 lanes x 2 FLOP (FMA) x 2.4 GHz.
-PEAK_ALU_TFLOPS = 78.6
+# Published MI355X FP32 vector peak.  This build emits no packed FP32
+# instructions, which caps the attainable rate at half of it (78.6 TFLOP/s);
+# the fraction is still reported against the published figure.
+PEAK_ALU_TFLOPS = 157.3
 
 # Algorithmic FP32 operations per (pixel, entry) pair, FMA counted as 2 and
 # a transcendental as 1 (see the design doc for the breakdown).

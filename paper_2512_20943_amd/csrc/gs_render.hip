@@ -122,7 +122,7 @@ __device__ __forceinline__ float wave_sum_lane63(float v) {
 // One 64-lane wave per 16x16 tile.  Lane l owns pixel (l & 7, l >> 3) of
 // each of the four 8x8 quadrants ("slot" w = quadrant w), so a record's
 // quadrant mask selects slots uniformly across the wave.
-constexpr int kFwdBatch = 128;  // records staged per batch (2 per lane)
+constexpr int kFwdBatch = 64;   // records staged per batch (1 per lane)
 constexpr int kBwdBatch = 64;   // records staged per backward batch (1 per lane)
 
 struct FwdShared {
