@@ -227,6 +227,30 @@ def l1(image, target):
     return float(loss), grad.reshape(np.shape(image))
 
 
+def l1_dssim(image, target, lam=0.2, with_map=False):
+    """Eq. (1): (1 - lambda) L1 + lambda (1 - SSIM) over (V, 3, H, W) images
+    (11x11 Gaussian window, sigma 1.5, zero padding, C1 = 0.01^2,
+    C2 = 0.03^2) and its gradient w.r.t. the image."""
+    lib = _load()
+    lib.or_l1_dssim.restype = ctypes.c_double
+    img = _f64(image)
+    tgt = _f64(target)
+    H, W = img.shape[-2], img.shape[-1]
+    planes = int(img.size // (H * W))
+    grad = np.zeros_like(img)
+    smap = np.zeros_like(img) if with_map else None
+    loss = lib.or_l1_dssim(ctypes.c_int(planes), ctypes.c_int(H), ctypes.c_int(W), _p(img),
+                           _p(tgt), ctypes.c_double(lam), _p(grad), _p(smap))
+    return (float(loss), grad, smap) if with_map else (float(loss), grad)
+
+
+def ssim_window():
+    lib = _load()
+    w = np.zeros(11)
+    lib.or_ssim_window(_p(w))
+    return w
+
+
 # --------------------------------------------------------------------------
 # backward steps
 # --------------------------------------------------------------------------

@@ -1107,3 +1107,113 @@ double or_forward_loss(int n, int ld, int deg, const float* mean, const float* l
   if (signature) *signature = h;
   return count ? loss / (double)count : 0.0;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Photometric loss of Eq. (1): L = (1 - lambda) L1 + lambda (1 - SSIM).      */
+/* SSIM per channel with an 11x11 Gaussian window (sigma 1.5, weights         */
+/* normalised to sum 1), zero padding outside the image, C1 = 0.01^2,        */
+/* C2 = 0.03^2; SSIM = mean of the per-pixel index over (V, 3, H, W).         */
+/* ------------------------------------------------------------------------ */
+#define OR_SSIM_R 5
+
+static void ssim_window(double w[2 * OR_SSIM_R + 1]) {
+  double s = 0.0;
+  for (int i = -OR_SSIM_R; i <= OR_SSIM_R; ++i) {
+    w[i + OR_SSIM_R] = exp(-(double)(i * i) / (2.0 * 1.5 * 1.5));
+    s += w[i + OR_SSIM_R];
+  }
+  for (int i = 0; i <= 2 * OR_SSIM_R; ++i) w[i] /= s;
+}
+
+void or_ssim_window(double* w) { ssim_window(w); }
+
+/* Windowed sum of one plane at (x, y): sum over the 11x11 window of
+ * w(i) w(j) f(y + j, x + i), samples outside the image taken as 0. */
+static double window_sum(const double* f, int W, int H, int x, int y, const double* w) {
+  double acc = 0.0;
+  for (int j = -OR_SSIM_R; j <= OR_SSIM_R; ++j) {
+    const int yy = y + j;
+    if (yy < 0 || yy >= H) continue;
+    for (int i = -OR_SSIM_R; i <= OR_SSIM_R; ++i) {
+      const int xx = x + i;
+      if (xx < 0 || xx >= W) continue;
+      acc += w[i + OR_SSIM_R] * w[j + OR_SSIM_R] * f[(size_t)yy * W + xx];
+    }
+  }
+  return acc;
+}
+
+/* Loss and gradient for `planes` image planes of H x W (V*3 planes).
+ * ssim_map (planes*H*W, nullable) receives the per-pixel index.  Returns
+ * (1 - lambda) mean|I - I*| + lambda (1 - mean SSIM); grad gets its exact
+ * derivative w.r.t. the image (sign(0) = 0 for the L1 part). */
+double or_l1_dssim(int planes, int H, int W, const double* img, const double* tgt,
+                   double lambda, double* grad, double* ssim_map) {
+  const double C1 = 0.01 * 0.01, C2 = 0.03 * 0.03;
+  const size_t pix = (size_t)W * H;
+  const double count = (double)planes * (double)pix;
+  double w[2 * OR_SSIM_R + 1];
+  ssim_window(w);
+  double ssim_sum = 0.0, l1_sum = 0.0;
+  for (int pl = 0; pl < planes; ++pl) {
+    const double* x = img + (size_t)pl * pix;
+    const double* y = tgt + (size_t)pl * pix;
+    double* xx = (double*)malloc(sizeof(double) * pix);
+    double* yy = (double*)malloc(sizeof(double) * pix);
+    double* xy = (double*)malloc(sizeof(double) * pix);
+    double* A1 = (double*)malloc(sizeof(double) * pix);
+    double* A2 = (double*)malloc(sizeof(double) * pix);
+    double* A3 = (double*)malloc(sizeof(double) * pix);
+    for (size_t p = 0; p < pix; ++p) {
+      xx[p] = x[p] * x[p];
+      yy[p] = y[p] * y[p];
+      xy[p] = x[p] * y[p];
+    }
+    double plane_sum = 0.0;
+#pragma omp parallel for reduction(+ : plane_sum) schedule(static)
+    for (int r = 0; r < H; ++r)
+      for (int c = 0; c < W; ++c) {
+        const double mx = window_sum(x, W, H, c, r, w), my = window_sum(y, W, H, c, r, w);
+        const double sxx = window_sum(xx, W, H, c, r, w) - mx * mx;
+        const double syy = window_sum(yy, W, H, c, r, w) - my * my;
+        const double sxy = window_sum(xy, W, H, c, r, w) - mx * my;
+        const double N1 = 2.0 * mx * my + C1, N2 = 2.0 * sxy + C2;
+        const double D1 = mx * mx + my * my + C1, D2 = sxx + syy + C2;
+        const double S = (N1 * N2) / (D1 * D2);
+        const size_t p = (size_t)r * W + c;
+        if (ssim_map) ssim_map[(size_t)pl * pix + p] = S;
+        plane_sum += S;
+        /* partials of S w.r.t. the windowed statistics */
+        const double dS_dmx = (2.0 * my * N2) / (D1 * D2) - S * (2.0 * mx) / D1;
+        const double dS_dsxx = -S / D2;
+        const double dS_dsxy = (2.0 * N1) / (D1 * D2);
+        /* sxx = E[x^2] - mx^2 and sxy = E[xy] - mx my, so through mx: */
+        A1[p] = dS_dmx - 2.0 * mx * dS_dsxx - my * dS_dsxy;
+        A2[p] = dS_dsxx;
+        A3[p] = dS_dsxy;
+      }
+    ssim_sum += plane_sum;
+    if (grad) {
+      /* adjoint of the windowed sums (the window is symmetric) */
+#pragma omp parallel for schedule(static)
+      for (int r = 0; r < H; ++r)
+        for (int c = 0; c < W; ++c) {
+          const size_t p = (size_t)r * W + c;
+          const double g_ssim = window_sum(A1, W, H, c, r, w) +
+                                2.0 * x[p] * window_sum(A2, W, H, c, r, w) +
+                                y[p] * window_sum(A3, W, H, c, r, w);
+          const double d = x[p] - y[p];
+          const double g_l1 = d > 0.0 ? 1.0 : (d < 0.0 ? -1.0 : 0.0);
+          grad[(size_t)pl * pix + p] = ((1.0 - lambda) * g_l1 - lambda * g_ssim) / count;
+        }
+    }
+    for (size_t p = 0; p < pix; ++p) l1_sum += fabs(x[p] - y[p]);
+    free(xx);
+    free(yy);
+    free(xy);
+    free(A1);
+    free(A2);
+    free(A3);
+  }
+  return (1.0 - lambda) * l1_sum / count + lambda * (1.0 - ssim_sum / count);
+}
