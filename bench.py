@@ -55,6 +55,7 @@ def parse():
     ap.add_argument("--views", type=int, default=20)
     ap.add_argument("--gaussians", type=int, default=300_000)
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-dssim-step", action="store_true")
     ap.add_argument("--serve-rates", default="500,2000",
                     help="aggregate Poisson arrival rates (requests/s)")
     ap.add_argument("--serve-seconds", type=float, default=2.0)
@@ -79,7 +80,7 @@ def copy_calibration():
 class TrainStep:
     """One per-frame training iteration on a fixed scene and camera set."""
 
-    def __init__(self, scene, cams, target_scene, frame_update=None):
+    def __init__(self, scene, cams, target_scene, frame_update=None, loss="l1"):
         import torch
 
         from paper_2512_20943_amd import gs
@@ -116,6 +117,12 @@ class TrainStep:
         self.target = self.r.forward(tg, self.cams)["image"].clone()
         self.dimg = torch.empty_like(self.target)
         self.loss = torch.zeros(1, dtype=torch.float64, device="cuda")
+        self.loss_kind = loss
+        if loss == "l1_dssim":
+            planes = self.target.numel() // (self.target.shape[-1] * self.target.shape[-2])
+            self.ws_ssim = torch.empty(
+                gs.l1_dssim_workspace_size(planes, self.target.shape[-2], self.target.shape[-1]),
+                dtype=torch.uint8, device="cuda")
         self.t = 0
         self.frame_update = frame_update
         if frame_update is not None:
@@ -139,7 +146,11 @@ class TrainStep:
             g = self.frame
         out = self.r.forward(g, self.cams)
         self.loss.zero_()
-        gs.gs_l1_loss_grad(self.ctx, out["image"], self.target, self.dimg, self.loss)
+        if self.loss_kind == "l1_dssim":
+            gs.gs_l1_dssim_loss_grad(self.ctx, out["image"], self.target, self.dimg, self.loss,
+                                     self.ws_ssim, 0.2)
+        else:
+            gs.gs_l1_loss_grad(self.ctx, out["image"], self.target, self.dimg, self.loss)
         if self.frame_update is None:
             self.r.backward(g, self.cams, out, self.dimg, self.grad)
             gs.gs_adam_step(self.ctx, self.flat, self.gflat, self.m, self.v, self.t)
@@ -194,6 +205,8 @@ def algorithmic_work(stage, ts, steps):
         return 28.0 * ts.nparam, "byte", "hbm", None
     if stage == "l1":
         return 12.0 * ts.target.numel(), "byte", "hbm", None
+    if stage == "dssim":
+        return 44.0 * ts.target.numel(), "byte", "hbm", None
     if stage == "emit":
         return V * n * 8.0 + M * 8.0, "byte", "hbm", None
     return None
@@ -202,7 +215,8 @@ def algorithmic_work(stage, ts, steps):
 STAGE_SOURCE = {"render_fwd": "gs_render.hip", "render_bwd": "gs_render.hip",
                 "project": "gs_project.hip", "project_bwd": "gs_project.hip",
                 "depth_sort": "gs_sort.hip", "segment_sort": "gs_sort.hip", "emit": "gs_sort.hip",
-                "adam": "gs_train.hip", "l1": "gs_train.hip"}
+                "adam": "gs_train.hip", "l1": "gs_train.hip",
+                "dssim": "gs_ssim.hip"}
 
 
 def counted_traffic(stage):
@@ -381,6 +395,21 @@ def main():
             "stage_ms_per_step": {k: round(v[0] / k2, 4) for k, v in st2.items() if v[1] > 0}}
         log(f"frame-update step: {wall2 / k2 * 1e3:.2f} ms")
         del fs
+    if not args.no_dssim_step:
+        ds = TrainStep(scene, cams, target_scene, loss="l1_dssim")
+        k3 = max(args.steps // 2, 3)
+        wall3, _, st3 = time_steps(ds, k3, 2)
+        ms3, n3 = st3.get("dssim", (0.0, 0))
+        launch_s = ms3 / max(n3, 1) / 1e3
+        bytes_per_launch = algorithmic_work("dssim", ds, k3)[0] * k3 / max(n3, 1)
+        result["dssim_step"] = {
+            "iters_per_s": round(k3 / wall3, 4), "ms_per_step": round(wall3 / k3 * 1e3, 3),
+            "loss": "(1 - 0.2) L1 + 0.2 (1 - SSIM), 11x11 Gaussian window",
+            "dssim_ms": round(launch_s * 1e3, 4),
+            "dssim_GBps": round(bytes_per_launch / launch_s / 1e9, 1) if n3 else None,
+            "stage_ms_per_step": {k: round(v[0] / k3, 4) for k, v in st3.items() if v[1] > 0}}
+        log(f"Eq. (1) L1 + D-SSIM step: {wall3 / k3 * 1e3:.2f} ms")
+        del ds
     if not args.no_serve:
         result["serving"] = serving(args, scene)
     if not args.no_cpu_baseline:

@@ -169,7 +169,7 @@ size_t gs_render_bwd_workspace_size(int n_views, int ld);
  *   0 apply, 1 project, 2 depth sort, 3 count scan, 4 emit, 5 segment sort,
  *   6 ranges, 7 render fwd, 8 render bwd, 9 project bwd, 10 apply bwd,
  *   11 l1, 12 adam, 13 fill. */
-#define GS_STAGE_COUNT 14
+#define GS_STAGE_COUNT 15
 gs_status gs_set_timing(gs_ctx* ctx, int enable);
 /* Sum of event-measured milliseconds and number of launches per stage since
  * the previous collection (host arrays of GS_STAGE_COUNT); blocks until the
@@ -259,6 +259,18 @@ gs_status gs_render_bwd(gs_ctx* ctx, const gs_gaussians* frame, const gs_project
  * grad = sign(image - target) / count (sign(0) = 0) WRITTEN. */
 gs_status gs_l1_loss_grad(gs_ctx* ctx, const float* image, const float* target, int64_t count,
                           float* grad, double* loss_dev, void* stream);
+
+/* Full photometric loss of Eq. (1): (1 - lambda) L1 + lambda (1 - SSIM) over
+ * `planes` image planes of H x W (V*3 for V RGB views), SSIM with an 11x11
+ * Gaussian window (sigma 1.5, weights summing to 1), zero padding, C1 =
+ * 0.01^2, C2 = 0.03^2, averaged over all values; lambda = 0.2 in the paper's
+ * setting (Sec. IV-A).  The loss is ACCUMULATED in FP64 into *loss_dev
+ * (device; caller zeroes); its gradient w.r.t. the image is WRITTEN to grad.
+ * workspace: gs_l1_dssim_workspace_size bytes. */
+size_t gs_l1_dssim_workspace_size(int planes, int H, int W);
+gs_status gs_l1_dssim_loss_grad(gs_ctx* ctx, const float* image, const float* target, int planes,
+                                int H, int W, float lambda, float* grad, double* loss_dev,
+                                void* workspace, size_t ws_bytes, void* stream);
 
 /* Sum of squared differences over count values, ACCUMULATED in FP64 into
  * *sum_dev (device; caller zeroes).  mean = sum / count gives the MSE behind

@@ -243,7 +243,8 @@ gs_status gs_collect_timing(gs_ctx* c, double* ms, int64_t* launches) {
 const char* gs_stage_name(int stage) {
   static const char* names[GS_STAGE_COUNT] = {
       "apply",  "project",    "depth_sort",  "count_scan", "emit", "segment_sort", "ranges",
-      "render_fwd", "render_bwd", "project_bwd", "apply_bwd", "l1",   "adam",         "fill"};
+      "render_fwd", "render_bwd", "project_bwd", "apply_bwd", "l1",   "adam",         "fill",
+      "dssim"};
   return (stage >= 0 && stage < GS_STAGE_COUNT) ? names[stage] : "?";
 }
 
@@ -455,6 +456,29 @@ gs_status gs_l1_loss_grad(gs_ctx* c, const float* image, const float* target, in
   GS_TRY(use_device(c));
   gs::launch_l1(image, target, count, grad, loss_dev, (hipStream_t)stream);
   GS_LAUNCHED(c, "l1");
+  return GS_OK;
+}
+
+size_t gs_l1_dssim_workspace_size(int planes, int H, int W) {
+  if (planes <= 0 || H <= 0 || W <= 0) return 0;
+  return gs::l1_dssim_workspace_bytes(planes, H, W);
+}
+
+gs_status gs_l1_dssim_loss_grad(gs_ctx* c, const float* image, const float* target, int planes,
+                                int H, int W, float lambda, float* grad, double* loss_dev,
+                                void* ws, size_t ws_bytes, void* stream) {
+  if (!c) return fail(nullptr, GS_ERR_INVALID_ARG, "ctx is NULL");
+  TimerGuard timer_guard(c);
+  if (planes <= 0 || H <= 0 || W <= 0 || planes > 65535)
+    return fail(c, GS_ERR_INVALID_ARG, "planes/H/W out of range");
+  if (!(lambda >= 0.f && lambda <= 1.f)) return fail(c, GS_ERR_INVALID_ARG, "lambda not in [0,1]");
+  if (!image || !target || !grad || !loss_dev) return fail(c, GS_ERR_INVALID_ARG, "NULL buffer");
+  const size_t need = gs::l1_dssim_workspace_bytes(planes, H, W);
+  if (!ws || ws_bytes < need)
+    return fail(c, GS_ERR_OOM, "l1_dssim workspace %zu < %zu bytes", ws_bytes, need);
+  GS_TRY(use_device(c));
+  gs::launch_l1_dssim(image, target, planes, H, W, lambda, grad, loss_dev, ws, (hipStream_t)stream);
+  GS_LAUNCHED(c, "l1_dssim");
   return GS_OK;
 }
 

@@ -29,7 +29,7 @@ __host__ __device__ inline int tiles_across(int px) { return (px + kTile - 1) / 
 // Stages whose device time the context can measure with HIP events.
 enum Stage {
   kStApply = 0, kStProject, kStDepthSort, kStCountScan, kStEmit, kStSegmentSort, kStRanges,
-  kStRenderFwd, kStRenderBwd, kStProjectBwd, kStApplyBwd, kStL1, kStAdam, kStFill, kStageCount
+  kStRenderFwd, kStRenderBwd, kStProjectBwd, kStApplyBwd, kStL1, kStAdam, kStFill, kStDssim, kStageCount
 };
 static_assert(kStageCount == GS_STAGE_COUNT, "stage table out of sync with the header");
 
@@ -96,6 +96,9 @@ void launch_render_bwd(const gs_projected& proj, const gs_tile_lists& lists, int
 // training support
 void launch_l1(const float* image, const float* target, int64_t count, float* grad,
                double* loss, hipStream_t s);
+size_t l1_dssim_workspace_bytes(int planes, int H, int W);
+void launch_l1_dssim(const float* image, const float* target, int planes, int H, int W,
+                     float lambda, float* grad, double* loss, void* ws, hipStream_t s);
 void launch_sq_error(const float* a, const float* b, int64_t count, double* sum, hipStream_t s);
 void launch_adam(float* p, const float* g, float* m, float* v, int64_t count, float lr, float b1,
                  float b2, float eps, float bc1, float bc2, hipStream_t s);

@@ -27,7 +27,7 @@ GS_ERR_HIP = 4
 TILE = 16
 SPLAT_FLOATS = 12
 GRAD2D_FLOATS = 12
-STAGE_COUNT = 14
+STAGE_COUNT = 15
 
 c_int32, c_int64, c_void_p, c_double, c_float = (ctypes.c_int32, ctypes.c_int64, ctypes.c_void_p,
                                                  ctypes.c_double, ctypes.c_float)
@@ -112,6 +112,12 @@ def load() -> ctypes.CDLL:
                                   c_void_p, ctypes.c_size_t, c_void_p]
     lib.gs_l1_loss_grad.argtypes = [c_void_p, c_void_p, c_void_p, c_int64, c_void_p, c_void_p,
                                     c_void_p]
+    lib.gs_l1_dssim_workspace_size.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int]
+    lib.gs_l1_dssim_workspace_size.restype = ctypes.c_size_t
+    lib.gs_l1_dssim_loss_grad.argtypes = [c_void_p, c_void_p, c_void_p, ctypes.c_int, ctypes.c_int,
+                                          ctypes.c_int, c_float, c_void_p, c_void_p, c_void_p,
+                                          ctypes.c_size_t, c_void_p]
+    lib.gs_l1_dssim_loss_grad.restype = c_int32
     lib.gs_sq_error.argtypes = [c_void_p, c_void_p, c_void_p, c_int64, c_void_p, c_void_p]
     lib.gs_sq_error.restype = c_int32
     lib.gs_adam_step.argtypes = [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_int64,
@@ -141,7 +147,8 @@ def exported_symbols():
             "gs_apply_frame_update", "gs_project", "gs_bin_sort", "gs_render_fwd",
             "gs_render_bwd", "gs_l1_loss_grad", "gs_adam_step", "gs_set_timing",
             "gs_collect_timing", "gs_stage_name", "gs_render_batched_workspace_size",
-            "gs_render_fwd_batched", "gs_sq_error"]
+            "gs_render_fwd_batched", "gs_sq_error", "gs_l1_dssim_workspace_size",
+            "gs_l1_dssim_loss_grad"]
 
 
 def _ptr(t):
@@ -410,6 +417,20 @@ def gs_render_bwd(ctx: Context, frame: Gaussians, proj: Projected, lists: TileLi
 def gs_l1_loss_grad(ctx: Context, image, target, grad, loss_dev, stream=None):
     ctx.check(ctx.lib.gs_l1_loss_grad(ctx.handle, _ptr(image), _ptr(target), image.numel(),
                                       _ptr(grad), _ptr(loss_dev), _stream(stream)))
+
+
+def gs_l1_dssim_loss_grad(ctx: Context, image, target, grad, loss_dev, workspace, lam=0.2,
+                          stream=None):
+    """Eq. (1) loss over (V, 3, H, W) images; grad written, loss accumulated."""
+    H, W = image.shape[-2], image.shape[-1]
+    planes = image.numel() // (H * W)
+    ctx.check(ctx.lib.gs_l1_dssim_loss_grad(ctx.handle, _ptr(image), _ptr(target), planes, H, W,
+                                            float(lam), _ptr(grad), _ptr(loss_dev),
+                                            _ptr(workspace), workspace.numel(), _stream(stream)))
+
+
+def l1_dssim_workspace_size(planes: int, H: int, W: int) -> int:
+    return int(load().gs_l1_dssim_workspace_size(planes, H, W))
 
 
 def gs_sq_error(ctx: Context, a, b, sum_dev, stream=None):

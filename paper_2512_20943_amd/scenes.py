@@ -228,3 +228,28 @@ def workload_large_2m(seed: int = 0, n: int = 2_000_000, n_views: int = 8,
     cams = arc_cameras(n_views, 5.0, width, height)
     target_scene = jitter_means(scene, 0.01, seed + 1000)
     return scene, cams, target_scene
+
+
+def image_pair(n_views: int, height: int, width: int, seed: int, noise: float = 0.05):
+    """Render-like (V, 3, H, W) FP32 image in [0, 1] (a few random low-frequency
+    cosines per channel plus a few flat rectangles) and a target that differs
+    by N(0, noise) and, in one rectangle, by a constant shift."""
+    g = rng(seed)
+    yy, xx = np.meshgrid(np.arange(height, dtype=np.float64), np.arange(width, dtype=np.float64),
+                         indexing="ij")
+    img = np.empty((n_views, 3, height, width), np.float64)
+    for v in range(n_views):
+        for c in range(3):
+            f = 0.5 * np.ones_like(xx)
+            for _ in range(4):
+                kx, ky = g.uniform(0.0, 0.08, 2)
+                f += g.uniform(0.05, 0.2) * np.cos(kx * xx + ky * yy + g.uniform(0, 2 * np.pi))
+            img[v, c] = f
+        for _ in range(3):
+            x0, y0 = int(g.integers(0, width)), int(g.integers(0, height))
+            img[v, :, y0:y0 + height // 6, x0:x0 + width // 6] = g.uniform(0, 1, (3, 1, 1))
+    img = np.clip(img, 0.0, 1.0)
+    tgt = img + g.normal(0.0, noise, img.shape)
+    x0, y0 = int(g.integers(0, width)), int(g.integers(0, height))
+    tgt[:, :, y0:y0 + height // 5, x0:x0 + width // 5] += 0.1
+    return img.astype(np.float32), np.clip(tgt, 0.0, 1.0).astype(np.float32)
