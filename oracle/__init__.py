@@ -318,6 +318,110 @@ def adam(theta, grad, m, v, t, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
 
 
 # --------------------------------------------------------------------------
+# temporal and keyframe terms (Sec. III-B), plain definitions in FP64
+# --------------------------------------------------------------------------
+
+# The delta images hold the update itself: translation, the rotation
+# quaternion dq applied as dq (x) q, and the opacity-logit increment.  "No
+# motion" is therefore (0, 0, 0, 1, 0, 0, 0, 0), and the temporal term
+# measures the distance of every delta from it.
+IDENTITY_UPDATE = np.array([0.0, 0.0, 0.0, 1.0, 0.0, 0.0, 0.0, 0.0])
+
+
+def temporal_l1(delta, n, weight):
+    """Eq. (6)/(7): weight * sum over texels i < n and the 8 channels of
+    |delta - identity update|, and its gradient weight * sign(.) (sign(0) = 0;
+    padding texels i >= n carry neither loss nor gradient)."""
+    d = _f64(delta).reshape(8, -1)
+    r = d[:, :n] - IDENTITY_UPDATE[:, None]
+    loss = weight * np.abs(r).sum()
+    grad = np.zeros_like(d)
+    grad[:, :n] = weight * np.sign(r)
+    return float(loss), grad.reshape(np.shape(delta))
+
+
+def keyframe_temporal_l1(x, x_prev, bound, weight):
+    """Eq. (9) with the weight of Eq. (10): weight * sum over parameter rows
+    and the first ``bound`` columns (the Gaussians carried over from the
+    previous frame) of |x - x_prev|; gradient w.r.t. x."""
+    a = _f64(x)
+    b = _f64(x_prev)
+    r = a[..., :bound] - b[..., :bound]
+    grad = np.zeros_like(a)
+    grad[..., :bound] = weight * np.sign(r)
+    return float(weight * np.abs(r).sum()), grad
+
+
+def densify_stats(flags, g2d):
+    """Densification statistics for keyframe reconstruction (Sec. III-B): per
+    Gaussian, the sum over the views where it is visible (flag 32) of the
+    Euclidean norm of dL/d(screen mean) in pixels, and that view count."""
+    vis = (np.asarray(flags) & 32) != 0
+    g = np.asarray(g2d, np.float64)
+    norm = np.sqrt(g[..., 0] ** 2 + g[..., 1] ** 2)
+    return (np.where(vis, norm, 0.0).sum(axis=0), vis.sum(axis=0).astype(np.int64))
+
+
+def low_opacity_keep(opacity_logit, n, min_opacity):
+    """Indices (ascending) of the Gaussians i < n kept by low-opacity culling:
+    sigmoid(logit) >= min_opacity, decided as logit >= log(m / (1 - m)) in
+    FP64 from the FP32 logit."""
+    x = np.asarray(opacity_logit, np.float32)[:n].astype(np.float64)
+    t = np.log(min_opacity / (1.0 - min_opacity))
+    return np.nonzero(x >= t)[0].astype(np.int64)
+
+
+# --------------------------------------------------------------------------
+# residual bookkeeping and quantised delta planes (Sec. III-C, Eq. (11)/(12))
+# --------------------------------------------------------------------------
+#
+# Stored planes are FP32, and each step below is one IEEE operation per
+# element (subtract, add, divide, multiply), so it is computed here in FP32:
+# that fixes the rounding the transmitted and reconstructed planes carry.
+
+def residual_delta(D_t, Dp_prev, mask, n):
+    """Eq. (11): the update sent for frame t is the pruning mask applied to
+    the residual between the true accumulated delta D_t and the accumulated
+    delta already sent, D'_(t-1).  Returns d'_t (8, gh, gw) FP32 (zero at
+    pruned and padding texels) and the per-channel max |d'_t| over i < n."""
+    D = np.asarray(D_t, np.float32).reshape(8, -1)
+    P = np.asarray(Dp_prev, np.float32).reshape(8, -1)
+    m = np.asarray(mask, np.uint8).reshape(-1)
+    d = np.zeros_like(D)
+    keep = np.zeros(D.shape[1], bool)
+    keep[:n] = m[:n] != 0
+    d[:, keep] = D[:, keep] - P[:, keep]
+    absmax = np.abs(d[:, :n]).max(axis=1) if n > 0 else np.zeros(8, np.float32)
+    return d.reshape(np.shape(D_t)), absmax.astype(np.float32)
+
+
+def quantize_delta(d, absmax, bits):
+    """Symmetric per-channel quantisation of an update to signed ``bits``-bit
+    codes: scale = absmax / (2^(bits-1) - 1) (0 when absmax is 0), code =
+    round-half-even(d / scale) clamped to +-(2^(bits-1) - 1) (0 when the scale
+    is 0).  Zero updates stay exactly zero."""
+    qmax = np.float32(2 ** (bits - 1) - 1)
+    a = np.asarray(absmax, np.float32)
+    scale = np.where(a > 0, a / qmax, np.float32(0)).astype(np.float32)
+    x = np.asarray(d, np.float32).reshape(8, -1)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        q = np.where(scale[:, None] > 0, np.rint(x / scale[:, None]), np.float32(0))
+    q = np.clip(q, -qmax, qmax).astype(np.int16 if bits == 16 else np.int8)
+    return q.reshape(np.shape(d)), scale
+
+
+def dequantize_delta(q, scale):
+    s = np.asarray(scale, np.float32)
+    x = np.asarray(q).reshape(8, -1).astype(np.float32)
+    return (x * s[:, None]).astype(np.float32).reshape(np.shape(q))
+
+
+def accumulate_sent(Dp_prev, d_sent):
+    """Eq. (12): D'_t = D'_(t-1) + d'_t (FP32)."""
+    return (np.asarray(Dp_prev, np.float32) + np.asarray(d_sent, np.float32)).astype(np.float32)
+
+
+# --------------------------------------------------------------------------
 # compositions used by tests
 # --------------------------------------------------------------------------
 
