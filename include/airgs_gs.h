@@ -82,11 +82,18 @@ typedef struct gs_camera {
  * usage (device, n uint32, nullable): when set, gs_render_fwd ADDS to
  * usage[i] the number of (view, pixel) pairs that composite Gaussian i --
  * the rendering usage frequency by which the paper prunes updates
- * (Sec. III-C).  Ignored by gs_render_fwd_batched and gs_render_bwd. */
+ * (Sec. III-C).  Ignored by gs_render_fwd_batched and gs_render_bwd.
+ * grad2d_norm, visible_views (device, n, nullable, used by gs_render_bwd):
+ * densification statistics for keyframe reconstruction (Sec. III-B, cloning
+ * and splitting where gradients are high): gs_render_bwd ADDS, per
+ * Gaussian, the sum over the views where it is visible of the Euclidean
+ * norm of dL/d(screen mean) in pixels, and the number of those views. */
 typedef struct gs_opts {
   float bg[3];
   float reserved;
   uint32_t* usage;
+  float* grad2d_norm;
+  uint32_t* visible_views;
 } gs_opts;
 
 /* Per (view, Gaussian) projection records, index v*ld + i:
@@ -131,13 +138,21 @@ typedef struct gs_tile_lists {
   uint32_t* ranges;
 } gs_tile_lists;
 
-/* Frame update for the backward pass to the delta images. */
+/* Frame update for the backward pass to the delta images.
+ * temporal_weight: lambda_t of Eq. (7); when nonzero the temporal term of
+ *   Eq. (6), lambda_t * sum_{i<n} |delta_i - e| over the 8 channels with e =
+ *   (0,0,0,1,0,0,0,0) the no-motion update, is fused into the delta gradient
+ *   (ADDED: lambda_t * sign(delta - e), sign(0) = 0, at every texel i < n
+ *   whatever its mask) and its value ACCUMULATED in FP64 into *temporal_loss
+ *   (device, nullable).  delta (8, gh, gw) is then required. */
 typedef struct gs_frame_update {
   const float* anchor_quat; /* (4, ld) anchor quaternions */
   int32_t ld;
   int32_t gw, gh;           /* texel grid, gw * gh >= n */
-  int32_t reserved;
+  float temporal_weight;
   const uint8_t* mask;      /* (gh, gw), 1 = the texel's update was applied */
+  const float* delta;       /* (8, gh, gw), read when temporal_weight != 0 */
+  double* temporal_loss;
 } gs_frame_update;
 
 /* ---- support ------------------------------------------------------------ */
@@ -168,8 +183,9 @@ size_t gs_render_bwd_workspace_size(int n_views, int ld);
  * enqueues is bracketed by HIP events on the call's stream.  Stages:
  *   0 apply, 1 project, 2 depth sort, 3 count scan, 4 emit, 5 segment sort,
  *   6 ranges, 7 render fwd, 8 render bwd, 9 project bwd, 10 apply bwd,
- *   11 l1, 12 adam, 13 fill. */
-#define GS_STAGE_COUNT 15
+ *   11 l1, 12 adam, 13 fill, 14 dssim, 15 compact (culling, gathers),
+ *   16 residual (bookkeeping, quantisation, quantised apply). */
+#define GS_STAGE_COUNT 17
 gs_status gs_set_timing(gs_ctx* ctx, int enable);
 /* Sum of event-measured milliseconds and number of launches per stage since
  * the previous collection (host arrays of GS_STAGE_COUNT); blocks until the
@@ -242,8 +258,8 @@ gs_status gs_render_fwd_batched(gs_ctx* ctx, const gs_projected* proj,
 /* Backward of gs_project + gs_render_fwd for dL/dimage (V, 3, H, W):
  * transmittance is recovered by walking each pixel's list back from
  * n_contrib.  Gradients w.r.t. the frame's mean, log_scale, quat, opacity
- * logit and SH are ADDED to `grad` (same shape as `frame`; the caller zeroes
- * it) summed over views.  If `upd` is non-NULL, dL/d(delta images) (8, gh,
+ * logit and SH, summed over views, are WRITTEN to `grad` (same shape as
+ * `frame`) for i < n.  If `upd` is non-NULL, dL/d(delta images) (8, gh,
  * gw) is WRITTEN to dL_ddelta (zero at masked and padding texels). */
 gs_status gs_render_bwd(gs_ctx* ctx, const gs_gaussians* frame, const gs_projected* proj,
                         const gs_tile_lists* lists, const gs_camera* cams_host,
@@ -283,6 +299,67 @@ gs_status gs_sq_error(gs_ctx* ctx, const float* a, const float* b, int64_t count
 gs_status gs_adam_step(gs_ctx* ctx, float* param, const float* grad, float* m, float* v,
                        int64_t count, int step, float lr, float beta1, float beta2, float eps,
                        void* stream);
+
+/* ---- keyframe reconstruction (Sec. III-B) ------------------------------- */
+
+/* Keyframe temporal term (Eq. (9) with its weight from Eq. (10)): over
+ * `rows` FP32 planes of stride ld (e.g. all parameter planes of a Gaussian
+ * set) and their first `bound` columns (the Gaussians carried over from the
+ * previous frame, U in the paper), ADDS weight * sign(x - x_prev) (sign(0) =
+ * 0) to grad and ACCUMULATES weight * sum |x - x_prev| in FP64 into
+ * *loss_dev (device, nullable). */
+gs_status gs_keyframe_temporal_l1(gs_ctx* ctx, const float* x, const float* x_prev, int rows,
+                                  int bound, int64_t ld, float weight, float* grad,
+                                  double* loss_dev, void* stream);
+
+/* Low-opacity culling (Sec. III-B: Gaussians whose opacity falls below a
+ * threshold are discarded during keyframe training).  Gaussian i < n is kept
+ * iff sigmoid(opacity_logit[i]) >= min_opacity, decided as logit >=
+ * log(m / (1 - m)) in FP64.  WRITES the kept indices in increasing order to
+ * kept_index (device, capacity n) and their number to *kept_host; blocks
+ * until the count has been read back.  workspace: gs_cull_workspace_size(n)
+ * bytes.  min_opacity must lie in (0, 1). */
+size_t gs_cull_workspace_size(int n);
+gs_status gs_cull_low_opacity(gs_ctx* ctx, const float* opacity_logit, int n, float min_opacity,
+                              int32_t* kept_index, int32_t* kept_host, void* workspace,
+                              size_t ws_bytes, void* stream);
+
+/* dst[p * dst_ld + j] = src[p * src_ld + index[j]] for planes p < `planes`
+ * and j < m: applies a kept-index list to parameter planes, gradients or
+ * optimizer moments.  Indices must lie in [0, src_ld); dst must not overlap
+ * src. */
+gs_status gs_gather_planes(gs_ctx* ctx, const float* src, int64_t src_ld, int planes,
+                           const int32_t* index, int m, float* dst, int64_t dst_ld,
+                           void* stream);
+
+/* ---- sent updates (Sec. III-C, Eq. (11), (12)) --------------------------- */
+/* All planes are (8, gh, gw) FP32 delta images as in gs_apply_frame_update;
+ * D' starts as the no-motion update (0,0,0,1,0,0,0,0) at every texel. */
+
+/* Eq. (11): d' = mask ? D_t - D'_(t-1) : 0 at texels i < n (0 at padding),
+ * WRITTEN to d_out; the per-channel max |d'| over i < n is ACCUMULATED by
+ * max into absmax (device, 8 floats; caller zeroes). */
+gs_status gs_residual_delta(gs_ctx* ctx, const float* D_t, const float* Dp_prev,
+                            const uint8_t* mask, int n, int gw, int gh, float* d_out,
+                            float* absmax, void* stream);
+
+/* Symmetric per-channel quantisation of d to signed `bits`-bit codes (bits
+ * 8: int8, 16: int16, layout of d): scale_c = absmax_c / (2^(bits-1) - 1)
+ * (0 if absmax_c is 0), code = round-half-even(d / scale_c) clamped to
+ * +-(2^(bits-1) - 1), 0 at padding texels i >= n.  scale_out (device, 8)
+ * WRITTEN.  If Dp is non-NULL, the server-side sum is advanced in place,
+ * Dp += code * scale_c (Eq. (12)), with the same FP32 rounding as the
+ * client's gs_apply_quantized_update. */
+gs_status gs_quantize_delta(gs_ctx* ctx, const float* d, const float* absmax, int bits, int n,
+                            int gw, int gh, void* q_out, float* scale_out, float* Dp,
+                            void* stream);
+
+/* Client side of Eq. (12): Dp += code * scale at texels i < n (in place),
+ * then frame = anchor with Dp applied, as gs_apply_frame_update with every
+ * texel kept (mean, quat, opacity of `frame` WRITTEN). */
+gs_status gs_apply_quantized_update(gs_ctx* ctx, const gs_gaussians* anchor, const void* q,
+                                    int bits, const float* scale, float* Dp, int gw, int gh,
+                                    gs_gaussians* frame, void* stream);
 
 #ifdef __cplusplus
 }

@@ -3,7 +3,8 @@
 // attribute images with one texel per Gaussian; Eq. (11): pruning mask).
 //
 // Elementwise and HBM-bound: 8 delta planes + 1 mask byte + 8 anchor values
-// read, 8 frame values written per Gaussian (97 B).  The arithmetic is done
+// read, 8 frame values written per Gaussian (97 B).  The backward optionally
+// carries the temporal term of Eq. (6)/(7) (8 more delta values read).  The arithmetic is done
 // in FP64 and rounded once to the FP32 parameter storage, so that the frame
 // is the correctly rounded result of the update, independent of the order a
 // compiler might pick.
@@ -57,16 +58,21 @@ __global__ __launch_bounds__(256) void k_apply(int n, int ld, size_t plane,
 }
 
 // dL/d(delta) from dL/d(frame): identity for the additive channels, the
-// transpose of q -> dq (x) q (a linear map of dq) for the quaternion.
+// transpose of q -> dq (x) q (a linear map of dq) for the quaternion.  With
+// TEMPORAL, the temporal term (Eq. (6)/(7)) adds w * sign(delta - e) at every
+// texel i < n, e the no-motion update, and its value w * sum |delta - e| is
+// reduced per block and added to *tloss.
+template <bool TEMPORAL>
 __global__ __launch_bounds__(256) void k_apply_bwd(int n, int ld, size_t plane,
                                                    const float* __restrict__ aq,
                                                    const uint8_t* __restrict__ mask,
                                                    const float* __restrict__ gmean,
                                                    const float* __restrict__ gquat,
                                                    const float* __restrict__ gopac,
-                                                   float* __restrict__ gdelta) {
+                                                   float* __restrict__ gdelta, float tw,
+                                                   const float* __restrict__ delta,
+                                                   double* __restrict__ tloss) {
   const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= plane) return;
   float out[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
   if (t < (size_t)n && mask[t]) {
     out[0] = gmean[t];
@@ -82,6 +88,28 @@ __global__ __launch_bounds__(256) void k_apply_bwd(int n, int ld, size_t plane,
     out[6] = -bz * g0 - by * g1 + bx * g2 + bw * g3;
     out[7] = gopac[t];
   }
+  if constexpr (TEMPORAL) {
+    float acc = 0.f;
+    if (t < (size_t)n) {
+#pragma unroll
+      for (int c = 0; c < 8; ++c) {
+        const float r = delta[c * plane + t] - (c == 3 ? 1.f : 0.f);
+        const float sg = r > 0.f ? 1.f : (r < 0.f ? -1.f : 0.f);
+        out[c] += tw * sg;
+        acc += fabsf(r);
+      }
+    }
+    if (tloss) {
+      double a = (double)acc;
+      for (int off = 32; off >= 1; off >>= 1) a += __shfl_xor(a, off, 64);
+      __shared__ double s_red[4];
+      if ((threadIdx.x & 63) == 0) s_red[threadIdx.x >> 6] = a;
+      __syncthreads();
+      if (threadIdx.x == 0)
+        atomicAdd(tloss, (double)tw * ((s_red[0] + s_red[1]) + (s_red[2] + s_red[3])));
+    }
+  }
+  if (t >= plane) return;
 #pragma unroll
   for (int c = 0; c < 8; ++c) gdelta[c * plane + t] = out[c];
 }
@@ -104,8 +132,14 @@ void launch_apply_bwd(int n, const gs_frame_update& u, const gs_gaussians& g, fl
   const int blocks = (int)((plane + 255) / 256);
   if (blocks == 0) return;
   StageScope scope(kStApplyBwd, s);
-  hipLaunchKernelGGL(k_apply_bwd, dim3(blocks), dim3(256), 0, s, n, u.ld, plane, u.anchor_quat,
-                     u.mask, g.mean, g.quat, g.opacity, gdelta);
+  if (u.temporal_weight != 0.f)
+    hipLaunchKernelGGL(k_apply_bwd<true>, dim3(blocks), dim3(256), 0, s, n, u.ld, plane,
+                       u.anchor_quat, u.mask, g.mean, g.quat, g.opacity, gdelta,
+                       u.temporal_weight, u.delta, u.temporal_loss);
+  else
+    hipLaunchKernelGGL(k_apply_bwd<false>, dim3(blocks), dim3(256), 0, s, n, u.ld, plane,
+                       u.anchor_quat, u.mask, g.mean, g.quat, g.opacity, gdelta, 0.f,
+                       (const float*)nullptr, (double*)nullptr);
 }
 
 }  // namespace gs

@@ -244,7 +244,7 @@ const char* gs_stage_name(int stage) {
   static const char* names[GS_STAGE_COUNT] = {
       "apply",  "project",    "depth_sort",  "count_scan", "emit", "segment_sort", "ranges",
       "render_fwd", "render_bwd", "project_bwd", "apply_bwd", "l1",   "adam",         "fill",
-      "dssim"};
+      "dssim", "compact", "residual"};
   return (stage >= 0 && stage < GS_STAGE_COUNT) ? names[stage] : "?";
 }
 
@@ -425,7 +425,13 @@ gs_status gs_render_bwd(gs_ctx* c, const gs_gaussians* frame, const gs_projected
     if (upd->ld != frame->ld || upd->gw <= 0 || upd->gh <= 0 ||
         (int64_t)upd->gw * upd->gh < frame->n)
       return fail(c, GS_ERR_INVALID_ARG, "frame update grid/stride mismatch");
+    if (!std::isfinite(upd->temporal_weight))
+      return fail(c, GS_ERR_INVALID_ARG, "temporal_weight is not finite");
+    if (upd->temporal_weight != 0.f && !upd->delta)
+      return fail(c, GS_ERR_INVALID_ARG, "temporal term needs the delta images");
   }
+  if (opts && ((opts->grad2d_norm == nullptr) != (opts->visible_views == nullptr)))
+    return fail(c, GS_ERR_INVALID_ARG, "grad2d_norm and visible_views go together");
   const size_t need = gs_render_bwd_workspace_size(V, frame->ld);
   if (!ws || ws_bytes < need)
     return fail(c, GS_ERR_OOM, "render_bwd workspace %zu < %zu bytes", ws_bytes, need);
@@ -437,7 +443,9 @@ gs_status gs_render_bwd(gs_ctx* c, const gs_gaussians* frame, const gs_projected
   gs::launch_render_bwd(*proj, *lists, V, ch[0].width, ch[0].height, opts ? opts->bg : zero,
                         final_T, n_contrib, dL_dimage, grad2d, s);
   GS_LAUNCHED(c, "render_bwd");
-  gs::launch_project_bwd(*frame, cd, V, *proj, grad2d, *grad, s);
+  float* st_norm = opts ? opts->grad2d_norm : nullptr;
+  uint32_t* st_views = opts ? opts->visible_views : nullptr;
+  gs::launch_project_bwd(*frame, cd, V, *proj, grad2d, *grad, st_norm, st_views, s);
   GS_LAUNCHED(c, "project_bwd");
   if (upd) {
     gs::launch_apply_bwd(frame->n, *upd, *grad, dL_ddelta, s);
@@ -510,6 +518,118 @@ gs_status gs_adam_step(gs_ctx* c, float* param, const float* grad, float* m, flo
   gs::launch_adam(param, grad, m, v, count, lr, b1, b2, eps, (float)bc1, (float)bc2,
                   (hipStream_t)stream);
   GS_LAUNCHED(c, "adam");
+  return GS_OK;
+}
+
+gs_status gs_keyframe_temporal_l1(gs_ctx* c, const float* x, const float* x_prev, int rows,
+                                  int bound, int64_t ld, float weight, float* grad,
+                                  double* loss_dev, void* stream) {
+  if (!c) return fail(nullptr, GS_ERR_INVALID_ARG, "ctx is NULL");
+  TimerGuard timer_guard(c);
+  if (rows < 0 || bound < 0 || (int64_t)bound > ld)
+    return fail(c, GS_ERR_INVALID_ARG, "rows/bound/ld out of range");
+  if (!std::isfinite(weight)) return fail(c, GS_ERR_INVALID_ARG, "weight is not finite");
+  if ((int64_t)rows * bound > 0 && (!x || !x_prev || !grad))
+    return fail(c, GS_ERR_INVALID_ARG, "NULL buffer");
+  GS_TRY(use_device(c));
+  gs::launch_l1_penalty(x, x_prev, rows, bound, ld, weight, grad, loss_dev, (hipStream_t)stream);
+  GS_LAUNCHED(c, "keyframe_temporal_l1");
+  return GS_OK;
+}
+
+size_t gs_cull_workspace_size(int n) { return n < 0 ? 0 : gs::keep_workspace_bytes(n); }
+
+gs_status gs_cull_low_opacity(gs_ctx* c, const float* logit, int n, float min_opacity,
+                              int32_t* kept_index, int32_t* kept_host, void* ws, size_t ws_bytes,
+                              void* stream) {
+  if (!c) return fail(nullptr, GS_ERR_INVALID_ARG, "ctx is NULL");
+  TimerGuard timer_guard(c);
+  if (n < 0) return fail(c, GS_ERR_INVALID_ARG, "n < 0");
+  if (!(min_opacity > 0.f && min_opacity < 1.f))
+    return fail(c, GS_ERR_INVALID_ARG, "min_opacity must lie in (0, 1)");
+  if (!kept_host || (n > 0 && (!logit || !kept_index)))
+    return fail(c, GS_ERR_INVALID_ARG, "NULL buffer");
+  const size_t need = gs::keep_workspace_bytes(n);
+  if (!ws || ws_bytes < need)
+    return fail(c, GS_ERR_OOM, "cull workspace %zu < %zu bytes", ws_bytes, need);
+  GS_TRY(use_device(c));
+  hipStream_t s = (hipStream_t)stream;
+  const uint32_t* d_total = gs::launch_keep_low_opacity(
+      logit, n, gs::opacity_logit_threshold(min_opacity), kept_index, ws, s);
+  GS_LAUNCHED(c, "cull_low_opacity");
+  hipError_t e = hipMemcpyAsync(c->pinned, d_total, sizeof(uint32_t), hipMemcpyDeviceToHost, s);
+  if (e != hipSuccess) return hip_fail(c, e, "kept count readback");
+  e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_fail(c, e, "hipStreamSynchronize");
+  *kept_host = (int32_t)*c->pinned;
+  return GS_OK;
+}
+
+gs_status gs_gather_planes(gs_ctx* c, const float* src, int64_t src_ld, int planes,
+                           const int32_t* index, int m, float* dst, int64_t dst_ld,
+                           void* stream) {
+  if (!c) return fail(nullptr, GS_ERR_INVALID_ARG, "ctx is NULL");
+  TimerGuard timer_guard(c);
+  if (planes < 0 || m < 0 || src_ld < 0 || dst_ld < m || (m > src_ld))
+    return fail(c, GS_ERR_INVALID_ARG, "planes/m/stride out of range");
+  if (planes > 0 && m > 0 && (!src || !dst || !index))
+    return fail(c, GS_ERR_INVALID_ARG, "NULL buffer");
+  GS_TRY(use_device(c));
+  gs::launch_gather(src, src_ld, planes, index, m, dst, dst_ld, (hipStream_t)stream);
+  GS_LAUNCHED(c, "gather_planes");
+  return GS_OK;
+}
+
+namespace {
+gs_status check_grid(gs_ctx* c, int n, int gw, int gh) {
+  if (n < 0 || gw <= 0 || gh <= 0 || (int64_t)gw * gh < n || (int64_t)gw * gh > (1ll << 31))
+    return fail(c, GS_ERR_INVALID_ARG, "texel grid %dx%d cannot hold %d Gaussians", gw, gh, n);
+  return GS_OK;
+}
+}  // namespace
+
+gs_status gs_residual_delta(gs_ctx* c, const float* D, const float* Dp, const uint8_t* mask,
+                            int n, int gw, int gh, float* d_out, float* absmax, void* stream) {
+  if (!c) return fail(nullptr, GS_ERR_INVALID_ARG, "ctx is NULL");
+  TimerGuard timer_guard(c);
+  GS_TRY(check_grid(c, n, gw, gh));
+  if (!D || !Dp || !mask || !d_out || !absmax) return fail(c, GS_ERR_INVALID_ARG, "NULL buffer");
+  GS_TRY(use_device(c));
+  gs::launch_residual(D, Dp, mask, n, gw, gh, d_out, absmax, (hipStream_t)stream);
+  GS_LAUNCHED(c, "residual_delta");
+  return GS_OK;
+}
+
+gs_status gs_quantize_delta(gs_ctx* c, const float* d, const float* absmax, int bits, int n,
+                            int gw, int gh, void* q_out, float* scale_out, float* Dp,
+                            void* stream) {
+  if (!c) return fail(nullptr, GS_ERR_INVALID_ARG, "ctx is NULL");
+  TimerGuard timer_guard(c);
+  GS_TRY(check_grid(c, n, gw, gh));
+  if (bits != 8 && bits != 16) return fail(c, GS_ERR_INVALID_ARG, "bits must be 8 or 16");
+  if (!d || !absmax || !q_out || !scale_out) return fail(c, GS_ERR_INVALID_ARG, "NULL buffer");
+  GS_TRY(use_device(c));
+  gs::launch_quantize(d, absmax, bits, n, gw, gh, q_out, scale_out, Dp, (hipStream_t)stream);
+  GS_LAUNCHED(c, "quantize_delta");
+  return GS_OK;
+}
+
+gs_status gs_apply_quantized_update(gs_ctx* c, const gs_gaussians* anchor, const void* q,
+                                    int bits, const float* scale, float* Dp, int gw, int gh,
+                                    gs_gaussians* frame, void* stream) {
+  if (!c) return fail(nullptr, GS_ERR_INVALID_ARG, "ctx is NULL");
+  TimerGuard timer_guard(c);
+  GS_TRY(check_gaussians(c, anchor, "anchor"));
+  if (!frame) return fail(c, GS_ERR_INVALID_ARG, "frame is NULL");
+  if (frame->n != anchor->n || frame->ld != anchor->ld)
+    return fail(c, GS_ERR_INVALID_ARG, "frame n/ld differ from the anchor's");
+  GS_TRY(check_grid(c, anchor->n, gw, gh));
+  if (bits != 8 && bits != 16) return fail(c, GS_ERR_INVALID_ARG, "bits must be 8 or 16");
+  if (anchor->n > 0 && (!q || !scale || !Dp || !frame->mean || !frame->quat || !frame->opacity))
+    return fail(c, GS_ERR_INVALID_ARG, "NULL buffer");
+  GS_TRY(use_device(c));
+  gs::launch_apply_quantized(*anchor, q, bits, scale, Dp, gw, gh, *frame, (hipStream_t)stream);
+  GS_LAUNCHED(c, "apply_quantized_update");
   return GS_OK;
 }
 

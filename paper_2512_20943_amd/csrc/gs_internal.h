@@ -29,7 +29,8 @@ __host__ __device__ inline int tiles_across(int px) { return (px + kTile - 1) / 
 // Stages whose device time the context can measure with HIP events.
 enum Stage {
   kStApply = 0, kStProject, kStDepthSort, kStCountScan, kStEmit, kStSegmentSort, kStRanges,
-  kStRenderFwd, kStRenderBwd, kStProjectBwd, kStApplyBwd, kStL1, kStAdam, kStFill, kStDssim, kStageCount
+  kStRenderFwd, kStRenderBwd, kStProjectBwd, kStApplyBwd, kStL1, kStAdam, kStFill, kStDssim,
+  kStCompact, kStResidual, kStageCount
 };
 static_assert(kStageCount == GS_STAGE_COUNT, "stage table out of sync with the header");
 
@@ -63,7 +64,7 @@ void launch_project(const gs_gaussians& g, const gs_camera* cams_dev, int n_view
                     const gs_projected& out, hipStream_t s);
 void launch_project_bwd(const gs_gaussians& g, const gs_camera* cams_dev, int n_views,
                         const gs_projected& proj, const float* grad2d, gs_gaussians& grad,
-                        hipStream_t s);
+                        float* st_norm, uint32_t* st_views, hipStream_t s);
 // sort / binning
 struct BinSortPlan {
   int n_views;
@@ -96,6 +97,22 @@ void launch_render_bwd(const gs_projected& proj, const gs_tile_lists& lists, int
 // training support
 void launch_l1(const float* image, const float* target, int64_t count, float* grad,
                double* loss, hipStream_t s);
+// low-opacity culling and plane gathers
+size_t keep_workspace_bytes(int n);
+double opacity_logit_threshold(float min_opacity);
+const uint32_t* launch_keep_low_opacity(const float* logit, int n, double thr, int32_t* index,
+                                        void* ws, hipStream_t s);
+void launch_gather(const float* src, int64_t src_ld, int planes, const int32_t* index, int m,
+                   float* dst, int64_t dst_ld, hipStream_t s);
+void launch_l1_penalty(const float* x, const float* ref, int rows, int bound, int64_t ld, float w,
+                       float* grad, double* loss, hipStream_t s);
+// residual bookkeeping and quantised updates
+void launch_residual(const float* D, const float* P, const uint8_t* mask, int n, int gw, int gh,
+                     float* d, float* absmax, hipStream_t s);
+void launch_quantize(const float* d, const float* absmax, int bits, int n, int gw, int gh,
+                     void* q, float* scale, float* P, hipStream_t s);
+void launch_apply_quantized(const gs_gaussians& a, const void* q, int bits, const float* scale,
+                            float* P, int gw, int gh, gs_gaussians& f, hipStream_t s);
 size_t l1_dssim_workspace_bytes(int planes, int H, int W);
 void launch_l1_dssim(const float* image, const float* target, int planes, int H, int W,
                      float lambda, float* grad, double* loss, void* ws, hipStream_t s);

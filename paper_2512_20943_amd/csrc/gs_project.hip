@@ -249,7 +249,7 @@ __global__ __launch_bounds__(256) void k_project_bwd(
     const gs_camera* __restrict__ cams, int n_views, const float4* __restrict__ splat,
     const uint8_t* __restrict__ flags, const float4* __restrict__ g2d, float* __restrict__ g_mean,
     float* __restrict__ g_lsc, float* __restrict__ g_quat, float* __restrict__ g_opac,
-    float* __restrict__ g_sh) {
+    float* __restrict__ g_sh, float* __restrict__ st_norm, uint32_t* __restrict__ st_views) {
   constexpr int K = (DEG + 1) * (DEG + 1);
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
@@ -297,12 +297,16 @@ __global__ __launch_bounds__(256) void k_project_bwd(
 #pragma unroll
   for (int k = 0; k < K * 3; ++k) gsh[k] = 0.f;
 
+  float st_acc = 0.f;
+  uint32_t st_cnt = 0;
   for (int v = 0; v < n_views; ++v) {
     const size_t j = (size_t)v * L + i;
     const uint8_t fl = flags[j];
     if (!(fl & kVisible)) continue;
     const float4 ga = g2d[3 * j + 0], gb = g2d[3 * j + 1], gc = g2d[3 * j + 2];
     const float g_px = ga.x, g_py = ga.y, g_A = ga.z, g_B = ga.w, g_C = gb.x, g_al = gb.y;
+    st_acc += sqrtf(g_px * g_px + g_py * g_py);
+    ++st_cnt;
     const float g_rgb[3] = {gb.z, gb.w, gc.x};
     if (g_px == 0.f && g_py == 0.f && g_A == 0.f && g_B == 0.f && g_C == 0.f && g_al == 0.f &&
         g_rgb[0] == 0.f && g_rgb[1] == 0.f && g_rgb[2] == 0.f)
@@ -459,6 +463,10 @@ __global__ __launch_bounds__(256) void k_project_bwd(
   g_opac[i] = gah * ah * (1.f - ah);
 #pragma unroll
   for (int k = 0; k < K * 3; ++k) g_sh[(size_t)k * L + i] = gsh[k];
+  if (st_norm) {  // densification statistics (uniform branch)
+    st_norm[i] += st_acc;
+    st_views[i] += st_cnt;
+  }
 }
 
 }  // namespace
@@ -485,7 +493,7 @@ void launch_project(const gs_gaussians& g, const gs_camera* cams, int V, const g
 
 void launch_project_bwd(const gs_gaussians& g, const gs_camera* cams, int V,
                         const gs_projected& p, const float* grad2d, gs_gaussians& gr,
-                        hipStream_t s) {
+                        float* st_norm, uint32_t* st_views, hipStream_t s) {
   const int blocks = (g.n + 255) / 256;
   if (blocks == 0) return;
   StageScope scope(kStProjectBwd, s);
@@ -494,7 +502,7 @@ void launch_project_bwd(const gs_gaussians& g, const gs_camera* cams, int V,
 #define GS_PROJ_BWD(D)                                                                        \
   hipLaunchKernelGGL(k_project_bwd<D>, dim3(blocks), dim3(256), 0, s, g.n, g.ld, g.mean,     \
                      g.log_scale, g.quat, g.opacity, g.sh, cams, V, sp, p.flags, g2, gr.mean, \
-                     gr.log_scale, gr.quat, gr.opacity, gr.sh)
+                     gr.log_scale, gr.quat, gr.opacity, gr.sh, st_norm, st_views)
   switch (g.sh_degree) {
     case 0: GS_PROJ_BWD(0); break;
     case 1: GS_PROJ_BWD(1); break;

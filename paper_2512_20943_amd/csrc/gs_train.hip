@@ -59,6 +59,33 @@ __global__ __launch_bounds__(256) void k_adam(float* __restrict__ p, const float
   }
 }
 
+// Keyframe temporal term (Eq. (9), weight of Eq. (10)): over `rows` planes
+// of stride ld and the first `bound` columns, grad += w * sign(x - x_prev)
+// and w * sum |x - x_prev| added to *loss.
+__global__ __launch_bounds__(256) void k_l1_penalty(const float* __restrict__ x,
+                                                    const float* __restrict__ ref, int rows,
+                                                    int bound, int64_t ld, float w,
+                                                    float* __restrict__ grad,
+                                                    double* __restrict__ loss) {
+  __shared__ double s_w[4];
+  double acc = 0.0;
+  const int64_t total = (int64_t)rows * bound;
+  for (int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x; k < total;
+       k += (int64_t)gridDim.x * 256) {
+    const int64_t r = k / bound, c = k - r * bound;
+    const int64_t i = r * ld + c;
+    const float d = x[i] - ref[i];
+    acc += (double)fabsf(d);
+    grad[i] += d > 0.f ? w : (d < 0.f ? -w : 0.f);
+  }
+  if (!loss) return;
+  for (int off = 32; off >= 1; off >>= 1) acc += __shfl_xor(acc, off, 64);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0) s_w[wave] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) atomicAdd(loss, (double)w * ((s_w[0] + s_w[1]) + (s_w[2] + s_w[3])));
+}
+
 inline int grid_for(int64_t count) {
   const int64_t want = (count + 255) / 256;
   return (int)(want < 8192 ? want : 8192);
@@ -86,6 +113,15 @@ void launch_adam(float* p, const float* g, float* m, float* v, int64_t count, fl
   StageScope scope(kStAdam, s);
   hipLaunchKernelGGL(k_adam, dim3(grid_for(count)), dim3(256), 0, s, p, g, m, v, count, lr, b1,
                      b2, eps, 1.f / bc1, 1.f / bc2);
+}
+
+void launch_l1_penalty(const float* x, const float* ref, int rows, int bound, int64_t ld, float w,
+                       float* grad, double* loss, hipStream_t s) {
+  const int64_t total = (int64_t)rows * bound;
+  if (total <= 0) return;
+  StageScope scope(kStL1, s);
+  hipLaunchKernelGGL(k_l1_penalty, dim3(grid_for(total)), dim3(256), 0, s, x, ref, rows, bound, ld,
+                     w, grad, loss);
 }
 
 }  // namespace gs

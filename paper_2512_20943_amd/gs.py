@@ -27,7 +27,7 @@ GS_ERR_HIP = 4
 TILE = 16
 SPLAT_FLOATS = 12
 GRAD2D_FLOATS = 12
-STAGE_COUNT = 15
+STAGE_COUNT = 17
 
 c_int32, c_int64, c_void_p, c_double, c_float = (ctypes.c_int32, ctypes.c_int64, ctypes.c_void_p,
                                                  ctypes.c_double, ctypes.c_float)
@@ -46,7 +46,8 @@ class GsCamera(ctypes.Structure):
 
 
 class GsOpts(ctypes.Structure):
-    _fields_ = [("bg", c_float * 3), ("reserved", c_float), ("usage", c_void_p)]
+    _fields_ = [("bg", c_float * 3), ("reserved", c_float), ("usage", c_void_p),
+                ("grad2d_norm", c_void_p), ("visible_views", c_void_p)]
 
 
 class GsProjected(ctypes.Structure):
@@ -62,7 +63,8 @@ class GsTileLists(ctypes.Structure):
 
 class GsFrameUpdate(ctypes.Structure):
     _fields_ = [("anchor_quat", c_void_p), ("ld", c_int32), ("gw", c_int32), ("gh", c_int32),
-                ("reserved", c_int32), ("mask", c_void_p)]
+                ("temporal_weight", c_float), ("mask", c_void_p), ("delta", c_void_p),
+                ("temporal_loss", c_void_p)]
 
 
 assert ctypes.sizeof(GsCamera) == 144
@@ -112,6 +114,26 @@ def load() -> ctypes.CDLL:
                                   c_void_p, ctypes.c_size_t, c_void_p]
     lib.gs_l1_loss_grad.argtypes = [c_void_p, c_void_p, c_void_p, c_int64, c_void_p, c_void_p,
                                     c_void_p]
+    lib.gs_keyframe_temporal_l1.argtypes = [c_void_p, c_void_p, c_void_p, ctypes.c_int,
+                                            ctypes.c_int, c_int64, c_float, c_void_p, c_void_p,
+                                            c_void_p]
+    lib.gs_cull_workspace_size.argtypes = [ctypes.c_int]
+    lib.gs_cull_workspace_size.restype = ctypes.c_size_t
+    lib.gs_cull_low_opacity.argtypes = [c_void_p, c_void_p, ctypes.c_int, c_float, c_void_p,
+                                        P(c_int32), c_void_p, ctypes.c_size_t, c_void_p]
+    lib.gs_gather_planes.argtypes = [c_void_p, c_void_p, c_int64, ctypes.c_int, c_void_p,
+                                     ctypes.c_int, c_void_p, c_int64, c_void_p]
+    lib.gs_residual_delta.argtypes = [c_void_p, c_void_p, c_void_p, c_void_p, ctypes.c_int,
+                                      ctypes.c_int, ctypes.c_int, c_void_p, c_void_p, c_void_p]
+    lib.gs_quantize_delta.argtypes = [c_void_p, c_void_p, c_void_p, ctypes.c_int, ctypes.c_int,
+                                      ctypes.c_int, ctypes.c_int, c_void_p, c_void_p, c_void_p,
+                                      c_void_p]
+    lib.gs_apply_quantized_update.argtypes = [c_void_p, P(GsGaussians), c_void_p, ctypes.c_int,
+                                              c_void_p, c_void_p, ctypes.c_int, ctypes.c_int,
+                                              P(GsGaussians), c_void_p]
+    for f in ("gs_keyframe_temporal_l1", "gs_cull_low_opacity", "gs_gather_planes",
+              "gs_residual_delta", "gs_quantize_delta", "gs_apply_quantized_update"):
+        getattr(lib, f).restype = c_int32
     lib.gs_l1_dssim_workspace_size.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int]
     lib.gs_l1_dssim_workspace_size.restype = ctypes.c_size_t
     lib.gs_l1_dssim_loss_grad.argtypes = [c_void_p, c_void_p, c_void_p, ctypes.c_int, ctypes.c_int,
@@ -148,7 +170,9 @@ def exported_symbols():
             "gs_render_bwd", "gs_l1_loss_grad", "gs_adam_step", "gs_set_timing",
             "gs_collect_timing", "gs_stage_name", "gs_render_batched_workspace_size",
             "gs_render_fwd_batched", "gs_sq_error", "gs_l1_dssim_workspace_size",
-            "gs_l1_dssim_loss_grad"]
+            "gs_l1_dssim_loss_grad", "gs_keyframe_temporal_l1", "gs_cull_workspace_size",
+            "gs_cull_low_opacity", "gs_gather_planes", "gs_residual_delta",
+            "gs_quantize_delta", "gs_apply_quantized_update"]
 
 
 def _ptr(t):
@@ -376,7 +400,7 @@ def gs_render_fwd(ctx: Context, proj: Projected, lists: TileLists, cams: Cameras
     """``usage`` (int32 tensor of n, nullable) accumulates composited-pixel
     counts per Gaussian."""
     pc = proj.c()
-    opts = GsOpts((c_float * 3)(*[float(x) for x in bg]), 0.0, _ptr(usage))
+    opts = GsOpts((c_float * 3)(*[float(x) for x in bg]), 0.0, _ptr(usage), None, None)
     ctx.check(ctx.lib.gs_render_fwd(ctx.handle, ctypes.byref(pc), ctypes.byref(lists.c()),
                                     cams.host, _ptr(cams.dev), cams.V, ctypes.byref(opts),
                                     _ptr(image), _ptr(final_T), _ptr(n_contrib),
@@ -386,7 +410,7 @@ def gs_render_fwd(ctx: Context, proj: Projected, lists: TileLists, cams: Cameras
 def gs_render_fwd_batched(ctx: Context, proj: Projected, lists: TileLists, cams: Cameras, bg,
                           images: torch.Tensor, workspace: torch.Tensor, stream=None):
     pc = proj.c()
-    opts = GsOpts((c_float * 3)(*[float(x) for x in bg]), 0.0, None)
+    opts = GsOpts((c_float * 3)(*[float(x) for x in bg]), 0.0, None, None, None)
     ctx.check(ctx.lib.gs_render_fwd_batched(ctx.handle, ctypes.byref(pc), ctypes.byref(lists.c()),
                                             cams.host, _ptr(cams.dev), cams.V, ctypes.byref(opts),
                                             _ptr(images), _ptr(workspace), workspace.numel(),
@@ -399,14 +423,21 @@ def render_batched_workspace_size(V: int) -> int:
 
 def gs_render_bwd(ctx: Context, frame: Gaussians, proj: Projected, lists: TileLists,
                   cams: Cameras, bg, final_T, n_contrib, dL_dimage, grad: Gaussians,
-                  workspace: torch.Tensor, upd=None, dL_ddelta=None, stream=None):
-    """``upd`` = (anchor_quat tensor, mask tensor, gw, gh) or None."""
+                  workspace: torch.Tensor, upd=None, dL_ddelta=None, stream=None,
+                  densify=None, temporal=None):
+    """``upd`` = (anchor_quat tensor, mask tensor, gw, gh) or None;
+    ``densify`` = (grad2d_norm float tensor, visible_views int32 tensor) or
+    None; ``temporal`` = (weight, delta tensor, loss float64 tensor or None)
+    or None, used with ``upd``."""
     fc, pc, gc = frame.c(), proj.c(), grad.c()
-    opts = GsOpts((c_float * 3)(*[float(x) for x in bg]), 0.0, None)
+    dn, dv = densify if densify is not None else (None, None)
+    opts = GsOpts((c_float * 3)(*[float(x) for x in bg]), 0.0, None, _ptr(dn), _ptr(dv))
     uc = None
     if upd is not None:
         aq, mask, gw, gh = upd
-        uc = ctypes.byref(GsFrameUpdate(_ptr(aq), frame.ld, gw, gh, 0, _ptr(mask)))
+        tw, td, tl = temporal if temporal is not None else (0.0, None, None)
+        uc = ctypes.byref(GsFrameUpdate(_ptr(aq), frame.ld, gw, gh, float(tw), _ptr(mask),
+                                        _ptr(td), _ptr(tl)))
     ctx.check(ctx.lib.gs_render_bwd(ctx.handle, ctypes.byref(fc), ctypes.byref(pc),
                                     ctypes.byref(lists.c()), cams.host, _ptr(cams.dev), cams.V,
                                     ctypes.byref(opts), _ptr(final_T), _ptr(n_contrib),
@@ -451,3 +482,62 @@ def bin_sort_workspace_size(V: int, ld: int, capacity: int, n_segments: int) -> 
 
 def render_bwd_workspace_size(V: int, ld: int) -> int:
     return int(load().gs_render_bwd_workspace_size(V, ld))
+
+
+# ---- keyframe reconstruction ---------------------------------------------
+
+def gs_keyframe_temporal_l1(ctx: Context, x, x_prev, bound: int, weight: float, grad,
+                            loss_dev=None, stream=None):
+    """Eq. (9): grad += weight * sign(x - x_prev) over the first ``bound``
+    columns of the (rows, ld) planes; loss accumulated when given."""
+    rows, ld = x.shape[0], x.shape[-1]
+    ctx.check(ctx.lib.gs_keyframe_temporal_l1(ctx.handle, _ptr(x), _ptr(x_prev), rows, bound, ld,
+                                              float(weight), _ptr(grad), _ptr(loss_dev),
+                                              _stream(stream)))
+
+
+def gs_cull_low_opacity(ctx: Context, opacity_logit, n: int, min_opacity: float, kept_index,
+                        workspace=None, stream=None) -> int:
+    """Indices of the Gaussians kept by low-opacity culling (written to
+    ``kept_index``); returns their number (blocking)."""
+    if workspace is None:
+        workspace = torch.empty(max(cull_workspace_size(n), 1), dtype=torch.uint8,
+                                device=opacity_logit.device)
+    out = c_int32(0)
+    ctx.check(ctx.lib.gs_cull_low_opacity(ctx.handle, _ptr(opacity_logit), n, float(min_opacity),
+                                          _ptr(kept_index), ctypes.byref(out), _ptr(workspace),
+                                          workspace.numel(), _stream(stream)))
+    return int(out.value)
+
+
+def cull_workspace_size(n: int) -> int:
+    return int(load().gs_cull_workspace_size(n))
+
+
+def gs_gather_planes(ctx: Context, src, index, m: int, dst, stream=None):
+    """dst[p, j] = src[p, index[j]] for the (planes, ld) views src and dst."""
+    planes = src.shape[0] if src.dim() > 1 else 1
+    ctx.check(ctx.lib.gs_gather_planes(ctx.handle, _ptr(src), src.shape[-1], planes, _ptr(index),
+                                       m, _ptr(dst), dst.shape[-1], _stream(stream)))
+
+
+# ---- sent updates --------------------------------------------------------
+
+def gs_residual_delta(ctx: Context, D_t, Dp_prev, mask, n: int, gw: int, gh: int, d_out, absmax,
+                      stream=None):
+    ctx.check(ctx.lib.gs_residual_delta(ctx.handle, _ptr(D_t), _ptr(Dp_prev), _ptr(mask), n, gw,
+                                        gh, _ptr(d_out), _ptr(absmax), _stream(stream)))
+
+
+def gs_quantize_delta(ctx: Context, d, absmax, bits: int, n: int, gw: int, gh: int, q_out,
+                      scale_out, Dp=None, stream=None):
+    ctx.check(ctx.lib.gs_quantize_delta(ctx.handle, _ptr(d), _ptr(absmax), bits, n, gw, gh,
+                                        _ptr(q_out), _ptr(scale_out), _ptr(Dp), _stream(stream)))
+
+
+def gs_apply_quantized_update(ctx: Context, anchor: Gaussians, q, bits: int, scale, Dp, gw: int,
+                              gh: int, frame: Gaussians, stream=None):
+    a, f = anchor.c(), frame.c()
+    ctx.check(ctx.lib.gs_apply_quantized_update(ctx.handle, ctypes.byref(a), _ptr(q), bits,
+                                                _ptr(scale), _ptr(Dp), gw, gh, ctypes.byref(f),
+                                                _stream(stream)))
