@@ -106,6 +106,16 @@ __device__ __forceinline__ float dpp_take(float x) {
       __builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, ROW_MASK, 0xF, BOUND));
 }
 
+// Sum over each row of 16 lanes, valid in lanes 15, 31, 47, 63.  Must be
+// called with all lanes active.
+__device__ __forceinline__ float row_sum_lane15(float v) {
+  v += dpp_take<0x111, 0xF, true>(v);  // row_shr:1
+  v += dpp_take<0x112, 0xF, true>(v);  // row_shr:2
+  v += dpp_take<0x114, 0xF, true>(v);  // row_shr:4
+  v += dpp_take<0x118, 0xF, true>(v);  // row_shr:8
+  return v;
+}
+
 // Sum over the 64 lanes, valid in lane 63.  Must be called with all lanes
 // active.
 __device__ __forceinline__ float wave_sum_lane63(float v) {
@@ -123,7 +133,7 @@ __device__ __forceinline__ float wave_sum_lane63(float v) {
 // each of the four 8x8 quadrants ("slot" w = quadrant w), so a record's
 // quadrant mask selects slots uniformly across the wave.
 constexpr int kFwdBatch = 64;   // records staged per batch (1 per lane)
-constexpr int kBwdBatch = 64;   // records staged per backward batch (1 per lane)
+constexpr int kBwdBatch = 32;   // records staged per backward batch
 
 struct FwdShared {
   float4 a[kFwdBatch];
@@ -348,7 +358,7 @@ struct BwdShared {
   float4 c[kBwdBatch];
   uint32_t m[kBwdBatch];
   uint32_t g[kBwdBatch];
-  float acc[9][kBwdBatch];
+  float acc[9][4][kBwdBatch];  // per value, per 16-lane row, per entry
 };
 
 __device__ __forceinline__ int wave_max(int x) {
@@ -402,9 +412,7 @@ __global__ __launch_bounds__(64) void k_render_bwd(
   for (int hi = jmax; hi > 0; hi -= kBwdBatch) {
     const int lo = hi > kBwdBatch ? hi - kBwdBatch : 0;
     __syncthreads();
-#pragma unroll
-    for (int r = 0; r < kBwdBatch / 64; ++r) {
-      const int k = r * 64 + lane;
+    for (int k = lane; k < kBwdBatch; k += 64) {
       if (lo + k < hi) {
         const uint32_t g = vals[rg.x + (uint32_t)(lo + k)];
         const float4 q0 = sv[3 * (size_t)g], q1 = sv[3 * (size_t)g + 1],
@@ -416,8 +424,10 @@ __global__ __launch_bounds__(64) void k_render_bwd(
         sh.g[k] = g;
         sh.m[k] = quadrant_mask(q0, q1, q2, ox, oy);
       }
-#pragma unroll
-      for (int c = 0; c < 9; ++c) sh.acc[c][k] = 0.f;
+    }
+    {
+      float4* z = reinterpret_cast<float4*>(&sh.acc[0][0][0]);
+      for (int t = lane; t < 9 * kBwdBatch; t += 64) z[t] = make_float4(0.f, 0.f, 0.f, 0.f);
     }
     __syncthreads();
     for (int k = hi - lo - 1; k >= 0; --k) {
@@ -454,14 +464,16 @@ __global__ __launch_bounds__(64) void k_render_bwd(
           const float da = (use && ea < kAlphaMax)
                                ? Tk * (g0[w] * dc0 + g1[w] * dc1 + g2[w] * dc2)
                                : 0.f;
+          // moments of dL/dpower: the conic and mean gradients are linear in
+          // them with per-entry coefficients, applied once per entry at flush
           const float gp = da * alpha;
-          const float A = -2.f * a.z;
-          gr[5] = fmaf(da, ea * c.y, gr[5]);  // d alpha / d opacity = exp(power)
-          gr[0] = fmaf(-gp, A * dx + c.z * dy, gr[0]);
-          gr[1] = fmaf(-gp, c.z * dx + c.w * dy, gr[1]);
-          gr[2] = fmaf(-0.5f * gp, dx * dx, gr[2]);
-          gr[3] = fmaf(-gp, dx * dy, gr[3]);
-          gr[4] = fmaf(-0.5f * gp, dy * dy, gr[4]);
+          const float u = gp * dx, vv = gp * dy;
+          gr[0] += u;
+          gr[1] += vv;
+          gr[2] = fmaf(u, dx, gr[2]);
+          gr[3] = fmaf(u, dy, gr[3]);
+          gr[4] = fmaf(vv, dy, gr[4]);
+          gr[5] = fmaf(da, ea, gr[5]);  // times 1/opacity at flush
           B0[w] = fmaf(au, dc0, B0[w]);
           B1[w] = fmaf(au, dc1, B1[w]);
           B2[w] = fmaf(au, dc2, B2[w]);
@@ -470,23 +482,37 @@ __global__ __launch_bounds__(64) void k_render_bwd(
         }
       }
       if (__builtin_amdgcn_ballot_w64(contrib) == 0) continue;
+      // row sums in lanes 15, 31, 47, 63; the four rows are added at flush
 #pragma unroll
-      for (int cc = 0; cc < 9; ++cc) {
-        const float s = wave_sum_lane63(gr[cc]);
-        if (lane == 63) sh.acc[cc][k] = s;
+      for (int cc = 0; cc < 9; ++cc) gr[cc] = row_sum_lane15(gr[cc]);
+      if ((lane & 15) == 15) {
+#pragma unroll
+        for (int cc = 0; cc < 9; ++cc) sh.acc[cc][lane >> 4][k] = gr[cc];
       }
     }
     __syncthreads();
-#pragma unroll
-    for (int r = 0; r < kBwdBatch / 64; ++r) {
-      const int k = r * 64 + lane;
+    for (int k = lane; k < kBwdBatch; k += 64) {
       if (lo + k < hi) {
         float* dst = grad2d + ((size_t)v * ld + sh.g[k]) * kGrad2dFloats;
+        float mom[9];
 #pragma unroll
-        for (int cc = 0; cc < 9; ++cc) {
-          const float s = sh.acc[cc][k];
-          if (s != 0.f) atomicAdd(dst + cc, s);
-        }
+        for (int cc = 0; cc < 9; ++cc)
+          mom[cc] = (sh.acc[cc][0][k] + sh.acc[cc][1][k]) + (sh.acc[cc][2][k] + sh.acc[cc][3][k]);
+        // power = -(A dx^2 + C dy^2)/2 - B dx dy with dx = px - x, dy = py - y
+        const float A = -2.f * sh.a[k].z, B = sh.c[k].z, C = sh.c[k].w;
+        float out[9];
+        out[0] = -(A * mom[0] + B * mom[1]);
+        out[1] = -(B * mom[0] + C * mom[1]);
+        out[2] = -0.5f * mom[2];
+        out[3] = -mom[3];
+        out[4] = -0.5f * mom[4];
+        out[5] = mom[5] * sh.c[k].y;
+        out[6] = mom[6];
+        out[7] = mom[7];
+        out[8] = mom[8];
+#pragma unroll
+        for (int cc = 0; cc < 9; ++cc)
+          if (out[cc] != 0.f) atomicAdd(dst + cc, out[cc]);
       }
     }
   }

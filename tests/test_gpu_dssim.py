@@ -48,7 +48,9 @@ def test_dssim_identical_images_zero():
     img, _ = scenes.image_pair(2, 40, 48, seed=3)
     loss, grad = _gpu(img, img)
     assert abs(loss) <= 1e-6
-    assert np.abs(grad).max() <= 1e-9
+    # the SSIM partials cancel only to FP32 rounding: terms of size
+    # lambda * 2 / C2 / count times 2^-24, far below one L1 gradient step 1/count
+    assert np.abs(grad).max() <= 1e-4 / img.size
 
 
 def test_dssim_full_frame_sampled_views():

@@ -129,8 +129,8 @@ def test_cull_then_gather_compacts_a_gaussian_set():
     g = gs.Gaussians.from_scene(sc)
     ctx = gs.default_context()
     idx = torch.empty(g.n, dtype=torch.int32, device="cuda")
-    m = gs.gs_cull_low_opacity(ctx, g.opacity, g.n, 0.01, idx)
-    want = oracle.low_opacity_keep(sc["opacity"], sc["n"], 0.01)
+    m = gs.gs_cull_low_opacity(ctx, g.opacity, g.n, 0.3, idx)
+    want = oracle.low_opacity_keep(sc["opacity"], sc["n"], 0.3)
     assert m == len(want) and 0 < m < g.n
     ld2 = scenes.round_up(m)
     for name in ("mean", "log_scale", "quat", "sh"):
