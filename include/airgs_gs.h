@@ -126,7 +126,13 @@ typedef struct gs_projected {
  *       (segment << 32) | depth_bits, ascending;
  *   vals (capacity) uint32: Gaussian id of each instance, in key order, ties
  *       (equal segment and depth) in ascending id;
- *   ranges (n_segments, 2) uint32: [start, end) of each segment in vals.
+ *   ranges (n_segments, 2) uint32: [start, end) of each segment in vals;
+ *   gv_base (gv_capacity >= n_views * ld) uint32, nullable for gs_bin_sort,
+ *       required by gs_render_bwd: for each (view v, Gaussian i) with
+ *       tiles_touched > 0, at v*ld + i, the index of its first instance in
+ *       the binning's emission order (its tiles row by row over its tile
+ *       rectangle, consecutive); the backward sums per-instance gradients
+ *       in that order without atomics.
  * capacity (in) bounds the instance count; count (out) is the instance count
  * M; n_segments (out) is the total tile count. */
 typedef struct gs_tile_lists {
@@ -136,6 +142,8 @@ typedef struct gs_tile_lists {
   uint64_t* keys;
   uint32_t* vals;
   uint32_t* ranges;
+  int64_t gv_capacity;
+  uint32_t* gv_base;
 } gs_tile_lists;
 
 /* Frame update for the backward pass to the delta images.
@@ -174,18 +182,21 @@ int64_t gs_num_segments(const gs_camera* cams_host, int n_views);
  * capacity and total segment count. */
 size_t gs_bin_sort_workspace_size(int n_views, int ld, int64_t capacity, int64_t n_segments);
 
-/* Workspace bytes for gs_render_bwd.  Its first n_views*ld*12 floats hold
- * the per-(view, Gaussian) screen-space gradients after the call:
- * [d px, d py, d A, d B, d C, d opacity, d r, d g, d b, 0, 0, 0]. */
-size_t gs_render_bwd_workspace_size(int n_views, int ld);
+/* Workspace bytes for gs_render_bwd over lists of `instances` entries.  Its
+ * first n_views*ld*12 floats hold the per-(view, Gaussian) screen-space
+ * gradients after the call (entries i < n):
+ * [d px, d py, d A, d B, d C, d opacity, d r, d g, d b, 0, 0, 0]; then one
+ * 9-float gradient row per instance. */
+size_t gs_render_bwd_workspace_size(int n_views, int ld, int64_t instances);
 
 /* Device-time measurement.  With timing enabled, every kernel stage a call
  * enqueues is bracketed by HIP events on the call's stream.  Stages:
  *   0 apply, 1 project, 2 depth sort, 3 count scan, 4 emit, 5 segment sort,
  *   6 ranges, 7 render fwd, 8 render bwd, 9 project bwd, 10 apply bwd,
  *   11 l1, 12 adam, 13 fill, 14 dssim, 15 compact (culling, gathers),
- *   16 residual (bookkeeping, quantisation, quantised apply). */
-#define GS_STAGE_COUNT 17
+ *   16 residual (bookkeeping, quantisation, quantised apply), 17 grad gather
+ *   (per-Gaussian sums of the backward's instance rows). */
+#define GS_STAGE_COUNT 18
 gs_status gs_set_timing(gs_ctx* ctx, int enable);
 /* Sum of event-measured milliseconds and number of launches per stage since
  * the previous collection (host arrays of GS_STAGE_COUNT); blocks until the

@@ -244,7 +244,7 @@ const char* gs_stage_name(int stage) {
   static const char* names[GS_STAGE_COUNT] = {
       "apply",  "project",    "depth_sort",  "count_scan", "emit", "segment_sort", "ranges",
       "render_fwd", "render_bwd", "project_bwd", "apply_bwd", "l1",   "adam",         "fill",
-      "dssim", "compact", "residual"};
+      "dssim", "compact", "residual", "grad_gather"};
   return (stage >= 0 && stage < GS_STAGE_COUNT) ? names[stage] : "?";
 }
 
@@ -258,9 +258,10 @@ size_t gs_bin_sort_workspace_size(int V, int ld, int64_t capacity, int64_t n_seg
   return gs::bin_sort_workspace_bytes(V, ld, capacity, n_segments);
 }
 
-size_t gs_render_bwd_workspace_size(int V, int ld) {
-  if (V <= 0 || ld <= 0) return 0;
-  return (size_t)V * (size_t)ld * gs::kGrad2dFloats * sizeof(float);
+size_t gs_render_bwd_workspace_size(int V, int ld, int64_t instances) {
+  if (V <= 0 || ld <= 0 || instances < 0) return 0;
+  const size_t g2d = (size_t)V * (size_t)ld * gs::kGrad2dFloats * sizeof(float);
+  return g2d + (size_t)instances * 9 * sizeof(float);
 }
 
 gs_status gs_apply_frame_update(gs_ctx* c, const gs_gaussians* anchor, const float* delta,
@@ -432,16 +433,20 @@ gs_status gs_render_bwd(gs_ctx* c, const gs_gaussians* frame, const gs_projected
   }
   if (opts && ((opts->grad2d_norm == nullptr) != (opts->visible_views == nullptr)))
     return fail(c, GS_ERR_INVALID_ARG, "grad2d_norm and visible_views go together");
-  const size_t need = gs_render_bwd_workspace_size(V, frame->ld);
+  if (!lists->gv_base || lists->gv_capacity < (int64_t)V * frame->ld)
+    return fail(c, GS_ERR_INVALID_ARG, "tile lists lack the per-Gaussian emission bases (gv_base)");
+  if (lists->count < 0 || lists->count > lists->capacity)
+    return fail(c, GS_ERR_INVALID_ARG, "tile list count out of range");
+  const size_t need = gs_render_bwd_workspace_size(V, frame->ld, lists->count);
   if (!ws || ws_bytes < need)
     return fail(c, GS_ERR_OOM, "render_bwd workspace %zu < %zu bytes", ws_bytes, need);
   GS_TRY(use_device(c));
   hipStream_t s = (hipStream_t)stream;
   float* grad2d = static_cast<float*>(ws);
-  gs::launch_fill_f32(grad2d, 0.f, (int64_t)(need / sizeof(float)), s);
+  float* rows = grad2d + (size_t)V * (size_t)frame->ld * gs::kGrad2dFloats;
   const float zero[3] = {0.f, 0.f, 0.f};
   gs::launch_render_bwd(*proj, *lists, V, ch[0].width, ch[0].height, opts ? opts->bg : zero,
-                        final_T, n_contrib, dL_dimage, grad2d, s);
+                        final_T, n_contrib, dL_dimage, rows, grad2d, s);
   GS_LAUNCHED(c, "render_bwd");
   float* st_norm = opts ? opts->grad2d_norm : nullptr;
   uint32_t* st_views = opts ? opts->visible_views : nullptr;

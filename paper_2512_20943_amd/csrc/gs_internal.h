@@ -30,7 +30,7 @@ __host__ __device__ inline int tiles_across(int px) { return (px + kTile - 1) / 
 enum Stage {
   kStApply = 0, kStProject, kStDepthSort, kStCountScan, kStEmit, kStSegmentSort, kStRanges,
   kStRenderFwd, kStRenderBwd, kStProjectBwd, kStApplyBwd, kStL1, kStAdam, kStFill, kStDssim,
-  kStCompact, kStResidual, kStageCount
+  kStCompact, kStResidual, kStGradGather, kStageCount
 };
 static_assert(kStageCount == GS_STAGE_COUNT, "stage table out of sync with the header");
 
@@ -91,9 +91,9 @@ size_t render_batched_workspace_bytes(int V);
 void launch_render_batched(const gs_projected& proj, const gs_tile_lists& lists,
                            const gs_camera* cams_dev, int V, int64_t total_segments,
                            const float bg[3], float* images, void* ws, hipStream_t s);
-void launch_render_bwd(const gs_projected& proj, const gs_tile_lists& lists, int n_views, int W,
-                       int H, const float bg[3], const float* final_T, const int32_t* n_contrib,
-                       const float* dL_dimage, float* grad2d, hipStream_t s);
+void launch_render_bwd(const gs_projected& proj, const gs_tile_lists& lists, int V, int W, int H,
+                       const float bg[3], const float* final_T, const int32_t* n_contrib,
+                       const float* dL_dimage, float* rows, float* grad2d, hipStream_t s);
 // training support
 void launch_l1(const float* image, const float* target, int64_t count, float* grad,
                double* loss, hipStream_t s);

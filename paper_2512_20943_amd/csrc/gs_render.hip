@@ -352,6 +352,14 @@ __global__ __launch_bounds__(64) void k_render_persistent(
 }
 
 // ---------------------------------------------------------------- backward
+constexpr int kRowFloats = 9;  // per-instance gradient row
+
+// Index of the instance of a (view, Gaussian) in tile (tx, ty): the binning
+// emits its tiles row by row over its tile rectangle starting at base.
+__device__ __forceinline__ uint32_t instance_row(int4 r, uint32_t base, int tx, int ty) {
+  return base + (uint32_t)((ty - r.y) * (r.z - r.x) + (tx - r.x));
+}
+
 struct BwdShared {
   float4 a[kBwdBatch];
   float4 b[kBwdBatch];
@@ -371,7 +379,8 @@ __global__ __launch_bounds__(64) void k_render_bwd(
     const float4* __restrict__ splat, int ld, const uint32_t* __restrict__ vals,
     const uint2* __restrict__ ranges, int W, int H, int TX, int tiles_per_view, float bg0,
     float bg1, float bg2, const float* __restrict__ final_T, const int32_t* __restrict__ n_contrib,
-    const float* __restrict__ dL_dimage, float* __restrict__ grad2d) {
+    const float* __restrict__ dL_dimage, const int4* __restrict__ rect,
+    const uint32_t* __restrict__ gv_base, float* __restrict__ rows) {
   __shared__ BwdShared sh;
   const int seg = blockIdx.x;
   const int v = seg / tiles_per_view, tile = seg - v * tiles_per_view;
@@ -379,6 +388,8 @@ __global__ __launch_bounds__(64) void k_render_bwd(
   const int lane = threadIdx.x;
   const uint2 rg = ranges[seg];
   const float4* sv = splat + 3 * (size_t)v * ld;
+  const int4* rv = rect + (size_t)v * ld;
+  const uint32_t* bv = gv_base + (size_t)v * ld;
   const size_t pix = (size_t)W * H;
   const float* gi = dL_dimage + 3 * pix * v;
 
@@ -421,7 +432,7 @@ __global__ __launch_bounds__(64) void k_render_bwd(
         sh.a[k] = rr.a;
         sh.b[k] = rr.b;
         sh.c[k] = rr.c;
-        sh.g[k] = g;
+        sh.g[k] = instance_row(rv[g], bv[g], tx, ty);
         sh.m[k] = quadrant_mask(q0, q1, q2, ox, oy);
       }
     }
@@ -493,7 +504,7 @@ __global__ __launch_bounds__(64) void k_render_bwd(
     __syncthreads();
     for (int k = lane; k < kBwdBatch; k += 64) {
       if (lo + k < hi) {
-        float* dst = grad2d + ((size_t)v * ld + sh.g[k]) * kGrad2dFloats;
+        float* dst = rows + (size_t)sh.g[k] * kRowFloats;
         float mom[9];
 #pragma unroll
         for (int cc = 0; cc < 9; ++cc)
@@ -511,11 +522,44 @@ __global__ __launch_bounds__(64) void k_render_bwd(
         out[7] = mom[7];
         out[8] = mom[8];
 #pragma unroll
-        for (int cc = 0; cc < 9; ++cc)
-          if (out[cc] != 0.f) atomicAdd(dst + cc, out[cc]);
+        for (int cc = 0; cc < 9; ++cc) dst[cc] = out[cc];
       }
     }
   }
+  // entries behind every pixel's last contributor carry zero gradient
+  const int cnt = (int)(rg.y - rg.x);
+  for (int j = jmax + lane; j < cnt; j += 64) {
+    const uint32_t g = vals[rg.x + (uint32_t)j];
+    float* dst = rows + (size_t)instance_row(rv[g], bv[g], tx, ty) * kRowFloats;
+#pragma unroll
+    for (int cc = 0; cc < 9; ++cc) dst[cc] = 0.f;
+  }
+}
+
+// Screen-space gradient of each (view, Gaussian): the sum of its instance
+// rows, which the binning emitted contiguously (one per covered tile).
+__global__ __launch_bounds__(256) void k_grad_gather(int n, int ld, int V,
+                                                     const int32_t* __restrict__ tiles,
+                                                     const uint32_t* __restrict__ gv_base,
+                                                     const float* __restrict__ rows,
+                                                     float* __restrict__ grad2d) {
+  const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (size_t)n * V) return;
+  const size_t v = t / (size_t)n, i = t - v * (size_t)n;
+  const size_t gv = v * (size_t)ld + i;
+  const int c = tiles[gv];
+  float acc[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  if (c > 0) {
+    const float* r = rows + (size_t)gv_base[gv] * kRowFloats;
+    for (int k = 0; k < c; ++k, r += kRowFloats) {
+#pragma unroll
+      for (int cc = 0; cc < 9; ++cc) acc[cc] += r[cc];
+    }
+  }
+  float4* o = reinterpret_cast<float4*>(grad2d + gv * kGrad2dFloats);
+  o[0] = make_float4(acc[0], acc[1], acc[2], acc[3]);
+  o[1] = make_float4(acc[4], acc[5], acc[6], acc[7]);
+  o[2] = make_float4(acc[8], 0.f, 0.f, 0.f);
 }
 
 }  // namespace
@@ -573,16 +617,24 @@ void launch_render_batched(const gs_projected& proj, const gs_tile_lists& lists,
 
 void launch_render_bwd(const gs_projected& proj, const gs_tile_lists& lists, int V, int W, int H,
                        const float bg[3], const float* final_T, const int32_t* n_contrib,
-                       const float* dL_dimage, float* grad2d, hipStream_t s) {
+                       const float* dL_dimage, float* rows, float* grad2d, hipStream_t s) {
   const int TX = tiles_across(W), TY = tiles_across(H);
   const int tpv = TX * TY;
   const int blocks = tpv * V;
   if (blocks == 0) return;
-  StageScope scope(kStRenderBwd, s);
-  hipLaunchKernelGGL(k_render_bwd, dim3(blocks), dim3(64), 0, s,
-                     reinterpret_cast<const float4*>(proj.splat), proj.ld, lists.vals,
-                     reinterpret_cast<const uint2*>(lists.ranges), W, H, TX, tpv, bg[0], bg[1],
-                     bg[2], final_T, n_contrib, dL_dimage, grad2d);
+  {
+    StageScope scope(kStRenderBwd, s);
+    hipLaunchKernelGGL(k_render_bwd, dim3(blocks), dim3(64), 0, s,
+                       reinterpret_cast<const float4*>(proj.splat), proj.ld, lists.vals,
+                       reinterpret_cast<const uint2*>(lists.ranges), W, H, TX, tpv, bg[0], bg[1],
+                       bg[2], final_T, n_contrib, dL_dimage,
+                       reinterpret_cast<const int4*>(proj.rect), lists.gv_base, rows);
+  }
+  const size_t nv = (size_t)proj.n * (size_t)V;
+  if (nv == 0) return;
+  StageScope scope(kStGradGather, s);
+  hipLaunchKernelGGL(k_grad_gather, dim3((unsigned)((nv + 255) / 256)), dim3(256), 0, s, proj.n,
+                     proj.ld, V, proj.tiles_touched, lists.gv_base, rows, grad2d);
 }
 
 }  // namespace gs

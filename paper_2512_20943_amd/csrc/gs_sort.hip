@@ -331,7 +331,9 @@ __global__ __launch_bounds__(kBlock) void k_count_scan(uint32_t N, const uint32_
   }
 }
 
-// Emit (segment, Gaussian id) for each tile of each depth-sorted entry.
+// Emit (segment, Gaussian id) for each tile of each depth-sorted entry, row
+// by row over its tile rectangle; optionally record where each (view,
+// Gaussian) starts in this order.
 __global__ __launch_bounds__(kBlock) void k_emit(uint32_t N, int ld,
                                                  const uint64_t* __restrict__ keys,
                                                  const uint32_t* __restrict__ vals,
@@ -341,7 +343,8 @@ __global__ __launch_bounds__(kBlock) void k_emit(uint32_t N, int ld,
                                                  const uint32_t* __restrict__ seg_base,
                                                  const int32_t* __restrict__ txv,
                                                  uint32_t* __restrict__ seg_out,
-                                                 uint32_t* __restrict__ id_out) {
+                                                 uint32_t* __restrict__ id_out,
+                                                 uint32_t* __restrict__ gv_base) {
   const uint32_t e = blockIdx.x * kBlock + threadIdx.x;
   if (e >= N || cnt[e] == 0) return;
   const uint32_t v = (uint32_t)(keys[e] >> 32), g = vals[e];
@@ -349,6 +352,7 @@ __global__ __launch_bounds__(kBlock) void k_emit(uint32_t N, int ld,
   const uint32_t sb = seg_base[v];
   const int tx = txv[v];
   uint32_t o = offs[e];
+  if (gv_base) gv_base[(size_t)v * ld + g] = o;
   for (int ty = r.y; ty < r.w; ++ty)
     for (int x = r.x; x < r.z; ++x) {
       seg_out[o] = sb + (uint32_t)(ty * tx + x);
@@ -591,7 +595,7 @@ hipError_t bin_sort_stage2(const BinSortPlan& p, const gs_projected& proj,
     hipLaunchKernelGGL(k_emit, dim3(cdiv(N, kBlock)), dim3(kBlock), 0, s, N, p.ld, sk, sv,
                        at<uint32_t>(ws, L.cnt), at<uint32_t>(ws, L.offs),
                        reinterpret_cast<const int4*>(proj.rect), at<uint32_t>(ws, L.seg_base),
-                       at<int32_t>(ws, L.txv), segk0, v0);
+                       at<int32_t>(ws, L.txv), segk0, v0, lists.gv_base);
   }
   int which2;
   {

@@ -27,7 +27,7 @@ GS_ERR_HIP = 4
 TILE = 16
 SPLAT_FLOATS = 12
 GRAD2D_FLOATS = 12
-STAGE_COUNT = 17
+STAGE_COUNT = 18
 
 c_int32, c_int64, c_void_p, c_double, c_float = (ctypes.c_int32, ctypes.c_int64, ctypes.c_void_p,
                                                  ctypes.c_double, ctypes.c_float)
@@ -58,7 +58,8 @@ class GsProjected(ctypes.Structure):
 
 class GsTileLists(ctypes.Structure):
     _fields_ = [("capacity", c_int64), ("count", c_int64), ("n_segments", c_int64),
-                ("keys", c_void_p), ("vals", c_void_p), ("ranges", c_void_p)]
+                ("keys", c_void_p), ("vals", c_void_p), ("ranges", c_void_p),
+                ("gv_capacity", c_int64), ("gv_base", c_void_p)]
 
 
 class GsFrameUpdate(ctypes.Structure):
@@ -97,7 +98,7 @@ def load() -> ctypes.CDLL:
     lib.gs_num_segments.restype = c_int64
     lib.gs_bin_sort_workspace_size.argtypes = [ctypes.c_int, ctypes.c_int, c_int64, c_int64]
     lib.gs_bin_sort_workspace_size.restype = ctypes.c_size_t
-    lib.gs_render_bwd_workspace_size.argtypes = [ctypes.c_int, ctypes.c_int]
+    lib.gs_render_bwd_workspace_size.argtypes = [ctypes.c_int, ctypes.c_int, c_int64]
     lib.gs_render_bwd_workspace_size.restype = ctypes.c_size_t
     lib.gs_apply_frame_update.argtypes = [c_void_p, P(GsGaussians), c_void_p, c_void_p,
                                           ctypes.c_int, ctypes.c_int, P(GsGaussians), c_void_p]
@@ -348,7 +349,11 @@ class Projected:
 
 
 class TileLists:
-    def __init__(self, capacity: int, n_segments: int, with_keys: bool = False, device="cuda"):
+    """Sorted tile lists; ``gv`` > 0 also allocates the per-(view, Gaussian)
+    emission bases (n_views * ld entries) the backward needs."""
+
+    def __init__(self, capacity: int, n_segments: int, with_keys: bool = False, device="cuda",
+                 gv: int = 0):
         self.capacity = int(capacity)
         self.n_segments = int(n_segments)
         self.count = 0
@@ -356,8 +361,11 @@ class TileLists:
         self.keys = (torch.empty(max(self.capacity, 1), dtype=torch.int64, device=device)
                      if with_keys else None)
         self.ranges = torch.empty(max(self.n_segments, 1), 2, dtype=torch.int32, device=device)
+        self.gv = int(gv)
+        self.gv_base = (torch.empty(self.gv, dtype=torch.int32, device=device)
+                        if self.gv > 0 else None)
         self._c = GsTileLists(self.capacity, 0, self.n_segments, _ptr(self.keys), _ptr(self.vals),
-                              _ptr(self.ranges))
+                              _ptr(self.ranges), self.gv, _ptr(self.gv_base))
 
     def c(self) -> GsTileLists:
         return self._c
@@ -480,8 +488,8 @@ def bin_sort_workspace_size(V: int, ld: int, capacity: int, n_segments: int) -> 
     return int(load().gs_bin_sort_workspace_size(V, ld, capacity, n_segments))
 
 
-def render_bwd_workspace_size(V: int, ld: int) -> int:
-    return int(load().gs_render_bwd_workspace_size(V, ld))
+def render_bwd_workspace_size(V: int, ld: int, instances: int) -> int:
+    return int(load().gs_render_bwd_workspace_size(V, ld, instances))
 
 
 # ---- keyframe reconstruction ---------------------------------------------

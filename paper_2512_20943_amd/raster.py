@@ -36,15 +36,18 @@ class Rasterizer:
 
     def _sort_buffers(self, V, ld, nseg, device):
         L = self._lists
-        if L is None or L.capacity < self.capacity or L.n_segments != nseg:
-            self._lists = gs.TileLists(self.capacity, nseg, self.with_keys, device)
+        if (L is None or L.capacity < self.capacity or L.n_segments != nseg
+                or L.gv < V * ld):
+            self._lists = gs.TileLists(self.capacity, nseg, self.with_keys, device, gv=V * ld)
         need = gs.bin_sort_workspace_size(V, ld, self._lists.capacity, nseg)
         if self._ws_sort is None or self._ws_sort.numel() < need:
             self._ws_sort = torch.empty(need, dtype=torch.uint8, device=device)
         return self._lists, self._ws_sort
 
-    def bwd_workspace(self, V, ld, device):
-        need = gs.render_bwd_workspace_size(V, ld)
+    def bwd_workspace(self, V, ld, device, instances=None):
+        if instances is None:
+            instances = self._lists.count if self._lists is not None else 0
+        need = gs.render_bwd_workspace_size(V, ld, instances)
         if self._ws_bwd is None or self._ws_bwd.numel() < need:
             self._ws_bwd = torch.empty(need, dtype=torch.uint8, device=device)
         return self._ws_bwd
@@ -83,7 +86,7 @@ class Rasterizer:
 
     def backward(self, g: gs.Gaussians, cams: gs.Cameras, state: dict, dL_dimage: torch.Tensor,
                  grad: gs.Gaussians, bg=(0.0, 0.0, 0.0), upd=None, dL_ddelta=None, stream=None):
-        ws = self.bwd_workspace(cams.V, g.ld, g.mean.device)
+        ws = self.bwd_workspace(cams.V, g.ld, g.mean.device, state["lists"].count)
         gs.gs_render_bwd(self.ctx, g, state["proj"], state["lists"], cams, bg, state["final_T"],
                          state["n_contrib"], dL_dimage.contiguous(), grad, ws, upd, dL_ddelta,
                          stream)
