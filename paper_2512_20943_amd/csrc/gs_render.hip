@@ -551,7 +551,18 @@ __global__ __launch_bounds__(256) void k_grad_gather(int n, int ld, int V,
   float acc[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
   if (c > 0) {
     const float* r = rows + (size_t)gv_base[gv] * kRowFloats;
-    for (int k = 0; k < c; ++k, r += kRowFloats) {
+    // four rows per step, all loads issued before the adds
+    int k = 0;
+    for (; k + 4 <= c; k += 4, r += 4 * kRowFloats) {
+      float x[36];
+#pragma unroll
+      for (int u = 0; u < 36; ++u) x[u] = r[u];
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int cc = 0; cc < 9; ++cc) acc[cc] += x[9 * u + cc];
+    }
+    for (; k < c; ++k, r += kRowFloats) {
 #pragma unroll
       for (int cc = 0; cc < 9; ++cc) acc[cc] += r[cc];
     }
