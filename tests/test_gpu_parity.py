@@ -482,3 +482,33 @@ def test_large_2m_8_views_sampled():
     out0 = {k: out[k][:1] for k in ("image", "final_T", "n_contrib")}
     err, near = compare_images(out0, img0)
     say(f"  view 0 max image error {err:.2e}, {near} near-threshold pixels")
+
+
+def test_emission_bases_index_every_instance_once():
+    """gv_base: the instances of each (view, Gaussian) occupy rows gv_base ..
+    gv_base + tiles_touched - 1 in row-major order over its tile rectangle,
+    and these rows, over all sorted instances, are a permutation of 0..M-1
+    (the backward writes one gradient row per instance there)."""
+    require_gpu()
+    scene, cams = small_frame_workload(3)
+    g, gc, r, out = gpu_forward(scene, cams)
+    L = out["lists"]
+    M = L.count
+    vals = L.vals[:M].cpu().numpy().astype(np.int64)
+    ranges = L.ranges[:L.n_segments].cpu().numpy().astype(np.int64)
+    seg_of = np.repeat(np.arange(L.n_segments), ranges[:, 1] - ranges[:, 0])
+    ld = g.ld
+    base = L.gv_base[:gc.V * ld].cpu().numpy().view(np.uint32).astype(np.int64)
+    rect = out["proj"].rect.cpu().numpy().reshape(gc.V, ld, 4)
+    tiles = out["proj"].tiles_touched.cpu().numpy().reshape(gc.V, ld)
+    tpv = [((w + 15) // 16) * ((h + 15) // 16) for (w, h) in cams["wh"]]
+    sb = np.concatenate([[0], np.cumsum(tpv)])
+    v = np.searchsorted(sb, seg_of, side="right") - 1
+    tile = seg_of - sb[v]
+    TX = np.array([(w + 15) // 16 for (w, h) in cams["wh"]])[v]
+    ty, tx = tile // TX, tile % TX
+    rc = rect[v, vals]
+    local = (ty - rc[:, 1]) * (rc[:, 2] - rc[:, 0]) + (tx - rc[:, 0])
+    assert np.all((local >= 0) & (local < tiles[v, vals]))
+    rows = base[v * ld + vals] + local
+    assert np.array_equal(np.sort(rows), np.arange(M))
