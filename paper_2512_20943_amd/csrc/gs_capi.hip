@@ -324,19 +324,20 @@ gs_status gs_bin_sort(gs_ctx* c, const gs_projected* proj, const gs_camera* ch,
   GS_TRY(use_device(c));
   hipStream_t s = (hipStream_t)stream;
   lists->n_segments = nseg;
-  uint32_t* d_count = nullptr;
-  hipError_t e = gs::bin_sort_stage1(plan, *proj, cd, ws, s, &d_count);
+  uint32_t* d_stats = nullptr;
+  hipError_t e = gs::bin_sort_stage1(plan, *proj, cd, ws, s, &d_stats);
   if (e != hipSuccess) return hip_fail(c, e, "bin_sort (count)");
-  e = hipMemcpyAsync(c->pinned, d_count, sizeof(uint32_t), hipMemcpyDeviceToHost, s);
+  e = hipMemcpyAsync(c->pinned, d_stats, 4 * sizeof(uint32_t), hipMemcpyDeviceToHost, s);
   if (e != hipSuccess) return hip_fail(c, e, "instance count readback");
   e = hipStreamSynchronize(s);
   if (e != hipSuccess) return hip_fail(c, e, "hipStreamSynchronize");
-  const uint32_t M = *c->pinned;
+  const uint32_t dmin = c->pinned[0], dmax = c->pinned[1];
+  const uint64_t M = (uint64_t)c->pinned[2] | ((uint64_t)c->pinned[3] << 32);
   lists->count = (int64_t)M;
-  if ((int64_t)M > lists->capacity)
-    return fail(c, GS_ERR_CAPACITY, "instance count %u exceeds capacity %lld", M,
-                (long long)lists->capacity);
-  e = gs::bin_sort_stage2(plan, *proj, cd, M, *lists, ws, s);
+  if (M > (uint64_t)lists->capacity)
+    return fail(c, GS_ERR_CAPACITY, "instance count %llu exceeds capacity %lld",
+                (unsigned long long)M, (long long)lists->capacity);
+  e = gs::bin_sort_stage2(plan, *proj, cd, (uint32_t)M, dmin, dmax, *lists, ws, s);
   if (e != hipSuccess) return hip_fail(c, e, "bin_sort (sort)");
   return GS_OK;
 }

@@ -74,15 +74,16 @@ struct BinSortPlan {
   int64_t n_segments;
 };
 size_t bin_sort_workspace_bytes(int n_views, int ld, int64_t capacity, int64_t n_segments);
-// Runs everything up to the instance count; returns the device pointer of M.
-// The second stage emits, sorts and builds ranges once M is known.
-struct BinSortState;
+// Stage 1 reduces the visible pairs' depth-bit range and instance count
+// into 4 device words {min bits, max bits, count (u64)}; the second stage,
+// once the host has read them, depth-sorts, emits, sorts by tile and builds
+// ranges.
 hipError_t bin_sort_stage1(const BinSortPlan& p, const gs_projected& proj,
                            const gs_camera* cams_dev, void* ws, hipStream_t s,
-                           uint32_t** d_count);
+                           uint32_t** d_stats);
 hipError_t bin_sort_stage2(const BinSortPlan& p, const gs_projected& proj,
-                           const gs_camera* cams_dev, uint32_t M, gs_tile_lists& lists, void* ws,
-                           hipStream_t s);
+                           const gs_camera* cams_dev, uint32_t M, uint32_t dmin, uint32_t dmax,
+                           gs_tile_lists& lists, void* ws, hipStream_t s);
 // render
 void launch_render_fwd(const gs_projected& proj, const gs_tile_lists& lists, int n_views, int W,
                        int H, const float bg[3], float* image, float* final_T,

@@ -537,40 +537,85 @@ __global__ __launch_bounds__(64) void k_render_bwd(
 }
 
 // Screen-space gradient of each (view, Gaussian): the sum of its instance
-// rows, which the binning emitted contiguously (one per covered tile).
+// rows, which the binning emitted contiguously (one per covered tile).  Each
+// wave takes 64 (view, Gaussian) pairs and walks the union of their rows 64
+// at a time (row f of the union on lane f mod 64, so long and short runs
+// balance and the loads coalesce within a run); a segmented scan over the
+// lanes sums each pair's rows of the step, and the lane at the end of a
+// pair's segment adds them to that pair's LDS accumulator.
 __global__ __launch_bounds__(256) void k_grad_gather(int n, int ld, int V,
                                                      const int32_t* __restrict__ tiles,
                                                      const uint32_t* __restrict__ gv_base,
                                                      const float* __restrict__ rows,
                                                      float* __restrict__ grad2d) {
+  __shared__ uint32_t s_pre[4][64];
+  __shared__ uint32_t s_base[4][64];
+  __shared__ float s_acc[4][9][64];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const size_t total = (size_t)n * V;
   const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= (size_t)n * V) return;
-  const size_t v = t / (size_t)n, i = t - v * (size_t)n;
-  const size_t gv = v * (size_t)ld + i;
-  const int c = tiles[gv];
-  float acc[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-  if (c > 0) {
-    const float* r = rows + (size_t)gv_base[gv] * kRowFloats;
-    // four rows per step, all loads issued before the adds
-    int k = 0;
-    for (; k + 4 <= c; k += 4, r += 4 * kRowFloats) {
-      float x[36];
-#pragma unroll
-      for (int u = 0; u < 36; ++u) x[u] = r[u];
-#pragma unroll
-      for (int u = 0; u < 4; ++u)
-#pragma unroll
-        for (int cc = 0; cc < 9; ++cc) acc[cc] += x[9 * u + cc];
-    }
-    for (; k < c; ++k, r += kRowFloats) {
-#pragma unroll
-      for (int cc = 0; cc < 9; ++cc) acc[cc] += r[cc];
+  size_t gv = 0;
+  uint32_t c = 0, base = 0;
+  if (t < total) {
+    const size_t v = t / (size_t)n, i = t - v * (size_t)n;
+    gv = v * (size_t)ld + i;
+    const int ct = tiles[gv];
+    if (ct > 0) {
+      c = (uint32_t)ct;
+      base = gv_base[gv];
     }
   }
-  float4* o = reinterpret_cast<float4*>(grad2d + gv * kGrad2dFloats);
-  o[0] = make_float4(acc[0], acc[1], acc[2], acc[3]);
-  o[1] = make_float4(acc[4], acc[5], acc[6], acc[7]);
-  o[2] = make_float4(acc[8], 0.f, 0.f, 0.f);
+  uint32_t incl = c;
+  for (int off = 1; off < 64; off <<= 1) {
+    const uint32_t y = __shfl_up(incl, off, 64);
+    if (lane >= off) incl += y;
+  }
+  const uint32_t R = __shfl(incl, 63, 64);
+  s_pre[wave][lane] = incl - c;
+  s_base[wave][lane] = base;
+#pragma unroll
+  for (int cc = 0; cc < 9; ++cc) s_acc[wave][cc][lane] = 0.f;
+  __syncthreads();
+  for (uint32_t f0 = 0; f0 < R; f0 += 64) {
+    const uint32_t f = f0 + lane;
+    const bool valid = f < R;
+    int q = 64;  // sentinel for lanes past the end
+    float x[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    if (valid) {
+      q = 0;
+#pragma unroll
+      for (int step = 32; step >= 1; step >>= 1)
+        if (s_pre[wave][q + step] <= f) q += step;
+      const float* r = rows + (size_t)(s_base[wave][q] + (f - s_pre[wave][q])) * kRowFloats;
+#pragma unroll
+      for (int cc = 0; cc < 9; ++cc) x[cc] = r[cc];
+    }
+    // segmented inclusive scan over lanes with equal q
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+      const int qo = __shfl_up(q, off, 64);
+      const bool take = lane >= off && qo == q;
+#pragma unroll
+      for (int cc = 0; cc < 9; ++cc) {
+        const float y = __shfl_up(x[cc], off, 64);
+        x[cc] += take ? y : 0.f;
+      }
+    }
+    const int qn = __shfl_down(q, 1, 64);
+    if (valid && (lane == 63 || qn != q)) {
+#pragma unroll
+      for (int cc = 0; cc < 9; ++cc) s_acc[wave][cc][q] += x[cc];
+    }
+  }
+  __syncthreads();
+  if (t < total) {
+    float4* o = reinterpret_cast<float4*>(grad2d + gv * kGrad2dFloats);
+    o[0] = make_float4(s_acc[wave][0][lane], s_acc[wave][1][lane], s_acc[wave][2][lane],
+                       s_acc[wave][3][lane]);
+    o[1] = make_float4(s_acc[wave][4][lane], s_acc[wave][5][lane], s_acc[wave][6][lane],
+                       s_acc[wave][7][lane]);
+    o[2] = make_float4(s_acc[wave][8][lane], 0.f, 0.f, 0.f);
+  }
 }
 
 }  // namespace

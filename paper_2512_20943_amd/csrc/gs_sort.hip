@@ -27,6 +27,7 @@ constexpr uint32_t kFlagAgg = 1u << 30;
 constexpr uint32_t kFlagPre = 2u << 30;
 constexpr uint32_t kValMask = (1u << 30) - 1u;
 constexpr int kMaxPasses = 8;
+constexpr int kLookWin = 8;    // look-back window (partitions loaded together)
 
 __device__ __forceinline__ uint64_t wave_ballot(bool p) { return __builtin_amdgcn_ballot_w64(p); }
 
@@ -202,16 +203,37 @@ __global__ __launch_bounds__(kBlock) void k_onesweep(
       s_dstart[d] = dstart;
       uint32_t excl = 0;
       if (part > 0) {
+        // look back over a window of up to kLookWin predecessors at a time:
+        // their flags are loaded together, then the window is consumed up to
+        // the nearest inclusive prefix (or entirely, if it holds only
+        // aggregates); a window with a not-yet-published entry before that
+        // point is loaded again
         int64_t p = (int64_t)part - 1;
         while (true) {
-          const uint32_t sv = ld_relaxed(lookback + (size_t)p * R + d);
-          if ((sv & ~kValMask) == 0u) {
+          uint32_t w[kLookWin];
+#pragma unroll
+          for (int h = 0; h < kLookWin; ++h)
+            w[h] = (p - h >= 0) ? ld_relaxed(lookback + (size_t)(p - h) * R + d) : kFlagPre;
+          uint32_t sum = 0;
+          int state = 0;  // 0 all aggregates, 1 prefix reached, 2 must wait
+#pragma unroll
+          for (int h = 0; h < kLookWin; ++h) {
+            if (state == 0) {
+              if ((w[h] & ~kValMask) == 0u) {
+                state = 2;
+              } else {
+                sum += w[h] & kValMask;
+                if (w[h] & kFlagPre) state = 1;
+              }
+            }
+          }
+          if (state == 2) {
             __builtin_amdgcn_s_sleep(1);
             continue;
           }
-          excl += sv & kValMask;
-          if (sv & kFlagPre) break;
-          --p;
+          excl += sum;
+          if (state == 1) break;
+          p -= kLookWin;
         }
         st_relaxed(lookback + (size_t)part * R + d, kFlagPre | (excl + run[i]));
       }
@@ -254,6 +276,72 @@ __global__ void k_view_info(const gs_camera* __restrict__ cams, int V, uint32_t*
   seg_base[V] = acc;
 }
 
+// Range of the depth bits of the visible (view, Gaussian) pairs and their
+// total instance count: stats = {min bits, max bits, count lo, count hi}.
+__global__ __launch_bounds__(kBlock) void k_depth_range(int n, int ld, int V,
+                                                        const uint32_t* __restrict__ depth_bits,
+                                                        const int32_t* __restrict__ tiles,
+                                                        uint32_t* __restrict__ stats) {
+  __shared__ uint32_t s_min[4], s_max[4];
+  __shared__ unsigned long long s_sum[4];
+  uint32_t mn = 0xFFFFFFFFu, mx = 0u;
+  unsigned long long sum = 0;
+  const uint32_t N = (uint32_t)n * (uint32_t)V;
+  for (uint32_t j = blockIdx.x * kBlock + threadIdx.x; j < N; j += gridDim.x * kBlock) {
+    const uint32_t v = j / (uint32_t)n, i = j - v * (uint32_t)n;
+    const size_t r = (size_t)v * ld + i;
+    const int t = tiles[r];
+    if (t > 0) {
+      const uint32_t d = depth_bits[r];
+      mn = min(mn, d);
+      mx = max(mx, d);
+      sum += (unsigned long long)t;
+    }
+  }
+  for (int off = 32; off >= 1; off >>= 1) {
+    mn = min(mn, (uint32_t)__shfl_xor((int)mn, off, 64));
+    mx = max(mx, (uint32_t)__shfl_xor((int)mx, off, 64));
+    sum += __shfl_xor(sum, off, 64);
+  }
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0) {
+    s_min[wave] = mn;
+    s_max[wave] = mx;
+    s_sum[wave] = sum;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    mn = min(min(s_min[0], s_min[1]), min(s_min[2], s_min[3]));
+    mx = max(max(s_max[0], s_max[1]), max(s_max[2], s_max[3]));
+    sum = (s_sum[0] + s_sum[1]) + (s_sum[2] + s_sum[3]);
+    atomicMin(stats + 0, mn);
+    atomicMax(stats + 1, mx);
+    atomicAdd(reinterpret_cast<unsigned long long*>(stats + 2), sum);
+  }
+}
+
+// 32-bit (view, depth) keys when they fit: view * span + (bits - min bits),
+// culled pairs at span - 1 (last in their view).
+__global__ __launch_bounds__(kBlock) void k_depth_keys32(int n, int ld, int V,
+                                                         const uint32_t* __restrict__ depth_bits,
+                                                         const int32_t* __restrict__ tiles,
+                                                         uint32_t dmin, uint32_t span,
+                                                         uint32_t* __restrict__ keys,
+                                                         uint32_t* __restrict__ vals) {
+  const uint32_t j = blockIdx.x * kBlock + threadIdx.x;
+  if (j >= (uint32_t)n * (uint32_t)V) return;
+  const uint32_t v = j / (uint32_t)n, i = j - v * (uint32_t)n;
+  const size_t r = (size_t)v * ld + i;
+  const uint32_t rel = tiles[r] > 0 ? depth_bits[r] - dmin : span - 1u;
+  keys[j] = v * span + rel;
+  vals[j] = i;
+}
+
+// View of a depth-sorted key: the high word of a 64-bit key, key / span of
+// a 32-bit one.
+__device__ __forceinline__ uint32_t view_of(uint64_t key, uint32_t) { return (uint32_t)(key >> 32); }
+__device__ __forceinline__ uint32_t view_of(uint32_t key, uint32_t span) { return key / span; }
+
 // (view, depth) keys of every (view, Gaussian); culled ones sort last.
 __global__ __launch_bounds__(kBlock) void k_depth_keys(int n, int ld, int V,
                                                        const uint32_t* __restrict__ depth_bits,
@@ -270,8 +358,9 @@ __global__ __launch_bounds__(kBlock) void k_depth_keys(int n, int ld, int V,
 }
 
 // Instance count of each depth-sorted entry, and partial sums per chunk.
-__global__ __launch_bounds__(kBlock) void k_count_reduce(uint32_t N, int ld,
-                                                         const uint64_t* __restrict__ keys,
+template <typename K>
+__global__ __launch_bounds__(kBlock) void k_count_reduce(uint32_t N, int ld, uint32_t span,
+                                                         const K* __restrict__ keys,
                                                          const uint32_t* __restrict__ vals,
                                                          const int32_t* __restrict__ tiles,
                                                          uint32_t* __restrict__ cnt,
@@ -282,7 +371,7 @@ __global__ __launch_bounds__(kBlock) void k_count_reduce(uint32_t N, int ld,
   for (int j = 0; j < kItems; ++j) {
     const uint32_t e = c0 + j * kBlock + threadIdx.x;
     if (e < N) {
-      const uint32_t v = (uint32_t)(keys[e] >> 32);
+      const uint32_t v = view_of(keys[e], span);
       const uint32_t c = (uint32_t)tiles[(size_t)v * ld + vals[e]];
       cnt[e] = c;
       acc += c;
@@ -333,9 +422,13 @@ __global__ __launch_bounds__(kBlock) void k_count_scan(uint32_t N, const uint32_
 
 // Emit (segment, Gaussian id) for each tile of each depth-sorted entry, row
 // by row over its tile rectangle; optionally record where each (view,
-// Gaussian) starts in this order.
-__global__ __launch_bounds__(kBlock) void k_emit(uint32_t N, int ld,
-                                                 const uint64_t* __restrict__ keys,
+// Gaussian) starts in this order.  Each wave takes 64 consecutive entries,
+// whose instances form one contiguous output range, and spreads that range
+// over its lanes (instance f on lane f mod 64), so that large and small
+// rectangles balance and the stores coalesce.
+template <typename K>
+__global__ __launch_bounds__(kBlock) void k_emit(uint32_t N, int ld, uint32_t span,
+                                                 const K* __restrict__ keys,
                                                  const uint32_t* __restrict__ vals,
                                                  const uint32_t* __restrict__ cnt,
                                                  const uint32_t* __restrict__ offs,
@@ -345,20 +438,49 @@ __global__ __launch_bounds__(kBlock) void k_emit(uint32_t N, int ld,
                                                  uint32_t* __restrict__ seg_out,
                                                  uint32_t* __restrict__ id_out,
                                                  uint32_t* __restrict__ gv_base) {
+  __shared__ uint32_t s_pre[4][64];
+  __shared__ uint32_t s_seg0[4][64];  // segment of the rectangle's first tile
+  __shared__ uint32_t s_id[4][64];
+  __shared__ uint32_t s_w[4][64];     // rectangle width in tiles
+  __shared__ uint32_t s_row[4][64];   // tiles per view row
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const uint32_t e = blockIdx.x * kBlock + threadIdx.x;
-  if (e >= N || cnt[e] == 0) return;
-  const uint32_t v = (uint32_t)(keys[e] >> 32), g = vals[e];
-  const int4 r = rect[(size_t)v * ld + g];
-  const uint32_t sb = seg_base[v];
-  const int tx = txv[v];
-  uint32_t o = offs[e];
-  if (gv_base) gv_base[(size_t)v * ld + g] = o;
-  for (int ty = r.y; ty < r.w; ++ty)
-    for (int x = r.x; x < r.z; ++x) {
-      seg_out[o] = sb + (uint32_t)(ty * tx + x);
-      id_out[o] = g;
-      ++o;
+  uint32_t c = 0, o0 = 0;
+  if (e < N) {
+    c = cnt[e];
+    o0 = offs[e];
+    if (c > 0) {
+      const uint32_t v = view_of(keys[e], span), g = vals[e];
+      const int4 r = rect[(size_t)v * ld + g];
+      const int tx = txv[v];
+      s_seg0[wave][lane] = seg_base[v] + (uint32_t)(r.y * tx + r.x);
+      s_id[wave][lane] = g;
+      s_w[wave][lane] = (uint32_t)(r.z - r.x);
+      s_row[wave][lane] = (uint32_t)tx;
+      if (gv_base) gv_base[(size_t)v * ld + g] = o0;
     }
+  }
+  // the wave's entries own output [first, first + total)
+  uint32_t incl = c;
+  for (int off = 1; off < 64; off <<= 1) {
+    const uint32_t y = __shfl_up(incl, off, 64);
+    if (lane >= off) incl += y;
+  }
+  const uint32_t total = __shfl(incl, 63, 64);
+  const uint32_t first = __shfl(o0, 0, 64);
+  s_pre[wave][lane] = incl - c;
+  __syncthreads();
+  for (uint32_t f = lane; f < total; f += 64) {
+    int q = 0;  // last entry whose first instance is <= f (it has one)
+#pragma unroll
+    for (int step = 32; step >= 1; step >>= 1)
+      if (s_pre[wave][q + step] <= f) q += step;
+    const uint32_t l = f - s_pre[wave][q];
+    const uint32_t w = s_w[wave][q];
+    const uint32_t dy = l / w, dx = l - dy * w;
+    seg_out[first + f] = s_seg0[wave][q] + dy * s_row[wave][q] + dx;
+    id_out[first + f] = s_id[wave][q];
+  }
 }
 
 __global__ __launch_bounds__(kBlock) void k_ranges(uint32_t M, const uint32_t* __restrict__ seg,
@@ -385,6 +507,15 @@ __global__ __launch_bounds__(kBlock) void k_keys64(uint32_t M, int V, int ld,
     if (seg_base[mid] <= s) lo = mid; else hi = mid - 1;
   }
   keys[j] = ((uint64_t)s << 32) | depth_bits[(size_t)lo * ld + ids[j]];
+}
+
+__global__ void k_stats_init(uint32_t* stats) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    stats[0] = 0xFFFFFFFFu;
+    stats[1] = 0u;
+    stats[2] = 0u;
+    stats[3] = 0u;
+  }
 }
 
 __global__ void k_fill_u32(uint32_t* p, uint32_t value, size_t count) {
@@ -427,7 +558,7 @@ inline uint32_t cdiv(uint64_t a, uint64_t b) { return (uint32_t)((a + b - 1) / b
 
 struct Layout {
   size_t dk0, dk1, dv0, dv1, cnt, offs, chunks, segk0, segk1, segv_alt, hist, digoff, counters,
-      lookback, seg_base, txv, total, bytes;
+      lookback, seg_base, txv, total, stats, bytes;
 };
 
 Layout make_layout(int V, int ld, int64_t cap, int64_t nseg) {
@@ -460,6 +591,7 @@ Layout make_layout(int V, int ld, int64_t cap, int64_t nseg) {
   L.seg_base = take(((size_t)V + 1) * 4);
   L.txv = take((size_t)V * 4);
   L.total = take(16);
+  L.stats = take(16);
   L.bytes = o;
   return L;
 }
@@ -533,55 +665,73 @@ size_t bin_sort_workspace_bytes(int V, int ld, int64_t cap, int64_t nseg) {
 
 hipError_t bin_sort_stage1(const BinSortPlan& p, const gs_projected& proj,
                            const gs_camera* cams_dev, void* ws, hipStream_t s,
-                           uint32_t** d_count) {
+                           uint32_t** d_stats) {
   const Layout L = make_layout(p.n_views, p.ld, p.capacity, p.n_segments);
   const uint32_t N = (uint32_t)p.n_views * (uint32_t)p.n;
-  uint32_t* total = at<uint32_t>(ws, L.total);
-  *d_count = total;
+  uint32_t* stats = at<uint32_t>(ws, L.stats);
+  *d_stats = stats;
   hipLaunchKernelGGL(k_view_info, dim3(1), dim3(64), 0, s, cams_dev, p.n_views,
                      at<uint32_t>(ws, L.seg_base), at<int32_t>(ws, L.txv));
-  if (N == 0) {
-    launch_fill_u32(total, 0u, 1, s);
-    return hipGetLastError();
-  }
-  uint64_t* dk0 = at<uint64_t>(ws, L.dk0);
-  uint64_t* dk1 = at<uint64_t>(ws, L.dk1);
+  hipLaunchKernelGGL(k_stats_init, dim3(1), dim3(1), 0, s, stats);
+  if (N == 0) return hipGetLastError();
+  StageScope scope(kStDepthSort, s);
+  const uint32_t blocks = std::min<uint32_t>(cdiv(N, kBlock), 1024u);
+  hipLaunchKernelGGL(k_depth_range, dim3(blocks), dim3(kBlock), 0, s, p.n, p.ld, p.n_views,
+                     proj.depth_bits, proj.tiles_touched, stats);
+  return hipGetLastError();
+}
+
+namespace {
+// Depth sort of the (view, Gaussian) pairs with keys K, instance offsets and
+// emission into (segk0, v0); span is the 32-bit key's per-view range.
+template <typename K>
+void depth_count_emit(const BinSortPlan& p, const gs_projected& proj, const Layout& L, void* ws,
+                      uint32_t N, uint32_t dmin, uint32_t span, int bits, uint32_t* segk0,
+                      uint32_t* v0, uint32_t* gv_base, hipStream_t s) {
+  K* k0 = at<K>(ws, L.dk0);
+  K* k1 = at<K>(ws, L.dk1);
   uint32_t* dv0 = at<uint32_t>(ws, L.dv0);
   uint32_t* dv1 = at<uint32_t>(ws, L.dv1);
-  const int dbits = depth_key_bits(p.n_views);
   int which;
   {
     StageScope scope(kStDepthSort, s);
-    hipLaunchKernelGGL(k_depth_keys, dim3(cdiv(N, kBlock)), dim3(kBlock), 0, s, p.n, p.ld,
-                       p.n_views, proj.depth_bits, proj.tiles_touched, dk0, dv0);
-    which = radix_sort<uint64_t>(dk0, dk1, dv0, dv1, N, dbits, ws, L, s);
+    if constexpr (sizeof(K) == 4)
+      hipLaunchKernelGGL(k_depth_keys32, dim3(cdiv(N, kBlock)), dim3(kBlock), 0, s, p.n, p.ld,
+                         p.n_views, proj.depth_bits, proj.tiles_touched, dmin, span, k0, dv0);
+    else
+      hipLaunchKernelGGL(k_depth_keys, dim3(cdiv(N, kBlock)), dim3(kBlock), 0, s, p.n, p.ld,
+                         p.n_views, proj.depth_bits, proj.tiles_touched, k0, dv0);
+    which = radix_sort<K>(k0, k1, dv0, dv1, N, bits, ws, L, s);
   }
-  const uint64_t* sk = which ? dk1 : dk0;
+  const K* sk = which ? k1 : k0;
   const uint32_t* sv = which ? dv1 : dv0;
   uint32_t* cnt = at<uint32_t>(ws, L.cnt);
   uint32_t* chunks = at<uint32_t>(ws, L.chunks);
   const uint32_t nch = cdiv(N, kPart);
-  StageScope scope(kStCountScan, s);
-  hipLaunchKernelGGL(k_count_reduce, dim3(nch), dim3(kBlock), 0, s, N, p.ld, sk, sv,
-                     proj.tiles_touched, cnt, chunks);
-  hipLaunchKernelGGL(k_chunk_scan, dim3(1), dim3(kBlock), 0, s, chunks, nch, total);
-  hipLaunchKernelGGL(k_count_scan, dim3(nch), dim3(kBlock), 0, s, N, cnt, chunks,
-                     at<uint32_t>(ws, L.offs));
-  return hipGetLastError();
+  {
+    StageScope scope(kStCountScan, s);
+    hipLaunchKernelGGL((k_count_reduce<K>), dim3(nch), dim3(kBlock), 0, s, N, p.ld, span, sk, sv,
+                       proj.tiles_touched, cnt, chunks);
+    hipLaunchKernelGGL(k_chunk_scan, dim3(1), dim3(kBlock), 0, s, chunks, nch,
+                       at<uint32_t>(ws, L.total));
+    hipLaunchKernelGGL(k_count_scan, dim3(nch), dim3(kBlock), 0, s, N, cnt, chunks,
+                       at<uint32_t>(ws, L.offs));
+  }
+  StageScope scope(kStEmit, s);
+  hipLaunchKernelGGL((k_emit<K>), dim3(cdiv(N, kBlock)), dim3(kBlock), 0, s, N, p.ld, span, sk,
+                     sv, cnt, at<uint32_t>(ws, L.offs), reinterpret_cast<const int4*>(proj.rect),
+                     at<uint32_t>(ws, L.seg_base), at<int32_t>(ws, L.txv), segk0, v0, gv_base);
 }
+}  // namespace
 
 hipError_t bin_sort_stage2(const BinSortPlan& p, const gs_projected& proj,
-                           const gs_camera* cams_dev, uint32_t M, gs_tile_lists& lists, void* ws,
-                           hipStream_t s) {
+                           const gs_camera* cams_dev, uint32_t M, uint32_t dmin, uint32_t dmax,
+                           gs_tile_lists& lists, void* ws, hipStream_t s) {
   (void)cams_dev;
   const Layout L = make_layout(p.n_views, p.ld, p.capacity, p.n_segments);
   const uint32_t N = (uint32_t)p.n_views * (uint32_t)p.n;
   launch_fill_u32(lists.ranges, 0u, 2 * p.n_segments, s);
   if (M == 0) return hipGetLastError();
-  // The depth sort's pass count is known on the host, so is its result buffer.
-  const int which = plan_digits(depth_key_bits(p.n_views)).passes & 1;
-  const uint64_t* sk = which ? at<uint64_t>(ws, L.dk1) : at<uint64_t>(ws, L.dk0);
-  const uint32_t* sv = which ? at<uint32_t>(ws, L.dv1) : at<uint32_t>(ws, L.dv0);
   const int sbits = bits_for((uint64_t)p.n_segments);
   const int spasses = plan_digits(sbits).passes;
   uint32_t* segk0 = at<uint32_t>(ws, L.segk0);
@@ -590,13 +740,16 @@ hipError_t bin_sort_stage2(const BinSortPlan& p, const gs_projected& proj,
   // emit into the buffer that makes the sorted ids land in lists.vals
   uint32_t* v0 = (spasses & 1) ? alt : lists.vals;
   uint32_t* v1 = (spasses & 1) ? lists.vals : alt;
-  {
-    StageScope scope(kStEmit, s);
-    hipLaunchKernelGGL(k_emit, dim3(cdiv(N, kBlock)), dim3(kBlock), 0, s, N, p.ld, sk, sv,
-                       at<uint32_t>(ws, L.cnt), at<uint32_t>(ws, L.offs),
-                       reinterpret_cast<const int4*>(proj.rect), at<uint32_t>(ws, L.seg_base),
-                       at<int32_t>(ws, L.txv), segk0, v0, lists.gv_base);
-  }
+  // (view, depth) keys fit 32 bits when the views times the visible depth
+  // bit range (plus one slot for culled pairs) do
+  const uint64_t span = (uint64_t)dmax - (uint64_t)dmin + 2u;
+  const uint64_t range = (uint64_t)p.n_views * span;
+  if (dmax >= dmin && range <= ((uint64_t)1 << 32))
+    depth_count_emit<uint32_t>(p, proj, L, ws, N, dmin, (uint32_t)span, bits_for(range), segk0,
+                               v0, lists.gv_base, s);
+  else
+    depth_count_emit<uint64_t>(p, proj, L, ws, N, 0u, 1u, depth_key_bits(p.n_views), segk0, v0,
+                               lists.gv_base, s);
   int which2;
   {
     StageScope scope(kStSegmentSort, s);
