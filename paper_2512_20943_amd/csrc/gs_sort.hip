@@ -21,7 +21,7 @@ namespace gs {
 namespace {
 
 constexpr int kBlock = 256;
-constexpr int kItems = 16;
+constexpr int kItems = 32;
 constexpr int kPart = kBlock * kItems;  // keys per onesweep partition
 constexpr uint32_t kFlagAgg = 1u << 30;
 constexpr uint32_t kFlagPre = 2u << 30;
