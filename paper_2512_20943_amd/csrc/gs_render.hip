@@ -395,7 +395,9 @@ __global__ __launch_bounds__(64) void k_render_bwd(
 
   const int x0 = tx * kTile + (lane & 7), y0 = ty * kTile + (lane >> 3);
   const float fx0 = (float)x0, fy0 = (float)y0;
-  float T[4], g0[4], g1[4], g2[4], B0[4], B1[4], B2[4];
+  // S[w] = dL/dcolour . B, B the colour composited behind the current entry
+  // (background included): only this dot product enters dL/dalpha
+  float T[4], g0[4], g1[4], g2[4], S[4];
   int nc[4], wmax[4];
   int jmax = 0;
 #pragma unroll
@@ -412,9 +414,7 @@ __global__ __launch_bounds__(64) void k_render_bwd(
       g1[w] = gi[pix + p];
       g2[w] = gi[2 * pix + p];
     }
-    B0[w] = bg0;
-    B1[w] = bg1;
-    B2[w] = bg2;
+    S[w] = g0[w] * bg0 + g1[w] * bg1 + g2[w] * bg2;
     wmax[w] = __builtin_amdgcn_readfirstlane(wave_max(nc[w]));
     jmax = max(jmax, wmax[w]);
   }
@@ -471,10 +471,9 @@ __global__ __launch_bounds__(64) void k_render_bwd(
           gr[6] = fmaf(g0[w], wt, gr[6]);
           gr[7] = fmaf(g1[w], wt, gr[7]);
           gr[8] = fmaf(g2[w], wt, gr[8]);
-          const float dc0 = b.z - B0[w], dc1 = b.w - B1[w], dc2 = c.x - B2[w];
-          const float da = (use && ea < kAlphaMax)
-                               ? Tk * (g0[w] * dc0 + g1[w] * dc1 + g2[w] * dc2)
-                               : 0.f;
+          // g . (c - B) with B updated as B + au (c - B)
+          const float gcb = fmaf(g2[w], c.x, fmaf(g1[w], b.w, g0[w] * b.z)) - S[w];
+          const float da = (use && ea < kAlphaMax) ? Tk * gcb : 0.f;
           // moments of dL/dpower: the conic and mean gradients are linear in
           // them with per-entry coefficients, applied once per entry at flush
           const float gp = da * alpha;
@@ -485,9 +484,7 @@ __global__ __launch_bounds__(64) void k_render_bwd(
           gr[3] = fmaf(u, dy, gr[3]);
           gr[4] = fmaf(vv, dy, gr[4]);
           gr[5] = fmaf(da, ea, gr[5]);  // times 1/opacity at flush
-          B0[w] = fmaf(au, dc0, B0[w]);
-          B1[w] = fmaf(au, dc1, B1[w]);
-          B2[w] = fmaf(au, dc2, B2[w]);
+          S[w] = fmaf(au, gcb, S[w]);
           T[w] = Tk;
           contrib = contrib || use;
         }
@@ -656,9 +653,11 @@ void launch_render_batched(const gs_projected& proj, const gs_tile_lists& lists,
   int64_t* pix_base = reinterpret_cast<int64_t*>(w);
   w += 256 * ((((size_t)V + 1) * 8 + 255) / 256);
   int2* wh = reinterpret_cast<int2*>(w);
-  int dev = 0, cus = 256;
-  hipGetDevice(&dev);
-  hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      cus <= 0)
+    cus = 256;  // the grid size only tunes occupancy; the queue drains either way
   const int64_t want = (int64_t)cus * 16;
   const int blocks = (int)(total_segments < want ? total_segments : want);
   StageScope scope(kStRenderFwd, s);
