@@ -188,6 +188,30 @@ def test_render_backward_parity(which):
         assert_grad_close(got, gr_or[name][..., :n], name)
 
 
+def test_render_backward_parity_with_background():
+    """A non-black background enters dL/dalpha through the colour
+    composited behind each entry; the oracle keeps that colour, the kernel
+    only its dot product with dL/dcolour."""
+    require_gpu()
+    bg = (0.25, 0.5, 0.75)
+    scene, cams = small_frame_workload(6)
+    g, gc, r, out = gpu_forward(scene, cams, bg)
+    P_or, L_or, img_or = oracle.forward(scene, cams, bg)
+    rng = np.random.default_rng(17)
+    _, gI = oracle.l1(img_or["image"], rng.uniform(0, 1, size=img_or["image"].shape))
+    gI[np.broadcast_to(img_or["near_threshold"][:, None], gI.shape)] = 0.0
+    g2d_or, gr_or = oracle.backward(scene, cams, P_or, L_or, gI, bg)
+    grad = gs.Gaussians.zeros_like(g)
+    ws = r.backward(g, gc, out, torch.from_numpy(gI.astype(np.float32)).cuda(), grad, bg)
+    torch.cuda.synchronize()
+    n = scene["n"]
+    g2d = ws.view(torch.float32)[: gc.V * g.ld * 12].view(gc.V, g.ld, 12)[:, :n, :9].cpu().numpy()
+    assert_grad_close(g2d, g2d_or, "screen-space gradients")
+    for name in ("mean", "opacity", "sh"):
+        got = getattr(grad, name).cpu().numpy()[..., :n]
+        assert_grad_close(got, gr_or[name][..., :n], name)
+
+
 def test_frame_update_gradient_parity():
     """Backward to the (8, gh, gw) delta images on the 2,000-Gaussian, 64x64
     subset of the temporal frame-update workload."""
