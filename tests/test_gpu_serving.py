@@ -79,3 +79,28 @@ def test_tiny_hbm_budget_serialises_but_completes(seq):
     server.run(trace)
     assert all(np.isfinite(r.t_done) for r in trace)
     assert max(server.batches) <= 2
+
+
+def test_serving_4k_requests_on_the_2m_scene():
+    """Two 3840x2160 requests on a two-frame sequence of the 2M-Gaussian
+    anchor: the batched launch equals the plain renderer bit for bit, and one
+    served image matches the oracle."""
+    require_gpu()
+    anchor = scenes.make_scene(2_000_000, 0, -6.0, 6.0, -4.5, 0.7, 3)
+    s = serve.ResidentSequence(anchor, 2, seed=5)
+    g = scenes.rng(41)
+    reqs = [serve.Request(k, k, scenes.sphere_camera(g, 4.0, 6.0, 3840, 2160), 0.0)
+            for k in range(2)]
+    w = serve.BatchWorker(s)
+    _, imgs = w.render(reqs)
+    imgs = [m.clone() for m in imgs]
+    plain = serve.PlainRenderer(s)
+    for r, m in zip(reqs, imgs):
+        assert torch.equal(plain.render(r), m), f"request {r.rid} differs plain vs batched"
+    d, m = s.frame_inputs(reqs[0].frame)
+    frame = oracle.apply(anchor, d, m, s.gw, s.gh)
+    _, _, ref = oracle.forward(frame, scenes.stack_cams([reqs[0].cam]))
+    keep = ~ref["near_threshold"][0]
+    err = np.abs(imgs[0].cpu().numpy() - ref["image"][0]).max(axis=0)[keep].max()
+    say(f"  4K request 0: max image error {err:.2e}, {int((~keep).sum())} near-threshold px")
+    assert err <= IMG_ATOL
