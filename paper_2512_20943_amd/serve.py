@@ -238,70 +238,86 @@ class Server:
         return request_bytes(r, self.seq.anchor.ld, ipt)
 
     def run(self, trace: list[Request], clock_start: float | None = None):
-        """Serve ``trace`` in real time; fills each request's t_done."""
+        """Serve ``trace`` in real time; fills each request's t_done.  One
+        long-lived thread per worker takes batches from its inbox, so a batch
+        starts without a thread being created for it."""
         t0 = time.perf_counter() if clock_start is None else clock_start
         pending = collections.deque()
         free = collections.deque(self.workers)
+        inbox = {id(w): collections.deque() for w in self.workers}
+        stop = [False]
         next_idx = 0
-        n_done = 0
         done_count = [0]
 
-        def work(worker, batch, nbytes):
-            try:
-                _, imgs = worker.render(batch)
-                now = time.perf_counter() - t0
-                for r, im in zip(batch, imgs):
-                    r.t_done = now
-                    if self.keep_images:
-                        r.image = im.clone()
-            except Exception as e:  # noqa: BLE001 - reported after the run
-                self.errors.append(e)
-                for r in batch:
-                    r.t_done = math.inf
-            with self.lock:
-                self.in_flight_bytes -= nbytes
-                free.append(worker)
-                done_count[0] += len(batch)
-                self.lock.notify_all()
+        def serve_loop(worker):
+            box = inbox[id(worker)]
+            while True:
+                with self.lock:
+                    while not box and not stop[0]:
+                        self.lock.wait()
+                    if not box:
+                        return
+                    batch, nbytes = box.popleft()
+                try:
+                    _, imgs = worker.render(batch)
+                    now = time.perf_counter() - t0
+                    for r, im in zip(batch, imgs):
+                        r.t_done = now
+                        if self.keep_images:
+                            r.image = im.clone()
+                except Exception as e:  # noqa: BLE001 - reported after the run
+                    self.errors.append(e)
+                    for r in batch:
+                        r.t_done = math.inf
+                with self.lock:
+                    self.in_flight_bytes -= nbytes
+                    free.append(worker)
+                    done_count[0] += len(batch)
+                    self.lock.notify_all()
 
-        threads = []
-        while True:
-            with self.lock:
-                now = time.perf_counter() - t0
-                while next_idx < len(trace) and trace[next_idx].arrival <= now:
-                    pending.append(trace[next_idx])
-                    next_idx += 1
-                n_done = done_count[0]
-                if n_done >= len(trace):
-                    break
-                launched = False
-                if pending and free:
-                    batch, nbytes = [], 0
-                    while pending and len(batch) < self.max_batch:
-                        need = self._estimate(pending[0])
-                        if self.in_flight_bytes + nbytes + need > self.budget and (
-                                batch or self.in_flight_bytes > 0):
-                            break
-                        batch.append(pending.popleft())
-                        nbytes += need
-                    if batch:
-                        worker = free.popleft()
-                        self.in_flight_bytes += nbytes
-                        self.max_in_flight_bytes = max(self.max_in_flight_bytes,
-                                                       self.in_flight_bytes)
-                        self.batches.append(len(batch))
-                        th = threading.Thread(target=work, args=(worker, batch, nbytes),
-                                              daemon=True)
-                        th.start()
-                        threads.append(th)
-                        launched = True
-                if not launched:
-                    wait = 0.05
-                    if next_idx < len(trace):
-                        wait = min(wait, max(trace[next_idx].arrival - now, 0.0))
-                    self.lock.wait(timeout=wait if wait > 0 else 0.0005)
+        threads = [threading.Thread(target=serve_loop, args=(w,), daemon=True)
+                   for w in self.workers]
         for th in threads:
-            th.join()
+            th.start()
+        try:
+            while True:
+                with self.lock:
+                    now = time.perf_counter() - t0
+                    while next_idx < len(trace) and trace[next_idx].arrival <= now:
+                        pending.append(trace[next_idx])
+                        next_idx += 1
+                    if done_count[0] >= len(trace):
+                        break
+                    launched = False
+                    if pending and free:
+                        batch, nbytes = [], 0
+                        while pending and len(batch) < self.max_batch:
+                            need = self._estimate(pending[0])
+                            if self.in_flight_bytes + nbytes + need > self.budget and (
+                                    batch or self.in_flight_bytes > 0):
+                                break
+                            batch.append(pending.popleft())
+                            nbytes += need
+                        if batch:
+                            worker = free.popleft()
+                            self.in_flight_bytes += nbytes
+                            self.max_in_flight_bytes = max(self.max_in_flight_bytes,
+                                                           self.in_flight_bytes)
+                            self.batches.append(len(batch))
+                            inbox[id(worker)].append((batch, nbytes))
+                            self.lock.notify_all()
+                            launched = True
+                    if not launched:
+                        wait = 0.05
+                        if next_idx < len(trace):
+                            wait = min(wait, max(trace[next_idx].arrival - now, 0.0))
+                        self.lock.wait(timeout=wait if wait > 0 else 0.0005)
+        finally:
+            with self.lock:
+                stop[0] = True
+                self.lock.notify_all()
+            for th in threads:
+                th.join()
         if self.errors:
             raise self.errors[0]
         return trace
