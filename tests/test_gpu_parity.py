@@ -561,3 +561,29 @@ def test_large_2m_backward_sparse_tiles():
     assert_grad_close(g2d, g2d_or, "screen-space gradients, views 0-1")
     for name in ("mean", "log_scale", "quat", "opacity", "sh"):
         assert_grad_close(getattr(grad, name).cpu().numpy()[..., :n], gr_or[name][..., :n], name)
+
+
+def test_lists_bit_exact_with_a_depth_range_beyond_32_bit_keys():
+    """Gaussians from z = 3 to z = 1e9 seen by 20 views: views times the
+    depth-bit range exceed 2^32, so the binning sorts 64-bit (view, depth)
+    keys; lists and keys stay bit-exact against the oracle."""
+    require_gpu()
+    base = scenes.subset(scenes.make_scene(10_000, 7, -1.0, 1.0, -4.0, 0.5, 0), 2000)
+    far = [(0.0, 0.0, 1e9), (2e7, 1e7, 1e9), (-3e7, 0.0, 5e8), (0.0, 0.0, 2e9)]
+    sc = {k: (v.copy() if isinstance(v, np.ndarray) else v) for k, v in base.items()}
+    for j, (x, y, z) in enumerate(far):
+        sc["mean"][:, j] = (x, y, z)
+        sc["log_scale"][:, j] = np.log(1e6)
+        sc["opacity"][j] = 3.0
+    one = scenes.axis_camera(64, 48, 4.0)
+    cams = {k: np.concatenate([v] * 20) for k, v in one.items()}
+    g, gc, r, out = gpu_forward(sc, cams)
+    P_or = oracle.project(sc, cams)
+    db = P_or["depth_bits"][P_or["tiles"] > 0]
+    assert 20 * (int(db.max()) - int(db.min()) + 2) > 2 ** 32
+    L_or = oracle.bin_sort(P_or, cams)
+    L_g = lists_to_numpy(out["lists"])
+    assert L_g["count"] == L_or["count"] > 0
+    np.testing.assert_array_equal(L_g["keys"], L_or["keys"])
+    np.testing.assert_array_equal(L_g["vals"], L_or["vals"])
+    np.testing.assert_array_equal(L_g["ranges"], L_or["ranges"])
