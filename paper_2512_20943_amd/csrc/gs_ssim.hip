@@ -23,6 +23,8 @@ namespace {
 constexpr int kR = 5;             // window radius
 constexpr int kT = 32;            // output tile side
 constexpr int kI = kT + 2 * kR;   // staged footprint side (42)
+constexpr int kIP = kI + 1;       // padded LDS row stride of the staged input
+constexpr int kTP = kT + 1;       // padded LDS row stride of the horizontal sums
 constexpr int kSeg = 8;           // columns per thread in the horizontal pass
 constexpr int kRows = 4;          // output rows per thread in the vertical pass
 constexpr float kC1 = 0.01f * 0.01f, kC2 = 0.03f * 0.03f;
@@ -31,17 +33,32 @@ struct Window {
   float w[2 * kR + 1];
 };
 
-// Stage a kI x kI footprint of NP planes with zero padding.
+// Stage a kI x kI footprint of NP planes with zero padding.  Every thread
+// issues all of its global loads before its first LDS store, so the loads of
+// one workgroup are in flight together.
 template <int NP>
-__device__ __forceinline__ void stage(float (*dst)[kI][kI], const float* const* src, int W, int H,
+__device__ __forceinline__ void stage(float (*dst)[kI][kIP], const float* const* src, int W, int H,
                                       int x0, int y0) {
-  for (int t = threadIdx.x; t < kI * kI; t += blockDim.x) {
+  constexpr int kPer = (kI * kI + 255) / 256;
+  float v[NP][kPer];
+#pragma unroll
+  for (int u = 0; u < kPer; ++u) {
+    const int t = threadIdx.x + u * 256;
     const int r = t / kI, c = t - r * kI;
     const int yy = y0 + r - kR, xx = x0 + c - kR;
-    const bool in = yy >= 0 && yy < H && xx >= 0 && xx < W;
-    const size_t p = (size_t)yy * W + xx;
+    const bool in = t < kI * kI && yy >= 0 && yy < H && xx >= 0 && xx < W;
+    const size_t p = in ? (size_t)yy * W + xx : 0;
 #pragma unroll
-    for (int q = 0; q < NP; ++q) dst[q][r][c] = in ? src[q][p] : 0.f;
+    for (int q = 0; q < NP; ++q) v[q][u] = in ? src[q][p] : 0.f;
+  }
+#pragma unroll
+  for (int u = 0; u < kPer; ++u) {
+    const int t = threadIdx.x + u * 256;
+    if (t < kI * kI) {
+      const int r = t / kI, c = t - r * kI;
+#pragma unroll
+      for (int q = 0; q < NP; ++q) dst[q][r][c] = v[q][u];
+    }
   }
 }
 
@@ -49,11 +66,13 @@ __device__ __forceinline__ void stage(float (*dst)[kI][kI], const float* const* 
 // columns per work item (kI rows x kT/kSeg segments), sliding in registers.
 // F maps the NP staged planes at one position to NS statistics.
 template <int NP, int NS, typename F>
-__device__ __forceinline__ void hpass(const float (*in)[kI][kI], float (*out)[kI][kT],
+__device__ __forceinline__ void hpass(const float (*in)[kI][kIP], float (*out)[kI][kTP],
                                       const Window& win, F stat) {
   constexpr int kItems = kI * (kT / kSeg);
   for (int t = threadIdx.x; t < kItems; t += blockDim.x) {
-    const int r = t / (kT / kSeg), c0 = (t - r * (kT / kSeg)) * kSeg;
+    // consecutive threads take consecutive rows (with the padded strides
+    // their LDS accesses fall into different banks)
+    const int seg = t / kI, r = t - seg * kI, c0 = seg * kSeg;
     float acc[kSeg][NS];
 #pragma unroll
     for (int o = 0; o < kSeg; ++o)
@@ -84,7 +103,7 @@ __device__ __forceinline__ void hpass(const float (*in)[kI][kI], float (*out)[kI
 
 // Vertical window: thread (c, g) produces rows 4g..4g+3 of column c.
 template <int NS>
-__device__ __forceinline__ void vpass(const float (*h)[kI][kT], const Window& win, int c, int g,
+__device__ __forceinline__ void vpass(const float (*h)[kI][kTP], const Window& win, int c, int g,
                                       float (*res)[NS]) {
 #pragma unroll
   for (int o = 0; o < kRows; ++o)
@@ -107,8 +126,8 @@ __device__ __forceinline__ void vpass(const float (*h)[kI][kT], const Window& wi
 }
 
 struct StatsShared {
-  float in[2][kI][kI];
-  float h[5][kI][kT];
+  float in[2][kI][kIP];
+  float h[5][kI][kTP];
   double red[4];
 };
 
@@ -187,8 +206,8 @@ __global__ __launch_bounds__(1024) void k_sum_partials(const double* __restrict_
 }
 
 struct GradShared {
-  float in[3][kI][kI];
-  float h[3][kI][kT];
+  float in[3][kI][kIP];
+  float h[3][kI][kTP];
 };
 
 __global__ __launch_bounds__(256) void k_ssim_grad(const float* __restrict__ img,
