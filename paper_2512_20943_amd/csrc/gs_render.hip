@@ -1,23 +1,28 @@
 // Tile compositing: forward and backward (the splatting renderer AirGS cites
 // in Sec. II; every training view and every delivered view runs it).
 //
-// One 256-thread workgroup per 16x16 tile; wave w (of 4) owns the 8x8
-// quadrant (w & 1, w >> 1), so the 64 lanes of a wave are a compact pixel
-// block.  The tile's instance list is walked in batches of 256 records
-// gathered into LDS.  While staging a record, its loader thread also tests
-// the Gaussian's alpha >= 1/255 ellipse against each quadrant's pixel box
-// (with a conservative margin): a wave skips, uniformly, every record whose
-// ellipse misses its quadrant, which is exact because every such pair would
-// be skipped per pixel anyway.  Transmittance saturation ends a wave with a
-// ballot and the block with a barrier count.
+// One 64-lane wave (one workgroup) per 16x16 tile.  Lane l owns pixel
+// (l & 7, l >> 3) of each of the tile's four 8x8 quadrants ("slots"), so a
+// slot is a compact 64-pixel block.  The tile's instance list is walked in
+// batches staged in LDS, one record per lane.  While staging a record, its
+// lane also tests the Gaussian's alpha >= 1/255 ellipse against each
+// quadrant's pixel box (exact box minimum of the quadratic form, with a
+// conservative margin): the wave skips, uniformly, every slot whose quadrant
+// the ellipse misses, which is exact because every such pair would be
+// skipped per pixel anyway.  A slot whose 64 pixels have all stopped is
+// dropped with a ballot; the tile ends when all four have.
 //
 // The backward walks each pixel's list back to front from its last
 // contributor, recovering T_k = T_{k+1} / (1 - alpha_k); alpha is recomputed
-// by the same device function as in the forward, so every skip and stop
-// decision is bit-identical.  Per-pair gradients are summed across the wave
-// with DPP row shifts and row broadcasts, across the 4 waves in LDS, and
-// leave the workgroup as one set of global float atomics per (tile,
-// Gaussian).
+// by the same device functions as in the forward, so every skip and stop
+// decision is bit-identical.  Per entry it accumulates, per lane, the colour
+// gradients and five moments of dL/dpower (the mean and conic gradients are
+// linear in them with per-entry coefficients), sums them over each 16-lane
+// row with DPP row shifts, adds the four row sums when the batch is flushed,
+// and writes one 9-float gradient row per (tile, Gaussian) at the
+// instance's index in the binning's emission order.  A second kernel sums
+// each (view, Gaussian)'s rows, which that order keeps contiguous: no
+// floating-point atomics, and the result does not depend on scheduling.
 #include "gs_internal.h"
 
 namespace gs {

@@ -2,16 +2,20 @@
 //
 // The order the renderer needs is, per tile segment, the instances sorted by
 // (FP32 depth, Gaussian id).  It is reached in two sorts that both use the
-// same LDS-resident onesweep LSD radix sort (stable, 8-bit digits, one
+// same LDS-resident onesweep LSD radix sort (stable, 8- or 9-bit digits, one
 // global histogram pass, then one pass per digit with decoupled look-back
 // over dynamically numbered partitions):
-//   1. the (view, depth) keys of the V*n projected Gaussians;
+//   1. the (view, depth) keys of the V*n projected Gaussians -- 32-bit keys
+//      view * span + (depth bits - min) when the views times the visible
+//      depth-bit range fit (a first pass reduces that range together with
+//      the instance count, which the host reads back), 64-bit keys
+//      (view << 32 | depth bits) otherwise;
 //   2. after emitting every Gaussian's tiles in that depth order, the
 //      instances by their segment id only.
 // Stability of (2) keeps the depth order of (1) inside each segment, and
 // stability of (1) keeps ascending ids for equal depths, so the result is
 // the (segment, depth, id) order -- while the per-instance sort moves only
-// ceil(log2(segments)/8) digits of 32-bit keys instead of 5-7 digits of
+// ceil(log2(segments)/9) digits of 32-bit keys instead of 5-7 digits of
 // 64-bit keys.
 #include <algorithm>
 

@@ -1,5 +1,7 @@
-// Training support: the L1 photometric term (AirGS Eq. (1)) and the Adam
-// update (Kingma & Ba 2015).  Both are elementwise and HBM-bound.
+// Training support, all elementwise and HBM-bound: the L1 photometric term
+// (AirGS Eq. (1)), the squared error behind the pruning sweep's PSNR
+// (Sec. III-C), the keyframe temporal term (Eq. (9)) and the Adam update
+// (Kingma & Ba 2015).
 #include "gs_internal.h"
 
 namespace gs {
