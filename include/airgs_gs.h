@@ -9,7 +9,10 @@
  * spherical harmonics, rotation and scale (Sec. II).  The renderer itself is
  * the differentiable splatting rasterizer the paper cites in Sec. II: EWA
  * projection, 16x16-tile binning, a depth-ordered front-to-back composite,
- * and its backward pass.
+ * and its backward pass.  Around it sit the terms the paper trains and
+ * delivers with: the Eq. (1) loss, Adam, usage counts for pruning, the
+ * temporal and keyframe terms, low-opacity culling, and the bookkeeping and
+ * quantisation of sent updates.
  *
  * Conventions shared by every call
  *   - All array pointers are DEVICE pointers unless a parameter says "host".
@@ -17,7 +20,8 @@
  *     call returns, except that enqueued kernels read and write them on the
  *     given stream until they complete.
  *   - Work is enqueued on `stream` (a hipStream_t; NULL = the null stream).
- *     Only gs_bin_sort blocks the host (it reads the instance count back).
+ *     Only gs_bin_sort and gs_cull_low_opacity block the host (they read a
+ *     count back through the context's pinned slot).
  *   - Argument checks are synchronous; a failed check returns an error code
  *     and enqueues nothing.  Kernel faults surface at the next synchronising
  *     HIP call.  gs_last_error() returns the text of the latest error.
