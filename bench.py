@@ -56,7 +56,7 @@ def parse():
     ap.add_argument("--gaussians", type=int, default=300_000)
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-dssim-step", action="store_true")
-    ap.add_argument("--serve-rates", default="500,2000",
+    ap.add_argument("--serve-rates", default="500,2000,4000",
                     help="aggregate Poisson arrival rates (requests/s)")
     ap.add_argument("--serve-seconds", type=float, default=2.0)
     ap.add_argument("--serve-warmup", type=float, default=0.5)
