@@ -576,3 +576,55 @@ def test_usage_total_counts_every_composited_pair(oracle_mod):
                     al = min(0.99, P["alpha_hat"][v, gid] * math.exp(pw))
                     total += int(pw <= 0 and al >= 1 / 255)
     assert img["usage"].sum() == total
+
+
+def test_apply_backward_fd_on_the_2000_gaussian_subset(oracle_mod):
+    """Delta-image gradient of the temporal frame-update workload's
+    2,000-Gaussian, 64x64 subset (the case the GPU parity test compares)
+    against FP64 central differences of the whole forward and L1 loss."""
+    full = scenes.make_scene(300_000, 0, -3.0, 3.0, -4.0, 0.5, 3)
+    sc = scenes.subset(full, 2000)
+    n = 2000
+    gw = gh = scenes.grid_side(n)
+    d = scenes.make_delta(n, gw, gh, 7)
+    mask = scenes.prune_mask(d, n, 0.3)
+    cams = scenes.arc_cameras(1, 5.0, 64, 64)
+    tgt = oracle_mod.forward(scenes.jitter_means(sc, 0.01, 8), cams)[2]["image"]
+    frame = oracle_mod.apply(sc, d, mask, gw, gh)
+    P, L, img = oracle_mod.forward(frame, cams)
+    _, gI = oracle_mod.l1(img["image"], tgt)
+    _, gf = oracle_mod.backward(frame, cams, P, L, gI)
+    gd = oracle_mod.apply_bwd(sc, mask, gw, gh, gf).reshape(8, -1)
+    mflat = mask.reshape(-1)
+    dd = d.astype(np.float64).reshape(8, -1)
+    gmax = np.abs(gd).max()
+    assert gmax > 0
+
+    def frame64(dv):
+        mu = sc["mean"].astype(np.float64).copy()
+        q = sc["quat"].astype(np.float64).copy()
+        o = sc["opacity"].astype(np.float64).copy()
+        k = np.nonzero(mflat[:n])[0]
+        mu[:, k] += dv[:3, k]
+        for i in k:
+            q[:, i] = oracle_mod.quat_mul(dv[3:7, i], q[:, i])
+        o[k] += dv[7, k]
+        return dict(mean=mu, quat=q, opacity=o)
+
+    # the largest-gradient entries of each channel (well above FD noise)
+    checked = 0
+    for c in range(8):
+        for i in np.argsort(-np.abs(gd[c, :n]))[:3]:
+            h = 1e-6 * max(1.0, abs(dd[c, i]))
+            res = []
+            for sgn in (-1, 1):
+                dv = dd.copy()
+                dv[c, i] += sgn * h
+                res.append(oracle_mod.forward_loss(sc, cams, tgt, overrides=frame64(dv)))
+            if res[0][1] != res[1][1]:
+                continue
+            fd = (res[1][0] - res[0][0]) / (2 * h)
+            an = gd[c, i]
+            assert abs(fd - an) <= 1e-4 * abs(an) + 1e-6 * gmax, (c, int(i), fd, an)
+            checked += 1
+    assert checked >= 16
