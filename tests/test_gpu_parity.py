@@ -383,6 +383,52 @@ def test_invalid_arguments_are_rejected():
     assert ei.value.code == gs.GS_ERR_OOM
 
 
+def _code(fn):
+    with pytest.raises(gs.GsError) as ei:
+        fn()
+    return ei.value.code
+
+
+def test_training_and_delivery_calls_reject_bad_arguments():
+    """The loss, keyframe, culling and sent-update calls validate before
+    enqueueing anything."""
+    require_gpu()
+    ctx = gs.default_context()
+    dev = "cuda"
+    img = torch.zeros(1, 3, 16, 16, device=dev)
+    grad = torch.empty_like(img)
+    loss = torch.zeros(1, dtype=torch.float64, device=dev)
+    small_ws = torch.empty(8, dtype=torch.uint8, device=dev)
+    assert _code(lambda: gs.gs_l1_dssim_loss_grad(ctx, img, img, grad, loss, small_ws)) == \
+        gs.GS_ERR_OOM
+    ws = torch.empty(gs.l1_dssim_workspace_size(3, 16, 16), dtype=torch.uint8, device=dev)
+    assert _code(lambda: gs.gs_l1_dssim_loss_grad(ctx, img, img, grad, loss, ws, 1.5)) == \
+        gs.GS_ERR_INVALID_ARG
+    x = torch.zeros(4, 64, device=dev)
+    assert _code(lambda: gs.gs_keyframe_temporal_l1(ctx, x, x, 65, 1e-3, x)) == \
+        gs.GS_ERR_INVALID_ARG                       # bound beyond the plane stride
+    logit = torch.zeros(100, device=dev)
+    idx = torch.empty(100, dtype=torch.int32, device=dev)
+    for bad in (0.0, 1.0, float("nan")):
+        assert _code(lambda: gs.gs_cull_low_opacity(ctx, logit, 100, bad, idx)) == \
+            gs.GS_ERR_INVALID_ARG
+    assert _code(lambda: gs.gs_cull_low_opacity(ctx, logit, 100, 0.1, idx, small_ws[:0])) == \
+        gs.GS_ERR_OOM
+    d = torch.zeros(8, 4, 4, device=dev)
+    m = torch.ones(4, 4, dtype=torch.uint8, device=dev)
+    amax = torch.zeros(8, device=dev)
+    assert _code(lambda: gs.gs_residual_delta(ctx, d, d, m, 17, 4, 4, d, amax)) == \
+        gs.GS_ERR_INVALID_ARG                       # 17 Gaussians on a 4x4 grid
+    q = torch.empty(8, 4, 4, dtype=torch.int16, device=dev)
+    assert _code(lambda: gs.gs_quantize_delta(ctx, d, amax, 12, 16, 4, 4, q, amax)) == \
+        gs.GS_ERR_INVALID_ARG                       # 12-bit codes
+    sc = scenes.make_scene(16, 1, -1, 1, -4, 0.5, 0)
+    a = gs.Gaussians.from_scene(sc)
+    f = frame_of(a)
+    assert _code(lambda: gs.gs_apply_quantized_update(ctx, a, q, 16, amax, d, 3, 3, f)) == \
+        gs.GS_ERR_INVALID_ARG                       # grid too small for 16 Gaussians
+
+
 # ---------------------------------------------------------------------------
 # full-size frame workload: sampled checks
 # ---------------------------------------------------------------------------
