@@ -192,7 +192,7 @@ def algorithmic_work(stage, ts, steps):
         f = FLOP_PER_PAIR_FWD if stage == "render_fwd" else FLOP_PER_PAIR_BWD
         return pairs * f, "flop", "alu", pairs
     if stage == "project":
-        return n * pbytes + V * n * 73.0, "byte", "hbm", None
+        return n * pbytes + V * n * 89.0, "byte", "hbm", None
     if stage == "project_bwd":
         return 2 * n * pbytes + V * n * (36.0 + 20 + 1), "byte", "hbm", None
     if stage == "segment_sort":

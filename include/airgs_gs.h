@@ -101,11 +101,16 @@ typedef struct gs_opts {
 } gs_opts;
 
 /* Per (view, Gaussian) projection records, index v*ld + i:
- *   splat (V, ld, 12) FP32: [px, py, A, B, C, opacity, r, g, b, depth, Q, 0]
+ *   splat (V, ld, 16) FP32 words, 64 B per record:
+ *       [px, py, A, B, C, opacity, r, g, b, depth, Q, 0, o, w, e, 0]
  *       screen mean, conic (power = -(A dx^2 + C dy^2)/2 - B dx dy), opacity
  *       sigmoid(logit), clamped SH colour, camera-space depth, and the conic
  *       determinant Q = A C - B^2 (from FP64, used for cancellation-free
- *       evaluation of the quadratic form);
+ *       evaluation of the quadratic form); words 12..15 are uint32 bit
+ *       patterns: o = tx0 | ty0 << 16 and w = tx1 - tx0 of the tile rectangle
+ *       (written by gs_project), e = the first instance of the pair in the
+ *       binning's emission order (written by gs_bin_sort, read by
+ *       gs_render_bwd);
  *   rect (V, ld, 4) int32: tile rectangle [tx0, ty0, tx1, ty1), all 0 if culled;
  *   tiles_touched (V, ld) int32: (tx1 - tx0) * (ty1 - ty0), 0 if culled;
  *   depth_bits (V, ld) uint32: bits of FP32(z);
@@ -131,12 +136,14 @@ typedef struct gs_projected {
  *   vals (capacity) uint32: Gaussian id of each instance, in key order, ties
  *       (equal segment and depth) in ascending id;
  *   ranges (n_segments, 2) uint32: [start, end) of each segment in vals;
- *   gv_base (gv_capacity >= n_views * ld) uint32, nullable for gs_bin_sort,
- *       required by gs_render_bwd: for each (view v, Gaussian i) with
- *       tiles_touched > 0, at v*ld + i, the index of its first instance in
- *       the binning's emission order (its tiles row by row over its tile
- *       rectangle, consecutive); the backward sums per-instance gradients
- *       in that order without atomics.
+ *   gv_base (gv_capacity >= n_views * ld) uint32, optional (NULL = not
+ *       written): for each (view v, Gaussian i) with tiles_touched > 0, at
+ *       v*ld + i, the index of its first instance in the binning's emission
+ *       order (its tiles row by row over its tile rectangle, consecutive).
+ *       The same index is always written to word 14 of the pair's projected
+ *       record, where gs_render_bwd reads it: the backward writes one
+ *       gradient row per instance in that order and sums each pair's rows
+ *       without atomics.
  * capacity (in) bounds the instance count; count (out) is the instance count
  * M; n_segments (out) is the total tile count. */
 typedef struct gs_tile_lists {
@@ -239,6 +246,9 @@ gs_status gs_project(gs_ctx* ctx, const gs_gaussians* g, const gs_camera* cams_h
  * depth, Gaussian id) with an LDS-resident onesweep radix sort.  Reads the
  * instance count back to the host (blocking).  Returns GS_ERR_CAPACITY with
  * lists->count = M when M > lists->capacity (nothing else is written).
+ * Besides the lists it writes word 14 of each listed record of proj->splat
+ * (the pair's first instance in emission order, also stored in
+ * lists->gv_base when that is given).
  * workspace must hold gs_bin_sort_workspace_size() bytes. */
 gs_status gs_bin_sort(gs_ctx* ctx, const gs_projected* proj, const gs_camera* cams_host,
                       const gs_camera* cams_dev, int n_views, gs_tile_lists* lists,

@@ -308,6 +308,9 @@ gs_status gs_bin_sort(gs_ctx* c, const gs_projected* proj, const gs_camera* ch,
   GS_TRY(check_projected(c, proj, V, proj->ld));
   if (!lists || !lists->vals || !lists->ranges)
     return fail(c, GS_ERR_INVALID_ARG, "tile lists (vals, ranges) are NULL");
+  if (lists->gv_base && lists->gv_capacity < (int64_t)V * proj->ld)
+    return fail(c, GS_ERR_INVALID_ARG, "gv_base holds %lld entries, n_views * ld = %lld",
+                (long long)lists->gv_capacity, (long long)V * proj->ld);
   if (lists->capacity < 0 || lists->capacity > GS_MAX_INSTANCES)
     return fail(c, GS_ERR_INVALID_ARG, "capacity %lld outside [0, 2^30]",
                 (long long)lists->capacity);
@@ -434,8 +437,6 @@ gs_status gs_render_bwd(gs_ctx* c, const gs_gaussians* frame, const gs_projected
   }
   if (opts && ((opts->grad2d_norm == nullptr) != (opts->visible_views == nullptr)))
     return fail(c, GS_ERR_INVALID_ARG, "grad2d_norm and visible_views go together");
-  if (!lists->gv_base || lists->gv_capacity < (int64_t)V * frame->ld)
-    return fail(c, GS_ERR_INVALID_ARG, "tile lists lack the per-Gaussian emission bases (gv_base)");
   if (lists->count < 0 || lists->count > lists->capacity)
     return fail(c, GS_ERR_INVALID_ARG, "tile list count out of range");
   const size_t need = gs_render_bwd_workspace_size(V, frame->ld, lists->count);

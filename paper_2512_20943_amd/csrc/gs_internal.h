@@ -22,6 +22,7 @@ constexpr uint8_t kClampR = 1, kClampG = 2, kClampB = 4, kClampU = 8, kClampV = 
 
 constexpr int kSplatFloats = 12;    // projected record stride (3 x float4)
 constexpr int kGrad2dFloats = 12;   // screen-space gradient record stride
+constexpr int kSplatF4 = 4;         // float4s per projected record (64 B)
 
 __host__ __device__ inline int tiles_across(int px) { return (px + kTile - 1) / kTile; }
 

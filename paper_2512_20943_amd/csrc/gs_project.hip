@@ -199,7 +199,7 @@ __global__ __launch_bounds__(256) void k_project(
         vis = nt > 0;
       }
     }
-    float4 o0 = make_float4(0.f, 0.f, 0.f, 0.f), o1 = o0, o2 = o0;
+    float4 o0 = make_float4(0.f, 0.f, 0.f, 0.f), o1 = o0, o2 = o0, o3 = o0;
     if (vis) {
       // colour along the world-space direction camera centre -> mean
       const float ccx = (float)-((R[0] * cam.t[0] + R[3] * cam.t[1]) + R[6] * cam.t[2]);
@@ -225,14 +225,19 @@ __global__ __launch_bounds__(256) void k_project(
       o0 = make_float4((float)px, (float)py, (float)A, (float)B);
       o1 = make_float4((float)C, alpha_hat, rgb[0], rgb[1]);
       o2 = make_float4(rgb[2], (float)z, (float)detq, 0.f);
+      // tile rectangle for the backward's instance rows (the emission base,
+      // component w, is filled in by the binning)
+      o3 = make_float4(__uint_as_float((uint32_t)rc.x | ((uint32_t)rc.y << 16)),
+                       __uint_as_float((uint32_t)(rc.z - rc.x)), 0.f, 0.f);
     } else {
       fl = 0;
       rc = make_int4(0, 0, 0, 0);
       nt = 0;
     }
-    splat[3 * j + 0] = o0;
-    splat[3 * j + 1] = o1;
-    splat[3 * j + 2] = o2;
+    splat[kSplatF4 * j + 0] = o0;
+    splat[kSplatF4 * j + 1] = o1;
+    splat[kSplatF4 * j + 2] = o2;
+    splat[kSplatF4 * j + 3] = o3;
     rect[j] = rc;
     tiles[j] = nt;
     flags[j] = fl;
@@ -361,8 +366,8 @@ __global__ __launch_bounds__(256) void k_project_bwd(
     float gz = -(g_px * fx * x0 + g_py * fy * x1) * iz2;
 
     // conic -> 2D covariance: G_S = -Q G_Q Q, G_Q = [[gA, gB/2], [gB/2, gC]]
-    const float4 s0 = splat[3 * j + 0];
-    const float4 s1 = splat[3 * j + 1];
+    const float4 s0 = splat[kSplatF4 * j + 0];
+    const float4 s1 = splat[kSplatF4 * j + 1];
     const float A = s0.z, B = s0.w, C = s1.x;
     const float q00 = A * g_A + B * 0.5f * g_B, q01 = A * 0.5f * g_B + B * g_C;
     const float q10 = B * g_A + C * 0.5f * g_B, q11 = B * 0.5f * g_B + C * g_C;

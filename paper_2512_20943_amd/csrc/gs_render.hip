@@ -199,8 +199,8 @@ __device__ __forceinline__ void render_tile_fwd(FwdShared& sh, UsageShared* us,
       const uint32_t e = b0 + (uint32_t)k;
       if (e < rg.y) {
         const uint32_t g = vals[e];
-        const float4 q0 = sv[3 * (size_t)g], q1 = sv[3 * (size_t)g + 1],
-                     q2 = sv[3 * (size_t)g + 2];
+        const float4 q0 = sv[kSplatF4 * (size_t)g], q1 = sv[kSplatF4 * (size_t)g + 1],
+                     q2 = sv[kSplatF4 * (size_t)g + 2];
         const Rec rr = make_rec(q0, q1, q2);
         sh.a[k] = rr.a;
         sh.b[k] = rr.b;
@@ -284,7 +284,7 @@ __global__ __launch_bounds__(64) void k_render_fwd(
   const int v = seg / tiles_per_view, tile = seg - v * tiles_per_view;
   const int ty = tile / TX, tx = tile - ty * TX;
   const size_t pix = (size_t)W * H;
-  render_tile_fwd<false>(sh, nullptr, splat + 3 * (size_t)v * ld, vals, ranges[seg], tx, ty, W,
+  render_tile_fwd<false>(sh, nullptr, splat + kSplatF4 * (size_t)v * ld, vals, ranges[seg], tx, ty, W,
                          H, bg0, bg1, bg2, image + 3 * pix * v, final_T + pix * v,
                          n_contrib + pix * v, nullptr);
 }
@@ -300,7 +300,7 @@ __global__ __launch_bounds__(64) void k_render_fwd_usage(
   const int v = seg / tiles_per_view, tile = seg - v * tiles_per_view;
   const int ty = tile / TX, tx = tile - ty * TX;
   const size_t pix = (size_t)W * H;
-  render_tile_fwd<true>(sh, &us, splat + 3 * (size_t)v * ld, vals, ranges[seg], tx, ty, W, H, bg0,
+  render_tile_fwd<true>(sh, &us, splat + kSplatF4 * (size_t)v * ld, vals, ranges[seg], tx, ty, W, H, bg0,
                         bg1, bg2, image + 3 * pix * v, final_T + pix * v, n_contrib + pix * v,
                         usage);
 }
@@ -350,7 +350,7 @@ __global__ __launch_bounds__(64) void k_render_persistent(
     const int TX = tiles_across(d.x);
     const int tile = (int)(item - seg_base[lo]);
     const int ty = tile / TX, tx = tile - ty * TX;
-    render_tile_fwd<false>(sh, nullptr, splat + 3 * (size_t)lo * ld, vals, ranges[item], tx, ty,
+    render_tile_fwd<false>(sh, nullptr, splat + kSplatF4 * (size_t)lo * ld, vals, ranges[item], tx, ty,
                            d.x, d.y, bg0, bg1, bg2, images + 3 * pix_base[lo], nullptr, nullptr,
                            nullptr);
   }
@@ -360,9 +360,12 @@ __global__ __launch_bounds__(64) void k_render_persistent(
 constexpr int kRowFloats = 9;  // per-instance gradient row
 
 // Index of the instance of a (view, Gaussian) in tile (tx, ty): the binning
-// emits its tiles row by row over its tile rectangle starting at base.
-__device__ __forceinline__ uint32_t instance_row(int4 r, uint32_t base, int tx, int ty) {
-  return base + (uint32_t)((ty - r.y) * (r.z - r.x) + (tx - r.x));
+// emits its tiles row by row over its tile rectangle, starting at the base it
+// stores in the record's fourth float4 = (tx0 | ty0 << 16, width, base, 0).
+__device__ __forceinline__ uint32_t instance_row(float4 q3, int tx, int ty) {
+  const uint32_t o = __float_as_uint(q3.x), w = __float_as_uint(q3.y),
+                 base = __float_as_uint(q3.z);
+  return base + ((uint32_t)ty - (o >> 16)) * w + ((uint32_t)tx - (o & 0xFFFFu));
 }
 
 struct BwdShared {
@@ -384,17 +387,14 @@ __global__ __launch_bounds__(64) void k_render_bwd(
     const float4* __restrict__ splat, int ld, const uint32_t* __restrict__ vals,
     const uint2* __restrict__ ranges, int W, int H, int TX, int tiles_per_view, float bg0,
     float bg1, float bg2, const float* __restrict__ final_T, const int32_t* __restrict__ n_contrib,
-    const float* __restrict__ dL_dimage, const int4* __restrict__ rect,
-    const uint32_t* __restrict__ gv_base, float* __restrict__ rows) {
+    const float* __restrict__ dL_dimage, float* __restrict__ rows) {
   __shared__ BwdShared sh;
   const int seg = blockIdx.x;
   const int v = seg / tiles_per_view, tile = seg - v * tiles_per_view;
   const int ty = tile / TX, tx = tile - ty * TX;
   const int lane = threadIdx.x;
   const uint2 rg = ranges[seg];
-  const float4* sv = splat + 3 * (size_t)v * ld;
-  const int4* rv = rect + (size_t)v * ld;
-  const uint32_t* bv = gv_base + (size_t)v * ld;
+  const float4* sv = splat + kSplatF4 * (size_t)v * ld;
   const size_t pix = (size_t)W * H;
   const float* gi = dL_dimage + 3 * pix * v;
 
@@ -431,13 +431,13 @@ __global__ __launch_bounds__(64) void k_render_bwd(
     for (int k = lane; k < kBwdBatch; k += 64) {
       if (lo + k < hi) {
         const uint32_t g = vals[rg.x + (uint32_t)(lo + k)];
-        const float4 q0 = sv[3 * (size_t)g], q1 = sv[3 * (size_t)g + 1],
-                     q2 = sv[3 * (size_t)g + 2];
+        const float4 q0 = sv[kSplatF4 * (size_t)g], q1 = sv[kSplatF4 * (size_t)g + 1],
+                     q2 = sv[kSplatF4 * (size_t)g + 2], q3 = sv[kSplatF4 * (size_t)g + 3];
         const Rec rr = make_rec(q0, q1, q2);
         sh.a[k] = rr.a;
         sh.b[k] = rr.b;
         sh.c[k] = rr.c;
-        sh.g[k] = instance_row(rv[g], bv[g], tx, ty);
+        sh.g[k] = instance_row(q3, tx, ty);
         sh.m[k] = quadrant_mask(q0, q1, q2, ox, oy);
       }
     }
@@ -532,7 +532,7 @@ __global__ __launch_bounds__(64) void k_render_bwd(
   const int cnt = (int)(rg.y - rg.x);
   for (int j = jmax + lane; j < cnt; j += 64) {
     const uint32_t g = vals[rg.x + (uint32_t)j];
-    float* dst = rows + (size_t)instance_row(rv[g], bv[g], tx, ty) * kRowFloats;
+    float* dst = rows + (size_t)instance_row(sv[kSplatF4 * (size_t)g + 3], tx, ty) * kRowFloats;
 #pragma unroll
     for (int cc = 0; cc < 9; ++cc) dst[cc] = 0.f;
   }
@@ -547,7 +547,7 @@ __global__ __launch_bounds__(64) void k_render_bwd(
 // pair's segment adds them to that pair's LDS accumulator.
 __global__ __launch_bounds__(256) void k_grad_gather(int n, int ld, int V,
                                                      const int32_t* __restrict__ tiles,
-                                                     const uint32_t* __restrict__ gv_base,
+                                                     const uint32_t* __restrict__ splat_words,
                                                      const float* __restrict__ rows,
                                                      float* __restrict__ grad2d) {
   __shared__ uint32_t s_pre[4][64];
@@ -564,7 +564,7 @@ __global__ __launch_bounds__(256) void k_grad_gather(int n, int ld, int V,
     const int ct = tiles[gv];
     if (ct > 0) {
       c = (uint32_t)ct;
-      base = gv_base[gv];
+      base = splat_words[gv * (4 * kSplatF4) + 14];  // first instance of the pair
     }
   }
   uint32_t incl = c;
@@ -687,14 +687,14 @@ void launch_render_bwd(const gs_projected& proj, const gs_tile_lists& lists, int
     hipLaunchKernelGGL(k_render_bwd, dim3(blocks), dim3(64), 0, s,
                        reinterpret_cast<const float4*>(proj.splat), proj.ld, lists.vals,
                        reinterpret_cast<const uint2*>(lists.ranges), W, H, TX, tpv, bg[0], bg[1],
-                       bg[2], final_T, n_contrib, dL_dimage,
-                       reinterpret_cast<const int4*>(proj.rect), lists.gv_base, rows);
+                       bg[2], final_T, n_contrib, dL_dimage, rows);
   }
   const size_t nv = (size_t)proj.n * (size_t)V;
   if (nv == 0) return;
   StageScope scope(kStGradGather, s);
   hipLaunchKernelGGL(k_grad_gather, dim3((unsigned)((nv + 255) / 256)), dim3(256), 0, s, proj.n,
-                     proj.ld, V, proj.tiles_touched, lists.gv_base, rows, grad2d);
+                     proj.ld, V, proj.tiles_touched,
+                     reinterpret_cast<const uint32_t*>(proj.splat), rows, grad2d);
 }
 
 }  // namespace gs

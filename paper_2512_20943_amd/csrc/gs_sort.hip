@@ -441,7 +441,8 @@ __global__ __launch_bounds__(kBlock) void k_emit(uint32_t N, int ld, uint32_t sp
                                                  const int32_t* __restrict__ txv,
                                                  uint32_t* __restrict__ seg_out,
                                                  uint32_t* __restrict__ id_out,
-                                                 uint32_t* __restrict__ gv_base) {
+                                                 uint32_t* __restrict__ gv_base,
+                                                 uint32_t* __restrict__ splat_words) {
   __shared__ uint32_t s_pre[4][64];
   __shared__ uint32_t s_seg0[4][64];  // segment of the rectangle's first tile
   __shared__ uint32_t s_id[4][64];
@@ -462,6 +463,8 @@ __global__ __launch_bounds__(kBlock) void k_emit(uint32_t N, int ld, uint32_t sp
       s_w[wave][lane] = (uint32_t)(r.z - r.x);
       s_row[wave][lane] = (uint32_t)tx;
       if (gv_base) gv_base[(size_t)v * ld + g] = o0;
+      // record word 14: this pair's first instance in emission order
+      splat_words[((size_t)v * ld + g) * (4 * kSplatF4) + 14] = o0;
     }
   }
   // the wave's entries own output [first, first + total)
@@ -724,7 +727,8 @@ void depth_count_emit(const BinSortPlan& p, const gs_projected& proj, const Layo
   StageScope scope(kStEmit, s);
   hipLaunchKernelGGL((k_emit<K>), dim3(cdiv(N, kBlock)), dim3(kBlock), 0, s, N, p.ld, span, sk,
                      sv, cnt, at<uint32_t>(ws, L.offs), reinterpret_cast<const int4*>(proj.rect),
-                     at<uint32_t>(ws, L.seg_base), at<int32_t>(ws, L.txv), segk0, v0, gv_base);
+                     at<uint32_t>(ws, L.seg_base), at<int32_t>(ws, L.txv), segk0, v0, gv_base,
+                     reinterpret_cast<uint32_t*>(proj.splat));
 }
 }  // namespace
 

@@ -25,7 +25,7 @@ GS_ERR_CAPACITY = 2
 GS_ERR_OOM = 3
 GS_ERR_HIP = 4
 TILE = 16
-SPLAT_FLOATS = 12
+SPLAT_FLOATS = 16
 GRAD2D_FLOATS = 12
 STAGE_COUNT = 18
 
@@ -324,7 +324,7 @@ class Projected:
     V: int
     n: int
     ld: int
-    splat: torch.Tensor          # (V, ld, 12) f32
+    splat: torch.Tensor          # (V, ld, 16) f32
     rect: torch.Tensor           # (V, ld, 4) i32
     tiles_touched: torch.Tensor  # (V, ld) i32
     depth_bits: torch.Tensor     # (V, ld) i32 (uint32 bits)
@@ -349,8 +349,8 @@ class Projected:
 
 
 class TileLists:
-    """Sorted tile lists; ``gv`` > 0 also allocates the per-(view, Gaussian)
-    emission bases (n_views * ld entries) the backward needs."""
+    """Sorted tile lists; ``gv`` > 0 also allocates the optional copy of the
+    per-(view, Gaussian) emission bases (at least n_views * ld entries)."""
 
     def __init__(self, capacity: int, n_segments: int, with_keys: bool = False, device="cuda",
                  gv: int = 0):

@@ -17,10 +17,15 @@ from . import gs
 
 class Rasterizer:
     def __init__(self, ctx: gs.Context | None = None, capacity: int = 1 << 20,
-                 with_keys: bool = False, growth: float = 1.25):
+                 with_keys: bool = False, growth: float = 1.25,
+                 emission_bases: bool = False):
         self.ctx = ctx or gs.default_context()
         self.capacity = int(capacity)
         self.with_keys = with_keys
+        # also store each pair's first instance index in lists.gv_base (the
+        # backward reads it from the projected record; this copy is for
+        # inspection)
+        self.emission_bases = emission_bases
         self.growth = growth
         self._lists = None
         self._ws_sort = None
@@ -36,9 +41,10 @@ class Rasterizer:
 
     def _sort_buffers(self, V, ld, nseg, device):
         L = self._lists
+        gv = V * ld if self.emission_bases else 0
         if (L is None or L.capacity < self.capacity or L.n_segments != nseg
-                or L.gv < V * ld):
-            self._lists = gs.TileLists(self.capacity, nseg, self.with_keys, device, gv=V * ld)
+                or L.gv < gv):
+            self._lists = gs.TileLists(self.capacity, nseg, self.with_keys, device, gv=gv)
         need = gs.bin_sort_workspace_size(V, ld, self._lists.capacity, nseg)
         if self._ws_sort is None or self._ws_sort.numel() < need:
             self._ws_sort = torch.empty(need, dtype=torch.uint8, device=device)

@@ -212,7 +212,7 @@ def request_bytes(r: Request, n_ld: int, instances_per_tile: float) -> int:
     w, h = r.wh
     tiles = math.ceil(w / 16) * math.ceil(h / 16)
     inst = 1.5 * instances_per_tile * tiles
-    return int(73 * n_ld + 28 * n_ld + 24 * inst + 12 * w * h)
+    return int(89 * n_ld + 28 * n_ld + 24 * inst + 12 * w * h)
 
 
 class Server:

@@ -37,10 +37,11 @@ def lists_to_numpy(L: gs.TileLists):
     return out
 
 
-def gpu_forward(scene, cams_np, bg=(0.0, 0.0, 0.0), with_keys=True, capacity=1 << 16):
+def gpu_forward(scene, cams_np, bg=(0.0, 0.0, 0.0), with_keys=True, capacity=1 << 16,
+                emission_bases=False):
     g = gs.Gaussians.from_scene(scene)
     cams = gs.Cameras(cams_np)
-    r = Rasterizer(capacity=capacity, with_keys=with_keys)
+    r = Rasterizer(capacity=capacity, with_keys=with_keys, emission_bases=emission_bases)
     out = r.forward(g, cams, bg)
     torch.cuda.synchronize()
     return g, cams, r, out

@@ -381,6 +381,9 @@ def test_invalid_arguments_are_rejected():
     with pytest.raises(gs.GsError) as ei:
         gs.gs_bin_sort(ctx, proj, gc, gs.TileLists(1000, gc.n_segments()), ws)
     assert ei.value.code == gs.GS_ERR_OOM
+    with pytest.raises(gs.GsError) as ei:  # emission-base copy shorter than V * ld
+        gs.gs_bin_sort(ctx, proj, gc, gs.TileLists(1000, gc.n_segments(), gv=1), ws)
+    assert ei.value.code == gs.GS_ERR_INVALID_ARG
 
 
 def _code(fn):
@@ -555,13 +558,15 @@ def test_large_2m_8_views_sampled():
 
 
 def test_emission_bases_index_every_instance_once():
-    """gv_base: the instances of each (view, Gaussian) occupy rows gv_base ..
-    gv_base + tiles_touched - 1 in row-major order over its tile rectangle,
-    and these rows, over all sorted instances, are a permutation of 0..M-1
-    (the backward writes one gradient row per instance there)."""
+    """Emission bases: the instances of each (view, Gaussian) occupy rows
+    base .. base + tiles_touched - 1 in row-major order over its tile
+    rectangle, and these rows, over all sorted instances, are a permutation
+    of 0..M-1 (the backward writes one gradient row per instance there).
+    The base in the projected record (word 14, next to the packed rectangle
+    in words 12, 13) and the optional gv_base copy agree."""
     require_gpu()
     scene, cams = small_frame_workload(3)
-    g, gc, r, out = gpu_forward(scene, cams)
+    g, gc, r, out = gpu_forward(scene, cams, emission_bases=True)
     L = out["lists"]
     M = L.count
     vals = L.vals[:M].cpu().numpy().astype(np.int64)
@@ -569,8 +574,15 @@ def test_emission_bases_index_every_instance_once():
     seg_of = np.repeat(np.arange(L.n_segments), ranges[:, 1] - ranges[:, 0])
     ld = g.ld
     base = L.gv_base[:gc.V * ld].cpu().numpy().view(np.uint32).astype(np.int64)
+    words = out["proj"].splat.cpu().numpy().view(np.uint32).reshape(gc.V, ld, 16)
     rect = out["proj"].rect.cpu().numpy().reshape(gc.V, ld, 4)
     tiles = out["proj"].tiles_touched.cpu().numpy().reshape(gc.V, ld)
+    touched = tiles > 0
+    touched[:, g.n:] = False  # records past n are never written
+    np.testing.assert_array_equal(words[..., 14][touched], base.reshape(gc.V, ld)[touched])
+    np.testing.assert_array_equal(words[..., 12][touched],
+                                  (rect[..., 0] | (rect[..., 1] << 16))[touched])
+    np.testing.assert_array_equal(words[..., 13][touched], (rect[..., 2] - rect[..., 0])[touched])
     tpv = [((w + 15) // 16) * ((h + 15) // 16) for (w, h) in cams["wh"]]
     sb = np.concatenate([[0], np.cumsum(tpv)])
     v = np.searchsorted(sb, seg_of, side="right") - 1
