@@ -17,8 +17,9 @@
 // by the same device functions as in the forward, so every skip and stop
 // decision is bit-identical.  Per entry it accumulates, per lane, the colour
 // gradients and five moments of dL/dpower (the mean and conic gradients are
-// linear in them with per-entry coefficients), sums them over each 16-lane
-// row with DPP row shifts, adds the four row sums when the batch is flushed,
+// linear in them with per-entry coefficients), sums the nine values over each
+// 16-lane row with DPP exchanges that leave one row sum per lane (27 adds and
+// selects, one LDS store), adds the four row sums when the batch is flushed,
 // and writes one 9-float gradient row per (tile, Gaussian) at the
 // instance's index in the binning's emission order.  A second kernel sums
 // each (view, Gaussian)'s rows, which that order keeps contiguous: no
@@ -111,26 +112,34 @@ __device__ __forceinline__ float dpp_take(float x) {
       __builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, ROW_MASK, 0xF, BOUND));
 }
 
-// Sum over each row of 16 lanes, valid in lanes 15, 31, 47, 63.  Must be
-// called with all lanes active.
-__device__ __forceinline__ float row_sum_lane15(float v) {
-  v += dpp_take<0x111, 0xF, true>(v);  // row_shr:1
-  v += dpp_take<0x112, 0xF, true>(v);  // row_shr:2
-  v += dpp_take<0x114, 0xF, true>(v);  // row_shr:4
-  v += dpp_take<0x118, 0xF, true>(v);  // row_shr:8
-  return v;
+// Row sums of nine values, scattered over the row: each step pairs every lane
+// with one in the other half of its group (row mirror, half-row mirror, then
+// quad swaps by 2 and by 1); the lower half keeps one value of each pair and
+// the upper half the other, so a step halves the values a lane carries.
+// Afterwards, with b_k bit k of (lane & 15), a lane holds its row's sum of
+// value 4 b1 + 2 b2 + b3 when b0 = 0, and of value 8 when b0 = 1.  Must be
+// called with all lanes active; u_k = (lane & (1 << k)) != 0.
+template <int CTRL>
+__device__ __forceinline__ float pair_step(float lo, float hi, bool upper) {
+  const float keep = upper ? hi : lo, send = upper ? lo : hi;
+  return keep + dpp_take<CTRL, 0xF, true>(send);
 }
 
-// Sum over the 64 lanes, valid in lane 63.  Must be called with all lanes
-// active.
-__device__ __forceinline__ float wave_sum_lane63(float v) {
-  v += dpp_take<0x111, 0xF, true>(v);  // row_shr:1
-  v += dpp_take<0x112, 0xF, true>(v);  // row_shr:2
-  v += dpp_take<0x114, 0xF, true>(v);  // row_shr:4
-  v += dpp_take<0x118, 0xF, true>(v);  // row_shr:8
-  v += dpp_take<0x142, 0xA, false>(v); // row_bcast:15 into rows 1, 3
-  v += dpp_take<0x143, 0xC, false>(v); // row_bcast:31 into rows 2, 3
-  return v;
+template <int CTRL>
+__device__ __forceinline__ float single_step(float v) {
+  return v + dpp_take<CTRL, 0xF, true>(v);
+}
+
+__device__ __forceinline__ float row_sums9(const float (&x)[9], bool u3, bool u2, bool u1,
+                                           bool u0) {
+  constexpr int kMirror = 0x140, kHalfMirror = 0x141, kSwap2 = 0x4E, kSwap1 = 0xB1;
+  const float y0 = pair_step<kMirror>(x[0], x[1], u3), y1 = pair_step<kMirror>(x[2], x[3], u3),
+              y2 = pair_step<kMirror>(x[4], x[5], u3), y3 = pair_step<kMirror>(x[6], x[7], u3),
+              y4 = single_step<kMirror>(x[8]);
+  const float z0 = pair_step<kHalfMirror>(y0, y1, u2), z1 = pair_step<kHalfMirror>(y2, y3, u2),
+              z2 = single_step<kHalfMirror>(y4);
+  const float w0 = pair_step<kSwap2>(z0, z1, u1), w1 = single_step<kSwap2>(z2);
+  return pair_step<kSwap1>(w0, w1, u0);
 }
 
 // ---------------------------------------------------------------- forward
@@ -153,11 +162,12 @@ struct UsageShared {
   uint32_t u[kFwdBatch];
 };
 
-__device__ __forceinline__ uint32_t live_mask(const bool (&done)[4]) {
+// Bit w set while some pixel of slot w still composites (T > 0).
+__device__ __forceinline__ uint32_t live_mask(const float (&T)[4]) {
   uint32_t live = 0;
 #pragma unroll
   for (int w = 0; w < 4; ++w)
-    if (__builtin_amdgcn_ballot_w64(!done[w]) != 0) live |= 1u << w;
+    if (__builtin_amdgcn_ballot_w64(T[w] > 0.f) != 0) live |= 1u << w;
   return live;
 }
 
@@ -179,17 +189,18 @@ __device__ __forceinline__ void render_tile_fwd(FwdShared& sh, UsageShared* us,
   // slot w's pixel is (x0 + 8 (w & 1), y0 + 8 (w >> 1))
   const int x0 = tx * kTile + (lane & 7), y0 = ty * kTile + (lane >> 3);
   const float fx0 = (float)x0, fy0 = (float)y0;
+  // T[w] > 0 while slot w's pixel composites; a pixel that has stopped holds
+  // its final transmittance negated (and one outside the image holds -1), so
+  // the sign is the per-lane "done" flag without a register of its own
   float T[4], c0[4], c1[4], c2[4];
   int last[4];
-  bool done[4];
 #pragma unroll
   for (int w = 0; w < 4; ++w) {
-    done[w] = !(x0 + 8 * (w & 1) < W && y0 + 8 * (w >> 1) < H);
-    T[w] = 1.f;
+    T[w] = (x0 + 8 * (w & 1) < W && y0 + 8 * (w >> 1) < H) ? 1.f : -1.f;
     c0[w] = c1[w] = c2[w] = 0.f;
     last[w] = 0;
   }
-  uint32_t live = live_mask(done);
+  uint32_t live = live_mask(T);
   const float ox = (float)(tx * kTile), oy = (float)(ty * kTile);
   for (uint32_t b0 = rg.x; b0 < rg.y && live != 0; b0 += kFwdBatch) {
     __syncthreads();
@@ -222,6 +233,8 @@ __device__ __forceinline__ void render_tile_fwd(FwdShared& sh, UsageShared* us,
       const float4 b = sh.b[k];
       const float cb = sh.c[k];
       const int pos = (int)(b0 - rg.x) + k + 1;
+      int posv;  // pos in a vector register, read by the per-slot selects
+      asm("v_mov_b32 %0, %1" : "=v"(posv) : "s"(pos));
       const float dxl = a.x - fx0, dyt = a.y - fy0;
 #pragma unroll
       for (int w = 0; w < 4; ++w) {
@@ -231,7 +244,7 @@ __device__ __forceinline__ void render_tile_fwd(FwdShared& sh, UsageShared* us,
           const float dy = (w >> 1) ? dyt - 8.f : dyt;
           const float power = eval_power(a, b.x, dx, dy);
           const float alpha = fminf(kAlphaMax, eval_ea(power, b.y));
-          const bool use = !done[w] && !(power > 0.f) && alpha >= kAlphaMin;
+          const bool use = T[w] > 0.f && !(power > 0.f) && alpha >= kAlphaMin;
           const float Tn = T[w] * (1.f - alpha);
           const bool stop = use && Tn < kTStop;
           const bool comp = use && !stop;
@@ -240,10 +253,12 @@ __device__ __forceinline__ void render_tile_fwd(FwdShared& sh, UsageShared* us,
           c1[w] = fmaf(b.w, wt, c1[w]);
           c2[w] = fmaf(cb, wt, c2[w]);
           T[w] = comp ? Tn : T[w];
-          last[w] = comp ? pos : last[w];
-          done[w] = done[w] || stop;
+          last[w] = comp ? posv : last[w];
           if constexpr (USAGE) used += (uint32_t)__popcll(__builtin_amdgcn_ballot_w64(comp));
-          if (__builtin_amdgcn_ballot_w64(!done[w]) == 0) live &= ~(1u << w);
+          if (__builtin_amdgcn_ballot_w64(stop) != 0) {  // once per pixel
+            T[w] = stop ? -T[w] : T[w];
+            if (__builtin_amdgcn_ballot_w64(T[w] > 0.f) == 0) live &= ~(1u << w);
+          }
         }
       }
       if constexpr (USAGE) {
@@ -266,10 +281,11 @@ __device__ __forceinline__ void render_tile_fwd(FwdShared& sh, UsageShared* us,
     const int x = x0 + 8 * (w & 1), y = y0 + 8 * (w >> 1);
     if (!(x < W && y < H)) continue;
     const size_t p = (size_t)y * W + x;
-    image[p] = c0[w] + T[w] * bg0;
-    image[pix + p] = c1[w] + T[w] * bg1;
-    image[2 * pix + p] = c2[w] + T[w] * bg2;
-    if (final_T) final_T[p] = T[w];
+    const float Tf = fabsf(T[w]);
+    image[p] = c0[w] + Tf * bg0;
+    image[pix + p] = c1[w] + Tf * bg1;
+    image[2 * pix + p] = c2[w] + Tf * bg2;
+    if (final_T) final_T[p] = Tf;
     if (n_contrib) n_contrib[p] = last[w];
   }
 }
@@ -368,13 +384,18 @@ __device__ __forceinline__ uint32_t instance_row(float4 q3, int tx, int ty) {
   return base + ((uint32_t)ty - (o >> 16)) * w + ((uint32_t)tx - (o & 0xFFFFu));
 }
 
+// Row sums of an entry: value cc of row r at acc[entry * kAccStride + 4 cc + r]
+// (odd stride: the 36 writers of an entry and the 32 readers of one value at
+// flush fall in distinct banks).
+constexpr int kAccStride = 37;
+
 struct BwdShared {
   float4 a[kBwdBatch];
   float4 b[kBwdBatch];
   float4 c[kBwdBatch];
   uint32_t m[kBwdBatch];
   uint32_t g[kBwdBatch];
-  float acc[9][4][kBwdBatch];  // per value, per 16-lane row, per entry
+  float4 acc4[(kBwdBatch * kAccStride + 3) / 4];
 };
 
 __device__ __forceinline__ int wave_max(int x) {
@@ -424,6 +445,11 @@ __global__ __launch_bounds__(64) void k_render_bwd(
     jmax = max(jmax, wmax[w]);
   }
   const float ox = (float)(tx * kTile), oy = (float)(ty * kTile);
+  // the row sum this lane ends up holding, and whether it stores it
+  const bool u3 = lane & 8, u2 = lane & 4, u1 = lane & 2, u0 = lane & 1;
+  const int acc_lane = 4 * (u0 ? 8 : 4 * (int)u1 + 2 * (int)u2 + (int)u3) + (lane >> 4);
+  const bool acc_writer = !u0 || (lane & 15) == 1;
+  float* acc = reinterpret_cast<float*>(sh.acc4);
 
   for (int hi = jmax; hi > 0; hi -= kBwdBatch) {
     const int lo = hi > kBwdBatch ? hi - kBwdBatch : 0;
@@ -441,10 +467,8 @@ __global__ __launch_bounds__(64) void k_render_bwd(
         sh.m[k] = quadrant_mask(q0, q1, q2, ox, oy);
       }
     }
-    {
-      float4* z = reinterpret_cast<float4*>(&sh.acc[0][0][0]);
-      for (int t = lane; t < 9 * kBwdBatch; t += 64) z[t] = make_float4(0.f, 0.f, 0.f, 0.f);
-    }
+    for (int t = lane; t < (kBwdBatch * kAccStride + 3) / 4; t += 64)
+      sh.acc4[t] = make_float4(0.f, 0.f, 0.f, 0.f);
     __syncthreads();
     for (int k = hi - lo - 1; k >= 0; --k) {
       const int j = lo + k;  // position in the tile list
@@ -477,7 +501,7 @@ __global__ __launch_bounds__(64) void k_render_bwd(
           gr[7] = fmaf(g1[w], wt, gr[7]);
           gr[8] = fmaf(g2[w], wt, gr[8]);
           // g . (c - B) with B updated as B + au (c - B)
-          const float gcb = fmaf(g2[w], c.x, fmaf(g1[w], b.w, g0[w] * b.z)) - S[w];
+          const float gcb = fmaf(g2[w], c.x, fmaf(g1[w], b.w, fmaf(g0[w], b.z, -S[w])));
           const float da = (use && ea < kAlphaMax) ? Tk * gcb : 0.f;
           // moments of dL/dpower: the conic and mean gradients are linear in
           // them with per-entry coefficients, applied once per entry at flush
@@ -495,13 +519,9 @@ __global__ __launch_bounds__(64) void k_render_bwd(
         }
       }
       if (__builtin_amdgcn_ballot_w64(contrib) == 0) continue;
-      // row sums in lanes 15, 31, 47, 63; the four rows are added at flush
-#pragma unroll
-      for (int cc = 0; cc < 9; ++cc) gr[cc] = row_sum_lane15(gr[cc]);
-      if ((lane & 15) == 15) {
-#pragma unroll
-        for (int cc = 0; cc < 9; ++cc) sh.acc[cc][lane >> 4][k] = gr[cc];
-      }
+      // nine row sums per row, one per lane; the four rows are added at flush
+      const float rs = row_sums9(gr, u3, u2, u1, u0);
+      if (acc_writer) acc[k * kAccStride + acc_lane] = rs;
     }
     __syncthreads();
     for (int k = lane; k < kBwdBatch; k += 64) {
@@ -509,8 +529,10 @@ __global__ __launch_bounds__(64) void k_render_bwd(
         float* dst = rows + (size_t)sh.g[k] * kRowFloats;
         float mom[9];
 #pragma unroll
-        for (int cc = 0; cc < 9; ++cc)
-          mom[cc] = (sh.acc[cc][0][k] + sh.acc[cc][1][k]) + (sh.acc[cc][2][k] + sh.acc[cc][3][k]);
+        for (int cc = 0; cc < 9; ++cc) {
+          const float* r4 = acc + k * kAccStride + 4 * cc;
+          mom[cc] = (r4[0] + r4[1]) + (r4[2] + r4[3]);
+        }
         // power = -(A dx^2 + C dy^2)/2 - B dx dy with dx = px - x, dy = py - y
         const float A = -2.f * sh.a[k].z, B = sh.c[k].z, C = sh.c[k].w;
         float out[9];
