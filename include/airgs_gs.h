@@ -48,6 +48,9 @@ typedef int32_t gs_status;
 #define GS_ERR_OOM 3         /* workspace smaller than the *_workspace_size() */
 #define GS_ERR_HIP 4         /* a HIP runtime call failed */
 
+/* Every `workspace` argument is device memory aligned to 256 bytes (as
+ * hipMalloc returns it); a misaligned one is GS_ERR_INVALID_ARG. */
+
 #define GS_TILE 16           /* tile side in pixels */
 #define GS_MAX_SH_DEGREE 3
 #define GS_MAX_INSTANCES ((int64_t)1 << 30)

@@ -298,6 +298,14 @@ gs_status gs_project(gs_ctx* c, const gs_gaussians* g, const gs_camera* ch, cons
   return GS_OK;
 }
 
+// Workspaces are carved into 256-byte aligned sub-buffers that kernels read
+// with 16-byte vector loads, so the base must keep that alignment.
+static gs_status check_ws_align(gs_ctx* c, const void* ws) {
+  if (reinterpret_cast<uintptr_t>(ws) % 256 != 0)
+    return fail(c, GS_ERR_INVALID_ARG, "workspace %p is not 256-byte aligned", ws);
+  return GS_OK;
+}
+
 gs_status gs_bin_sort(gs_ctx* c, const gs_projected* proj, const gs_camera* ch,
                       const gs_camera* cd, int V, gs_tile_lists* lists, void* ws, size_t ws_bytes,
                       void* stream) {
@@ -318,6 +326,7 @@ gs_status gs_bin_sort(gs_ctx* c, const gs_projected* proj, const gs_camera* ch,
   if (nseg >= ((int64_t)1 << 31))
     return fail(c, GS_ERR_INVALID_ARG, "too many tile segments (%lld)", (long long)nseg);
   if (!ws) return fail(c, GS_ERR_INVALID_ARG, "workspace is NULL");
+  GS_TRY(check_ws_align(c, ws));
   if ((int64_t)V * proj->n >= ((int64_t)1 << 32))
     return fail(c, GS_ERR_INVALID_ARG, "n_views * n too large");
   gs::BinSortPlan plan{V, proj->n, proj->ld, lists->capacity, nseg};
@@ -393,6 +402,7 @@ gs_status gs_render_fwd_batched(gs_ctx* c, const gs_projected* proj, const gs_ti
   const size_t need = gs::render_batched_workspace_bytes(V);
   if (!ws || ws_bytes < need)
     return fail(c, GS_ERR_OOM, "batched render workspace %zu < %zu bytes", ws_bytes, need);
+  GS_TRY(check_ws_align(c, ws));
   GS_TRY(use_device(c));
   const float zero[3] = {0.f, 0.f, 0.f};
   gs::launch_render_batched(*proj, *lists, cd, V, nseg, opts ? opts->bg : zero, images, ws,
@@ -442,6 +452,7 @@ gs_status gs_render_bwd(gs_ctx* c, const gs_gaussians* frame, const gs_projected
   const size_t need = gs_render_bwd_workspace_size(V, frame->ld, lists->count);
   if (!ws || ws_bytes < need)
     return fail(c, GS_ERR_OOM, "render_bwd workspace %zu < %zu bytes", ws_bytes, need);
+  GS_TRY(check_ws_align(c, ws));
   GS_TRY(use_device(c));
   hipStream_t s = (hipStream_t)stream;
   float* grad2d = static_cast<float*>(ws);
@@ -491,6 +502,7 @@ gs_status gs_l1_dssim_loss_grad(gs_ctx* c, const float* image, const float* targ
   const size_t need = gs::l1_dssim_workspace_bytes(planes, H, W);
   if (!ws || ws_bytes < need)
     return fail(c, GS_ERR_OOM, "l1_dssim workspace %zu < %zu bytes", ws_bytes, need);
+  GS_TRY(check_ws_align(c, ws));
   GS_TRY(use_device(c));
   gs::launch_l1_dssim(image, target, planes, H, W, lambda, grad, loss_dev, ws, (hipStream_t)stream);
   GS_LAUNCHED(c, "l1_dssim");
@@ -559,6 +571,7 @@ gs_status gs_cull_low_opacity(gs_ctx* c, const float* logit, int n, float min_op
   const size_t need = gs::keep_workspace_bytes(n);
   if (!ws || ws_bytes < need)
     return fail(c, GS_ERR_OOM, "cull workspace %zu < %zu bytes", ws_bytes, need);
+  GS_TRY(check_ws_align(c, ws));
   GS_TRY(use_device(c));
   hipStream_t s = (hipStream_t)stream;
   const uint32_t* d_total = gs::launch_keep_low_opacity(

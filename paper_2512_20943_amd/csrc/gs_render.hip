@@ -34,9 +34,11 @@ constexpr float kLn255 = 5.541263545158426f;
 
 // Screen-space record as staged in LDS:
 //   a = (px, py, nA, r1), b = (n2, log2 opacity, r, g), c = (b, 1/opacity, B, C)
-// with power = nA (dx + r1 dy)^2 + n2 dy^2, nA = -A/2, r1 = B/A,
-// n2 = -(AC - B^2) / (2A): the conic quadratic form written as a sum of two
-// non-positive squares, so FP32 evaluation has no cancellation.
+// with power log2(e) = nA (dx + r1 dy)^2 + n2 dy^2, nA = -log2(e) A/2,
+// r1 = B/A, n2 = -log2(e) (AC - B^2) / (2A): the conic quadratic form written
+// as a sum of two non-positive squares (A > 0 and AC - B^2 > 0 for every
+// projected conic), in base-2 units, so FP32 evaluation has no cancellation
+// and never exceeds 0.
 struct Rec {
   float4 a, b, c;
 };
@@ -46,20 +48,23 @@ __device__ __forceinline__ Rec make_rec(float4 s0, float4 s1, float4 s2) {
   Rec r;
   const float A = s0.z, B = s0.w, C = s1.x, dq = s2.z;
   const float iA = 1.f / A;
-  r.a = make_float4(s0.x, s0.y, -0.5f * A, B * iA);
-  r.b = make_float4(-0.5f * dq * iA, __log2f(s1.y), s1.z, s1.w);
+  r.a = make_float4(s0.x, s0.y, (-0.5f * kLog2e) * A, B * iA);
+  r.b = make_float4((-0.5f * kLog2e) * dq * iA, __log2f(s1.y), s1.z, s1.w);
   r.c = make_float4(s2.x, 1.f / s1.y, B, C);
   return r;
 }
 
-__device__ __forceinline__ float eval_power(const float4& a, float n2, float dx, float dy) {
-  const float t = fmaf(a.w, dy, dx);
-  return fmaf(a.z * t, t, n2 * (dy * dy));
+// ea = opacity * exp(power) = exp2(nA (dx + r1 dy)^2 + q), where
+// q = n2 dy^2 + log2(opacity) depends on the pixel row only.  Both squares
+// carry non-positive coefficients, so the exponent never exceeds
+// log2(opacity): power > 0 cannot occur in this form and is not tested.
+__device__ __forceinline__ float row_q(const float4& b, float dy) {
+  return fmaf(b.x, dy * dy, b.y);
 }
 
-// ea = opacity * exp(power) evaluated as exp2(power log2e + log2 opacity).
-__device__ __forceinline__ float eval_ea(float power, float l2o) {
-  return __builtin_amdgcn_exp2f(fmaf(power, kLog2e, l2o));
+__device__ __forceinline__ float eval_ea(const float4& a, float q, float dx, float dy) {
+  const float t = fmaf(a.w, dy, dx);
+  return __builtin_amdgcn_exp2f(fmaf(a.z * t, t, q));
 }
 
 // Minimum over the box [u0,u1] x [v0,v1] of q(u,v) = A u^2 + 2B uv + C v^2,
@@ -242,9 +247,8 @@ __device__ __forceinline__ void render_tile_fwd(FwdShared& sh, UsageShared* us,
           // per-lane decisions as selects: no divergent branches in the slot
           const float dx = (w & 1) ? dxl - 8.f : dxl;
           const float dy = (w >> 1) ? dyt - 8.f : dyt;
-          const float power = eval_power(a, b.x, dx, dy);
-          const float alpha = fminf(kAlphaMax, eval_ea(power, b.y));
-          const bool use = T[w] > 0.f && !(power > 0.f) && alpha >= kAlphaMin;
+          const float alpha = fminf(kAlphaMax, eval_ea(a, row_q(b, dy), dx, dy));
+          const bool use = T[w] > 0.f && alpha >= kAlphaMin;
           const float Tn = T[w] * (1.f - alpha);
           const bool stop = use && Tn < kTStop;
           const bool comp = use && !stop;
@@ -395,6 +399,7 @@ struct BwdShared {
   float4 c[kBwdBatch];
   uint32_t m[kBwdBatch];
   uint32_t g[kBwdBatch];
+  float A[kBwdBatch];  // conic A, for the mean gradient at flush
   float4 acc4[(kBwdBatch * kAccStride + 3) / 4];
 };
 
@@ -463,6 +468,7 @@ __global__ __launch_bounds__(64) void k_render_bwd(
         sh.a[k] = rr.a;
         sh.b[k] = rr.b;
         sh.c[k] = rr.c;
+        sh.A[k] = q0.z;
         sh.g[k] = instance_row(q3, tx, ty);
         sh.m[k] = quadrant_mask(q0, q1, q2, ox, oy);
       }
@@ -490,10 +496,9 @@ __global__ __launch_bounds__(64) void k_render_bwd(
           // leaves T and B unchanged and contributes nothing
           const float dx = (w & 1) ? dxl - 8.f : dxl;
           const float dy = (w >> 1) ? dyt - 8.f : dyt;
-          const float power = eval_power(a, b.x, dx, dy);
-          const float ea = eval_ea(power, b.y);
+          const float ea = eval_ea(a, row_q(b, dy), dx, dy);
           const float alpha = fminf(kAlphaMax, ea);
-          const bool use = j < nc[w] && !(power > 0.f) && alpha >= kAlphaMin;
+          const bool use = j < nc[w] && alpha >= kAlphaMin;
           const float au = use ? alpha : 0.f;
           const float Tk = T[w] * __builtin_amdgcn_rcpf(1.f - au);
           const float wt = au * Tk;
@@ -534,7 +539,7 @@ __global__ __launch_bounds__(64) void k_render_bwd(
           mom[cc] = (r4[0] + r4[1]) + (r4[2] + r4[3]);
         }
         // power = -(A dx^2 + C dy^2)/2 - B dx dy with dx = px - x, dy = py - y
-        const float A = -2.f * sh.a[k].z, B = sh.c[k].z, C = sh.c[k].w;
+        const float A = sh.A[k], B = sh.c[k].z, C = sh.c[k].w;
         float out[9];
         out[0] = -(A * mom[0] + B * mom[1]);
         out[1] = -(B * mom[0] + C * mom[1]);

@@ -490,13 +490,37 @@ __global__ __launch_bounds__(kBlock) void k_emit(uint32_t N, int ld, uint32_t sp
   }
 }
 
+// Segment boundaries of the sorted segment ids, four per thread (one 16-B
+// load; the neighbours across the thread's group come from the adjacent
+// lanes, or from memory at the wave's edges).
 __global__ __launch_bounds__(kBlock) void k_ranges(uint32_t M, const uint32_t* __restrict__ seg,
                                                    uint32_t* __restrict__ ranges) {
-  const uint32_t j = blockIdx.x * kBlock + threadIdx.x;
-  if (j >= M) return;
-  const uint32_t s = seg[j];
-  if (j == 0 || seg[j - 1] != s) ranges[2 * (size_t)s] = j;
-  if (j == M - 1 || seg[j + 1] != s) ranges[2 * (size_t)s + 1] = j + 1;
+  const uint32_t t = blockIdx.x * kBlock + threadIdx.x;
+  const uint32_t j0 = 4 * t;
+  const int lane = threadIdx.x & 63;
+  uint32_t s[4] = {0u, 0u, 0u, 0u};
+  if (j0 + 3 < M) {
+    const uint4 q = *reinterpret_cast<const uint4*>(seg + j0);
+    s[0] = q.x; s[1] = q.y; s[2] = q.z; s[3] = q.w;
+  } else {
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+      if (j0 + i < M) s[i] = seg[j0 + i];
+  }
+  uint32_t prev = (uint32_t)__shfl_up((int)s[3], 1, 64);
+  uint32_t next = (uint32_t)__shfl_down((int)s[0], 1, 64);
+  if (lane == 0 && j0 > 0 && j0 - 1 < M) prev = seg[j0 - 1];
+  if (lane == 63 && j0 + 4 < M) next = seg[j0 + 4];
+  if (j0 >= M) return;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const uint32_t j = j0 + i;
+    if (j >= M) break;
+    const uint32_t before = i == 0 ? prev : s[i - 1];
+    const uint32_t after = i == 3 ? next : s[i + 1];
+    if (j == 0 || before != s[i]) ranges[2 * (size_t)s[i]] = j;
+    if (j == M - 1 || after != s[i]) ranges[2 * (size_t)s[i] + 1] = j + 1;
+  }
 }
 
 __global__ __launch_bounds__(kBlock) void k_keys64(uint32_t M, int V, int ld,
@@ -765,8 +789,8 @@ hipError_t bin_sort_stage2(const BinSortPlan& p, const gs_projected& proj,
   }
   const uint32_t* seg_sorted = which2 ? segk1 : segk0;
   StageScope scope(kStRanges, s);
-  hipLaunchKernelGGL(k_ranges, dim3(cdiv(M, kBlock)), dim3(kBlock), 0, s, M, seg_sorted,
-                     lists.ranges);
+  hipLaunchKernelGGL(k_ranges, dim3(cdiv(cdiv(M, 4u), kBlock)), dim3(kBlock), 0, s, M,
+                     seg_sorted, lists.ranges);
   if (lists.keys)
     hipLaunchKernelGGL(k_keys64, dim3(cdiv(M, kBlock)), dim3(kBlock), 0, s, M, p.n_views, p.ld,
                        seg_sorted, lists.vals, at<uint32_t>(ws, L.seg_base), proj.depth_bits,

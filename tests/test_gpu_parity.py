@@ -384,6 +384,11 @@ def test_invalid_arguments_are_rejected():
     with pytest.raises(gs.GsError) as ei:  # emission-base copy shorter than V * ld
         gs.gs_bin_sort(ctx, proj, gc, gs.TileLists(1000, gc.n_segments(), gv=1), ws)
     assert ei.value.code == gs.GS_ERR_INVALID_ARG
+    need = gs.bin_sort_workspace_size(gc.V, g.ld, 1000, gc.n_segments())
+    big = torch.empty(need + 256, dtype=torch.uint8, device="cuda")
+    with pytest.raises(gs.GsError) as ei:  # workspace off its 256-byte alignment
+        gs.gs_bin_sort(ctx, proj, gc, gs.TileLists(1000, gc.n_segments()), big[16:])
+    assert ei.value.code == gs.GS_ERR_INVALID_ARG
 
 
 def _code(fn):
