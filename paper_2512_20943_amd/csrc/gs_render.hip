@@ -565,6 +565,22 @@ __global__ __launch_bounds__(64) void k_render_bwd(
   }
 }
 
+// One step of a segmented inclusive scan of nine values over the wave: add
+// the value of the lane CTRL names when it carries the same pair index q.
+// q does not decrease over the lanes, so equal ends mean that every lane in
+// between belongs to the same pair.  A lane with no source (outside its row
+// for the shifts, or in a row the mask leaves out) adds 0.
+template <int CTRL, int ROW_MASK, bool BOUND>
+__device__ __forceinline__ void seg_scan_step(int q, float (&x)[9]) {
+  const int qs = __builtin_amdgcn_update_dpp(-1, q, CTRL, ROW_MASK, 0xF, BOUND);
+  const bool take = qs == q;
+#pragma unroll
+  for (int cc = 0; cc < 9; ++cc) {
+    const float sum = x[cc] + dpp_take<CTRL, ROW_MASK, BOUND>(x[cc]);
+    x[cc] = take ? sum : x[cc];
+  }
+}
+
 // Screen-space gradient of each (view, Gaussian): the sum of its instance
 // rows, which the binning emitted contiguously (one per covered tile).  Each
 // wave takes 64 (view, Gaussian) pairs and walks the union of their rows 64
@@ -619,17 +635,14 @@ __global__ __launch_bounds__(256) void k_grad_gather(int n, int ld, int V,
 #pragma unroll
       for (int cc = 0; cc < 9; ++cc) x[cc] = r[cc];
     }
-    // segmented inclusive scan over lanes with equal q
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-      const int qo = __shfl_up(q, off, 64);
-      const bool take = lane >= off && qo == q;
-#pragma unroll
-      for (int cc = 0; cc < 9; ++cc) {
-        const float y = __shfl_up(x[cc], off, 64);
-        x[cc] += take ? y : 0.f;
-      }
-    }
+    // segmented inclusive scan over lanes with equal q: shifts by 1, 2, 4, 8
+    // within each 16-lane row, then each row's last lane into the rows after
+    seg_scan_step<0x111, 0xF, true>(q, x);   // row_shr:1
+    seg_scan_step<0x112, 0xF, true>(q, x);   // row_shr:2
+    seg_scan_step<0x114, 0xF, true>(q, x);   // row_shr:4
+    seg_scan_step<0x118, 0xF, true>(q, x);   // row_shr:8
+    seg_scan_step<0x142, 0xA, false>(q, x);  // row_bcast:15 into rows 1, 3
+    seg_scan_step<0x143, 0xC, false>(q, x);  // row_bcast:31 into rows 2, 3
     const int qn = __shfl_down(q, 1, 64);
     if (valid && (lane == 63 || qn != q)) {
 #pragma unroll

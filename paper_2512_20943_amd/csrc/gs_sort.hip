@@ -290,16 +290,17 @@ __global__ __launch_bounds__(kBlock) void k_depth_range(int n, int ld, int V,
   __shared__ unsigned long long s_sum[4];
   uint32_t mn = 0xFFFFFFFFu, mx = 0u;
   unsigned long long sum = 0;
-  const uint32_t N = (uint32_t)n * (uint32_t)V;
-  for (uint32_t j = blockIdx.x * kBlock + threadIdx.x; j < N; j += gridDim.x * kBlock) {
-    const uint32_t v = j / (uint32_t)n, i = j - v * (uint32_t)n;
-    const size_t r = (size_t)v * ld + i;
-    const int t = tiles[r];
-    if (t > 0) {
-      const uint32_t d = depth_bits[r];
-      mn = min(mn, d);
-      mx = max(mx, d);
-      sum += (unsigned long long)t;
+  for (int v = blockIdx.y; v < V; v += gridDim.y) {
+    const int32_t* tv = tiles + (size_t)v * ld;
+    const uint32_t* dv = depth_bits + (size_t)v * ld;
+    for (uint32_t i = blockIdx.x * kBlock + threadIdx.x; i < (uint32_t)n; i += gridDim.x * kBlock) {
+      const int t = tv[i];
+      if (t > 0) {
+        const uint32_t d = dv[i];
+        mn = min(mn, d);
+        mx = max(mx, d);
+        sum += (unsigned long long)t;
+      }
     }
   }
   for (int off = 32; off >= 1; off >>= 1) {
@@ -332,13 +333,15 @@ __global__ __launch_bounds__(kBlock) void k_depth_keys32(int n, int ld, int V,
                                                          uint32_t dmin, uint32_t span,
                                                          uint32_t* __restrict__ keys,
                                                          uint32_t* __restrict__ vals) {
-  const uint32_t j = blockIdx.x * kBlock + threadIdx.x;
-  if (j >= (uint32_t)n * (uint32_t)V) return;
-  const uint32_t v = j / (uint32_t)n, i = j - v * (uint32_t)n;
-  const size_t r = (size_t)v * ld + i;
-  const uint32_t rel = tiles[r] > 0 ? depth_bits[r] - dmin : span - 1u;
-  keys[j] = v * span + rel;
-  vals[j] = i;
+  const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= (uint32_t)n) return;
+  for (uint32_t v = blockIdx.y; v < (uint32_t)V; v += gridDim.y) {
+    const size_t r = (size_t)v * ld + i;
+    const uint32_t j = v * (uint32_t)n + i;
+    const uint32_t rel = tiles[r] > 0 ? depth_bits[r] - dmin : span - 1u;
+    keys[j] = v * span + rel;
+    vals[j] = i;
+  }
 }
 
 // View of a depth-sorted key: the high word of a 64-bit key, key / span of
@@ -352,13 +355,15 @@ __global__ __launch_bounds__(kBlock) void k_depth_keys(int n, int ld, int V,
                                                        const int32_t* __restrict__ tiles,
                                                        uint64_t* __restrict__ keys,
                                                        uint32_t* __restrict__ vals) {
-  const uint32_t j = blockIdx.x * kBlock + threadIdx.x;
-  if (j >= (uint32_t)n * (uint32_t)V) return;
-  const uint32_t v = j / (uint32_t)n, i = j - v * (uint32_t)n;
-  const size_t r = (size_t)v * ld + i;
-  const uint32_t d = tiles[r] > 0 ? depth_bits[r] : 0xFFFFFFFFu;
-  keys[j] = ((uint64_t)v << 32) | d;
-  vals[j] = i;
+  const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= (uint32_t)n) return;
+  for (uint32_t v = blockIdx.y; v < (uint32_t)V; v += gridDim.y) {
+    const size_t r = (size_t)v * ld + i;
+    const uint32_t j = v * (uint32_t)n + i;
+    const uint32_t d = tiles[r] > 0 ? depth_bits[r] : 0xFFFFFFFFu;
+    keys[j] = ((uint64_t)v << 32) | d;
+    vals[j] = i;
+  }
 }
 
 // Instance count of each depth-sorted entry, and partial sums per chunk.
@@ -706,8 +711,10 @@ hipError_t bin_sort_stage1(const BinSortPlan& p, const gs_projected& proj,
   hipLaunchKernelGGL(k_stats_init, dim3(1), dim3(1), 0, s, stats);
   if (N == 0) return hipGetLastError();
   StageScope scope(kStDepthSort, s);
-  const uint32_t blocks = std::min<uint32_t>(cdiv(N, kBlock), 1024u);
-  hipLaunchKernelGGL(k_depth_range, dim3(blocks), dim3(kBlock), 0, s, p.n, p.ld, p.n_views,
+  // one grid row per view (views beyond 65535 loop), about 1024 blocks
+  const uint32_t gy = std::min<uint32_t>((uint32_t)p.n_views, 65535u);
+  const uint32_t gx = std::max<uint32_t>(1u, std::min<uint32_t>(cdiv(p.n, kBlock), 1024u / gy));
+  hipLaunchKernelGGL(k_depth_range, dim3(gx, gy), dim3(kBlock), 0, s, p.n, p.ld, p.n_views,
                      proj.depth_bits, proj.tiles_touched, stats);
   return hipGetLastError();
 }
@@ -726,11 +733,12 @@ void depth_count_emit(const BinSortPlan& p, const gs_projected& proj, const Layo
   int which;
   {
     StageScope scope(kStDepthSort, s);
+    const dim3 key_grid(cdiv(p.n, kBlock), std::min<uint32_t>((uint32_t)p.n_views, 65535u));
     if constexpr (sizeof(K) == 4)
-      hipLaunchKernelGGL(k_depth_keys32, dim3(cdiv(N, kBlock)), dim3(kBlock), 0, s, p.n, p.ld,
+      hipLaunchKernelGGL(k_depth_keys32, key_grid, dim3(kBlock), 0, s, p.n, p.ld,
                          p.n_views, proj.depth_bits, proj.tiles_touched, dmin, span, k0, dv0);
     else
-      hipLaunchKernelGGL(k_depth_keys, dim3(cdiv(N, kBlock)), dim3(kBlock), 0, s, p.n, p.ld,
+      hipLaunchKernelGGL(k_depth_keys, key_grid, dim3(kBlock), 0, s, p.n, p.ld,
                          p.n_views, proj.depth_bits, proj.tiles_touched, k0, dv0);
     which = radix_sort<K>(k0, k1, dv0, dv1, N, bits, ws, L, s);
   }
