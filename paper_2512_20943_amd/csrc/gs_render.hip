@@ -47,10 +47,10 @@ __device__ __forceinline__ Rec make_rec(float4 s0, float4 s1, float4 s2) {
   // s0 = (px, py, A, B), s1 = (C, opacity, r, g), s2 = (b, depth, detQ, 0)
   Rec r;
   const float A = s0.z, B = s0.w, C = s1.x, dq = s2.z;
-  const float iA = 1.f / A;
+  const float iA = __builtin_amdgcn_rcpf(A);  // hardware reciprocal (1 ulp)
   r.a = make_float4(s0.x, s0.y, (-0.5f * kLog2e) * A, B * iA);
   r.b = make_float4((-0.5f * kLog2e) * dq * iA, __log2f(s1.y), s1.z, s1.w);
-  r.c = make_float4(s2.x, 1.f / s1.y, B, C);
+  r.c = make_float4(s2.x, __builtin_amdgcn_rcpf(s1.y), B, C);
   return r;
 }
 
@@ -100,7 +100,9 @@ __device__ __forceinline__ uint32_t quadrant_mask(float4 s0, float4 s1, float4 s
   const float qmax = 2.f * (kLn255 + __logf(op));
   const float thr = qmax + 2e-4f * fabsf(qmax) + 1e-3f;
   if (!(thr > 0.f)) return 0u;
-  const float r1 = B / A, r2 = B / C, dA = dq / A, dC = dq / C;
+  // hardware reciprocals: their error is far inside the threshold's margin
+  const float iA = __builtin_amdgcn_rcpf(A), iC = __builtin_amdgcn_rcpf(C);
+  const float r1 = B * iA, r2 = B * iC, dA = dq * iA, dC = dq * iC;
   uint32_t m = 0;
 #pragma unroll
   for (int w = 0; w < 4; ++w) {
