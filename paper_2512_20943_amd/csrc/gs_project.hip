@@ -226,7 +226,7 @@ __global__ __launch_bounds__(256) void k_project(
       o1 = make_float4((float)C, alpha_hat, rgb[0], rgb[1]);
       o2 = make_float4(rgb[2], (float)z, (float)detq, 0.f);
       // tile rectangle for the backward's instance rows (the emission base,
-      // component w, is filled in by the binning)
+      // component z, is filled in by the binning)
       o3 = make_float4(__uint_as_float((uint32_t)rc.x | ((uint32_t)rc.y << 16)),
                        __uint_as_float((uint32_t)(rc.z - rc.x)), 0.f, 0.f);
     } else {

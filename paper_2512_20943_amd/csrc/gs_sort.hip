@@ -27,6 +27,8 @@ namespace {
 constexpr int kBlock = 256;
 constexpr int kItems = 32;
 constexpr int kPart = kBlock * kItems;  // keys per onesweep partition
+constexpr int kCountItems = 8;          // entries per thread in the instance count and scan
+constexpr int kCountChunk = kBlock * kCountItems;
 constexpr uint32_t kFlagAgg = 1u << 30;
 constexpr uint32_t kFlagPre = 2u << 30;
 constexpr uint32_t kValMask = (1u << 30) - 1u;
@@ -281,11 +283,12 @@ __global__ void k_view_info(const gs_camera* __restrict__ cams, int V, uint32_t*
 }
 
 // Range of the depth bits of the visible (view, Gaussian) pairs and their
-// total instance count: stats = {min bits, max bits, count lo, count hi}.
+// instance count, per block: part[block] = {min bits, max bits, count lo,
+// count hi}.
 __global__ __launch_bounds__(kBlock) void k_depth_range(int n, int ld, int V,
                                                         const uint32_t* __restrict__ depth_bits,
                                                         const int32_t* __restrict__ tiles,
-                                                        uint32_t* __restrict__ stats) {
+                                                        uint4* __restrict__ part) {
   __shared__ uint32_t s_min[4], s_max[4];
   __shared__ unsigned long long s_sum[4];
   uint32_t mn = 0xFFFFFFFFu, mx = 0u;
@@ -293,13 +296,25 @@ __global__ __launch_bounds__(kBlock) void k_depth_range(int n, int ld, int V,
   for (int v = blockIdx.y; v < V; v += gridDim.y) {
     const int32_t* tv = tiles + (size_t)v * ld;
     const uint32_t* dv = depth_bits + (size_t)v * ld;
-    for (uint32_t i = blockIdx.x * kBlock + threadIdx.x; i < (uint32_t)n; i += gridDim.x * kBlock) {
-      const int t = tv[i];
-      if (t > 0) {
-        const uint32_t d = dv[i];
-        mn = min(mn, d);
-        mx = max(mx, d);
-        sum += (unsigned long long)t;
+    // eight entries per thread per round, loaded before they are used
+    constexpr int U = 8;
+    const uint32_t stride = gridDim.x * kBlock;
+    for (uint32_t i0 = blockIdx.x * kBlock + threadIdx.x; i0 < (uint32_t)n; i0 += U * stride) {
+      int t[U];
+      uint32_t d[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const uint32_t i = i0 + u * stride;
+        t[u] = i < (uint32_t)n ? tv[i] : 0;
+        d[u] = i < (uint32_t)n ? dv[i] : 0u;
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        if (t[u] > 0) {
+          mn = min(mn, d[u]);
+          mx = max(mx, d[u]);
+          sum += (unsigned long long)t[u];
+        }
       }
     }
   }
@@ -319,9 +334,44 @@ __global__ __launch_bounds__(kBlock) void k_depth_range(int n, int ld, int V,
     mn = min(min(s_min[0], s_min[1]), min(s_min[2], s_min[3]));
     mx = max(max(s_max[0], s_max[1]), max(s_max[2], s_max[3]));
     sum = (s_sum[0] + s_sum[1]) + (s_sum[2] + s_sum[3]);
-    atomicMin(stats + 0, mn);
-    atomicMax(stats + 1, mx);
-    atomicAdd(reinterpret_cast<unsigned long long*>(stats + 2), sum);
+    part[blockIdx.y * gridDim.x + blockIdx.x] =
+        make_uint4(mn, mx, (uint32_t)sum, (uint32_t)(sum >> 32));
+  }
+}
+
+// stats = {min bits, max bits, count lo, count hi} over the per-block
+// partials of k_depth_range (one block; device-wide atomics on three
+// addresses from every block serialise at the memory side).
+__global__ __launch_bounds__(kBlock) void k_stats_reduce(const uint4* __restrict__ part, int nb,
+                                                         uint32_t* __restrict__ stats) {
+  __shared__ uint32_t s_min[4], s_max[4];
+  __shared__ unsigned long long s_sum[4];
+  uint32_t mn = 0xFFFFFFFFu, mx = 0u;
+  unsigned long long sum = 0;
+  for (int b = threadIdx.x; b < nb; b += kBlock) {
+    const uint4 q = part[b];
+    mn = min(mn, q.x);
+    mx = max(mx, q.y);
+    sum += (unsigned long long)q.z | ((unsigned long long)q.w << 32);
+  }
+  for (int off = 32; off >= 1; off >>= 1) {
+    mn = min(mn, (uint32_t)__shfl_xor((int)mn, off, 64));
+    mx = max(mx, (uint32_t)__shfl_xor((int)mx, off, 64));
+    sum += __shfl_xor(sum, off, 64);
+  }
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0) {
+    s_min[wave] = mn;
+    s_max[wave] = mx;
+    s_sum[wave] = sum;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    sum = (s_sum[0] + s_sum[1]) + (s_sum[2] + s_sum[3]);
+    stats[0] = min(min(s_min[0], s_min[1]), min(s_min[2], s_min[3]));
+    stats[1] = max(max(s_max[0], s_max[1]), max(s_max[2], s_max[3]));
+    stats[2] = (uint32_t)sum;
+    stats[3] = (uint32_t)(sum >> 32);
   }
 }
 
@@ -375,9 +425,10 @@ __global__ __launch_bounds__(kBlock) void k_count_reduce(uint32_t N, int ld, uin
                                                          uint32_t* __restrict__ cnt,
                                                          uint32_t* __restrict__ chunk_sums) {
   __shared__ uint32_t s_wave[4];
-  const uint32_t c0 = blockIdx.x * (uint32_t)kPart;
+  const uint32_t c0 = blockIdx.x * (uint32_t)kCountChunk;
   uint32_t acc = 0;
-  for (int j = 0; j < kItems; ++j) {
+#pragma unroll
+  for (int j = 0; j < kCountItems; ++j) {
     const uint32_t e = c0 + j * kBlock + threadIdx.x;
     if (e < N) {
       const uint32_t v = view_of(keys[e], span);
@@ -413,17 +464,17 @@ __global__ __launch_bounds__(kBlock) void k_count_scan(uint32_t N, const uint32_
                                                        const uint32_t* __restrict__ chunk_off,
                                                        uint32_t* __restrict__ offs) {
   __shared__ uint32_t s_wave[4];
-  const uint32_t e0 = blockIdx.x * (uint32_t)kPart + threadIdx.x * kItems;
-  uint32_t c[kItems];
+  const uint32_t e0 = blockIdx.x * (uint32_t)kCountChunk + threadIdx.x * kCountItems;
+  uint32_t c[kCountItems];
   uint32_t acc = 0;
 #pragma unroll
-  for (int j = 0; j < kItems; ++j) {
+  for (int j = 0; j < kCountItems; ++j) {
     c[j] = (e0 + j < N) ? cnt[e0 + j] : 0u;
     acc += c[j];
   }
   uint32_t run = chunk_off[blockIdx.x] + block_exclusive_scan(acc, s_wave, nullptr);
 #pragma unroll
-  for (int j = 0; j < kItems; ++j) {
+  for (int j = 0; j < kCountItems; ++j) {
     if (e0 + j < N) offs[e0 + j] = run;
     run += c[j];
   }
@@ -593,7 +644,7 @@ inline int depth_key_bits(int V) { return 32 + bits_for((uint64_t)V); }
 inline uint32_t cdiv(uint64_t a, uint64_t b) { return (uint32_t)((a + b - 1) / b); }
 
 struct Layout {
-  size_t dk0, dk1, dv0, dv1, cnt, offs, chunks, segk0, segk1, segv_alt, hist, digoff, counters,
+  size_t dk0, dk1, dv0, dv1, cnt, offs, chunks, segk0, segk1, segv_alt, hist, digoff, counters, dparts,
       lookback, seg_base, txv, total, stats, bytes;
 };
 
@@ -616,7 +667,7 @@ Layout make_layout(int V, int ld, int64_t cap, int64_t nseg) {
   L.dv1 = take(N * 4);
   L.cnt = take(N * 4);
   L.offs = take(N * 4);
-  L.chunks = take(((size_t)cdiv(N, kPart) + 1) * 4);
+  L.chunks = take(((size_t)cdiv(N, kCountChunk) + 1) * 4);
   L.segk0 = take((size_t)cap * 4);
   L.segk1 = take((size_t)cap * 4);
   L.segv_alt = take((size_t)cap * 4);
@@ -628,6 +679,7 @@ Layout make_layout(int V, int ld, int64_t cap, int64_t nseg) {
   L.txv = take((size_t)V * 4);
   L.total = take(16);
   L.stats = take(16);
+  L.dparts = take((size_t)std::max(1024, std::min(V, 65535)) * 16);
   L.bytes = o;
   return L;
 }
@@ -714,8 +766,10 @@ hipError_t bin_sort_stage1(const BinSortPlan& p, const gs_projected& proj,
   // one grid row per view (views beyond 65535 loop), about 1024 blocks
   const uint32_t gy = std::min<uint32_t>((uint32_t)p.n_views, 65535u);
   const uint32_t gx = std::max<uint32_t>(1u, std::min<uint32_t>(cdiv(p.n, kBlock), 1024u / gy));
+  uint4* part = at<uint4>(ws, L.dparts);
   hipLaunchKernelGGL(k_depth_range, dim3(gx, gy), dim3(kBlock), 0, s, p.n, p.ld, p.n_views,
-                     proj.depth_bits, proj.tiles_touched, stats);
+                     proj.depth_bits, proj.tiles_touched, part);
+  hipLaunchKernelGGL(k_stats_reduce, dim3(1), dim3(kBlock), 0, s, part, (int)(gx * gy), stats);
   return hipGetLastError();
 }
 
@@ -746,7 +800,7 @@ void depth_count_emit(const BinSortPlan& p, const gs_projected& proj, const Layo
   const uint32_t* sv = which ? dv1 : dv0;
   uint32_t* cnt = at<uint32_t>(ws, L.cnt);
   uint32_t* chunks = at<uint32_t>(ws, L.chunks);
-  const uint32_t nch = cdiv(N, kPart);
+  const uint32_t nch = cdiv(N, kCountChunk);
   {
     StageScope scope(kStCountScan, s);
     hipLaunchKernelGGL((k_count_reduce<K>), dim3(nch), dim3(kBlock), 0, s, N, p.ld, span, sk, sv,
