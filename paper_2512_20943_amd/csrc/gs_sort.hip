@@ -154,31 +154,49 @@ __global__ __launch_bounds__(kBlock) void k_onesweep(
 
   K k[kItems];
   uint32_t val[kItems], rank[kItems], dig[kItems];
+  // every partition but the last is full: no bounds tests on its loads
+  const bool full = part * (uint64_t)kPart + kPart <= n;
+  if (full) {
+    const K* kb = kin + base + lane;
+    const uint32_t* vb = vin + base + lane;
 #pragma unroll
-  for (int j = 0; j < kItems; ++j) {
-    const uint32_t idx = base + j * 64 + lane;
-    if (idx < n) {
-      k[j] = kin[idx];
-      val[j] = vin[idx];
-    } else {
-      k[j] = 0;
-      val[j] = 0;
+    for (int j = 0; j < kItems; ++j) {
+      k[j] = kb[j * 64];
+      val[j] = vb[j * 64];
+    }
+  } else {
+#pragma unroll
+    for (int j = 0; j < kItems; ++j) {
+      const uint32_t idx = base + j * 64 + lane;
+      if (idx < n) {
+        k[j] = kin[idx];
+        val[j] = vin[idx];
+      } else {
+        k[j] = 0;
+        val[j] = 0;
+      }
     }
   }
-  const uint64_t lower = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  const uint32_t lower_lo = lane >= 32 ? ~0u : ((1u << lane) - 1u);
+  const uint32_t lower_hi = lane <= 32 ? 0u : (~0u >> (64 - lane));
 #pragma unroll
   for (int j = 0; j < kItems; ++j) {
-    const bool valid = base + j * 64 + lane < n;
+    const bool valid = full || base + j * 64 + lane < n;
     const uint32_t d = valid ? digit_of<BITS>(k[j], shift) : 0u;
-    uint64_t peers = wave_ballot(valid);
+    // lanes holding the same digit: for each bit, keep the lanes whose bit
+    // agrees with this lane's (flip = all ones when this lane's bit is 0)
+    const uint64_t vmask = wave_ballot(valid);
+    uint32_t pl = (uint32_t)vmask, ph = (uint32_t)(vmask >> 32);
+    const uint32_t nd = ~d;
 #pragma unroll
     for (int b = 0; b < BITS; ++b) {
-      const bool bit = (d >> b) & 1u;
-      const uint64_t bb = wave_ballot(bit);
-      peers &= bit ? bb : ~bb;
+      const uint32_t flip = (uint32_t)((int32_t)(nd << (31 - b)) >> 31);
+      const uint64_t bb = wave_ballot(flip == 0u);
+      pl &= (uint32_t)bb ^ flip;
+      ph &= (uint32_t)(bb >> 32) ^ flip;
     }
-    const uint32_t below = (uint32_t)__popcll(peers & lower);
-    const uint32_t cnt = (uint32_t)__popcll(peers);
+    const uint32_t below = (uint32_t)(__popc(pl & lower_lo) + __popc(ph & lower_hi));
+    const uint32_t cnt = (uint32_t)(__popc(pl) + __popc(ph));
     uint32_t prev = 0;
     if (valid) prev = s_wh[wave][d];
     if (valid && below == cnt - 1) s_wh[wave][d] = prev + cnt;
