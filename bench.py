@@ -144,13 +144,14 @@ class TrainStep:
             gs.gs_apply_frame_update(self.ctx, self.g, self.delta, self.mask, self.gw, self.gh,
                                      self.frame)
             g = self.frame
-        out = self.r.forward(g, self.cams)
         self.loss.zero_()
         if self.loss_kind == "l1_dssim":
+            out = self.r.forward(g, self.cams)
             gs.gs_l1_dssim_loss_grad(self.ctx, out["image"], self.target, self.dimg, self.loss,
                                      self.ws_ssim, 0.2)
         else:
-            gs.gs_l1_loss_grad(self.ctx, out["image"], self.target, self.dimg, self.loss)
+            # the L1 term is evaluated where the forward composites its pixels
+            out = self.r.forward_l1(g, self.cams, self.target, self.dimg, self.loss)
         if self.frame_update is None:
             self.r.backward(g, self.cams, out, self.dimg, self.grad)
             gs.gs_adam_step(self.ctx, self.flat, self.gflat, self.m, self.v, self.t)

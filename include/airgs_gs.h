@@ -268,6 +268,21 @@ gs_status gs_render_fwd(gs_ctx* ctx, const gs_projected* proj, const gs_tile_lis
                         const gs_opts* opts, float* image, float* final_T, int32_t* n_contrib,
                         void* stream);
 
+/* gs_render_fwd with the L1 term of Eq. (1) evaluated on the composited
+ * pixels, as gs_l1_loss_grad would on the written image: with
+ * count = n_views * 3 * H * W and d = image - target (target (V, 3, H, W)),
+ * dL_dimage = sign(d) / count is WRITTEN (sign(0) = 0) and mean |d| is
+ * ACCUMULATED in FP64 into *loss_dev (device; caller zeroes).  image may be
+ * NULL (then it is not written); final_T and n_contrib are required.
+ * opts->usage must be NULL.  workspace: gs_render_fwd_l1_workspace_size
+ * bytes (one FP64 partial sum per tile). */
+size_t gs_render_fwd_l1_workspace_size(int n_views, int width, int height);
+gs_status gs_render_fwd_l1(gs_ctx* ctx, const gs_projected* proj, const gs_tile_lists* lists,
+                           const gs_camera* cams_host, const gs_camera* cams_dev, int n_views,
+                           const gs_opts* opts, const float* target, float* image,
+                           float* final_T, int32_t* n_contrib, float* dL_dimage,
+                           double* loss_dev, void* workspace, size_t ws_bytes, void* stream);
+
 /* Batched rendering of n_views requests of (possibly) different sizes in one
  * persistent launch: workgroups take (request, tile) items from a shared
  * device-wide queue until it is drained (view delivery, Sec. IV-B: the

@@ -379,6 +379,45 @@ gs_status gs_render_fwd(gs_ctx* c, const gs_projected* proj, const gs_tile_lists
   return GS_OK;
 }
 
+size_t gs_render_fwd_l1_workspace_size(int V, int W, int H) {
+  if (V <= 0 || W <= 0 || H <= 0) return 0;
+  return gs::render_fwd_l1_workspace_bytes(V, W, H);
+}
+
+gs_status gs_render_fwd_l1(gs_ctx* c, const gs_projected* proj, const gs_tile_lists* lists,
+                           const gs_camera* ch, const gs_camera* cd, int V, const gs_opts* opts,
+                           const float* target, float* image, float* final_T,
+                           int32_t* n_contrib, float* dL_dimage, double* loss_dev, void* ws,
+                           size_t ws_bytes, void* stream) {
+  if (!c) return fail(nullptr, GS_ERR_INVALID_ARG, "ctx is NULL");
+  TimerGuard timer_guard(c);
+  GS_TRY(check_cams(c, ch, cd, V));
+  if (!proj) return fail(c, GS_ERR_INVALID_ARG, "projected is NULL");
+  GS_TRY(check_projected(c, proj, V, proj->ld));
+  if (!lists || !lists->vals || !lists->ranges)
+    return fail(c, GS_ERR_INVALID_ARG, "tile lists are NULL");
+  if (lists->n_segments != segments_of(ch, V))
+    return fail(c, GS_ERR_INVALID_ARG, "tile lists were built for other cameras");
+  for (int v = 1; v < V; ++v)
+    if (ch[v].width != ch[0].width || ch[v].height != ch[0].height)
+      return fail(c, GS_ERR_INVALID_ARG, "views must share width and height");
+  if (!target || !final_T || !n_contrib || !dL_dimage || !loss_dev)
+    return fail(c, GS_ERR_INVALID_ARG, "NULL buffer");
+  if (opts && opts->usage)
+    return fail(c, GS_ERR_INVALID_ARG, "usage counts are not produced by the fused L1 forward");
+  const size_t need = gs::render_fwd_l1_workspace_bytes(V, ch[0].width, ch[0].height);
+  if (!ws || ws_bytes < need)
+    return fail(c, GS_ERR_OOM, "render_fwd_l1 workspace %zu < %zu bytes", ws_bytes, need);
+  GS_TRY(check_ws_align(c, ws));
+  GS_TRY(use_device(c));
+  const float zero[3] = {0.f, 0.f, 0.f};
+  gs::launch_render_fwd_l1(*proj, *lists, V, ch[0].width, ch[0].height, opts ? opts->bg : zero,
+                           target, image, final_T, n_contrib, dL_dimage, loss_dev, ws,
+                           (hipStream_t)stream);
+  GS_LAUNCHED(c, "render_fwd_l1");
+  return GS_OK;
+}
+
 size_t gs_render_batched_workspace_size(int V) {
   if (V <= 0) return 0;
   return gs::render_batched_workspace_bytes(V);

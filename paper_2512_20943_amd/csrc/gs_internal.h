@@ -89,6 +89,11 @@ hipError_t bin_sort_stage2(const BinSortPlan& p, const gs_projected& proj,
 void launch_render_fwd(const gs_projected& proj, const gs_tile_lists& lists, int n_views, int W,
                        int H, const float bg[3], float* image, float* final_T,
                        int32_t* n_contrib, uint32_t* usage, hipStream_t s);
+size_t render_fwd_l1_workspace_bytes(int V, int W, int H);
+void launch_render_fwd_l1(const gs_projected& proj, const gs_tile_lists& lists, int V, int W,
+                          int H, const float bg[3], const float* target, float* image,
+                          float* final_T, int32_t* n_contrib, float* grad, double* loss,
+                          void* ws, hipStream_t s);
 size_t render_batched_workspace_bytes(int V);
 void launch_render_batched(const gs_projected& proj, const gs_tile_lists& lists,
                            const gs_camera* cams_dev, int V, int64_t total_segments,

@@ -178,12 +178,23 @@ __device__ __forceinline__ uint32_t live_mask(const float (&T)[4]) {
   return live;
 }
 
+// The L1 term of Eq. (1) evaluated where the forward writes its pixels:
+// target and grad point at the view's (3, H, W) planes, partial at the
+// tile's slot for the sum of |image - target| over its pixels.
+struct L1Out {
+  const float* target;
+  float* grad;
+  float inv_count;
+  double* partial;
+};
+
 // Composites one tile; all 64 lanes of the workgroup call it.  image points
-// at the view's (3, H, W) planes; final_T / n_contrib at its (H, W) planes or
-// are null.
+// at the view's (3, H, W) planes (with L1 it may be null: not written);
+// final_T / n_contrib at its (H, W) planes or are null.
 // With USAGE, the number of the tile's pixels that composite each entry is
-// added to usage[Gaussian id].
-template <bool USAGE>
+// added to usage[Gaussian id].  With L1, dL/dimage = sign(image - target) /
+// count is written and the tile's sum of |image - target| stored.
+template <bool USAGE, bool L1 = false>
 __device__ __forceinline__ void render_tile_fwd(FwdShared& sh, UsageShared* us,
                                                 const float4* __restrict__ sv,
                                                 const uint32_t* __restrict__ vals, uint2 rg,
@@ -191,7 +202,8 @@ __device__ __forceinline__ void render_tile_fwd(FwdShared& sh, UsageShared* us,
                                                 float bg1, float bg2, float* __restrict__ image,
                                                 float* __restrict__ final_T,
                                                 int32_t* __restrict__ n_contrib,
-                                                uint32_t* __restrict__ usage) {
+                                                uint32_t* __restrict__ usage,
+                                                const L1Out* l1 = nullptr) {
   const int lane = threadIdx.x;
   // slot w's pixel is (x0 + 8 (w & 1), y0 + 8 (w >> 1))
   const int x0 = tx * kTile + (lane & 7), y0 = ty * kTile + (lane >> 3);
@@ -282,17 +294,36 @@ __device__ __forceinline__ void render_tile_fwd(FwdShared& sh, UsageShared* us,
     }
   }
   const size_t pix = (size_t)W * H;
+  double l1sum = 0.0;
 #pragma unroll
   for (int w = 0; w < 4; ++w) {
     const int x = x0 + 8 * (w & 1), y = y0 + 8 * (w >> 1);
     if (!(x < W && y < H)) continue;
     const size_t p = (size_t)y * W + x;
     const float Tf = fabsf(T[w]);
-    image[p] = c0[w] + Tf * bg0;
-    image[pix + p] = c1[w] + Tf * bg1;
-    image[2 * pix + p] = c2[w] + Tf * bg2;
+    const float o0 = c0[w] + Tf * bg0, o1 = c1[w] + Tf * bg1, o2 = c2[w] + Tf * bg2;
+    if (!L1 || image) {
+      image[p] = o0;
+      image[pix + p] = o1;
+      image[2 * pix + p] = o2;
+    }
+    if constexpr (L1) {
+      const float d[3] = {o0 - l1->target[p], o1 - l1->target[pix + p],
+                          o2 - l1->target[2 * pix + p]};
+      const float iv = l1->inv_count;
+#pragma unroll
+      for (int ch = 0; ch < 3; ++ch) {
+        l1->grad[ch * pix + p] = d[ch] > 0.f ? iv : (d[ch] < 0.f ? -iv : 0.f);
+        l1sum += (double)fabsf(d[ch]);
+      }
+    }
     if (final_T) final_T[p] = Tf;
     if (n_contrib) n_contrib[p] = last[w];
+  }
+  if constexpr (L1) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) l1sum += __shfl_xor(l1sum, off, 64);
+    if (lane == 0) *l1->partial = l1sum;
   }
 }
 
@@ -309,6 +340,43 @@ __global__ __launch_bounds__(64) void k_render_fwd(
   render_tile_fwd<false>(sh, nullptr, splat + kSplatF4 * (size_t)v * ld, vals, ranges[seg], tx, ty, W,
                          H, bg0, bg1, bg2, image + 3 * pix * v, final_T + pix * v,
                          n_contrib + pix * v, nullptr);
+}
+
+// Forward with the L1 term fused: per tile, the pixels' dL/dimage and the sum
+// of |image - target| (added up by k_l1_tile_sum).
+__global__ __launch_bounds__(64) void k_render_fwd_l1(
+    const float4* __restrict__ splat, int ld, const uint32_t* __restrict__ vals,
+    const uint2* __restrict__ ranges, int W, int H, int TX, int tiles_per_view, float bg0,
+    float bg1, float bg2, float* __restrict__ image, float* __restrict__ final_T,
+    int32_t* __restrict__ n_contrib, const float* __restrict__ target, float* __restrict__ grad,
+    float inv_count, double* __restrict__ partial) {
+  __shared__ FwdShared sh;
+  const int seg = blockIdx.x;
+  const int v = seg / tiles_per_view, tile = seg - v * tiles_per_view;
+  const int ty = tile / TX, tx = tile - ty * TX;
+  const size_t pix = (size_t)W * H;
+  const L1Out o{target + 3 * pix * v, grad + 3 * pix * v, inv_count, partial + seg};
+  render_tile_fwd<false, true>(sh, nullptr, splat + kSplatF4 * (size_t)v * ld, vals, ranges[seg],
+                               tx, ty, W, H, bg0, bg1, bg2,
+                               image ? image + 3 * pix * v : nullptr, final_T + pix * v,
+                               n_contrib + pix * v, nullptr, &o);
+}
+
+// loss += (sum of the per-tile partials) / count, in one block.
+__global__ __launch_bounds__(1024) void k_l1_tile_sum(const double* __restrict__ partial,
+                                                      uint32_t n, double inv_count,
+                                                      double* __restrict__ loss) {
+  __shared__ double s[16];
+  double acc = 0.0;
+  for (uint32_t i = threadIdx.x; i < n; i += 1024) acc += partial[i];
+  for (int off = 32; off >= 1; off >>= 1) acc += __shfl_xor(acc, off, 64);
+  if ((threadIdx.x & 63) == 0) s[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int w = 0; w < 16; ++w) t += s[w];
+    atomicAdd(loss, t * inv_count);
+  }
 }
 
 __global__ __launch_bounds__(64) void k_render_fwd_usage(
@@ -682,6 +750,30 @@ void launch_render_fwd(const gs_projected& proj, const gs_tile_lists& lists, int
                        reinterpret_cast<const float4*>(proj.splat), proj.ld, lists.vals,
                        reinterpret_cast<const uint2*>(lists.ranges), W, H, TX, tpv, bg[0], bg[1],
                        bg[2], image, final_T, n_contrib);
+}
+
+size_t render_fwd_l1_workspace_bytes(int V, int W, int H) {
+  return (size_t)V * (size_t)tiles_across(W) * (size_t)tiles_across(H) * sizeof(double);
+}
+
+void launch_render_fwd_l1(const gs_projected& proj, const gs_tile_lists& lists, int V, int W,
+                          int H, const float bg[3], const float* target, float* image,
+                          float* final_T, int32_t* n_contrib, float* grad, double* loss,
+                          void* ws, hipStream_t s) {
+  const int TX = tiles_across(W), TY = tiles_across(H);
+  const int tpv = TX * TY;
+  const int blocks = tpv * V;
+  if (blocks == 0) return;
+  const double count = 3.0 * (double)V * (double)W * (double)H;
+  double* partial = static_cast<double*>(ws);
+  StageScope scope(kStRenderFwd, s);
+  hipLaunchKernelGGL(k_render_fwd_l1, dim3(blocks), dim3(64), 0, s,
+                     reinterpret_cast<const float4*>(proj.splat), proj.ld, lists.vals,
+                     reinterpret_cast<const uint2*>(lists.ranges), W, H, TX, tpv, bg[0], bg[1],
+                     bg[2], image, final_T, n_contrib, target, grad, (float)(1.0 / count),
+                     partial);
+  hipLaunchKernelGGL(k_l1_tile_sum, dim3(1), dim3(1024), 0, s, (const double*)partial,
+                     (uint32_t)blocks, 1.0 / count, loss);
 }
 
 size_t render_batched_workspace_bytes(int V) {

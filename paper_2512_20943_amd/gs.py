@@ -109,6 +109,13 @@ def load() -> ctypes.CDLL:
     lib.gs_render_fwd.argtypes = [c_void_p, P(GsProjected), P(GsTileLists), P(GsCamera),
                                   c_void_p, ctypes.c_int, P(GsOpts), c_void_p, c_void_p,
                                   c_void_p, c_void_p]
+    lib.gs_render_fwd_l1_workspace_size.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int]
+    lib.gs_render_fwd_l1_workspace_size.restype = ctypes.c_size_t
+    lib.gs_render_fwd_l1.argtypes = [c_void_p, P(GsProjected), P(GsTileLists), P(GsCamera),
+                                     c_void_p, ctypes.c_int, P(GsOpts), c_void_p, c_void_p,
+                                     c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
+                                     ctypes.c_size_t, c_void_p]
+    lib.gs_render_fwd_l1.restype = c_int32
     lib.gs_render_bwd.argtypes = [c_void_p, P(GsGaussians), P(GsProjected), P(GsTileLists),
                                   P(GsCamera), c_void_p, ctypes.c_int, P(GsOpts), c_void_p,
                                   c_void_p, c_void_p, P(GsGaussians), P(GsFrameUpdate), c_void_p,
@@ -173,7 +180,8 @@ def exported_symbols():
             "gs_render_fwd_batched", "gs_sq_error", "gs_l1_dssim_workspace_size",
             "gs_l1_dssim_loss_grad", "gs_keyframe_temporal_l1", "gs_cull_workspace_size",
             "gs_cull_low_opacity", "gs_gather_planes", "gs_residual_delta",
-            "gs_quantize_delta", "gs_apply_quantized_update"]
+            "gs_quantize_delta", "gs_apply_quantized_update", "gs_render_fwd_l1_workspace_size",
+            "gs_render_fwd_l1"]
 
 
 def _ptr(t):
@@ -413,6 +421,25 @@ def gs_render_fwd(ctx: Context, proj: Projected, lists: TileLists, cams: Cameras
                                     cams.host, _ptr(cams.dev), cams.V, ctypes.byref(opts),
                                     _ptr(image), _ptr(final_T), _ptr(n_contrib),
                                     _stream(stream)))
+
+
+def render_fwd_l1_workspace_size(V: int, width: int, height: int) -> int:
+    return int(load().gs_render_fwd_l1_workspace_size(V, width, height))
+
+
+def gs_render_fwd_l1(ctx: Context, proj: Projected, lists: TileLists, cams: Cameras, bg,
+                     target: torch.Tensor, image: torch.Tensor | None, final_T: torch.Tensor,
+                     n_contrib: torch.Tensor, dL_dimage: torch.Tensor, loss_dev: torch.Tensor,
+                     workspace: torch.Tensor, stream=None):
+    """Forward fused with the L1 term: dL/dimage written, mean |image -
+    target| accumulated into ``loss_dev``; ``image`` may be None."""
+    pc = proj.c()
+    opts = GsOpts((c_float * 3)(*[float(x) for x in bg]), 0.0, None, None, None)
+    ctx.check(ctx.lib.gs_render_fwd_l1(ctx.handle, ctypes.byref(pc), ctypes.byref(lists.c()),
+                                       cams.host, _ptr(cams.dev), cams.V, ctypes.byref(opts),
+                                       _ptr(target), _ptr(image), _ptr(final_T),
+                                       _ptr(n_contrib), _ptr(dL_dimage), _ptr(loss_dev),
+                                       _ptr(workspace), workspace.numel(), _stream(stream)))
 
 
 def gs_render_fwd_batched(ctx: Context, proj: Projected, lists: TileLists, cams: Cameras, bg,

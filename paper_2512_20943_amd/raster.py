@@ -31,6 +31,7 @@ class Rasterizer:
         self._ws_sort = None
         self._proj = None
         self._ws_bwd = None
+        self._ws_l1 = None
 
     # -- buffers ------------------------------------------------------------
     def _projected(self, V, n, ld, device):
@@ -88,6 +89,26 @@ class Rasterizer:
         n_contrib = torch.empty(cams.V, H, W, dtype=torch.int32, device=device)
         gs.gs_render_fwd(self.ctx, proj, lists, cams, bg, image, final_T, n_contrib, stream,
                          usage=usage)
+        return dict(image=image, final_T=final_T, n_contrib=n_contrib, proj=proj, lists=lists)
+
+    def forward_l1(self, g: gs.Gaussians, cams: gs.Cameras, target: torch.Tensor,
+                   dL_dimage: torch.Tensor, loss: torch.Tensor, bg=(0.0, 0.0, 0.0), stream=None,
+                   keep_image=False):
+        """Forward with the L1 term of Eq. (1) fused into the compositing:
+        dL_dimage written, mean |image - target| added to ``loss``; the image
+        itself is written only with ``keep_image``."""
+        W, H = cams.wh[0]
+        device = g.mean.device
+        proj = self.project(g, cams, stream)
+        lists = self.bin_sort(proj, cams, stream)
+        image = torch.empty(cams.V, 3, H, W, device=device) if keep_image else None
+        final_T = torch.empty(cams.V, H, W, device=device)
+        n_contrib = torch.empty(cams.V, H, W, dtype=torch.int32, device=device)
+        need = gs.render_fwd_l1_workspace_size(cams.V, W, H)
+        if self._ws_l1 is None or self._ws_l1.numel() < need:
+            self._ws_l1 = torch.empty(need, dtype=torch.uint8, device=device)
+        gs.gs_render_fwd_l1(self.ctx, proj, lists, cams, bg, target.contiguous(), image, final_T,
+                            n_contrib, dL_dimage, loss, self._ws_l1, stream)
         return dict(image=image, final_T=final_T, n_contrib=n_contrib, proj=proj, lists=lists)
 
     def backward(self, g: gs.Gaussians, cams: gs.Cameras, state: dict, dL_dimage: torch.Tensor,

@@ -157,6 +157,66 @@ def test_render_forward_is_deterministic():
     assert torch.equal(a["n_contrib"], b["n_contrib"])
 
 
+@pytest.mark.parametrize("bg", [(0.0, 0.0, 0.0), (0.25, 0.5, 0.75)])
+def test_fused_forward_l1_equals_forward_then_l1(bg):
+    """gs_render_fwd_l1 gives the image, final_T and n_contrib of
+    gs_render_fwd and the gradient of gs_l1_loss_grad bit for bit (the same
+    FP32 operations), the loss to FP64 summation order; the oracle's L1 of
+    the GPU image pins the loss."""
+    require_gpu()
+    scene, cams = small_frame_workload(4)
+    g, gc, r, out = gpu_forward(scene, cams, bg)
+    ctx = gs.default_context()
+    gen = torch.Generator(device="cuda").manual_seed(5)
+    target = torch.rand(out["image"].shape, device="cuda", generator=gen)
+    d_ref = torch.empty_like(target)
+    loss_ref = torch.zeros(1, dtype=torch.float64, device="cuda")
+    gs.gs_l1_loss_grad(ctx, out["image"], target, d_ref, loss_ref)
+    for keep in (True, False):
+        d = torch.full_like(target, 7.0)
+        loss = torch.zeros(1, dtype=torch.float64, device="cuda")
+        out2 = r.forward_l1(g, gc, target, d, loss, bg, keep_image=keep)
+        torch.cuda.synchronize()
+        if keep:
+            assert torch.equal(out2["image"], out["image"])
+        else:
+            assert out2["image"] is None
+        assert torch.equal(out2["final_T"], out["final_T"])
+        assert torch.equal(out2["n_contrib"], out["n_contrib"])
+        assert torch.equal(d, d_ref)
+        assert abs(loss.item() - loss_ref.item()) <= 1e-12 * max(1.0, loss_ref.item())
+    loss_or, _ = oracle.l1(out["image"].cpu().numpy(), target.cpu().numpy())
+    assert abs(loss_ref.item() - loss_or) <= 1e-9
+
+
+def test_fused_forward_l1_rejects_bad_arguments():
+    require_gpu()
+    scene, cams = small_frame_workload(4)
+    g, gc, r, out = gpu_forward(scene, cams)
+    ctx = gs.default_context()
+    V, _, H, W = out["image"].shape
+    target = torch.zeros_like(out["image"])
+    d = torch.empty_like(target)
+    loss = torch.zeros(1, dtype=torch.float64, device="cuda")
+    need = gs.render_fwd_l1_workspace_size(V, W, H)
+    assert need == V * ((W + 15) // 16) * ((H + 15) // 16) * 8
+    ws = torch.empty(need + 256, dtype=torch.uint8, device="cuda")
+    proj, lists = out["proj"], out["lists"]
+
+    def call(tgt, workspace):
+        gs.gs_render_fwd_l1(ctx, proj, lists, gc, (0, 0, 0), tgt, None, out["final_T"],
+                            out["n_contrib"], d, loss, workspace)
+
+    for tgt, workspace, code in ((None, ws, gs.GS_ERR_INVALID_ARG),
+                                 (target, ws[:need - 8], gs.GS_ERR_OOM),
+                                 (target, ws[16:], gs.GS_ERR_INVALID_ARG)):
+        with pytest.raises(gs.GsError) as ei:
+            call(tgt, workspace)
+        assert ei.value.code == code
+    call(target, ws)
+    torch.cuda.synchronize()
+
+
 def _oracle_grads(scene, cams, P_or, L_or, img_or, seed):
     rng = np.random.default_rng(seed)
     target = rng.uniform(0, 1, size=img_or["image"].shape)
@@ -282,6 +342,30 @@ def test_l1_and_adam_match_closed_forms():
         gs.gs_adam_step(ctx, p_t, g_t, m_t, v_t, step)
     torch.cuda.synchronize()
     np.testing.assert_allclose(p_t.cpu().numpy(), ref, rtol=0, atol=1e-6)
+
+
+@pytest.mark.parametrize("count,offset", [(5003, 0), (5003, 1), (3_000_001, 0)])
+def test_l1_vector_and_scalar_paths(count, offset):
+    """The L1 kernel takes four values per step when the three buffers are
+    16-byte aligned and one at a time otherwise and in the tail; a grid of at
+    most 1024 blocks strides over large counts."""
+    require_gpu()
+    ctx = gs.default_context()
+    rng = np.random.default_rng(count + offset)
+    img = rng.uniform(0, 1, count).astype(np.float32)
+    tgt = img.copy()
+    tgt[::3] = rng.uniform(0, 1, tgt[::3].shape)
+    loss_or, g_or = oracle.l1(img, tgt)
+    img_d = torch.empty(count + offset, device="cuda")
+    tgt_d = torch.empty(count + offset, device="cuda")
+    grad = torch.empty(count + offset, device="cuda")
+    img_d[offset:] = torch.from_numpy(img).cuda()
+    tgt_d[offset:] = torch.from_numpy(tgt).cuda()
+    loss = torch.zeros(1, dtype=torch.float64, device="cuda")
+    gs.gs_l1_loss_grad(ctx, img_d[offset:], tgt_d[offset:], grad[offset:], loss)
+    torch.cuda.synchronize()
+    assert abs(loss.item() - loss_or) <= 1e-9
+    np.testing.assert_allclose(grad[offset:].cpu().numpy(), g_or, rtol=1e-6, atol=0)
 
 
 # ---------------------------------------------------------------------------
