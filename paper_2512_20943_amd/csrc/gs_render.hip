@@ -337,8 +337,8 @@ __global__ __launch_bounds__(64) void k_render_fwd(
   const int v = seg / tiles_per_view, tile = seg - v * tiles_per_view;
   const int ty = tile / TX, tx = tile - ty * TX;
   const size_t pix = (size_t)W * H;
-  render_tile_fwd<false>(sh, nullptr, splat + kSplatF4 * (size_t)v * ld, vals, ranges[seg], tx, ty, W,
-                         H, bg0, bg1, bg2, image + 3 * pix * v, final_T + pix * v,
+  render_tile_fwd<false>(sh, nullptr, splat + kSplatF4 * (size_t)v * ld, vals, ranges[seg], tx,
+                         ty, W, H, bg0, bg1, bg2, image + 3 * pix * v, final_T + pix * v,
                          n_contrib + pix * v, nullptr);
 }
 
@@ -390,9 +390,9 @@ __global__ __launch_bounds__(64) void k_render_fwd_usage(
   const int v = seg / tiles_per_view, tile = seg - v * tiles_per_view;
   const int ty = tile / TX, tx = tile - ty * TX;
   const size_t pix = (size_t)W * H;
-  render_tile_fwd<true>(sh, &us, splat + kSplatF4 * (size_t)v * ld, vals, ranges[seg], tx, ty, W, H, bg0,
-                        bg1, bg2, image + 3 * pix * v, final_T + pix * v, n_contrib + pix * v,
-                        usage);
+  render_tile_fwd<true>(sh, &us, splat + kSplatF4 * (size_t)v * ld, vals, ranges[seg], tx, ty,
+                        W, H, bg0, bg1, bg2, image + 3 * pix * v, final_T + pix * v,
+                        n_contrib + pix * v, usage);
 }
 
 // Per-request geometry for the batched renderer: segment base (V+1), pixel
@@ -440,9 +440,9 @@ __global__ __launch_bounds__(64) void k_render_persistent(
     const int TX = tiles_across(d.x);
     const int tile = (int)(item - seg_base[lo]);
     const int ty = tile / TX, tx = tile - ty * TX;
-    render_tile_fwd<false>(sh, nullptr, splat + kSplatF4 * (size_t)lo * ld, vals, ranges[item], tx, ty,
-                           d.x, d.y, bg0, bg1, bg2, images + 3 * pix_base[lo], nullptr, nullptr,
-                           nullptr);
+    render_tile_fwd<false>(sh, nullptr, splat + kSplatF4 * (size_t)lo * ld, vals, ranges[item],
+                           tx, ty, d.x, d.y, bg0, bg1, bg2, images + 3 * pix_base[lo], nullptr,
+                           nullptr, nullptr);
   }
 }
 
@@ -777,7 +777,8 @@ void launch_render_fwd_l1(const gs_projected& proj, const gs_tile_lists& lists, 
 }
 
 size_t render_batched_workspace_bytes(int V) {
-  return 256 + 256 * ((((size_t)V + 1) * 4 + 255) / 256) + 256 * ((((size_t)V + 1) * 8 + 255) / 256) +
+  return 256 + 256 * ((((size_t)V + 1) * 4 + 255) / 256) +
+         256 * ((((size_t)V + 1) * 8 + 255) / 256) +
          256 * (((size_t)V * 8 + 255) / 256);
 }
 

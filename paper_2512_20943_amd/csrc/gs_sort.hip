@@ -414,7 +414,9 @@ __global__ __launch_bounds__(kBlock) void k_depth_keys32(int n, int ld, int V,
 
 // View of a depth-sorted key: the high word of a 64-bit key, key / span of
 // a 32-bit one.
-__device__ __forceinline__ uint32_t view_of(uint64_t key, uint32_t) { return (uint32_t)(key >> 32); }
+__device__ __forceinline__ uint32_t view_of(uint64_t key, uint32_t) {
+  return (uint32_t)(key >> 32);
+}
 __device__ __forceinline__ uint32_t view_of(uint32_t key, uint32_t span) { return key / span; }
 
 // (view, depth) keys of every (view, Gaussian); culled ones sort last.
@@ -662,8 +664,8 @@ inline int depth_key_bits(int V) { return 32 + bits_for((uint64_t)V); }
 inline uint32_t cdiv(uint64_t a, uint64_t b) { return (uint32_t)((a + b - 1) / b); }
 
 struct Layout {
-  size_t dk0, dk1, dv0, dv1, cnt, offs, chunks, segk0, segk1, segv_alt, hist, digoff, counters, dparts,
-      lookback, seg_base, txv, total, stats, bytes;
+  size_t dk0, dk1, dv0, dv1, cnt, offs, chunks, segk0, segk1, segv_alt, hist, digoff, counters,
+      dparts, lookback, seg_base, txv, total, stats, bytes;
 };
 
 Layout make_layout(int V, int ld, int64_t cap, int64_t nseg) {
