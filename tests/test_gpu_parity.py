@@ -132,6 +132,24 @@ def test_projection_and_lists_bit_exact(which):
     np.testing.assert_array_equal(L_g["vals"], L_rep["vals"])
 
 
+def test_many_small_views_bit_exact():
+    """1,100 views of 16x16 pixels (one tile each) on an arc around 200
+    Gaussians: more views than the depth-range and key kernels have grid
+    rows below 1,024, and a (view, depth) range beyond 32-bit keys.  Lists
+    are bit-exact and images match the oracle."""
+    require_gpu()
+    scene = scenes.make_scene(200, 31, log_scale_mu=-2.5)
+    cams = scenes.arc_cameras(1100, 4.0, 16, 16, azimuth_deg=300.0)
+    g, gc, r, out = gpu_forward(scene, cams, capacity=1 << 20)
+    P_or, L_or, img_or = oracle.forward(scene, cams)
+    L_g = lists_to_numpy(out["lists"])
+    assert L_g["count"] == L_or["count"] > 0
+    np.testing.assert_array_equal(L_g["keys"], L_or["keys"])
+    np.testing.assert_array_equal(L_g["vals"], L_or["vals"])
+    np.testing.assert_array_equal(L_g["ranges"], L_or["ranges"])
+    compare_images(out, img_or)
+
+
 @pytest.mark.parametrize("which", ["plain_10k", "frame_20k_4v"])
 def test_render_forward_parity(which):
     require_gpu()
