@@ -300,7 +300,9 @@ gs_status gs_render_fwd_batched(gs_ctx* ctx, const gs_projected* proj,
 
 /* Backward of gs_project + gs_render_fwd for dL/dimage (V, 3, H, W):
  * transmittance is recovered by walking each pixel's list back from
- * n_contrib.  Gradients w.r.t. the frame's mean, log_scale, quat, opacity
+ * n_contrib.  proj and lists must be the ones gs_bin_sort last processed
+ * together (the backward reads the emission bases that call stores in the
+ * projected records).  Gradients w.r.t. the frame's mean, log_scale, quat, opacity
  * logit and SH, summed over views, are WRITTEN to `grad` (same shape as
  * `frame`) for i < n.  If `upd` is non-NULL, dL/d(delta images) (8, gh,
  * gw) is WRITTEN to dL_ddelta (zero at masked and padding texels). */
