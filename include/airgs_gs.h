@@ -115,15 +115,24 @@ typedef struct gs_opts {
  *       binning's emission order (written by gs_bin_sort, read by
  *       gs_render_bwd);
  *   rect (V, ld, 4) int32: tile rectangle [tx0, ty0, tx1, ty1), all 0 if culled;
+ *       with GS_PROJECT_TIGHT_RECT in `options` it is narrowed to the tiles
+ *       that meet the bounding box of the ellipse where alpha could reach
+ *       1/255 (with the quadrant test's margin): the lists then hold fewer
+ *       instances, every one dropped is skipped by every pixel of its tile,
+ *       so images and final_T are unchanged and n_contrib counts positions
+ *       in the shorter lists; a Gaussian whose opacity cannot reach 1/255
+ *       anywhere gets no tiles;
  *   tiles_touched (V, ld) int32: (tx1 - tx0) * (ty1 - ty0), 0 if culled;
  *   depth_bits (V, ld) uint32: bits of FP32(z);
  *   flags (V, ld) uint8: 1,2,4 colour channel clamped at 0; 8, 16 guard band
  *       clamp of x/z, y/z; 32 visible. */
+#define GS_PROJECT_TIGHT_RECT 1  /* gs_projected.options: opacity-aware rectangles */
+
 typedef struct gs_projected {
   int32_t n_views;
   int32_t n;       /* Gaussians per view (records i >= n are never read) */
   int32_t ld;
-  int32_t reserved;
+  int32_t options; /* 0 or GS_PROJECT_TIGHT_RECT (read by gs_project) */
   float* splat;
   int32_t* rect;
   int32_t* tiles_touched;

@@ -90,7 +90,7 @@ __global__ __launch_bounds__(256) void k_project(
     const float* __restrict__ quat, const float* __restrict__ opac, const float* __restrict__ sh,
     const gs_camera* __restrict__ cams, int n_views, float4* __restrict__ splat,
     int4* __restrict__ rect, int32_t* __restrict__ tiles, uint32_t* __restrict__ depth_bits,
-    uint8_t* __restrict__ flags) {
+    uint8_t* __restrict__ flags, bool tight) {
 #pragma clang fp contract(off)
   constexpr int K = (DEG + 1) * (DEG + 1);
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -190,11 +190,28 @@ __global__ __launch_bounds__(256) void k_project(
         const double lam = mid + sqrt(disc);
         const double rad = ceil(3.0 * sqrt(lam));
         const double TX = (double)tiles_across(cam.width), TY = (double)tiles_across(cam.height);
-        const double t0 = clampd(floor((px - rad) / (double)kTile), 0.0, TX);
-        const double t2 = clampd(floor((px + rad) / (double)kTile) + 1.0, 0.0, TX);
-        const double t1 = clampd(floor((py - rad) / (double)kTile), 0.0, TY);
-        const double t3 = clampd(floor((py + rad) / (double)kTile) + 1.0, 0.0, TY);
-        rc = make_int4((int)t0, (int)t1, (int)t2, (int)t3);
+        double t0 = clampd(floor((px - rad) / (double)kTile), 0.0, TX);
+        double t2 = clampd(floor((px + rad) / (double)kTile) + 1.0, 0.0, TX);
+        double t1 = clampd(floor((py - rad) / (double)kTile), 0.0, TY);
+        double t3 = clampd(floor((py + rad) / (double)kTile) + 1.0, 0.0, TY);
+        if (tight) {
+          // alpha >= 1/255 needs q = A dx^2 + 2B dx dy + C dy^2 <= 2 ln(255
+          // opacity); with the renderer's quadrant-test margin on top, the
+          // ellipse q <= thr has half-extents sqrt(thr C / Q), sqrt(thr A / Q)
+          const double qm = 2.0 * (log(255.0) + log((double)alpha_hat));
+          const double thr = qm + 2e-4 * fabs(qm) + 1e-3;
+          if (thr > 0.0) {
+            const double ex = sqrt(thr * C / detq), ey = sqrt(thr * A / detq);
+            t0 = fmax(t0, clampd(floor((px - ex) / (double)kTile), 0.0, TX));
+            t2 = fmin(t2, clampd(floor((px + ex) / (double)kTile) + 1.0, 0.0, TX));
+            t1 = fmax(t1, clampd(floor((py - ey) / (double)kTile), 0.0, TY));
+            t3 = fmin(t3, clampd(floor((py + ey) / (double)kTile) + 1.0, 0.0, TY));
+          } else {
+            t2 = t0;  // no pixel can reach alpha 1/255
+          }
+        }
+        rc = t2 > t0 && t3 > t1 ? make_int4((int)t0, (int)t1, (int)t2, (int)t3)
+                                : make_int4(0, 0, 0, 0);
         nt = (rc.z - rc.x) * (rc.w - rc.y);
         vis = nt > 0;
       }
@@ -486,7 +503,7 @@ void launch_project(const gs_gaussians& g, const gs_camera* cams, int V, const g
 #define GS_PROJ(D)                                                                           \
   hipLaunchKernelGGL(k_project<D>, dim3(blocks), dim3(256), 0, s, g.n, g.ld, g.mean,        \
                      g.log_scale, g.quat, g.opacity, g.sh, cams, V, sp, rc, o.tiles_touched, \
-                     o.depth_bits, o.flags)
+                     o.depth_bits, o.flags, (o.options & GS_PROJECT_TIGHT_RECT) != 0)
   switch (g.sh_degree) {
     case 0: GS_PROJ(0); break;
     case 1: GS_PROJ(1); break;

@@ -26,6 +26,7 @@ GS_ERR_OOM = 3
 GS_ERR_HIP = 4
 TILE = 16
 SPLAT_FLOATS = 16
+GS_PROJECT_TIGHT_RECT = 1
 GRAD2D_FLOATS = 12
 STAGE_COUNT = 18
 
@@ -51,7 +52,7 @@ class GsOpts(ctypes.Structure):
 
 
 class GsProjected(ctypes.Structure):
-    _fields_ = [("n_views", c_int32), ("n", c_int32), ("ld", c_int32), ("reserved", c_int32),
+    _fields_ = [("n_views", c_int32), ("n", c_int32), ("ld", c_int32), ("options", c_int32),
                 ("splat", c_void_p), ("rect", c_void_p), ("tiles_touched", c_void_p),
                 ("depth_bits", c_void_p), ("flags", c_void_p)]
 
@@ -337,6 +338,7 @@ class Projected:
     tiles_touched: torch.Tensor  # (V, ld) i32
     depth_bits: torch.Tensor     # (V, ld) i32 (uint32 bits)
     flags: torch.Tensor          # (V, ld) u8
+    options: int = 0             # GS_PROJECT_TIGHT_RECT: opacity-aware rectangles
 
     @staticmethod
     def empty(V: int, n: int, ld: int, device="cuda") -> "Projected":
@@ -349,11 +351,13 @@ class Projected:
     def slice(self, start: int, count: int) -> "Projected":
         return Projected(count, self.n, self.ld, self.splat[start:start + count],
                          self.rect[start:start + count], self.tiles_touched[start:start + count],
-                         self.depth_bits[start:start + count], self.flags[start:start + count])
+                         self.depth_bits[start:start + count], self.flags[start:start + count],
+                         self.options)
 
     def c(self) -> GsProjected:
-        return GsProjected(self.V, self.n, self.ld, 0, _ptr(self.splat), _ptr(self.rect),
-                           _ptr(self.tiles_touched), _ptr(self.depth_bits), _ptr(self.flags))
+        return GsProjected(self.V, self.n, self.ld, self.options, _ptr(self.splat),
+                           _ptr(self.rect), _ptr(self.tiles_touched), _ptr(self.depth_bits),
+                           _ptr(self.flags))
 
 
 class TileLists:
