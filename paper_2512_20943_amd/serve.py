@@ -117,7 +117,8 @@ class BatchWorker:
         self.bg = bg
         self.stream = torch.cuda.Stream(device=device)
         self.ctx = gs.Context(torch.cuda.current_device())
-        self.raster = Rasterizer(ctx=self.ctx, capacity=1 << 22)
+        # opacity-aware tile rectangles: same images, shorter lists
+        self.raster = Rasterizer(ctx=self.ctx, capacity=1 << 22, tight_rect=True)
         self.frames: list[gs.Gaussians] = []
         self._proj = None
         self._ws = None
@@ -131,6 +132,7 @@ class BatchWorker:
     def _projected(self, B):
         if self._proj is None or self._proj.V < B:
             self._proj = gs.Projected.empty(max(B, 8), self.seq.n, self.seq.anchor.ld, self.device)
+            self._proj.options = gs.GS_PROJECT_TIGHT_RECT
         return self._proj.slice(0, B)
 
     def render(self, reqs: list[Request]):
@@ -190,7 +192,7 @@ class PlainRenderer:
         self.bg = bg
         self.stream = torch.cuda.Stream(device=device)
         self.ctx = gs.Context(torch.cuda.current_device())
-        self.raster = Rasterizer(ctx=self.ctx, capacity=1 << 22)
+        self.raster = Rasterizer(ctx=self.ctx, capacity=1 << 22, tight_rect=True)
         self.frame = frame_of(seq.anchor)
 
     def render(self, r: Request) -> torch.Tensor:
