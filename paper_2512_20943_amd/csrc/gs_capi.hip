@@ -341,7 +341,7 @@ gs_status gs_bin_sort(gs_ctx* c, const gs_projected* proj, const gs_camera* ch,
   uint32_t* d_stats = nullptr;
   hipError_t e = gs::bin_sort_stage1(plan, *proj, cd, ws, s, &d_stats);
   if (e != hipSuccess) return hip_fail(c, e, "bin_sort (count)");
-  e = hipMemcpyAsync(c->pinned, d_stats, 4 * sizeof(uint32_t), hipMemcpyDeviceToHost, s);
+  e = hipMemcpyAsync(c->pinned, d_stats, 5 * sizeof(uint32_t), hipMemcpyDeviceToHost, s);
   if (e != hipSuccess) return hip_fail(c, e, "instance count readback");
   e = hipStreamSynchronize(s);
   if (e != hipSuccess) return hip_fail(c, e, "hipStreamSynchronize");
@@ -351,7 +351,8 @@ gs_status gs_bin_sort(gs_ctx* c, const gs_projected* proj, const gs_camera* ch,
   if (M > (uint64_t)lists->capacity)
     return fail(c, GS_ERR_CAPACITY, "instance count %llu exceeds capacity %lld",
                 (unsigned long long)M, (long long)lists->capacity);
-  e = gs::bin_sort_stage2(plan, *proj, cd, (uint32_t)M, dmin, dmax, *lists, ws, s);
+  const uint32_t n_visible = c->pinned[4];
+  e = gs::bin_sort_stage2(plan, *proj, cd, (uint32_t)M, dmin, dmax, n_visible, *lists, ws, s);
   if (e != hipSuccess) return hip_fail(c, e, "bin_sort (sort)");
   return GS_OK;
 }

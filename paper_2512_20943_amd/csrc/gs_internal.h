@@ -84,7 +84,7 @@ hipError_t bin_sort_stage1(const BinSortPlan& p, const gs_projected& proj,
                            uint32_t** d_stats);
 hipError_t bin_sort_stage2(const BinSortPlan& p, const gs_projected& proj,
                            const gs_camera* cams_dev, uint32_t M, uint32_t dmin, uint32_t dmax,
-                           gs_tile_lists& lists, void* ws, hipStream_t s);
+                           uint32_t n_visible, gs_tile_lists& lists, void* ws, hipStream_t s);
 // render
 void launch_render_fwd(const gs_projected& proj, const gs_tile_lists& lists, int n_views, int W,
                        int H, const float bg[3], float* image, float* final_T,

@@ -300,60 +300,59 @@ __global__ void k_view_info(const gs_camera* __restrict__ cams, int V, uint32_t*
   seg_base[V] = acc;
 }
 
-// Range of the depth bits of the visible (view, Gaussian) pairs and their
-// instance count, per block: part[block] = {min bits, max bits, count lo,
-// count hi}.
+// Per chunk of kCountChunk Gaussians of one view (grid x; views on grid y,
+// looping past 65535 of them), chunk c = v * gridDim.x + blockIdx.x: the
+// range of the depth bits of its visible pairs and their instance count,
+// part[c] = {min bits, max bits, count lo, count hi}, and the number of its
+// visible pairs, vis[c].  Thread t owns Gaussians 8t .. 8t + 7.
 __global__ __launch_bounds__(kBlock) void k_depth_range(int n, int ld, int V,
                                                         const uint32_t* __restrict__ depth_bits,
                                                         const int32_t* __restrict__ tiles,
-                                                        uint4* __restrict__ part) {
-  __shared__ uint32_t s_min[4], s_max[4];
+                                                        uint4* __restrict__ part,
+                                                        uint32_t* __restrict__ vis) {
+  __shared__ uint32_t s_min[4], s_max[4], s_cnt[4];
   __shared__ unsigned long long s_sum[4];
-  uint32_t mn = 0xFFFFFFFFu, mx = 0u;
-  unsigned long long sum = 0;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   for (int v = blockIdx.y; v < V; v += gridDim.y) {
     const int32_t* tv = tiles + (size_t)v * ld;
     const uint32_t* dv = depth_bits + (size_t)v * ld;
-    // eight entries per thread per round, loaded before they are used
-    constexpr int U = 8;
-    const uint32_t stride = gridDim.x * kBlock;
-    for (uint32_t i0 = blockIdx.x * kBlock + threadIdx.x; i0 < (uint32_t)n; i0 += U * stride) {
-      int t[U];
-      uint32_t d[U];
+    const uint32_t i0 = blockIdx.x * (uint32_t)kCountChunk + threadIdx.x * kCountItems;
+    uint32_t mn = 0xFFFFFFFFu, mx = 0u, cnt = 0u;
+    unsigned long long sum = 0;
 #pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const uint32_t i = i0 + u * stride;
-        t[u] = i < (uint32_t)n ? tv[i] : 0;
-        d[u] = i < (uint32_t)n ? dv[i] : 0u;
-      }
-#pragma unroll
-      for (int u = 0; u < U; ++u) {
-        if (t[u] > 0) {
-          mn = min(mn, d[u]);
-          mx = max(mx, d[u]);
-          sum += (unsigned long long)t[u];
-        }
+    for (int j = 0; j < kCountItems; ++j) {
+      const uint32_t i = i0 + j;
+      const int t = i < (uint32_t)n ? tv[i] : 0;
+      if (t > 0) {
+        const uint32_t d = dv[i];
+        mn = min(mn, d);
+        mx = max(mx, d);
+        sum += (unsigned long long)t;
+        ++cnt;
       }
     }
-  }
-  for (int off = 32; off >= 1; off >>= 1) {
-    mn = min(mn, (uint32_t)__shfl_xor((int)mn, off, 64));
-    mx = max(mx, (uint32_t)__shfl_xor((int)mx, off, 64));
-    sum += __shfl_xor(sum, off, 64);
-  }
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  if (lane == 0) {
-    s_min[wave] = mn;
-    s_max[wave] = mx;
-    s_sum[wave] = sum;
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    mn = min(min(s_min[0], s_min[1]), min(s_min[2], s_min[3]));
-    mx = max(max(s_max[0], s_max[1]), max(s_max[2], s_max[3]));
-    sum = (s_sum[0] + s_sum[1]) + (s_sum[2] + s_sum[3]);
-    part[blockIdx.y * gridDim.x + blockIdx.x] =
-        make_uint4(mn, mx, (uint32_t)sum, (uint32_t)(sum >> 32));
+    for (int off = 32; off >= 1; off >>= 1) {
+      mn = min(mn, (uint32_t)__shfl_xor((int)mn, off, 64));
+      mx = max(mx, (uint32_t)__shfl_xor((int)mx, off, 64));
+      sum += __shfl_xor(sum, off, 64);
+      cnt += (uint32_t)__shfl_xor((int)cnt, off, 64);
+    }
+    if (lane == 0) {
+      s_min[wave] = mn;
+      s_max[wave] = mx;
+      s_sum[wave] = sum;
+      s_cnt[wave] = cnt;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      mn = min(min(s_min[0], s_min[1]), min(s_min[2], s_min[3]));
+      mx = max(max(s_max[0], s_max[1]), max(s_max[2], s_max[3]));
+      sum = (s_sum[0] + s_sum[1]) + (s_sum[2] + s_sum[3]);
+      const size_t c = (size_t)v * gridDim.x + blockIdx.x;
+      part[c] = make_uint4(mn, mx, (uint32_t)sum, (uint32_t)(sum >> 32));
+      vis[c] = (s_cnt[0] + s_cnt[1]) + (s_cnt[2] + s_cnt[3]);
+    }
+    __syncthreads();
   }
 }
 
@@ -393,23 +392,53 @@ __global__ __launch_bounds__(kBlock) void k_stats_reduce(const uint4* __restrict
   }
 }
 
-// 32-bit (view, depth) keys when they fit: view * span + (bits - min bits),
-// culled pairs at span - 1 (last in their view).
+// Keys of the visible (view, Gaussian) pairs only, in (view, Gaussian)
+// order: chunk c (as in k_depth_range) writes its visible pairs from
+// chunk_off[c] on.  KeyOf(v, bits) gives the key.
+template <typename K, typename KeyOf>
+__device__ __forceinline__ void visible_keys(int n, int ld, int V,
+                                             const uint32_t* __restrict__ depth_bits,
+                                             const int32_t* __restrict__ tiles,
+                                             const uint32_t* __restrict__ chunk_off, KeyOf key,
+                                             K* __restrict__ keys, uint32_t* __restrict__ vals) {
+  __shared__ uint32_t s_wave[4];
+  for (int v = blockIdx.y; v < V; v += gridDim.y) {
+    const int32_t* tv = tiles + (size_t)v * ld;
+    const uint32_t* dv = depth_bits + (size_t)v * ld;
+    const uint32_t i0 = blockIdx.x * (uint32_t)kCountChunk + threadIdx.x * kCountItems;
+    uint32_t mask = 0, c = 0;
+#pragma unroll
+    for (int j = 0; j < kCountItems; ++j) {
+      const uint32_t i = i0 + j;
+      if (i < (uint32_t)n && tv[i] > 0) {
+        mask |= 1u << j;
+        ++c;
+      }
+    }
+    uint32_t r = chunk_off[(size_t)v * gridDim.x + blockIdx.x] +
+                 block_exclusive_scan(c, s_wave, nullptr);
+#pragma unroll
+    for (int j = 0; j < kCountItems; ++j) {
+      if (mask & (1u << j)) {
+        keys[r] = key((uint32_t)v, dv[i0 + j]);
+        vals[r] = i0 + j;
+        ++r;
+      }
+    }
+  }
+}
+
+// 32-bit (view, depth) keys when they fit: view * span + (bits - min bits).
 __global__ __launch_bounds__(kBlock) void k_depth_keys32(int n, int ld, int V,
                                                          const uint32_t* __restrict__ depth_bits,
                                                          const int32_t* __restrict__ tiles,
+                                                         const uint32_t* __restrict__ chunk_off,
                                                          uint32_t dmin, uint32_t span,
                                                          uint32_t* __restrict__ keys,
                                                          uint32_t* __restrict__ vals) {
-  const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
-  if (i >= (uint32_t)n) return;
-  for (uint32_t v = blockIdx.y; v < (uint32_t)V; v += gridDim.y) {
-    const size_t r = (size_t)v * ld + i;
-    const uint32_t j = v * (uint32_t)n + i;
-    const uint32_t rel = tiles[r] > 0 ? depth_bits[r] - dmin : span - 1u;
-    keys[j] = v * span + rel;
-    vals[j] = i;
-  }
+  visible_keys<uint32_t>(n, ld, V, depth_bits, tiles, chunk_off,
+                         [=](uint32_t v, uint32_t d) { return v * span + (d - dmin); }, keys,
+                         vals);
 }
 
 // View of a depth-sorted key: the high word of a 64-bit key, key / span of
@@ -419,21 +448,16 @@ __device__ __forceinline__ uint32_t view_of(uint64_t key, uint32_t) {
 }
 __device__ __forceinline__ uint32_t view_of(uint32_t key, uint32_t span) { return key / span; }
 
-// (view, depth) keys of every (view, Gaussian); culled ones sort last.
+// 64-bit (view << 32 | depth bits) keys otherwise.
 __global__ __launch_bounds__(kBlock) void k_depth_keys(int n, int ld, int V,
                                                        const uint32_t* __restrict__ depth_bits,
                                                        const int32_t* __restrict__ tiles,
+                                                       const uint32_t* __restrict__ chunk_off,
                                                        uint64_t* __restrict__ keys,
                                                        uint32_t* __restrict__ vals) {
-  const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
-  if (i >= (uint32_t)n) return;
-  for (uint32_t v = blockIdx.y; v < (uint32_t)V; v += gridDim.y) {
-    const size_t r = (size_t)v * ld + i;
-    const uint32_t j = v * (uint32_t)n + i;
-    const uint32_t d = tiles[r] > 0 ? depth_bits[r] : 0xFFFFFFFFu;
-    keys[j] = ((uint64_t)v << 32) | d;
-    vals[j] = i;
-  }
+  visible_keys<uint64_t>(n, ld, V, depth_bits, tiles, chunk_off,
+                         [](uint32_t v, uint32_t d) { return ((uint64_t)v << 32) | d; }, keys,
+                         vals);
 }
 
 // Instance count of each depth-sorted entry, and partial sums per chunk.
@@ -622,6 +646,7 @@ __global__ void k_stats_init(uint32_t* stats) {
     stats[1] = 0u;
     stats[2] = 0u;
     stats[3] = 0u;
+    stats[4] = 0u;
   }
 }
 
@@ -665,7 +690,7 @@ inline uint32_t cdiv(uint64_t a, uint64_t b) { return (uint32_t)((a + b - 1) / b
 
 struct Layout {
   size_t dk0, dk1, dv0, dv1, cnt, offs, chunks, segk0, segk1, segv_alt, hist, digoff, counters,
-      dparts, lookback, seg_base, txv, total, stats, bytes;
+      dparts, vparts, lookback, seg_base, txv, total, stats, bytes;
 };
 
 Layout make_layout(int V, int ld, int64_t cap, int64_t nseg) {
@@ -698,8 +723,11 @@ Layout make_layout(int V, int ld, int64_t cap, int64_t nseg) {
   L.seg_base = take(((size_t)V + 1) * 4);
   L.txv = take((size_t)V * 4);
   L.total = take(16);
-  L.stats = take(16);
-  L.dparts = take((size_t)std::max(1024, std::min(V, 65535)) * 16);
+  // {min bits, max bits, instances lo, hi, visible pairs}
+  L.stats = take(32);
+  const size_t nchunk = (size_t)V * cdiv((uint64_t)ld, kCountChunk);
+  L.dparts = take(nchunk * 16);
+  L.vparts = take((nchunk + 1) * 4);
   L.bytes = o;
   return L;
 }
@@ -783,13 +811,19 @@ hipError_t bin_sort_stage1(const BinSortPlan& p, const gs_projected& proj,
   hipLaunchKernelGGL(k_stats_init, dim3(1), dim3(1), 0, s, stats);
   if (N == 0) return hipGetLastError();
   StageScope scope(kStDepthSort, s);
-  // one grid row per view (views beyond 65535 loop), about 1024 blocks
+  // chunks of kCountChunk Gaussians per view; views on grid rows (beyond
+  // 65535 they loop)
+  const uint32_t gx = cdiv((uint64_t)p.n, kCountChunk);
   const uint32_t gy = std::min<uint32_t>((uint32_t)p.n_views, 65535u);
-  const uint32_t gx = std::max<uint32_t>(1u, std::min<uint32_t>(cdiv(p.n, kBlock), 1024u / gy));
+  const uint32_t nchunk = gx * (uint32_t)p.n_views;
   uint4* part = at<uint4>(ws, L.dparts);
+  uint32_t* vis = at<uint32_t>(ws, L.vparts);
   hipLaunchKernelGGL(k_depth_range, dim3(gx, gy), dim3(kBlock), 0, s, p.n, p.ld, p.n_views,
-                     proj.depth_bits, proj.tiles_touched, part);
-  hipLaunchKernelGGL(k_stats_reduce, dim3(1), dim3(kBlock), 0, s, part, (int)(gx * gy), stats);
+                     proj.depth_bits, proj.tiles_touched, part, vis);
+  hipLaunchKernelGGL(k_stats_reduce, dim3(1), dim3(kBlock), 0, s, part, (int)nchunk, stats);
+  // where each chunk's visible pairs go in the depth sort's input; stats[4]
+  // = their number
+  hipLaunchKernelGGL(k_chunk_scan, dim3(1), dim3(kBlock), 0, s, vis, nchunk, stats + 4);
   return hipGetLastError();
 }
 
@@ -807,13 +841,16 @@ void depth_count_emit(const BinSortPlan& p, const gs_projected& proj, const Layo
   int which;
   {
     StageScope scope(kStDepthSort, s);
-    const dim3 key_grid(cdiv(p.n, kBlock), std::min<uint32_t>((uint32_t)p.n_views, 65535u));
+    // keys of the visible pairs only (the chunk offsets from stage 1)
+    const dim3 key_grid(cdiv((uint64_t)p.n, kCountChunk),
+                        std::min<uint32_t>((uint32_t)p.n_views, 65535u));
+    const uint32_t* vis_off = at<uint32_t>(ws, L.vparts);
     if constexpr (sizeof(K) == 4)
-      hipLaunchKernelGGL(k_depth_keys32, key_grid, dim3(kBlock), 0, s, p.n, p.ld,
-                         p.n_views, proj.depth_bits, proj.tiles_touched, dmin, span, k0, dv0);
+      hipLaunchKernelGGL(k_depth_keys32, key_grid, dim3(kBlock), 0, s, p.n, p.ld, p.n_views,
+                         proj.depth_bits, proj.tiles_touched, vis_off, dmin, span, k0, dv0);
     else
-      hipLaunchKernelGGL(k_depth_keys, key_grid, dim3(kBlock), 0, s, p.n, p.ld,
-                         p.n_views, proj.depth_bits, proj.tiles_touched, k0, dv0);
+      hipLaunchKernelGGL(k_depth_keys, key_grid, dim3(kBlock), 0, s, p.n, p.ld, p.n_views,
+                         proj.depth_bits, proj.tiles_touched, vis_off, k0, dv0);
     which = radix_sort<K>(k0, k1, dv0, dv1, N, bits, ws, L, s);
   }
   const K* sk = which ? k1 : k0;
@@ -840,10 +877,9 @@ void depth_count_emit(const BinSortPlan& p, const gs_projected& proj, const Layo
 
 hipError_t bin_sort_stage2(const BinSortPlan& p, const gs_projected& proj,
                            const gs_camera* cams_dev, uint32_t M, uint32_t dmin, uint32_t dmax,
-                           gs_tile_lists& lists, void* ws, hipStream_t s) {
+                           uint32_t N, gs_tile_lists& lists, void* ws, hipStream_t s) {
   (void)cams_dev;
   const Layout L = make_layout(p.n_views, p.ld, p.capacity, p.n_segments);
-  const uint32_t N = (uint32_t)p.n_views * (uint32_t)p.n;
   launch_fill_u32(lists.ranges, 0u, 2 * p.n_segments, s);
   if (M == 0) return hipGetLastError();
   const int sbits = bits_for((uint64_t)p.n_segments);
@@ -855,7 +891,7 @@ hipError_t bin_sort_stage2(const BinSortPlan& p, const gs_projected& proj,
   uint32_t* v0 = (spasses & 1) ? alt : lists.vals;
   uint32_t* v1 = (spasses & 1) ? lists.vals : alt;
   // (view, depth) keys fit 32 bits when the views times the visible depth
-  // bit range (plus one slot for culled pairs) do
+  // bit range (plus one spare slot) do; only the N visible pairs are sorted
   const uint64_t span = (uint64_t)dmax - (uint64_t)dmin + 2u;
   const uint64_t range = (uint64_t)p.n_views * span;
   if (dmax >= dmin && range <= ((uint64_t)1 << 32))
