@@ -52,6 +52,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-frame-step", action="store_true")
+    ap.add_argument("--no-autograd-step", action="store_true")
     ap.add_argument("--views", type=int, default=20)
     ap.add_argument("--gaussians", type=int, default=300_000)
     ap.add_argument("--no-serve", action="store_true")
@@ -163,6 +164,42 @@ class TrainStep:
                             upd=(self.g.quat, self.mask, self.gw, self.gh), dL_ddelta=self.dd)
             gs.gs_adam_step(self.ctx, self.delta, self.dd, self.dm, self.dv, self.t)
         self.last = out
+
+
+class AutogradTrainStep:
+    """The same training step written as a user of torch.autograd would: the
+    hand-written backward behind GSRender and the L1 term behind GSL1Loss,
+    loss.backward(), then the Adam kernel on the flat parameter buffer."""
+
+    def __init__(self, ts):
+        import torch
+
+        from paper_2512_20943_amd.raster import GSL1Loss, GSRender
+        self.torch, self.gs, self.ts = torch, ts.gs, ts
+        self.ctx = ts.ctx
+        self.GSRender, self.GSL1Loss = GSRender, GSL1Loss
+        self.flat = ts.flat.detach().clone().requires_grad_(True)
+        self.m = torch.zeros_like(ts.m)
+        self.v = torch.zeros_like(ts.v)
+        self.t = 0
+        g = ts.g
+        self.meta = (ts.r, ts.cams, g.n, g.deg, (0.0, 0.0, 0.0))
+        self.shapes = ((3, g.ld), (3, g.ld), (4, g.ld), (g.ld,), ((g.deg + 1) ** 2, 3, g.ld))
+        self.last = None
+
+    def step(self):
+        self.t += 1
+        self.flat.grad = None
+        planes, o = [], 0
+        for shape in self.shapes:
+            cnt = math.prod(shape)
+            planes.append(self.flat[o:o + cnt].view(*shape))
+            o += cnt
+        image = self.GSRender.apply(*planes, self.meta)
+        loss = self.GSL1Loss.apply(image, self.ts.target, self.ctx)
+        loss.backward()
+        self.gs.gs_adam_step(self.ctx, self.flat.detach(), self.flat.grad, self.m, self.v,
+                             self.t)
 
 
 def time_steps(ts, steps, warmup):
@@ -401,6 +438,16 @@ def main():
         "stage_ms_per_step": stage_ms,
         "roofline": rf,
     }
+    if not args.no_autograd_step:
+        ag = AutogradTrainStep(ts)
+        k4 = max(args.steps // 2, 3)
+        wall4, _, st4 = time_steps(ag, k4, 2)
+        result["autograd_step"] = {
+            "iters_per_s": round(k4 / wall4, 4), "ms_per_step": round(wall4 / k4 * 1e3, 3),
+            "path": "GSRender and GSL1Loss torch.autograd.Functions, loss.backward(), Adam",
+            "stage_ms_per_step": {k: round(v[0] / k4, 4) for k, v in st4.items() if v[1] > 0}}
+        log(f"autograd step: {wall4 / k4 * 1e3:.2f} ms")
+        del ag
     del ts
     torch.cuda.empty_cache()
     if not args.no_frame_step:

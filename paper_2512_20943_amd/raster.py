@@ -146,6 +146,25 @@ class GSRender(torch.autograd.Function):
         return grad.mean, grad.log_scale, grad.quat, grad.opacity, grad.sh, None
 
 
+class GSL1Loss(torch.autograd.Function):
+    """loss = mean |image - target| (the L1 term of Eq. (1)) and its gradient
+    from gs_l1_loss_grad; the backward scales that gradient by the incoming
+    one."""
+
+    @staticmethod
+    def forward(ctx, image, target, gs_ctx):
+        grad = torch.empty_like(image)
+        loss = torch.zeros(1, dtype=torch.float64, device=image.device)
+        gs.gs_l1_loss_grad(gs_ctx, image.contiguous(), target.contiguous(), grad, loss)
+        ctx.save_for_backward(grad)
+        return loss[0]
+
+    @staticmethod
+    def backward(ctx, g):
+        (grad,) = ctx.saved_tensors
+        return grad * g.to(grad.dtype), None, None
+
+
 class GSFrameRender(torch.autograd.Function):
     """images = render(apply(anchor, delta, mask)); gradient to the (8, gh, gw)
     delta images, anchor frozen."""

@@ -412,6 +412,24 @@ def test_l1_and_adam_match_closed_forms():
     np.testing.assert_allclose(p_t.cpu().numpy(), ref, rtol=0, atol=1e-6)
 
 
+def test_l1_autograd_function_matches_oracle():
+    """GSL1Loss returns mean |image - target| and hands sign(d) / count,
+    scaled by the incoming gradient, back to the image."""
+    require_gpu()
+    from paper_2512_20943_amd.raster import GSL1Loss
+    ctx = gs.default_context()
+    rng = np.random.default_rng(10)
+    img = rng.uniform(0, 1, (2, 3, 17, 23)).astype(np.float32)
+    tgt = img.copy()
+    tgt[:, :, ::2] = rng.uniform(0, 1, tgt[:, :, ::2].shape)
+    loss_or, g_or = oracle.l1(img.ravel(), tgt.ravel())
+    x = torch.from_numpy(img).cuda().requires_grad_(True)
+    loss = GSL1Loss.apply(x, torch.from_numpy(tgt).cuda(), ctx)
+    (2.5 * loss).backward()
+    assert abs(loss.item() - loss_or) <= 1e-9
+    np.testing.assert_allclose(x.grad.cpu().numpy().ravel(), 2.5 * g_or, rtol=1e-6, atol=0)
+
+
 @pytest.mark.parametrize("count,offset", [(5003, 0), (5003, 1), (3_000_001, 0)])
 def test_l1_vector_and_scalar_paths(count, offset):
     """The L1 kernel takes four values per step when the three buffers are
