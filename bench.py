@@ -52,6 +52,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-frame-step", action="store_true")
+    # opacity-aware rectangles only, without the per-row spans (comparison)
+    ap.add_argument("--no-tile-spans", action="store_true")
     ap.add_argument("--no-autograd-step", action="store_true")
     ap.add_argument("--views", type=int, default=20)
     ap.add_argument("--gaussians", type=int, default=300_000)
@@ -81,7 +83,8 @@ def copy_calibration():
 class TrainStep:
     """One per-frame training iteration on a fixed scene and camera set."""
 
-    def __init__(self, scene, cams, target_scene, frame_update=None, loss="l1"):
+    def __init__(self, scene, cams, target_scene, frame_update=None, loss="l1",
+                 tile_spans=True):
         import torch
 
         from paper_2512_20943_amd import gs
@@ -113,10 +116,10 @@ class TrainStep:
         self.g = gs.Gaussians(n, deg, ld, *planes)
         self.grad = gs.Gaussians(n, deg, ld, *views(self.gflat))
         self.cams = gs.Cameras(cams)
-        # opacity-aware tile rectangles: the lists omit (Gaussian, tile) pairs
-        # that no pixel of the tile can composite; images and gradients are
-        # those of the full rectangles
-        self.r = Rasterizer(capacity=1 << 25, tight_rect=True)
+        # opacity-aware tile rectangles and per-row tile spans: the lists omit
+        # (Gaussian, tile) pairs that no pixel of the tile can composite;
+        # images and gradients are those of the full rectangles
+        self.r = Rasterizer(capacity=1 << 25, tight_rect=True, tile_spans=tile_spans)
         tg = gs.Gaussians.from_scene(target_scene)
         self.target = self.r.forward(tg, self.cams)["image"].clone()
         self.dimg = torch.empty_like(self.target)
@@ -417,7 +420,7 @@ def main():
     torch.cuda.set_device(0)
     log("generating the 300k-Gaussian frame workload")
     scene, cams, target_scene = scenes.workload_frame_300k(0, n=args.gaussians, n_views=args.views)
-    ts = TrainStep(scene, cams, target_scene)
+    ts = TrainStep(scene, cams, target_scene, tile_spans=not args.no_tile_spans)
     log(f"instances per step: {ts.r.forward(ts.g, ts.cams)['lists'].count}")
     wall, dev_s, stages = time_steps(ts, args.steps, args.warmup)
     ms_per_step = wall / args.steps * 1e3
@@ -434,7 +437,8 @@ def main():
                                f"{args.views} views 1352x1014, L1 + Adam",
                    "gaussians": args.gaussians, "views": args.views, "width": 1352,
                    "height": 1014, "instances_per_step": ts.last["lists"].count,
-                   "instances_full_rectangles": getattr(ts, "_def_instances", None)},
+                   "instances_full_rectangles": getattr(ts, "_def_instances", None),
+                   "tile_spans": not args.no_tile_spans},
         "stage_ms_per_step": stage_ms,
         "roofline": rf,
     }
@@ -455,7 +459,8 @@ def main():
         gw = gh = scenes.grid_side(n)
         d = scenes.make_delta(n, gw, gh, 1)
         mask = scenes.prune_mask(d, n, 0.3)
-        fs = TrainStep(scene, cams, target_scene, frame_update=(d, mask, gw, gh))
+        fs = TrainStep(scene, cams, target_scene, frame_update=(d, mask, gw, gh),
+                       tile_spans=not args.no_tile_spans)
         wall2, _, st2 = time_steps(fs, max(args.steps // 2, 3), 2)
         k2 = max(args.steps // 2, 3)
         result["frame_update_step"] = {
@@ -465,7 +470,8 @@ def main():
         log(f"frame-update step: {wall2 / k2 * 1e3:.2f} ms")
         del fs
     if not args.no_dssim_step:
-        ds = TrainStep(scene, cams, target_scene, loss="l1_dssim")
+        ds = TrainStep(scene, cams, target_scene, loss="l1_dssim",
+                       tile_spans=not args.no_tile_spans)
         k3 = max(args.steps // 2, 3)
         wall3, _, st3 = time_steps(ds, k3, 2)
         ms3, n3 = st3.get("dssim", (0.0, 0))

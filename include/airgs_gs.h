@@ -105,15 +105,16 @@ typedef struct gs_opts {
 
 /* Per (view, Gaussian) projection records, index v*ld + i:
  *   splat (V, ld, 16) FP32 words, 64 B per record:
- *       [px, py, A, B, C, opacity, r, g, b, depth, Q, 0, o, w, e, 0]
+ *       [px, py, A, B, C, opacity, r, g, b, depth, Q, 0, o, w, e, s]
  *       screen mean, conic (power = -(A dx^2 + C dy^2)/2 - B dx dy), opacity
  *       sigmoid(logit), clamped SH colour, camera-space depth, and the conic
  *       determinant Q = A C - B^2 (from FP64, used for cancellation-free
  *       evaluation of the quadratic form); words 12..15 are uint32 bit
  *       patterns: o = tx0 | ty0 << 16 and w = tx1 - tx0 of the tile rectangle
- *       (written by gs_project), e = the first instance of the pair in the
- *       binning's emission order (written by gs_bin_sort, read by
- *       gs_render_bwd);
+ *       (written by gs_project; w has bit 31 set when the record carries
+ *       tile spans, see GS_PROJECT_TILE_SPANS), e = the first instance of
+ *       the pair in the binning's emission order (written by gs_bin_sort,
+ *       read by gs_render_bwd), s = the tile spans or 0;
  *   rect (V, ld, 4) int32: tile rectangle [tx0, ty0, tx1, ty1), all 0 if culled;
  *       with GS_PROJECT_TIGHT_RECT in `options` it is narrowed to the tiles
  *       that meet the bounding box of the ellipse where alpha could reach
@@ -122,17 +123,27 @@ typedef struct gs_opts {
  *       so images and final_T are unchanged and n_contrib counts positions
  *       in the shorter lists; a Gaussian whose opacity cannot reach 1/255
  *       anywhere gets no tiles;
- *   tiles_touched (V, ld) int32: (tx1 - tx0) * (ty1 - ty0), 0 if culled;
+ *       with GS_PROJECT_TILE_SPANS (which implies the narrowed rectangle),
+ *       a pair whose rectangle is at most 4 tile rows tall and 15 tiles wide
+ *       keeps, in each tile row r, only the columns [tx0 + a_r, tx0 + b_r)
+ *       whose 16x16 pixel box meets that ellipse (computed exactly per row
+ *       band, with 1e-3 px of slack); byte r of record word 15 is
+ *       a_r | b_r << 4 (0 for an empty row), and the same reasoning keeps
+ *       images and final_T unchanged;
+ *   tiles_touched (V, ld) int32: the pair's instance count: (tx1 - tx0) *
+ *       (ty1 - ty0), or the sum of its spans, 0 if culled;
  *   depth_bits (V, ld) uint32: bits of FP32(z);
  *   flags (V, ld) uint8: 1,2,4 colour channel clamped at 0; 8, 16 guard band
  *       clamp of x/z, y/z; 32 visible. */
 #define GS_PROJECT_TIGHT_RECT 1  /* gs_projected.options: opacity-aware rectangles */
+#define GS_PROJECT_TILE_SPANS 2  /* gs_projected.options: ... and per-row tile spans */
 
 typedef struct gs_projected {
   int32_t n_views;
   int32_t n;       /* Gaussians per view (records i >= n are never read) */
   int32_t ld;
-  int32_t options; /* 0 or GS_PROJECT_TIGHT_RECT (read by gs_project) */
+  int32_t options; /* 0 or GS_PROJECT_TIGHT_RECT | GS_PROJECT_TILE_SPANS
+                      (read by gs_project) */
   float* splat;
   int32_t* rect;
   int32_t* tiles_touched;

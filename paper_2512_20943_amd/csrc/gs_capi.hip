@@ -292,7 +292,7 @@ gs_status gs_project(gs_ctx* c, const gs_gaussians* g, const gs_camera* ch, cons
   GS_TRY(check_cams(c, ch, cd, V));
   GS_TRY(check_projected(c, out, V, g->ld));
   if (out->n != g->n) return fail(c, GS_ERR_INVALID_ARG, "projected n != gaussians n");
-  if (out->options & ~GS_PROJECT_TIGHT_RECT)
+  if (out->options & ~(GS_PROJECT_TIGHT_RECT | GS_PROJECT_TILE_SPANS))
     return fail(c, GS_ERR_INVALID_ARG, "unknown projection options %d", out->options);
   GS_TRY(use_device(c));
   gs::launch_project(*g, cd, V, *out, (hipStream_t)stream);

@@ -24,6 +24,17 @@ constexpr int kSplatFloats = 12;    // projected record stride (3 x float4)
 constexpr int kGrad2dFloats = 12;   // screen-space gradient record stride
 constexpr int kSplatF4 = 4;         // float4s per projected record (64 B)
 
+// Per-row tile spans (GS_PROJECT_TILE_SPANS): a record whose opacity-aware
+// rectangle is at most kSpanRows tile rows tall and kSpanWidth tiles wide
+// keeps, per tile row r, only the columns [tx0 + a_r, tx0 + b_r) whose pixel
+// box meets the ellipse; byte r of record word 15 holds a_r | b_r << 4
+// (a_r = b_r = 0 for an empty row) and kSpanFlag is set in word 13.  Its
+// instances are emitted row by row over these spans.
+constexpr int kSpanRows = 4;
+constexpr int kSpanWidth = 15;
+constexpr double kSpanEps = 1e-3;   // px of slack on every span edge
+constexpr uint32_t kSpanFlag = 0x80000000u;
+
 __host__ __device__ inline int tiles_across(int px) { return (px + kTile - 1) / kTile; }
 
 // ---------------------------------------------------------------- timing

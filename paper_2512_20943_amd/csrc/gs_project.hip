@@ -90,7 +90,7 @@ __global__ __launch_bounds__(256) void k_project(
     const float* __restrict__ quat, const float* __restrict__ opac, const float* __restrict__ sh,
     const gs_camera* __restrict__ cams, int n_views, float4* __restrict__ splat,
     int4* __restrict__ rect, int32_t* __restrict__ tiles, uint32_t* __restrict__ depth_bits,
-    uint8_t* __restrict__ flags, bool tight) {
+    uint8_t* __restrict__ flags, bool tight, bool spans) {
 #pragma clang fp contract(off)
   constexpr int K = (DEG + 1) * (DEG + 1);
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -145,6 +145,8 @@ __global__ __launch_bounds__(256) void k_project(
     double px = 0, py = 0, A = 0, B = 0, C = 0, detq = 0;
     int4 rc = make_int4(0, 0, 0, 0);
     int nt = 0;
+    uint32_t span_word = 0;  // per-row tile spans, when span_mode
+    bool span_mode = false;
     if (vis) {
       // V = W S W^T, W = camera rotation
       double T1[9], Vm[9];
@@ -200,8 +202,11 @@ __global__ __launch_bounds__(256) void k_project(
           // ellipse q <= thr has half-extents sqrt(thr C / Q), sqrt(thr A / Q)
           const double qm = 2.0 * (log(255.0) + log((double)alpha_hat));
           const double thr = qm + 2e-4 * fabs(qm) + 1e-3;
+          double ex_thr = 0.0, ey_thr = 0.0;  // half-extents of that ellipse
           if (thr > 0.0) {
             const double ex = sqrt(thr * C / detq), ey = sqrt(thr * A / detq);
+            ex_thr = ex;
+            ey_thr = ey;
             t0 = fmax(t0, clampd(floor((px - ex) / (double)kTile), 0.0, TX));
             t2 = fmin(t2, clampd(floor((px + ex) / (double)kTile) + 1.0, 0.0, TX));
             t1 = fmax(t1, clampd(floor((py - ey) / (double)kTile), 0.0, TY));
@@ -209,10 +214,67 @@ __global__ __launch_bounds__(256) void k_project(
           } else {
             t2 = t0;  // no pixel can reach alpha 1/255
           }
+          rc = t2 > t0 && t3 > t1 ? make_int4((int)t0, (int)t1, (int)t2, (int)t3)
+                                  : make_int4(0, 0, 0, 0);
+          nt = (rc.z - rc.x) * (rc.w - rc.y);
+          if (spans && nt > 0 && rc.w - rc.y <= kSpanRows && rc.z - rc.x <= kSpanWidth) {
+            // Per tile row, the columns whose pixel box meets the same
+            // ellipse.  Row r takes the band of y within half a pixel of its
+            // pixel centres, so neighbouring rows share an edge: over a band,
+            // the ellipse's right end x(y) is concave with its maximum ex at
+            // y = dys (its rightmost point) and the left end is the mirror
+            // image, so each extreme is ex (or -ex) when that point lies in
+            // the band and otherwise the larger (smaller) of the band edges'
+            // values.  The hardware square root and reciprocal (relative
+            // error near 2^-23) move an end by under 2e-5 px at these sizes,
+            // inside the kSpanEps slack.
+            const double ey = ey_thr, iA = __builtin_amdgcn_rcp(A);
+            const double dys = -B * ex_thr / C;
+            const double ath = A * thr;
+            // ends of the ellipse's chord at offset dy (clamped into it)
+            auto chord = [&](double dy, double& xl, double& xr) {
+              const double y = clampd(dy, -ey, ey);
+              const double hw = __builtin_amdgcn_sqrt(fmax(0.0, ath - detq * y * y));
+              xr = (-B * y + hw) * iA;
+              xl = (-B * y - hw) * iA;
+              return y;
+            };
+            double e0 = (double)(rc.y * kTile) - 0.5 - py;
+            double xl0, xr0;
+            double y0 = chord(e0, xl0, xr0);
+            uint32_t packed = 0;
+            int cnt = 0;
+            for (int r = 0; r < rc.w - rc.y; ++r) {
+              const double e1 = e0 + (double)kTile;
+              double xl1, xr1;
+              const double y1 = chord(e1, xl1, xr1);
+              if (!(e0 > ey + kSpanEps || e1 < -ey - kSpanEps)) {
+                const double xmax = (dys >= y0 && dys <= y1) ? ex_thr : fmax(xr0, xr1);
+                const double xmin = (-dys >= y0 && -dys <= y1) ? -ex_thr : fmin(xl0, xl1);
+                const double xs = fmax(t0, ceil((px + xmin - kSpanEps - (double)(kTile - 1)) *
+                                                (1.0 / kTile)));
+                const double xe = fmin(t2, floor((px + xmax + kSpanEps) * (1.0 / kTile)) + 1.0);
+                if (xe > xs) {
+                  const uint32_t a0 = (uint32_t)(xs - t0), a1 = (uint32_t)(xe - t0);
+                  packed |= (a0 | a1 << 4) << (8 * r);
+                  cnt += (int)(a1 - a0);
+                }
+              }
+              e0 = e1;
+              y0 = y1;
+              xl0 = xl1;
+              xr0 = xr1;
+            }
+            span_word = packed;
+            span_mode = true;
+            nt = cnt;
+            if (nt == 0) rc = make_int4(0, 0, 0, 0);
+          }
+        } else {
+          rc = t2 > t0 && t3 > t1 ? make_int4((int)t0, (int)t1, (int)t2, (int)t3)
+                                  : make_int4(0, 0, 0, 0);
+          nt = (rc.z - rc.x) * (rc.w - rc.y);
         }
-        rc = t2 > t0 && t3 > t1 ? make_int4((int)t0, (int)t1, (int)t2, (int)t3)
-                                : make_int4(0, 0, 0, 0);
-        nt = (rc.z - rc.x) * (rc.w - rc.y);
         vis = nt > 0;
       }
     }
@@ -245,7 +307,8 @@ __global__ __launch_bounds__(256) void k_project(
       // tile rectangle for the backward's instance rows (the emission base,
       // component z, is filled in by the binning)
       o3 = make_float4(__uint_as_float((uint32_t)rc.x | ((uint32_t)rc.y << 16)),
-                       __uint_as_float((uint32_t)(rc.z - rc.x)), 0.f, 0.f);
+                       __uint_as_float((uint32_t)(rc.z - rc.x) | (span_mode ? kSpanFlag : 0u)),
+                       0.f, __uint_as_float(span_word));
     } else {
       fl = 0;
       rc = make_int4(0, 0, 0, 0);
@@ -503,7 +566,9 @@ void launch_project(const gs_gaussians& g, const gs_camera* cams, int V, const g
 #define GS_PROJ(D)                                                                           \
   hipLaunchKernelGGL(k_project<D>, dim3(blocks), dim3(256), 0, s, g.n, g.ld, g.mean,        \
                      g.log_scale, g.quat, g.opacity, g.sh, cams, V, sp, rc, o.tiles_touched, \
-                     o.depth_bits, o.flags, (o.options & GS_PROJECT_TIGHT_RECT) != 0)
+                     o.depth_bits, o.flags,                                              \
+                     (o.options & (GS_PROJECT_TIGHT_RECT | GS_PROJECT_TILE_SPANS)) != 0,    \
+                     (o.options & GS_PROJECT_TILE_SPANS) != 0)
   switch (g.sh_degree) {
     case 0: GS_PROJ(0); break;
     case 1: GS_PROJ(1); break;

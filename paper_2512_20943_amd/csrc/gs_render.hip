@@ -450,12 +450,22 @@ __global__ __launch_bounds__(64) void k_render_persistent(
 constexpr int kRowFloats = 9;  // per-instance gradient row
 
 // Index of the instance of a (view, Gaussian) in tile (tx, ty): the binning
-// emits its tiles row by row over its tile rectangle, starting at the base it
-// stores in the record's fourth float4 = (tx0 | ty0 << 16, width, base, 0).
+// emits its tiles row by row, starting at the base it stores in the record's
+// fourth float4 = (tx0 | ty0 << 16, width | kSpanFlag, base, spans): over the
+// whole rectangle, or, with the flag, over columns [tx0 + a_r, tx0 + b_r) of
+// row r (byte r of spans = a_r | b_r << 4, at most four rows).
 __device__ __forceinline__ uint32_t instance_row(float4 q3, int tx, int ty) {
   const uint32_t o = __float_as_uint(q3.x), w = __float_as_uint(q3.y),
-                 base = __float_as_uint(q3.z);
-  return base + ((uint32_t)ty - (o >> 16)) * w + ((uint32_t)tx - (o & 0xFFFFu));
+                 base = __float_as_uint(q3.z), m = __float_as_uint(q3.w);
+  const uint32_t r = (uint32_t)ty - (o >> 16), c = (uint32_t)tx - (o & 0xFFFFu);
+  if (w & kSpanFlag) {
+    // instances in the rows above: the byte sum of the spans b - a below row r
+    const uint32_t sp = ((m >> 4) & 0x0F0F0F0Fu) - (m & 0x0F0F0F0Fu);
+    const uint32_t sh = 8u * r;
+    const uint32_t pre = ((sp & ((1u << sh) - 1u)) * 0x01010101u) >> 24;
+    return base + pre + c - ((m >> sh) & 15u);
+  }
+  return base + r * w + c;
 }
 
 // Row sums of an entry: value cc of row r at acc[entry * kAccStride + 4 cc + r]

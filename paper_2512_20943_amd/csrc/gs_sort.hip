@@ -525,8 +525,10 @@ __global__ __launch_bounds__(kBlock) void k_count_scan(uint32_t N, const uint32_
 }
 
 // Emit (segment, Gaussian id) for each tile of each depth-sorted entry, row
-// by row over its tile rectangle; optionally record where each (view,
-// Gaussian) starts in this order.  Each wave takes 64 consecutive entries,
+// by row over its tile rectangle, or over its per-row spans when the record
+// carries them (the rectangle and spans come from the record's words 12, 13
+// and 15); optionally record where each (view, Gaussian) starts in this
+// order.  Each wave takes 64 consecutive entries,
 // whose instances form one contiguous output range, and spreads that range
 // over its lanes (instance f on lane f mod 64), so that large and small
 // rectangles balance and the stores coalesce.
@@ -536,7 +538,6 @@ __global__ __launch_bounds__(kBlock) void k_emit(uint32_t N, int ld, uint32_t sp
                                                  const uint32_t* __restrict__ vals,
                                                  const uint32_t* __restrict__ cnt,
                                                  const uint32_t* __restrict__ offs,
-                                                 const int4* __restrict__ rect,
                                                  const uint32_t* __restrict__ seg_base,
                                                  const int32_t* __restrict__ txv,
                                                  uint32_t* __restrict__ seg_out,
@@ -546,7 +547,8 @@ __global__ __launch_bounds__(kBlock) void k_emit(uint32_t N, int ld, uint32_t sp
   __shared__ uint32_t s_pre[4][64];
   __shared__ uint32_t s_seg0[4][64];  // segment of the rectangle's first tile
   __shared__ uint32_t s_id[4][64];
-  __shared__ uint32_t s_w[4][64];     // rectangle width in tiles
+  __shared__ uint32_t s_w[4][64];     // rectangle width in tiles | kSpanFlag
+  __shared__ uint32_t s_sp[4][64];    // per-row spans (record word 15)
   __shared__ uint32_t s_row[4][64];   // tiles per view row
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const uint32_t e = blockIdx.x * kBlock + threadIdx.x;
@@ -556,15 +558,17 @@ __global__ __launch_bounds__(kBlock) void k_emit(uint32_t N, int ld, uint32_t sp
     o0 = offs[e];
     if (c > 0) {
       const uint32_t v = view_of(keys[e], span), g = vals[e];
-      const int4 r = rect[(size_t)v * ld + g];
-      const int tx = txv[v];
-      s_seg0[wave][lane] = seg_base[v] + (uint32_t)(r.y * tx + r.x);
+      uint32_t* rw = splat_words + ((size_t)v * ld + g) * (4 * kSplatF4) + 12;
+      const uint4 q3 = *reinterpret_cast<const uint4*>(rw);  // o, w | flag, e, spans
+      const uint32_t tx = (uint32_t)txv[v];
+      s_seg0[wave][lane] = seg_base[v] + (q3.x >> 16) * tx + (q3.x & 0xFFFFu);
       s_id[wave][lane] = g;
-      s_w[wave][lane] = (uint32_t)(r.z - r.x);
-      s_row[wave][lane] = (uint32_t)tx;
+      s_w[wave][lane] = q3.y;
+      s_sp[wave][lane] = q3.w;
+      s_row[wave][lane] = tx;
       if (gv_base) gv_base[(size_t)v * ld + g] = o0;
       // record word 14: this pair's first instance in emission order
-      splat_words[((size_t)v * ld + g) * (4 * kSplatF4) + 14] = o0;
+      rw[2] = o0;
     }
   }
   // the wave's entries own output [first, first + total)
@@ -584,7 +588,20 @@ __global__ __launch_bounds__(kBlock) void k_emit(uint32_t N, int ld, uint32_t sp
       if (s_pre[wave][q + step] <= f) q += step;
     const uint32_t l = f - s_pre[wave][q];
     const uint32_t w = s_w[wave][q];
-    const uint32_t dy = l / w, dx = l - dy * w;
+    uint32_t dy, dx;
+    if (w & kSpanFlag) {
+      // spans s_r = b_r - a_r per byte; instances before row r: p_r
+      const uint32_t m = s_sp[wave][q];
+      const uint32_t sp = ((m >> 4) & 0x0F0F0F0Fu) - (m & 0x0F0F0F0Fu);
+      const uint32_t p1 = sp & 0xFFu, p2 = p1 + ((sp >> 8) & 0xFFu),
+                     p3 = p2 + ((sp >> 16) & 0xFFu);
+      dy = (uint32_t)(l >= p1) + (uint32_t)(l >= p2) + (uint32_t)(l >= p3);
+      const uint32_t pre = dy == 0 ? 0u : (dy == 1 ? p1 : (dy == 2 ? p2 : p3));
+      dx = ((m >> (8 * dy)) & 15u) + (l - pre);
+    } else {
+      dy = l / w;
+      dx = l - dy * w;
+    }
     seg_out[first + f] = s_seg0[wave][q] + dy * s_row[wave][q] + dx;
     id_out[first + f] = s_id[wave][q];
   }
@@ -869,8 +886,7 @@ void depth_count_emit(const BinSortPlan& p, const gs_projected& proj, const Layo
   }
   StageScope scope(kStEmit, s);
   hipLaunchKernelGGL((k_emit<K>), dim3(cdiv(N, kBlock)), dim3(kBlock), 0, s, N, p.ld, span, sk,
-                     sv, cnt, at<uint32_t>(ws, L.offs), reinterpret_cast<const int4*>(proj.rect),
-                     at<uint32_t>(ws, L.seg_base), at<int32_t>(ws, L.txv), segk0, v0, gv_base,
+                     sv, cnt, at<uint32_t>(ws, L.offs), at<uint32_t>(ws, L.seg_base), at<int32_t>(ws, L.txv), segk0, v0, gv_base,
                      reinterpret_cast<uint32_t*>(proj.splat));
 }
 }  // namespace

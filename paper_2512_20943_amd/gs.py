@@ -27,6 +27,7 @@ GS_ERR_HIP = 4
 TILE = 16
 SPLAT_FLOATS = 16
 GS_PROJECT_TIGHT_RECT = 1
+GS_PROJECT_TILE_SPANS = 2
 GRAD2D_FLOATS = 12
 STAGE_COUNT = 18
 
@@ -338,7 +339,7 @@ class Projected:
     tiles_touched: torch.Tensor  # (V, ld) i32
     depth_bits: torch.Tensor     # (V, ld) i32 (uint32 bits)
     flags: torch.Tensor          # (V, ld) u8
-    options: int = 0             # GS_PROJECT_TIGHT_RECT: opacity-aware rectangles
+    options: int = 0             # GS_PROJECT_TIGHT_RECT | GS_PROJECT_TILE_SPANS
 
     @staticmethod
     def empty(V: int, n: int, ld: int, device="cuda") -> "Projected":

@@ -85,7 +85,8 @@ class PruningSweep:
         self.cams = cams
         self.levels = np.linspace(0.0, 1.0, 11) if levels is None else np.asarray(levels)
         # opacity-aware tile rectangles: same images and usage, shorter lists
-        self.raster = Rasterizer(ctx=self.ctx, capacity=1 << 22, tight_rect=True)
+        self.raster = Rasterizer(ctx=self.ctx, capacity=1 << 22, tight_rect=True,
+                                 tile_spans=True)
 
     def usage(self, bg=(0.0, 0.0, 0.0)):
         """Reference render of the unpruned frame and per-Gaussian usage."""
@@ -119,7 +120,7 @@ class PruningSweep:
                               np.array([h.fx, h.fy, h.cx, h.cy]), (h.width, h.height)))
         cams = gs.Cameras.from_list(items, dev)
         proj = gs.Projected.empty(L * V, n, self.anchor.ld, dev)
-        proj.options = gs.GS_PROJECT_TIGHT_RECT
+        proj.options = gs.GS_PROJECT_TIGHT_RECT | gs.GS_PROJECT_TILE_SPANS
         for k, f in enumerate(frames):
             gs.gs_project(self.ctx, f, cams.slice(k * V, V), proj.slice(k * V, V))
         lists = self.raster.bin_sort(proj, cams)

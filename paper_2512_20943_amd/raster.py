@@ -18,11 +18,14 @@ from . import gs
 class Rasterizer:
     def __init__(self, ctx: gs.Context | None = None, capacity: int = 1 << 20,
                  with_keys: bool = False, growth: float = 1.25,
-                 emission_bases: bool = False, tight_rect: bool = False):
+                 emission_bases: bool = False, tight_rect: bool = False,
+                 tile_spans: bool = False):
         self.ctx = ctx or gs.default_context()
         # opacity-aware tile rectangles: same images and gradients, shorter
-        # lists (GS_PROJECT_TIGHT_RECT)
+        # lists (GS_PROJECT_TIGHT_RECT); with tile_spans also the per-row
+        # spans of small rectangles (GS_PROJECT_TILE_SPANS)
         self.tight_rect = tight_rect
+        self.tile_spans = tile_spans
         self.capacity = int(capacity)
         self.with_keys = with_keys
         # also store each pair's first instance index in lists.gv_base (the
@@ -41,7 +44,8 @@ class Rasterizer:
         p = self._proj
         if p is None or p.V != V or p.n != n or p.ld != ld:
             self._proj = gs.Projected.empty(V, n, ld, device)
-        self._proj.options = gs.GS_PROJECT_TIGHT_RECT if self.tight_rect else 0
+        self._proj.options = ((gs.GS_PROJECT_TIGHT_RECT if self.tight_rect else 0)
+                              | (gs.GS_PROJECT_TILE_SPANS if self.tile_spans else 0))
         return self._proj
 
     def _sort_buffers(self, V, ld, nseg, device):

@@ -118,7 +118,8 @@ class BatchWorker:
         self.stream = torch.cuda.Stream(device=device)
         self.ctx = gs.Context(torch.cuda.current_device())
         # opacity-aware tile rectangles: same images, shorter lists
-        self.raster = Rasterizer(ctx=self.ctx, capacity=1 << 22, tight_rect=True)
+        self.raster = Rasterizer(ctx=self.ctx, capacity=1 << 22, tight_rect=True,
+                                 tile_spans=True)
         self.frames: list[gs.Gaussians] = []
         self._proj = None
         self._ws = None
@@ -132,7 +133,7 @@ class BatchWorker:
     def _projected(self, B):
         if self._proj is None or self._proj.V < B:
             self._proj = gs.Projected.empty(max(B, 8), self.seq.n, self.seq.anchor.ld, self.device)
-            self._proj.options = gs.GS_PROJECT_TIGHT_RECT
+            self._proj.options = gs.GS_PROJECT_TIGHT_RECT | gs.GS_PROJECT_TILE_SPANS
         return self._proj.slice(0, B)
 
     def render(self, reqs: list[Request]):
@@ -192,7 +193,8 @@ class PlainRenderer:
         self.bg = bg
         self.stream = torch.cuda.Stream(device=device)
         self.ctx = gs.Context(torch.cuda.current_device())
-        self.raster = Rasterizer(ctx=self.ctx, capacity=1 << 22, tight_rect=True)
+        self.raster = Rasterizer(ctx=self.ctx, capacity=1 << 22, tight_rect=True,
+                                 tile_spans=True)
         self.frame = frame_of(seq.anchor)
 
     def render(self, r: Request) -> torch.Tensor:

@@ -133,12 +133,14 @@ def test_projection_and_lists_bit_exact(which):
 
 
 @pytest.mark.parametrize("which", ["plain_10k", "frame_20k_4v"])
-def test_tight_rectangles_keep_images_and_gradients(which):
+@pytest.mark.parametrize("mode", ["tight", "spans"])
+def test_tight_rectangles_keep_images_and_gradients(which, mode):
     """With GS_PROJECT_TIGHT_RECT the rectangles shrink to the tiles the
-    alpha >= 1/255 ellipse can reach: images and final_T are bit-identical to
-    the full rectangles', the kept instances appear in the full lists in the
-    same order, and the gradients agree up to FP32 summation order (only
-    all-zero gradient rows are dropped)."""
+    alpha >= 1/255 ellipse can reach, and with GS_PROJECT_TILE_SPANS small
+    rectangles keep, per tile row, only the columns that meet it: images and
+    final_T are bit-identical to the full rectangles', the kept instances
+    appear in the full lists in the same order, and the gradients agree up to
+    FP32 summation order (only all-zero gradient rows are dropped)."""
     require_gpu()
     if which == "plain_10k":
         scene, cams, _ = scenes.workload_plain_10k(0)
@@ -148,8 +150,8 @@ def test_tight_rectangles_keep_images_and_gradients(which):
     gc = gs.Cameras(cams)
     outs, grads = [], []
     gen = torch.Generator(device="cuda").manual_seed(3)
-    for tight in (False, True):
-        r = Rasterizer(capacity=1 << 20, with_keys=True, tight_rect=tight)
+    for tight, spans in ((False, False), (True, False), (True, mode == "spans")):
+        r = Rasterizer(capacity=1 << 20, with_keys=True, tight_rect=tight, tile_spans=spans)
         out = r.forward(g, gc)
         if not outs:
             dimg = torch.randn(out["image"].shape, device="cuda", generator=gen)
@@ -158,12 +160,20 @@ def test_tight_rectangles_keep_images_and_gradients(which):
         torch.cuda.synchronize()
         outs.append(out)
         grads.append(grad)
-    full, tight = outs
+    full, rect_only, tight = outs
     assert torch.equal(tight["image"], full["image"])
     assert torch.equal(tight["final_T"], full["final_T"])
     Lf, Lt = lists_to_numpy(full["lists"]), lists_to_numpy(tight["lists"])
-    assert 0 < Lt["count"] < Lf["count"]
-    say(f"  tight rectangles keep {Lt['count']} of {Lf['count']} instances")
+    Lr = lists_to_numpy(rect_only["lists"])
+    assert 0 < Lt["count"] <= Lr["count"] < Lf["count"]
+    say(f"  {mode}: keep {Lt['count']} of {Lf['count']} instances")
+    tt = tight["proj"].tiles_touched.cpu().numpy()[:, :g.n]
+    assert int(tt.sum()) == Lt["count"]
+    if mode == "spans":
+        assert Lt["count"] < Lr["count"]
+        w13 = tight["proj"].splat.view(torch.int32).cpu().numpy()[:, :g.n, 13]
+        flagged = (w13 < 0) & (tt > 0)
+        assert flagged.any()
     # kept instances, in order, among the full lists' (key, id) pairs
     kf = (Lf["keys"].astype(object) << 32) | Lf["vals"].astype(object)
     kt = (Lt["keys"].astype(object) << 32) | Lt["vals"].astype(object)
@@ -171,12 +181,12 @@ def test_tight_rectangles_keep_images_and_gradients(which):
     assert np.all(pos < len(kf)) and np.array_equal(kf[pos], kt)
     rf = full["proj"].rect.cpu().numpy()
     rt = tight["proj"].rect.cpu().numpy()
-    vis = tight["proj"].tiles_touched.cpu().numpy()[:, :g.n] > 0
+    vis = tt > 0
     inside = ((rt[:, :g.n, 0] >= rf[:, :g.n, 0]) & (rt[:, :g.n, 1] >= rf[:, :g.n, 1]) &
               (rt[:, :g.n, 2] <= rf[:, :g.n, 2]) & (rt[:, :g.n, 3] <= rf[:, :g.n, 3]))
     assert np.all(inside[vis])
     for name in ("mean", "log_scale", "quat", "opacity", "sh"):
-        a = getattr(grads[1], name).cpu().numpy()
+        a = getattr(grads[2], name).cpu().numpy()
         b = getattr(grads[0], name).cpu().numpy()
         np.testing.assert_allclose(a, b, rtol=1e-4, atol=1e-6 * max(1.0, np.abs(b).max()),
                                    err_msg=name)

@@ -61,3 +61,18 @@ def test_product_package_does_not_import_the_oracle():
                 src = open(os.path.join(dirpath, fn)).read()
                 assert "import oracle" not in src and "from oracle" not in src, fn
                 assert "gs_oracle" not in src, fn
+
+
+def test_binding_constants_match_header():
+    """Every numeric #define of the header that the binding mirrors (status
+    codes, tile size, record stride, projection options) has its value."""
+    import paper_2512_20943_amd.gs as gsmod
+    text = open(HEADER).read()
+    defines = dict(re.findall(r"#define\s+(GS_[A-Z0-9_]+)\s+(-?\d+)\b", text))
+    assert "GS_PROJECT_TILE_SPANS" in defines and "GS_PROJECT_TIGHT_RECT" in defines
+    checked = 0
+    for name, value in defines.items():
+        if hasattr(gsmod, name):
+            assert getattr(gsmod, name) == int(value), name
+            checked += 1
+    assert checked >= 2
