@@ -59,6 +59,8 @@ def parse():
     ap.add_argument("--gaussians", type=int, default=300_000)
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-dssim-step", action="store_true")
+    ap.add_argument("--no-sweep", action="store_true",
+                    help="skip the pruning-sweep and sent-update codec legs")
     ap.add_argument("--serve-rates", default="500,2000,4000",
                     help="aggregate Poisson arrival rates (requests/s)")
     ap.add_argument("--serve-seconds", type=float, default=2.0)
@@ -203,6 +205,76 @@ class AutogradTrainStep:
         loss.backward()
         self.gs.gs_adam_step(self.ctx, self.flat.detach(), self.flat.grad, self.m, self.v,
                              self.t)
+
+
+class SweepStep:
+    """One pruning-level sweep of a frame (usage render, 11 masked frames,
+    one batched render of every (level, view) pair, squared error per pair,
+    level selection by Alg. 1 on the host)."""
+
+    def __init__(self, scene, n_views):
+        import torch
+
+        from paper_2512_20943_amd import gs, scenes
+        from paper_2512_20943_amd.prune import PruningSweep
+        self.torch, self.gs = torch, gs
+        self.ctx = gs.default_context()
+        n = scene["n"]
+        gw = gh = scenes.grid_side(n)
+        anchor = gs.Gaussians.from_scene(scene)
+        delta = torch.from_numpy(scenes.make_delta(n, gw, gh, 2)).cuda()
+        self.cams = gs.Cameras(scenes.arc_cameras(n_views, 5.0, 1352, 1014))
+        self.sweep = PruningSweep(anchor, delta, gw, gh, self.cams, ctx=self.ctx)
+        self.last = None
+
+    def step(self):
+        self.last = self.sweep.run()
+
+
+class CodecStep:
+    """One frame of sent updates at the server and the client (Eq. (11),
+    (12)): residual against what was sent, 8-bit quantisation with the
+    server's running sum, and the client's dequantise + accumulate + apply."""
+
+    # algorithmic bytes per texel: residual reads D, D' (32 B each) and the
+    # mask (1 B) and writes d (32 B); quantisation reads d and D' and writes
+    # the codes (8 B) and D'; the client reads the codes, D' and the anchor's
+    # mean, quaternion and opacity (32 B) and writes D' and the frame's
+    BYTES_PER_TEXEL = (32 + 32 + 1 + 32) + (32 + 32 + 8 + 32) + (8 + 32 + 32 + 32 + 32)
+
+    def __init__(self, scene):
+        import torch
+
+        from paper_2512_20943_amd import gs, scenes
+        from paper_2512_20943_amd.raster import frame_of
+        self.torch, self.gs = torch, gs
+        self.ctx = gs.default_context()
+        n = scene["n"]
+        self.n = n
+        self.gw = self.gh = gw = scenes.grid_side(n)
+        self.anchor = gs.Gaussians.from_scene(scene)
+        self.frame = frame_of(self.anchor)
+        ident = np.zeros((8, gw, gw), np.float32)
+        ident[3] = 1.0
+        d = scenes.make_delta(n, gw, gw, 3)
+        self.D = torch.from_numpy(d).cuda()
+        self.mask = torch.from_numpy(scenes.prune_mask(d, n, 0.3)).cuda()
+        self.P_srv = torch.from_numpy(ident).cuda()
+        self.P_cli = self.P_srv.clone()
+        self.d = torch.empty_like(self.D)
+        self.amax = torch.zeros(8, device="cuda")
+        self.q = torch.empty((8, gw, gw), dtype=torch.int8, device="cuda")
+        self.scale = torch.empty(8, device="cuda")
+
+    def step(self):
+        gs, c = self.gs, self.ctx
+        self.amax.zero_()
+        gs.gs_residual_delta(c, self.D, self.P_srv, self.mask, self.n, self.gw, self.gh, self.d,
+                             self.amax)
+        gs.gs_quantize_delta(c, self.d, self.amax, 8, self.n, self.gw, self.gh, self.q,
+                             self.scale, self.P_srv)
+        gs.gs_apply_quantized_update(c, self.anchor, self.q, 8, self.scale, self.P_cli, self.gw,
+                                     self.gh, self.frame)
 
 
 def time_steps(ts, steps, warmup):
@@ -485,6 +557,30 @@ def main():
             "stage_ms_per_step": {k: round(v[0] / k3, 4) for k, v in st3.items() if v[1] > 0}}
         log(f"Eq. (1) L1 + D-SSIM step: {wall3 / k3 * 1e3:.2f} ms")
         del ds
+    if not args.no_sweep:
+        sw = SweepStep(scene, 4)
+        k5 = 3
+        wall5, _, st5 = time_steps(sw, k5, 1)
+        last = sw.last
+        result["pruning_sweep"] = {
+            "sweeps_per_s": round(k5 / wall5, 4), "ms_per_sweep": round(wall5 / k5 * 1e3, 3),
+            "levels": len(last["levels"]), "views": 4, "width": 1352, "height": 1014,
+            "selected_level": last["levels"][last["selected"]],
+            "stage_ms_per_sweep": {k: round(v[0] / k5, 4) for k, v in st5.items() if v[1] > 0}}
+        log(f"pruning sweep: {wall5 / k5 * 1e3:.2f} ms")
+        del sw
+        cs = CodecStep(scene)
+        k6 = 50
+        wall6, dev6, st6 = time_steps(cs, k6, 3)
+        nbytes = CodecStep.BYTES_PER_TEXEL * cs.n
+        result["sent_update_codec"] = {
+            "frames_per_s": round(k6 / wall6, 2), "device_ms_per_frame": round(dev6 / k6 * 1e3, 4),
+            "grid": [cs.gh, cs.gw], "bits": 8, "prune_level": 0.3,
+            "algorithmic_bytes_per_frame": nbytes,
+            "device_GBps": round(nbytes / (dev6 / k6) / 1e9, 1),
+            "stage_ms_per_frame": {k: round(v[0] / k6, 4) for k, v in st6.items() if v[1] > 0}}
+        log(f"sent-update codec: {dev6 / k6 * 1e3:.3f} ms device time per frame")
+        del cs
     if not args.no_serve:
         result["serving"] = serving(args, scene)
     if not args.no_cpu_baseline:
