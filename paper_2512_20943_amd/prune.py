@@ -36,12 +36,20 @@ PSNR_CAP = 100.0
 def usage_keep_mask(usage: np.ndarray, n: int, gw: int, gh: int, level: float) -> np.ndarray:
     """Keep-mask (gh, gw) that drops floor(level * n) updates of the least
     used Gaussians (equal usage: lower id dropped first); padding texels 0."""
+    return usage_keep_masks(usage, n, gw, gh, [level])[0]
+
+
+def usage_keep_masks(usage: np.ndarray, n: int, gw: int, gh: int, levels) -> list:
+    """usage_keep_mask for every level, sharing one stable ordering."""
     u = np.asarray(usage[:n], dtype=np.int64)
     order = np.argsort(u, kind="stable")
-    m = np.zeros(gh * gw, np.uint8)
-    m[:n] = 1
-    m[order[: int(math.floor(level * n + 1e-9))]] = 0
-    return m.reshape(gh, gw)
+    out = []
+    for level in levels:
+        m = np.zeros(gh * gw, np.uint8)
+        m[:n] = 1
+        m[order[: int(math.floor(level * n + 1e-9))]] = 0
+        out.append(m.reshape(gh, gw))
+    return out
 
 
 def select_level(space, beta: float, bandwidth: float, rate: float) -> int:
@@ -87,6 +95,7 @@ class PruningSweep:
         # opacity-aware tile rectangles: same images and usage, shorter lists
         self.raster = Rasterizer(ctx=self.ctx, capacity=1 << 22, tight_rect=True,
                                  tile_spans=True)
+        self._proj = None  # projected records of every (level, view), reused
 
     def usage(self, bg=(0.0, 0.0, 0.0)):
         """Reference render of the unpruned frame and per-Gaussian usage."""
@@ -104,7 +113,7 @@ class PruningSweep:
         ref, usage = self.usage(bg)
         u = usage.cpu().numpy().view(np.uint32).astype(np.int64)
         n, L, V = self.anchor.n, len(self.levels), self.cams.V
-        masks = [usage_keep_mask(u, n, self.gw, self.gh, lv) for lv in self.levels]
+        masks = usage_keep_masks(u, n, self.gw, self.gh, self.levels)
         frames = []
         for m in masks:
             f = frame_of(self.anchor)
@@ -119,7 +128,9 @@ class PruningSweep:
                 items.append((np.array(h.R[:]).reshape(3, 3), np.array(h.t[:]),
                               np.array([h.fx, h.fy, h.cx, h.cy]), (h.width, h.height)))
         cams = gs.Cameras.from_list(items, dev)
-        proj = gs.Projected.empty(L * V, n, self.anchor.ld, dev)
+        proj = self._proj
+        if proj is None or proj.V != L * V:
+            proj = self._proj = gs.Projected.empty(L * V, n, self.anchor.ld, dev)
         proj.options = gs.GS_PROJECT_TIGHT_RECT | gs.GS_PROJECT_TILE_SPANS
         for k, f in enumerate(frames):
             gs.gs_project(self.ctx, f, cams.slice(k * V, V), proj.slice(k * V, V))

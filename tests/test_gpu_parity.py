@@ -440,6 +440,24 @@ def test_l1_autograd_function_matches_oracle():
     np.testing.assert_allclose(x.grad.cpu().numpy().ravel(), 2.5 * g_or, rtol=1e-6, atol=0)
 
 
+@pytest.mark.parametrize("count,offset", [(1, 0), (5003, 1), (4_112_537, 0)])
+def test_sq_error_vector_and_scalar_paths(count, offset):
+    """gs_sq_error adds sum (a - b)^2, each term formed in FP64 from the two
+    FP32 values, to an FP64 scalar: 16-byte loads when both buffers are
+    aligned, one value at a time otherwise and in the tail, at most 1024
+    blocks striding over large counts."""
+    require_gpu()
+    ctx = gs.default_context()
+    rng = np.random.default_rng(count)
+    a = rng.uniform(0, 1, count + offset).astype(np.float32)
+    b = (a + rng.normal(0, 0.1, a.shape)).astype(np.float32)
+    ref = float(((a[offset:].astype(np.float64) - b[offset:].astype(np.float64)) ** 2).sum())
+    s = torch.full((1,), 0.5, dtype=torch.float64, device="cuda")
+    gs.gs_sq_error(ctx, torch.from_numpy(a).cuda()[offset:], torch.from_numpy(b).cuda()[offset:], s)
+    torch.cuda.synchronize()
+    assert abs(s.item() - 0.5 - ref) <= 1e-12 * max(1.0, ref) * max(1.0, np.log2(count))
+
+
 @pytest.mark.parametrize("count,offset", [(5003, 0), (5003, 1), (3_000_001, 0)])
 def test_l1_vector_and_scalar_paths(count, offset):
     """The L1 kernel takes four values per step when the three buffers are
