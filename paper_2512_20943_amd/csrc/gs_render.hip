@@ -24,6 +24,8 @@
 // instance's index in the binning's emission order.  A second kernel sums
 // each (view, Gaussian)'s rows, which that order keeps contiguous: no
 // floating-point atomics, and the result does not depend on scheduling.
+#include <type_traits>
+
 #include "gs_internal.h"
 
 namespace gs {
@@ -170,12 +172,22 @@ struct UsageShared {
 };
 
 // Bit w set while some pixel of slot w still composites (T > 0).
-__device__ __forceinline__ uint32_t live_mask(const float (&T)[4]) {
-  uint32_t live = 0;
-#pragma unroll
-  for (int w = 0; w < 4; ++w)
-    if (__builtin_amdgcn_ballot_w64(T[w] > 0.f) != 0) live |= 1u << w;
-  return live;
+// One pixel slot of the forward: transmittance (its sign is the "still
+// compositing" flag), colour sums and the last composited list position.
+// Each slot is its own variable, not an element of an array: indexing an
+// array by the unrolled slot number lets the compiler keep the four slots
+// in one vector register tuple, whose merge points cost register copies on
+// every list entry.
+struct FwdSlot {
+  float T, c0, c1, c2;
+  int last;
+};
+
+template <int W>
+using SlotId = std::integral_constant<int, W>;
+
+__device__ __forceinline__ uint32_t live_bit(const FwdSlot& s, int w) {
+  return __builtin_amdgcn_ballot_w64(s.T > 0.f) != 0 ? 1u << w : 0u;
 }
 
 // The L1 term of Eq. (1) evaluated where the forward writes its pixels:
@@ -208,18 +220,18 @@ __device__ __forceinline__ void render_tile_fwd(FwdShared& sh, UsageShared* us,
   // slot w's pixel is (x0 + 8 (w & 1), y0 + 8 (w >> 1))
   const int x0 = tx * kTile + (lane & 7), y0 = ty * kTile + (lane >> 3);
   const float fx0 = (float)x0, fy0 = (float)y0;
-  // T[w] > 0 while slot w's pixel composites; a pixel that has stopped holds
+  // T > 0 while a slot's pixel composites; a pixel that has stopped holds
   // its final transmittance negated (and one outside the image holds -1), so
   // the sign is the per-lane "done" flag without a register of its own
-  float T[4], c0[4], c1[4], c2[4];
-  int last[4];
-#pragma unroll
-  for (int w = 0; w < 4; ++w) {
-    T[w] = (x0 + 8 * (w & 1) < W && y0 + 8 * (w >> 1) < H) ? 1.f : -1.f;
-    c0[w] = c1[w] = c2[w] = 0.f;
-    last[w] = 0;
-  }
-  uint32_t live = live_mask(T);
+  auto init = [&](int w) {
+    FwdSlot st;
+    st.T = (x0 + 8 * (w & 1) < W && y0 + 8 * (w >> 1) < H) ? 1.f : -1.f;
+    st.c0 = st.c1 = st.c2 = 0.f;
+    st.last = 0;
+    return st;
+  };
+  FwdSlot s0 = init(0), s1 = init(1), s2 = init(2), s3 = init(3);
+  uint32_t live = live_bit(s0, 0) | live_bit(s1, 1) | live_bit(s2, 2) | live_bit(s3, 3);
   const float ox = (float)(tx * kTile), oy = (float)(ty * kTile);
   for (uint32_t b0 = rg.x; b0 < rg.y && live != 0; b0 += kFwdBatch) {
     __syncthreads();
@@ -255,30 +267,35 @@ __device__ __forceinline__ void render_tile_fwd(FwdShared& sh, UsageShared* us,
       int posv;  // pos in a vector register, read by the per-slot selects
       asm("v_mov_b32 %0, %1" : "=v"(posv) : "s"(pos));
       const float dxl = a.x - fx0, dyt = a.y - fy0;
-#pragma unroll
-      for (int w = 0; w < 4; ++w) {
+      auto slot = [&](auto wid, FwdSlot& st) {
+        constexpr int w = decltype(wid)::value;
         if (m & (1u << w)) {
           // per-lane decisions as selects: no divergent branches in the slot
           const float dx = (w & 1) ? dxl - 8.f : dxl;
           const float dy = (w >> 1) ? dyt - 8.f : dyt;
           const float alpha = fminf(kAlphaMax, eval_ea(a, row_q(b, dy), dx, dy));
-          const bool use = T[w] > 0.f && alpha >= kAlphaMin;
-          const float Tn = T[w] * (1.f - alpha);
+          const float Tk = st.T;
+          const bool use = Tk > 0.f && alpha >= kAlphaMin;
+          const float Tn = Tk * (1.f - alpha);
           const bool stop = use && Tn < kTStop;
           const bool comp = use && !stop;
-          const float wt = comp ? alpha * T[w] : 0.f;
-          c0[w] = fmaf(b.z, wt, c0[w]);
-          c1[w] = fmaf(b.w, wt, c1[w]);
-          c2[w] = fmaf(cb, wt, c2[w]);
-          T[w] = comp ? Tn : T[w];
-          last[w] = comp ? posv : last[w];
+          const float wt = comp ? alpha * Tk : 0.f;
+          st.c0 = fmaf(b.z, wt, st.c0);
+          st.c1 = fmaf(b.w, wt, st.c1);
+          st.c2 = fmaf(cb, wt, st.c2);
+          // a stopping pixel keeps its transmittance, negated
+          st.T = comp ? Tn : (stop ? -Tk : Tk);
+          st.last = comp ? posv : st.last;
           if constexpr (USAGE) used += (uint32_t)__popcll(__builtin_amdgcn_ballot_w64(comp));
           if (__builtin_amdgcn_ballot_w64(stop) != 0) {  // once per pixel
-            T[w] = stop ? -T[w] : T[w];
-            if (__builtin_amdgcn_ballot_w64(T[w] > 0.f) == 0) live &= ~(1u << w);
+            if (__builtin_amdgcn_ballot_w64(st.T > 0.f) == 0) live &= ~(1u << w);
           }
         }
-      }
+      };
+      slot(SlotId<0>{}, s0);
+      slot(SlotId<1>{}, s1);
+      slot(SlotId<2>{}, s2);
+      slot(SlotId<3>{}, s3);
       if constexpr (USAGE) {
         if (lane == 0 && used) us->u[k] = used;
       }
@@ -295,13 +312,12 @@ __device__ __forceinline__ void render_tile_fwd(FwdShared& sh, UsageShared* us,
   }
   const size_t pix = (size_t)W * H;
   double l1sum = 0.0;
-#pragma unroll
-  for (int w = 0; w < 4; ++w) {
+  auto write = [&](int w, const FwdSlot& st) {
     const int x = x0 + 8 * (w & 1), y = y0 + 8 * (w >> 1);
-    if (!(x < W && y < H)) continue;
+    if (!(x < W && y < H)) return;
     const size_t p = (size_t)y * W + x;
-    const float Tf = fabsf(T[w]);
-    const float o0 = c0[w] + Tf * bg0, o1 = c1[w] + Tf * bg1, o2 = c2[w] + Tf * bg2;
+    const float Tf = fabsf(st.T);
+    const float o0 = st.c0 + Tf * bg0, o1 = st.c1 + Tf * bg1, o2 = st.c2 + Tf * bg2;
     if (!L1 || image) {
       image[p] = o0;
       image[pix + p] = o1;
@@ -318,8 +334,12 @@ __device__ __forceinline__ void render_tile_fwd(FwdShared& sh, UsageShared* us,
       }
     }
     if (final_T) final_T[p] = Tf;
-    if (n_contrib) n_contrib[p] = last[w];
-  }
+    if (n_contrib) n_contrib[p] = st.last;
+  };
+  write(0, s0);
+  write(1, s1);
+  write(2, s2);
+  write(3, s3);
   if constexpr (L1) {
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) l1sum += __shfl_xor(l1sum, off, 64);
