@@ -38,10 +38,11 @@ def lists_to_numpy(L: gs.TileLists):
 
 
 def gpu_forward(scene, cams_np, bg=(0.0, 0.0, 0.0), with_keys=True, capacity=1 << 16,
-                emission_bases=False):
+                emission_bases=False, tight_rect=False, tile_spans=False):
     g = gs.Gaussians.from_scene(scene)
     cams = gs.Cameras(cams_np)
-    r = Rasterizer(capacity=capacity, with_keys=with_keys, emission_bases=emission_bases)
+    r = Rasterizer(capacity=capacity, with_keys=with_keys, emission_bases=emission_bases,
+                   tight_rect=tight_rect, tile_spans=tile_spans)
     out = r.forward(g, cams, bg)
     torch.cuda.synchronize()
     return g, cams, r, out

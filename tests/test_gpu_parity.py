@@ -640,9 +640,11 @@ def test_training_and_delivery_calls_reject_bad_arguments():
 # ---------------------------------------------------------------------------
 
 def test_full_frame_300k_20_views_sampled():
-    """300,000 Gaussians, SH 3, 20 views at 1352x1014, in the launch
-    configuration the benchmark times: every projection record is compared,
-    view 0's tile lists bit for bit, and view 0's image in full."""
+    """300,000 Gaussians, SH 3, 20 views at 1352x1014: every projection record
+    is compared, view 0's tile lists bit for bit (full rectangles, as the
+    definition bins), view 0's image in full; then the benchmark's binning
+    (opacity-aware rectangles with per-row tile spans) must give the same
+    images and final transmittance bit for bit from fewer instances."""
     require_gpu()
     say("full frame 300k x 20 views")
     scene, cams, _ = scenes.workload_frame_300k(0)
@@ -666,6 +668,12 @@ def test_full_frame_300k_20_views_sampled():
     out0 = {k: out[k][:1] for k in ("image", "final_T", "n_contrib")}
     err, near = compare_images(out0, img0)
     say(f"  view 0 max image error {err:.2e}, {near} near-threshold pixels")
+    _, _, _, out_s = gpu_forward(scene, cams, with_keys=False, capacity=1 << 26,
+                                 tight_rect=True, tile_spans=True)
+    say(f"  spans: {out_s['lists'].count} instances")
+    assert 0 < out_s["lists"].count < out["lists"].count
+    assert torch.equal(out_s["image"], out["image"])
+    assert torch.equal(out_s["final_T"], out["final_T"])
 
 
 def _sparse_tile_gradient(img_shape, n_tiles, seed, W, H):
@@ -686,12 +694,14 @@ def _sparse_tile_gradient(img_shape, n_tiles, seed, W, H):
 
 def test_full_frame_backward_sparse_tiles():
     """Backward at the full 300k-Gaussian / 20-view / 1352x1014 size and in the
-    benchmark's launch configuration, with the image gradient restricted to
-    30 random tiles per view (the oracle walks only those)."""
+    benchmark's launch configuration (opacity-aware rectangles with per-row
+    tile spans), with the image gradient restricted to 30 random tiles per
+    view (the oracle, binning full rectangles, walks only those)."""
     require_gpu()
     say("full frame backward, sparse tiles")
     scene, cams, _ = scenes.workload_frame_300k(0)
-    g, gc, r, out = gpu_forward(scene, cams, with_keys=False, capacity=1 << 26)
+    g, gc, r, out = gpu_forward(scene, cams, with_keys=False, capacity=1 << 26,
+                                tight_rect=True, tile_spans=True)
     P_or, L_or, img_or = oracle.forward(scene, cams)
     gI = _sparse_tile_gradient(img_or["image"].shape, 30, 21, 1352, 1014)
     gI[np.broadcast_to(img_or["near_threshold"][:, None], gI.shape)] = 0.0
@@ -723,7 +733,7 @@ def test_full_frame_update_delta_gradient_sparse_tiles():
     _, gr_or = oracle.backward(frame, cams, P_or, L_or, gI)
     gd_or = oracle.apply_bwd(scene, mask, gw, gh, gr_or)
     anchor = gs.Gaussians.from_scene(scene)
-    r = Rasterizer(capacity=1 << 26)
+    r = Rasterizer(capacity=1 << 26, tight_rect=True, tile_spans=True)  # as benchmarked
     fr = frame_of(anchor)
     delta = torch.from_numpy(d).cuda().requires_grad_(True)
     img = GSFrameRender.apply(delta, (r, gs.Cameras(cams), anchor, torch.from_numpy(mask).cuda(),
