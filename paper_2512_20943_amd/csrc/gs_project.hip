@@ -226,8 +226,9 @@ __global__ __launch_bounds__(256) void k_project(
             // image, so each extreme is ex (or -ex) when that point lies in
             // the band and otherwise the larger (smaller) of the band edges'
             // values.  The hardware square root and reciprocal (relative
-            // error near 2^-23) move an end by under 2e-5 px at these sizes,
-            // inside the kSpanEps slack.
+            // error near 2^-23) move an end by under 1e-4 px at these sizes
+            // (chord ends within 120 px of the centre), inside the kSpanEps
+            // slack.
             const double ey = ey_thr, iA = __builtin_amdgcn_rcp(A);
             const double dys = -B * ex_thr / C;
             const double ath = A * thr;
