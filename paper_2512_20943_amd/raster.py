@@ -120,11 +120,14 @@ class Rasterizer:
         return dict(image=image, final_T=final_T, n_contrib=n_contrib, proj=proj, lists=lists)
 
     def backward(self, g: gs.Gaussians, cams: gs.Cameras, state: dict, dL_dimage: torch.Tensor,
-                 grad: gs.Gaussians, bg=(0.0, 0.0, 0.0), upd=None, dL_ddelta=None, stream=None):
+                 grad: gs.Gaussians, bg=(0.0, 0.0, 0.0), upd=None, dL_ddelta=None, stream=None,
+                 temporal=None):
+        """``temporal`` = (weight, delta, loss) adds the temporal term of
+        Eq. (6)/(7) to the delta gradient (with ``upd``); see gs_render_bwd."""
         ws = self.bwd_workspace(cams.V, g.ld, g.mean.device, state["lists"].count)
         gs.gs_render_bwd(self.ctx, g, state["proj"], state["lists"], cams, bg, state["final_T"],
                          state["n_contrib"], dL_dimage.contiguous(), grad, ws, upd, dL_ddelta,
-                         stream)
+                         stream, temporal=temporal)
         return ws
 
 
