@@ -31,13 +31,18 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
-# Published MI355X FP32 vector peak.  This build emits no packed FP32
-# instructions, which caps the attainable rate at half of it (78.6 TFLOP/s);
-# the fraction is still reported against the published figure.
+# Published MI355X FP32 vector peak.  The library is compiled without packed
+# FP32 instructions, which caps the rate of executed FP32 arithmetic at half
+# of it (78.6 TFLOP/s); the fraction is still reported against the published
+# figure, and it counts the pairs the compositing definition evaluates, some
+# of which the kernels skip cheaply (whole quadrants below alpha 1/255).
 PEAK_ALU_TFLOPS = 157.3
 
 # Algorithmic FP32 operations per (pixel, entry) pair, FMA counted as 2 and
-# a transcendental as 1 (see the design doc for the breakdown).
+# a transcendental as 1, on the definition's own formulas: forward = offsets,
+# quadratic form, exp, alpha cap and the two tests, T update, weight and three
+# colour FMAs; backward = that recompute plus the T recovery, colour, alpha
+# and power gradients and their moments.
 FLOP_PER_PAIR_FWD = 26
 FLOP_PER_PAIR_BWD = 68
 
@@ -515,8 +520,8 @@ def serving(args, scene):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported by this build "
-              f"(the multi-GPU sharding is described in DESIGN.md, not built)", file=sys.stderr)
+        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported (sharding "
+              f"the views over several GPUs is not implemented)", file=sys.stderr)
         sys.exit(2)
     if args.copy_calibration:
         copy_calibration()
