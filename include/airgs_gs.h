@@ -162,7 +162,8 @@ typedef struct gs_projected {
  *   gv_base (gv_capacity >= n_views * ld) uint32, optional (NULL = not
  *       written): for each (view v, Gaussian i) with tiles_touched > 0, at
  *       v*ld + i, the index of its first instance in the binning's emission
- *       order (its tiles row by row over its tile rectangle, consecutive).
+ *       order (its tiles row by row over its tile rectangle or its spans,
+ *       consecutive).
  *       The same index is always written to word 14 of the pair's projected
  *       record, where gs_render_bwd reads it: the backward writes one
  *       gradient row per instance in that order and sums each pair's rows
@@ -265,8 +266,10 @@ gs_status gs_project(gs_ctx* ctx, const gs_gaussians* g, const gs_camera* cams_h
                      const gs_camera* cams_dev, int n_views, gs_projected* out, void* stream);
 
 /* Binning and depth ordering: every (visible Gaussian, tile of its
- * rectangle) pair is an instance; instances are ordered by (segment, FP32
- * depth, Gaussian id) with an LDS-resident onesweep radix sort.  Reads the
+ * rectangle, or of its per-row spans when the record carries them, see
+ * GS_PROJECT_TILE_SPANS) pair is an instance; instances are ordered by
+ * (segment, FP32 depth, Gaussian id) with an LDS-resident onesweep radix
+ * sort.  Reads the
  * instance count back to the host (blocking).  Returns GS_ERR_CAPACITY with
  * lists->count = M when M > lists->capacity (nothing else is written).
  * Besides the lists it writes word 14 of each listed record of proj->splat
