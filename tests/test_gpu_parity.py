@@ -770,16 +770,20 @@ def test_large_2m_8_views_sampled():
     say(f"  view 0 max image error {err:.2e}, {near} near-threshold pixels")
 
 
-def test_emission_bases_index_every_instance_once():
+@pytest.mark.parametrize("mode", ["rect", "spans"])
+def test_emission_bases_index_every_instance_once(mode):
     """Emission bases: the instances of each (view, Gaussian) occupy rows
     base .. base + tiles_touched - 1 in row-major order over its tile
-    rectangle, and these rows, over all sorted instances, are a permutation
-    of 0..M-1 (the backward writes one gradient row per instance there).
-    The base in the projected record (word 14, next to the packed rectangle
-    in words 12, 13) and the optional gv_base copy agree."""
+    rectangle, or over its per-row spans (record word 15, flagged in bit 31
+    of word 13), and these rows, over all sorted instances, are a
+    permutation of 0..M-1 (the backward writes one gradient row per instance
+    there).  The base in the projected record (word 14, next to the packed
+    rectangle in words 12, 13) and the optional gv_base copy agree."""
     require_gpu()
     scene, cams = small_frame_workload(3)
-    g, gc, r, out = gpu_forward(scene, cams, emission_bases=True)
+    spans = mode == "spans"
+    g, gc, r, out = gpu_forward(scene, cams, emission_bases=True, tight_rect=spans,
+                                tile_spans=spans)
     L = out["lists"]
     M = L.count
     vals = L.vals[:M].cpu().numpy().astype(np.int64)
@@ -795,7 +799,10 @@ def test_emission_bases_index_every_instance_once():
     np.testing.assert_array_equal(words[..., 14][touched], base.reshape(gc.V, ld)[touched])
     np.testing.assert_array_equal(words[..., 12][touched],
                                   (rect[..., 0] | (rect[..., 1] << 16))[touched])
-    np.testing.assert_array_equal(words[..., 13][touched], (rect[..., 2] - rect[..., 0])[touched])
+    flag = (words[..., 13] >> 31).astype(bool)
+    np.testing.assert_array_equal((words[..., 13] & 0x7FFFFFFF)[touched],
+                                  (rect[..., 2] - rect[..., 0])[touched])
+    assert flag[touched].any() == spans
     tpv = [((w + 15) // 16) * ((h + 15) // 16) for (w, h) in cams["wh"]]
     sb = np.concatenate([[0], np.cumsum(tpv)])
     v = np.searchsorted(sb, seg_of, side="right") - 1
@@ -803,7 +810,24 @@ def test_emission_bases_index_every_instance_once():
     TX = np.array([(w + 15) // 16 for (w, h) in cams["wh"]])[v]
     ty, tx = tile // TX, tile % TX
     rc = rect[v, vals]
-    local = (ty - rc[:, 1]) * (rc[:, 2] - rc[:, 0]) + (tx - rc[:, 0])
+    dy, dx = ty - rc[:, 1], tx - rc[:, 0]
+    local = dy * (rc[:, 2] - rc[:, 0]) + dx
+    sp = flag[v, vals]
+    if sp.any():
+        # spans: byte r of word 15 = a_r | b_r << 4; an instance lies in its
+        # row's span and follows the spans of the rows above it
+        m = words[..., 15][v, vals].astype(np.int64)
+        a = np.stack([(m >> (8 * k)) & 15 for k in range(4)], axis=1)
+        b = np.stack([(m >> (8 * k + 4)) & 15 for k in range(4)], axis=1)
+        assert np.all(dy[sp] < 4)
+        rows_ = np.arange(len(vals))
+        dyc = np.minimum(dy, 3)
+        a_r, b_r = a[rows_, dyc], b[rows_, dyc]
+        assert np.all((a_r[sp] <= dx[sp]) & (dx[sp] < b_r[sp]))
+        pre = np.where(np.arange(4)[None, :] < dyc[:, None], b - a, 0).sum(axis=1)
+        local = np.where(sp, pre + dx - a_r, local)
+        cnt = (b - a).sum(axis=1)
+        np.testing.assert_array_equal(cnt[sp], tiles[v, vals][sp])
     assert np.all((local >= 0) & (local < tiles[v, vals]))
     rows = base[v * ld + vals] + local
     assert np.array_equal(np.sort(rows), np.arange(M))
