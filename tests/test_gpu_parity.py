@@ -188,6 +188,62 @@ def test_tight_rectangles_keep_images_and_gradients(which, mode):
                                    err_msg=name)
 
 
+def _box_min_q(A, B, C, px, py, x0, x1, y0, y1):
+    """Minimum over the box [x0, x1] x [y0, y1] of the conic's quadratic form
+    q(d) = A dx^2 + 2 B dx dy + C dy^2 around (px, py): 0 inside, else the
+    smallest value on its four edges (q is convex)."""
+    def edge(xa, ya, xb, yb):
+        ux, uy = xb - xa, yb - ya
+        dx, dy = xa - px, ya - py
+        a = A * ux * ux + 2 * B * ux * uy + C * uy * uy
+        b = A * dx * ux + B * (dx * uy + dy * ux) + C * dy * uy
+        t = np.clip(-b / np.maximum(a, 1e-300), 0.0, 1.0)
+        ex, ey = dx + t * ux, dy + t * uy
+        return A * ex * ex + 2 * B * ex * ey + C * ey * ey
+    inside = (px >= x0) & (px <= x1) & (py >= y0) & (py <= y1)
+    m = np.minimum.reduce([edge(x0, y0, x1, y0), edge(x0, y1, x1, y1),
+                           edge(x0, y0, x0, y1), edge(x1, y0, x1, y1)])
+    return np.where(inside, 0.0, m)
+
+
+def test_spans_keep_only_tiles_the_ellipse_meets():
+    """Every instance that per-row tile spans keep lies in a tile whose pixel
+    columns, over its row's band (pixel centres +- 0.5 px in y), meet the
+    ellipse where alpha reaches 1/255 (plus the quadrant test's margin), by
+    the oracle's FP64 projection of the same scene: the spans drop only
+    tiles outside it (that they drop all of those up to the band rounding is
+    what the bit-identical images and shorter lists of the span tests show)."""
+    require_gpu()
+    scene, cams = small_frame_workload(7)
+    g, gc, r, out = gpu_forward(scene, cams, capacity=1 << 20, tight_rect=True,
+                                tile_spans=True)
+    L = out["lists"]
+    M = L.count
+    vals = L.vals[:M].cpu().numpy().astype(np.int64)
+    ranges = L.ranges[:L.n_segments].cpu().numpy().astype(np.int64)
+    seg_of = np.repeat(np.arange(L.n_segments), ranges[:, 1] - ranges[:, 0])
+    words = out["proj"].splat.cpu().numpy().view(np.uint32).reshape(gc.V, g.ld, 16)
+    tpv = [((w + 15) // 16) * ((h + 15) // 16) for (w, h) in cams["wh"]]
+    sb = np.concatenate([[0], np.cumsum(tpv)])
+    v = np.searchsorted(sb, seg_of, side="right") - 1
+    tile = seg_of - sb[v]
+    TX = np.array([(w + 15) // 16 for (w, h) in cams["wh"]])[v]
+    ty, tx = tile // TX, tile % TX
+    sp = (words[v, vals, 13] >> 31).astype(bool)
+    assert sp.sum() > 1000
+    P = oracle.project(scene, cams)
+    px, py = P["mean2d"][v, vals, 0], P["mean2d"][v, vals, 1]
+    A, B, C = (P["conic"][v, vals, k] for k in range(3))
+    qm = 2.0 * (np.log(255.0) + np.log(P["alpha_hat"][v, vals]))
+    thr = qm + 2e-4 * np.abs(qm) + 1e-3
+    x0, y0 = 16.0 * tx, 16.0 * ty - 0.5
+    # the spans' own slack: 1e-3 px on every edge, rows kept when the band
+    # comes within it of the ellipse
+    qmin = _box_min_q(A, B, C, px, py, x0 - 2e-3, x0 + 15.0 + 2e-3, y0 - 2e-3, y0 + 16.0 + 2e-3)
+    bad = sp & (qmin > thr * (1 + 1e-5) + 1e-4)
+    assert not bad.any(), (int(bad.sum()), qmin[bad][:3], thr[bad][:3])
+
+
 def test_many_small_views_bit_exact():
     """1,100 views of 16x16 pixels (one tile each) on an arc around 200
     Gaussians: more views than the depth-range and key kernels have grid
