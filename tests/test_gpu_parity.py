@@ -424,10 +424,9 @@ def test_frame_update_gradient_parity():
     anchor = gs.Gaussians.from_scene(sc)
     r = Rasterizer(capacity=1 << 16)
     gc = gs.Cameras(cams)
-    fr = frame_of(anchor)
     delta = torch.from_numpy(d).cuda().requires_grad_(True)
     mask_t = torch.from_numpy(mask).cuda()
-    img = GSFrameRender.apply(delta, (r, gc, anchor, mask_t, gw, gh, (0.0, 0.0, 0.0), fr))
+    img = GSFrameRender.apply(delta, (r, gc, anchor, mask_t, gw, gh, (0.0, 0.0, 0.0)))
     img.backward(torch.from_numpy(gI.astype(np.float32)).cuda())
     torch.cuda.synchronize()
     got = delta.grad.cpu().numpy()
@@ -436,18 +435,77 @@ def test_frame_update_gradient_parity():
     assert_grad_close(got, gd_or, "delta images")
 
 
-def test_autograd_function_returns_all_parameter_grads():
+@pytest.mark.parametrize("which", ["plain_10k", "frame_20k_4v"])
+def test_autograd_render_matches_oracle_for_all_parameter_groups(which):
+    """GSRender through torch.autograd: the image equals the oracle's and the
+    gradients of means, log-scales, quaternions, opacity logits and SH
+    coefficients match the oracle's analytic backward."""
     require_gpu()
-    scene, cams, _ = scenes.workload_plain_10k(1)
+    say(f"GSRender autograd {which}")
+    if which == "plain_10k":
+        scene, cams, _ = scenes.workload_plain_10k(1)
+    else:
+        scene, cams = small_frame_workload(9)
+    P_or, L_or, img_or = oracle.forward(scene, cams)
+    gI, _, gr_or = _oracle_grads(scene, cams, P_or, L_or, img_or, 21)
     g = gs.Gaussians.from_scene(scene)
     gc = gs.Cameras(cams)
     r = Rasterizer(capacity=1 << 16)
     leaves = [t.clone().requires_grad_(True) for t in g.planes()]
     img = GSRender.apply(*leaves, (r, gc, g.n, g.deg, (0.0, 0.0, 0.0)))
-    (img.abs().sum()).backward()
-    for t in leaves:
-        assert t.grad is not None and torch.isfinite(t.grad).all()
-    assert leaves[0].grad.abs().sum() > 0
+    keep = ~img_or["near_threshold"]
+    err = np.abs(img.detach().cpu().numpy() - img_or["image"]).max(axis=1)[keep].max()
+    assert err <= IMG_ATOL, f"image error {err:.3e}"
+    img.backward(torch.from_numpy(gI.astype(np.float32)).cuda())
+    torch.cuda.synchronize()
+    n = scene["n"]
+    for name, t in zip(("mean", "log_scale", "quat", "opacity", "sh"), leaves):
+        assert t.grad is not None
+        assert_grad_close(t.grad.cpu().numpy()[..., :n], gr_or[name][..., :n], name)
+
+
+def test_two_renders_differentiated_together():
+    """Two forwards on one rasterizer and one backward through both: each
+    render keeps its own projected records and lists, so the gradient is the
+    sum of the two separate backwards (up to FP32 addition order).  A plain
+    forward state whose buffers a later forward reused is refused."""
+    require_gpu()
+    say("two renders, one backward")
+    scene, cams = small_frame_workload(10)
+    g = gs.Gaussians.from_scene(scene)
+    gc = gs.Cameras(cams)
+    rng = np.random.default_rng(3)
+    gA = torch.from_numpy(rng.uniform(-1, 1, (4, 3, 150, 200)).astype(np.float32)).cuda()
+    gB = torch.from_numpy(rng.uniform(-1, 1, (4, 3, 150, 200)).astype(np.float32)).cuda()
+    shift = torch.zeros_like(g.mean)
+    shift[0] = 0.05  # the second render sees every mean moved along x
+
+    def grads(weights):
+        leaves = [t.clone().requires_grad_(True) for t in g.planes()]
+        r = Rasterizer(capacity=1 << 16)
+        meta = (r, gc, g.n, g.deg, (0.0, 0.0, 0.0))
+        loss = 0.0
+        if weights[0]:
+            loss = loss + (GSRender.apply(*leaves, meta) * gA).sum()
+        if weights[1]:
+            moved = [leaves[0] + shift] + leaves[1:]
+            loss = loss + (GSRender.apply(*moved, meta) * gB).sum()
+        loss.backward()
+        torch.cuda.synchronize()
+        return [t.grad.cpu().numpy()[..., :g.n].astype(np.float64) for t in leaves]
+
+    both, a, b = grads((1, 1)), grads((1, 0)), grads((0, 1))
+    for name, x, y, z in zip(("mean", "log_scale", "quat", "opacity", "sh"), both, a, b):
+        assert_grad_close(x, y + z, name)
+    # the plain path: a second forward makes the first state stale
+    r = Rasterizer(capacity=1 << 16)
+    s1 = r.forward(g, gc)
+    s2 = r.forward(g, gc)
+    grad = gs.Gaussians.zeros_like(g)
+    with pytest.raises(RuntimeError, match="stale"):
+        r.backward(g, gc, s1, gA, grad)
+    r.backward(g, gc, s2, gA, grad)
+    torch.cuda.synchronize()
 
 
 def test_l1_and_adam_match_closed_forms():
@@ -790,10 +848,9 @@ def test_full_frame_update_delta_gradient_sparse_tiles():
     gd_or = oracle.apply_bwd(scene, mask, gw, gh, gr_or)
     anchor = gs.Gaussians.from_scene(scene)
     r = Rasterizer(capacity=1 << 26, tight_rect=True, tile_spans=True)  # as benchmarked
-    fr = frame_of(anchor)
     delta = torch.from_numpy(d).cuda().requires_grad_(True)
     img = GSFrameRender.apply(delta, (r, gs.Cameras(cams), anchor, torch.from_numpy(mask).cuda(),
-                                      gw, gh, (0.0, 0.0, 0.0), fr))
+                                      gw, gh, (0.0, 0.0, 0.0)))
     img.backward(torch.from_numpy(gI.astype(np.float32)).cuda())
     torch.cuda.synchronize()
     assert_grad_close(delta.grad.cpu().numpy(), gd_or, "delta images")
