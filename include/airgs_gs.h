@@ -53,7 +53,9 @@ typedef int32_t gs_status;
 
 #define GS_TILE 16           /* tile side in pixels */
 #define GS_MAX_SH_DEGREE 3
-#define GS_MAX_INSTANCES ((int64_t)1 << 30)
+/* Largest instance capacity and largest n_views * ld that gs_bin_sort takes:
+ * the radix sort's look-back words carry 30-bit prefix counts. */
+#define GS_MAX_INSTANCES (((int64_t)1 << 30) - 1)
 
 typedef struct gs_ctx gs_ctx;
 
@@ -214,7 +216,8 @@ const char* gs_last_error(const gs_ctx* ctx);
 int64_t gs_num_segments(const gs_camera* cams_host, int n_views);
 
 /* Workspace bytes for gs_bin_sort with the given views, stride, instance
- * capacity and total segment count. */
+ * capacity and total segment count; 0 when an argument is out of range
+ * (capacity or n_views * ld above GS_MAX_INSTANCES, or n_segments >= 2^31). */
 size_t gs_bin_sort_workspace_size(int n_views, int ld, int64_t capacity, int64_t n_segments);
 
 /* Workspace bytes for gs_render_bwd over lists of `instances` entries.  Its

@@ -168,6 +168,16 @@ gs_status use_device(gs_ctx* c) {
   return GS_OK;
 }
 
+// Sizes gs_bin_sort accepts: the look-back words of its radix sort carry
+// 30-bit prefix counts, so the instance capacity (which bounds the count
+// that is sorted) and the number of (view, Gaussian) depth keys stay below
+// 2^30; segment ids are 31-bit.
+bool bin_sort_sizes_ok(int V, int ld, int64_t capacity, int64_t n_segments) {
+  return V > 0 && ld > 0 && capacity >= 0 && capacity <= GS_MAX_INSTANCES &&
+         (int64_t)V * ld <= GS_MAX_INSTANCES && n_segments >= 0 &&
+         n_segments < ((int64_t)1 << 31);
+}
+
 int64_t segments_of(const gs_camera* h, int V) {
   int64_t s = 0;
   for (int v = 0; v < V; ++v)
@@ -254,7 +264,7 @@ int64_t gs_num_segments(const gs_camera* cams, int V) {
 }
 
 size_t gs_bin_sort_workspace_size(int V, int ld, int64_t capacity, int64_t n_segments) {
-  if (V <= 0 || ld <= 0 || capacity < 0 || n_segments < 0) return 0;
+  if (!bin_sort_sizes_ok(V, ld, capacity, n_segments)) return 0;
   return gs::bin_sort_workspace_bytes(V, ld, capacity, n_segments);
 }
 
@@ -321,16 +331,13 @@ gs_status gs_bin_sort(gs_ctx* c, const gs_projected* proj, const gs_camera* ch,
   if (lists->gv_base && lists->gv_capacity < (int64_t)V * proj->ld)
     return fail(c, GS_ERR_INVALID_ARG, "gv_base holds %lld entries, n_views * ld = %lld",
                 (long long)lists->gv_capacity, (long long)V * proj->ld);
-  if (lists->capacity < 0 || lists->capacity > GS_MAX_INSTANCES)
-    return fail(c, GS_ERR_INVALID_ARG, "capacity %lld outside [0, 2^30]",
-                (long long)lists->capacity);
   const int64_t nseg = segments_of(ch, V);
-  if (nseg >= ((int64_t)1 << 31))
-    return fail(c, GS_ERR_INVALID_ARG, "too many tile segments (%lld)", (long long)nseg);
+  if (!bin_sort_sizes_ok(V, proj->ld, lists->capacity, nseg))
+    return fail(c, GS_ERR_INVALID_ARG,
+                "capacity %lld or n_views * ld = %lld outside [0, 2^30 - 1], or %lld segments",
+                (long long)lists->capacity, (long long)V * proj->ld, (long long)nseg);
   if (!ws) return fail(c, GS_ERR_INVALID_ARG, "workspace is NULL");
   GS_TRY(check_ws_align(c, ws));
-  if ((int64_t)V * proj->n >= ((int64_t)1 << 32))
-    return fail(c, GS_ERR_INVALID_ARG, "n_views * n too large");
   gs::BinSortPlan plan{V, proj->n, proj->ld, lists->capacity, nseg};
   const size_t need = gs::bin_sort_workspace_bytes(V, proj->ld, lists->capacity, nseg);
   if (ws_bytes < need)

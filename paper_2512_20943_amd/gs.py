@@ -25,6 +25,7 @@ GS_ERR_CAPACITY = 2
 GS_ERR_OOM = 3
 GS_ERR_HIP = 4
 TILE = 16
+GS_MAX_INSTANCES = (1 << 30) - 1
 SPLAT_FLOATS = 16
 GS_PROJECT_TIGHT_RECT = 1
 GS_PROJECT_TILE_SPANS = 2

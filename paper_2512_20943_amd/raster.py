@@ -114,9 +114,10 @@ class Rasterizer:
                 gs.gs_bin_sort(self.ctx, proj, cams, lists, ws, stream)
                 return lists
             except gs.GsError as e:
-                if e.code != gs.GS_ERR_CAPACITY:
+                if e.code != gs.GS_ERR_CAPACITY or lists.count > gs.GS_MAX_INSTANCES:
                     raise
-                self.capacity = max(int(lists.count * self.growth) + 1024, self.capacity * 2)
+                self.capacity = min(max(int(lists.count * self.growth) + 1024,
+                                        self.capacity * 2), gs.GS_MAX_INSTANCES)
 
     def _state(self, own, **kw):
         kw["gen"] = None if own else self._gen

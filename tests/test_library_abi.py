@@ -76,3 +76,25 @@ def test_binding_constants_match_header():
             assert getattr(gsmod, name) == int(value), name
             checked += 1
     assert checked >= 2
+
+
+def test_bin_sort_size_guard(lib_path):
+    """The radix sort's look-back words carry 30-bit prefix counts: the
+    sizes query (the same guard gs_bin_sort applies) refuses an instance
+    capacity or a number of (view, Gaussian) keys of 2^30 and accepts
+    2^30 - 1."""
+    import ctypes
+    lib = ctypes.CDLL(lib_path)
+    f = lib.gs_bin_sort_workspace_size
+    f.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int64, ctypes.c_int64]
+    f.restype = ctypes.c_size_t
+    top = (1 << 30) - 1
+    assert f(20, 300_032, 1 << 25, 108_800) > 0
+    assert f(1, 64, top, 16) > 0
+    assert f(1, 64, top + 1, 16) == 0                     # capacity 2^30
+    assert f(1, 64, -1, 16) == 0
+    assert f(16, (1 << 26) - 64, 1 << 20, 16) > 0         # 16 * ld < 2^30
+    assert f(16, 1 << 26, 1 << 20, 16) == 0               # 16 * ld = 2^30
+    assert f(1, 64, 1 << 20, 1 << 31) == 0                # segment ids are 31-bit
+    text = open(HEADER).read()
+    assert re.search(r"#define GS_MAX_INSTANCES \(\(\(int64_t\)1 << 30\) - 1\)", text)
