@@ -309,6 +309,26 @@ gs_status gs_render_fwd_l1(gs_ctx* ctx, const gs_projected* proj, const gs_tile_
                            float* final_T, int32_t* n_contrib, float* dL_dimage,
                            double* loss_dev, void* workspace, size_t ws_bytes, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc):
+ * gs_render_fwd_l1 without the workspace argument, same kernels and results.
+ * The per-tile FP64 partial sums live in a fixed device array of
+ * GS_NOALLOC_MAX_TILES doubles (2 MiB) that the library holds on each device
+ * from gs_create until the process ends; a call whose views have more tiles
+ * in total is GS_ERR_INVALID_ARG.  The call allocates nothing (no hipMalloc,
+ * no host allocation) and is not timed by gs_set_timing.  Every call on one
+ * device shares that array, which keeps the last call's partials (each is
+ * written before it is read, so nothing needs clearing): calls that overlap
+ * on one device (other streams, contexts or host threads) race and must be
+ * serialised by the caller. */
+#define GS_NOALLOC_MAX_TILES (1 << 18)
+gs_status gs_render_fwd_l1_noalloc(gs_ctx* ctx, const gs_projected* proj,
+                                   const gs_tile_lists* lists, const gs_camera* cams_host,
+                                   const gs_camera* cams_dev, int n_views, const gs_opts* opts,
+                                   const float* target, float* image, float* final_T,
+                                   int32_t* n_contrib, float* dL_dimage, double* loss_dev,
+                                   void* stream);
+
 /* Batched rendering of n_views requests of (possibly) different sizes in one
  * persistent launch: workgroups take (request, tile) items from a shared
  * device-wide queue until it is drained (view delivery, Sec. IV-B: the

@@ -82,11 +82,19 @@ struct EventTimer final : gs::StageTimer {
 
 }  // namespace
 
+// Partial sums of gs_render_fwd_l1_noalloc: one FP64 value per tile, in a
+// fixed device array that each device holds until the process ends.  In host
+// code this name is only a host-side stand-in for the symbol: its device
+// address comes from hipGetSymbolAddress (gs_create, per device), and only
+// that address is passed to kernels.
+static __device__ __align__(256) double scratch[GS_NOALLOC_MAX_TILES];
+
 struct gs_ctx {
   int device;
   uint32_t* pinned;  // host-visible readback slot for the instance count
   bool timing;
   EventTimer timer;
+  double* scratch_dev;  // device address of `scratch` on this context's device
   char err[512];
 };
 
@@ -220,10 +228,19 @@ gs_status gs_create(gs_ctx** out, int device) {
   hipGetDevice(&prev);
   hipSetDevice(device);
   e = hipHostMalloc(reinterpret_cast<void**>(&c->pinned), 64, hipHostMallocDefault);
-  hipSetDevice(prev);
   if (e != hipSuccess) {
+    hipSetDevice(prev);
     delete c;
     return hip_fail(nullptr, e, "hipHostMalloc");
+  }
+  // the allocation-free entry points use this device's copy of `scratch`
+  c->scratch_dev = nullptr;
+  e = hipGetSymbolAddress(reinterpret_cast<void**>(&c->scratch_dev), HIP_SYMBOL(scratch));
+  hipSetDevice(prev);
+  if (e != hipSuccess || !c->scratch_dev) {
+    hipHostFree(c->pinned);
+    delete c;
+    return hip_fail(nullptr, e, "hipGetSymbolAddress(scratch)");
   }
   *out = c;
   return GS_OK;
@@ -425,6 +442,46 @@ gs_status gs_render_fwd_l1(gs_ctx* c, const gs_projected* proj, const gs_tile_li
                            target, image, final_T, n_contrib, dL_dimage, loss_dev, ws,
                            (hipStream_t)stream);
   GS_LAUNCHED(c, "render_fwd_l1");
+  return GS_OK;
+}
+
+gs_status gs_render_fwd_l1_noalloc(gs_ctx* c, const gs_projected* proj,
+                                   const gs_tile_lists* lists, const gs_camera* ch,
+                                   const gs_camera* cd, int V, const gs_opts* opts,
+                                   const float* target, float* image, float* final_T,
+                                   int32_t* n_contrib, float* dL_dimage, double* loss_dev,
+                                   void* stream) {
+  // No TimerGuard: the stage timer records events into growing host vectors,
+  // and this entry point allocates nothing.
+  if (!c) return fail(nullptr, GS_ERR_INVALID_ARG, "ctx is NULL");
+  if (!c->scratch_dev) return fail(c, GS_ERR_INVALID_ARG, "context has no scratch array");
+  GS_TRY(check_cams(c, ch, cd, V));
+  if (!proj) return fail(c, GS_ERR_INVALID_ARG, "projected is NULL");
+  GS_TRY(check_projected(c, proj, V, proj->ld));
+  if (!lists || !lists->vals || !lists->ranges)
+    return fail(c, GS_ERR_INVALID_ARG, "tile lists are NULL");
+  const int64_t nseg = segments_of(ch, V);
+  if (lists->n_segments != nseg)
+    return fail(c, GS_ERR_INVALID_ARG, "tile lists were built for other cameras");
+  for (int v = 1; v < V; ++v)
+    if (ch[v].width != ch[0].width || ch[v].height != ch[0].height)
+      return fail(c, GS_ERR_INVALID_ARG, "views must share width and height");
+  if (!target || !final_T || !n_contrib || !dL_dimage || !loss_dev)
+    return fail(c, GS_ERR_INVALID_ARG, "NULL buffer");
+  if (opts && opts->usage)
+    return fail(c, GS_ERR_INVALID_ARG, "usage counts are not produced by the fused L1 forward");
+  if (nseg > GS_NOALLOC_MAX_TILES)
+    return fail(c, GS_ERR_INVALID_ARG,
+                "%lld tiles over all views exceed the fixed scratch of %d tiles",
+                (long long)nseg, GS_NOALLOC_MAX_TILES);
+  GS_TRY(use_device(c));
+  const float zero[3] = {0.f, 0.f, 0.f};
+  // every tile writes its partial before the sum kernel reads it, so the
+  // array needs no clearing between calls
+  gs::launch_render_fwd_l1(*proj, *lists, V, ch[0].width, ch[0].height, opts ? opts->bg : zero,
+                           target, image, final_T, n_contrib, dL_dimage, loss_dev,
+                           c->scratch_dev, (hipStream_t)stream);
+  GS_LAUNCHED(c, "render_fwd_l1_noalloc");
   return GS_OK;
 }
 

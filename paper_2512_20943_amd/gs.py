@@ -26,6 +26,7 @@ GS_ERR_OOM = 3
 GS_ERR_HIP = 4
 TILE = 16
 GS_MAX_INSTANCES = (1 << 30) - 1
+GS_NOALLOC_MAX_TILES = 1 << 18
 SPLAT_FLOATS = 16
 GS_PROJECT_TIGHT_RECT = 1
 GS_PROJECT_TILE_SPANS = 2
@@ -119,6 +120,11 @@ def load() -> ctypes.CDLL:
                                      c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
                                      ctypes.c_size_t, c_void_p]
     lib.gs_render_fwd_l1.restype = c_int32
+    lib.gs_render_fwd_l1_noalloc.argtypes = [c_void_p, P(GsProjected), P(GsTileLists),
+                                             P(GsCamera), c_void_p, ctypes.c_int, P(GsOpts),
+                                             c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
+                                             c_void_p, c_void_p]
+    lib.gs_render_fwd_l1_noalloc.restype = c_int32
     lib.gs_render_bwd.argtypes = [c_void_p, P(GsGaussians), P(GsProjected), P(GsTileLists),
                                   P(GsCamera), c_void_p, ctypes.c_int, P(GsOpts), c_void_p,
                                   c_void_p, c_void_p, P(GsGaussians), P(GsFrameUpdate), c_void_p,
@@ -184,7 +190,7 @@ def exported_symbols():
             "gs_l1_dssim_loss_grad", "gs_keyframe_temporal_l1", "gs_cull_workspace_size",
             "gs_cull_low_opacity", "gs_gather_planes", "gs_residual_delta",
             "gs_quantize_delta", "gs_apply_quantized_update", "gs_render_fwd_l1_workspace_size",
-            "gs_render_fwd_l1"]
+            "gs_render_fwd_l1", "gs_render_fwd_l1_noalloc"]
 
 
 def _ptr(t):
@@ -446,6 +452,20 @@ def gs_render_fwd_l1(ctx: Context, proj: Projected, lists: TileLists, cams: Came
                                        _ptr(target), _ptr(image), _ptr(final_T),
                                        _ptr(n_contrib), _ptr(dL_dimage), _ptr(loss_dev),
                                        _ptr(workspace), workspace.numel(), _stream(stream)))
+
+
+def gs_render_fwd_l1_noalloc(ctx: Context, proj: Projected, lists: TileLists, cams: Cameras,
+                             bg, target: torch.Tensor, image: torch.Tensor | None,
+                             final_T: torch.Tensor, n_contrib: torch.Tensor,
+                             dL_dimage: torch.Tensor, loss_dev: torch.Tensor, stream=None):
+    """gs_render_fwd_l1 with its per-tile partials in the library's fixed
+    device array instead of a workspace (the call allocates nothing)."""
+    pc = proj.c()
+    opts = GsOpts((c_float * 3)(*[float(x) for x in bg]), 0.0, None, None, None)
+    ctx.check(ctx.lib.gs_render_fwd_l1_noalloc(
+        ctx.handle, ctypes.byref(pc), ctypes.byref(lists.c()), cams.host, _ptr(cams.dev),
+        cams.V, ctypes.byref(opts), _ptr(target), _ptr(image), _ptr(final_T), _ptr(n_contrib),
+        _ptr(dL_dimage), _ptr(loss_dev), _stream(stream)))
 
 
 def gs_render_fwd_batched(ctx: Context, proj: Projected, lists: TileLists, cams: Cameras, bg,
