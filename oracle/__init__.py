@@ -119,9 +119,18 @@ def apply(scene, delta, mask, gw, gh):
     return out
 
 
-def project(scene, cams):
+TILESETS = {"rect": 0, "tight": 1, "spans": 2}
+SPAN_ROWS = 4
+F_SPANS = 64
+
+
+def project(scene, cams, tileset="rect"):
     """Steps 2-6: per (view, Gaussian) screen mean, conic, colour, opacity,
-    depth, radius, tile rectangle and flags, all in FP64."""
+    depth, radius, tile rectangle and flags, all in FP64.  ``tileset``
+    selects step 5b: "rect" keeps the step-5 rectangle, "tight" cuts it to
+    the alpha >= 1/255 ellipse's bounding box, "spans" also keeps per-row
+    column spans on small rectangles (``spans`` (V, n, 4, 2) absolute
+    [first, end) columns, flag bit F_SPANS)."""
     lib = _load()
     n, ld, deg = scene["n"], scene["ld"], scene["deg"]
     R, t, f, wh, V = _cam_arrays(cams)
@@ -137,28 +146,42 @@ def project(scene, cams):
                    _p(t), _p(f), _p(wh), _p(out["mean2d"]), _p(out["conic"]), _p(out["rgb"]),
                    _p(out["alpha_hat"]), _p(out["depth"]), _p(out["depth_bits"]),
                    _p(out["rect"]), _p(out["tiles"]), _p(out["radius"]), _p(out["flags"]))
+    out["spans"] = np.zeros((V, n, SPAN_ROWS, 2), np.int32)
+    mode = TILESETS[tileset]
+    if mode > 0:
+        lib.or_tile_sets(ctypes.c_int(V), ctypes.c_int(n), _p(wh), _p(out["mean2d"]),
+                         _p(out["conic"]), _p(out["alpha_hat"]), ctypes.c_int(mode),
+                         _p(out["rect"]), _p(out["tiles"]), _p(out["spans"]), _p(out["flags"]))
     out["n"] = n
     out["V"] = V
+    out["tileset"] = tileset
     return out
 
 
 def bin_sort(proj, cams, depth_bits=None, rect=None, tiles=None):
     """Step 7: instances (Gaussian, tile) ordered by (segment, FP32 depth,
-    Gaussian id); keys = (segment << 32) | depth bits.  The binning inputs may
-    be overridden (to replay another implementation's rectangles)."""
+    Gaussian id); keys = (segment << 32) | depth bits.  Tile sets come from
+    the projection (rectangles, or per-row spans where flagged).  The binning
+    inputs may be overridden (to replay another implementation's
+    rectangles; overriding uses plain rectangles)."""
     lib = _load()
     V, n = proj["V"], proj["n"]
     db = np.ascontiguousarray(proj["depth_bits"] if depth_bits is None else depth_bits,
                               dtype=np.uint32)
     rc = np.ascontiguousarray(proj["rect"] if rect is None else rect, dtype=np.int32)
     tl = np.ascontiguousarray(proj["tiles"] if tiles is None else tiles, dtype=np.int32)
+    replay = rect is not None or tiles is not None
+    spans = None if replay or "spans" not in proj else np.ascontiguousarray(proj["spans"],
+                                                                          dtype=np.int32)
+    flags = None if spans is None else np.ascontiguousarray(proj["flags"], dtype=np.uint8)
     base, txv, nseg = segment_bases(cams)
     M = int(lib.or_count_instances(ctypes.c_int(V), ctypes.c_int(n), _p(tl)))
     keys = np.zeros(max(M, 1), np.uint64)
     vals = np.zeros(max(M, 1), np.uint32)
     ranges = np.zeros((nseg, 2), np.uint32)
-    lib.or_bin_sort(ctypes.c_int(V), ctypes.c_int(n), _p(db), _p(rc), _p(tl), _p(base), _p(txv),
-                    ctypes.c_int64(nseg), _p(keys), _p(vals), _p(ranges))
+    lib.or_bin_sort(ctypes.c_int(V), ctypes.c_int(n), _p(db), _p(rc), _p(tl), _p(spans),
+                    _p(flags), _p(base), _p(txv), ctypes.c_int64(nseg), _p(keys), _p(vals),
+                    _p(ranges))
     return dict(keys=keys[:M], vals=vals[:M], ranges=ranges, count=M, seg_base=base,
                 n_segments=nseg)
 
@@ -197,7 +220,7 @@ def render_fwd(proj, lists, cams, bg=None):
 
 def render_brute(proj, cams, view=0, bg=None):
     """Plain definition of one view's image: every pixel composites all
-    visible Gaussians whose rectangle holds its tile, ordered by (FP32 depth,
+    visible Gaussians whose tile set holds its tile, ordered by (FP32 depth,
     id), with no binning or sorting machinery."""
     lib = _load()
     n = proj["n"]
@@ -212,7 +235,10 @@ def render_brute(proj, cams, view=0, bg=None):
                         _p(_f64(proj["alpha_hat"][view])),
                         _p(np.ascontiguousarray(proj["depth_bits"][view], np.uint32)),
                         _p(np.ascontiguousarray(proj["rect"][view], np.int32)),
-                        _p(np.ascontiguousarray(proj["tiles"][view], np.int32)), ctypes.c_int(W),
+                        _p(np.ascontiguousarray(proj["tiles"][view], np.int32)),
+                        _p(np.ascontiguousarray(proj["spans"][view], np.int32)
+                           if "spans" in proj else None),
+                        _p(np.ascontiguousarray(proj["flags"][view], np.uint8)), ctypes.c_int(W),
                         ctypes.c_int(H), _p(bgv), _p(image), _p(T), _p(nc))
     return dict(image=image, final_T=T, n_contrib=nc)
 
@@ -422,12 +448,73 @@ def accumulate_sent(Dp_prev, d_sent):
 
 
 # --------------------------------------------------------------------------
+# usage-frequency pruning and pruning-level selection (Sec. III-C, Alg. 1)
+# --------------------------------------------------------------------------
+
+def usage_keep_mask(usage, n, gw, gh, level):
+    """p(.) of Sec. III-C: keep every update except those of the
+    floor(level * n) least used Gaussians (usage = composited (view, pixel)
+    pairs); among equal usage the lower id is dropped first.  Returns the
+    (gh, gw) uint8 mask, 1 = keep, padding texels 0.  level * n is taken
+    within 1e-9 of an integer as that integer (levels are decimal steps)."""
+    drop = int(np.floor(level * n + 1e-9))
+    ranked = sorted(range(n), key=lambda i: (int(usage[i]), i))
+    m = np.zeros(gh * gw, np.uint8)
+    m[:n] = 1
+    for i in ranked[:drop]:
+        m[i] = 0
+    return m.reshape(gh, gw)
+
+
+def select_level(space, beta, bandwidth, rate):
+    """Alg. 1: ``space`` lists (quality, size) per pruning level, least
+    pruned first.  Walk the levels from the second on, comparing each
+    quality drop (quality of the level minus that of the level before) with
+    the drop before it, the first comparison being the second level's drop
+    with itself; the first level whose drop exceeds beta times the previous
+    drop is the cliff, and the levels before it are the candidates.  The
+    result is the first candidate (least pruned) whose size is at most
+    B / R; if none is, the cliff level.
+    Readings where the algorithm is silent: a previous drop of exactly 0
+    makes a level a cliff when its own drop is negative (a loss after a
+    lossless step); with no cliff and no fitting candidate the most pruned
+    level is returned."""
+    budget = bandwidth / rate
+    candidates = [0]
+    cliff = None
+    previous = space[1][0] - space[0][0] if len(space) > 1 else 0.0
+    for i in range(1, len(space)):
+        drop = space[i][0] - space[i - 1][0]
+        if previous == 0.0:
+            is_cliff = drop < 0.0
+        else:
+            is_cliff = drop / previous > beta
+        if is_cliff:
+            cliff = i
+            break
+        candidates.append(i)
+        previous = drop
+    for i in candidates:
+        if space[i][1] <= budget:
+            return i
+    return cliff if cliff is not None else len(space) - 1
+
+
+def psnr(image, reference):
+    """Mean over views of the PSNR (data range 1) of (V, 3, H, W) images."""
+    a = np.asarray(image, np.float64)
+    b = np.asarray(reference, np.float64)
+    mse = ((a - b) ** 2).reshape(a.shape[0], -1).mean(axis=1)
+    return float(np.mean(-10.0 * np.log10(mse)))
+
+
+# --------------------------------------------------------------------------
 # compositions used by tests
 # --------------------------------------------------------------------------
 
-def forward(scene, cams, bg=None):
+def forward(scene, cams, bg=None, tileset="rect"):
     """Steps 2-8 for a scene: projection, lists and images."""
-    proj = project(scene, cams)
+    proj = project(scene, cams, tileset)
     lists = bin_sort(proj, cams)
     img = render_fwd(proj, lists, cams, bg)
     return proj, lists, img

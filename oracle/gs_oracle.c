@@ -464,8 +464,143 @@ void or_project(int n, int ld, int deg, const float* mean, const float* lsc, con
 }
 
 /* ------------------------------------------------------------------------ */
+/* Step 5b (optional): tile sets narrower than the rectangle.                 */
+/*                                                                            */
+/* Step 8 skips a Gaussian at every pixel where its alpha stays below 1/255, */
+/* so listing it in a tile none of whose pixels reach that level changes no   */
+/* image, transmittance or gradient; only the list positions (n_contrib)      */
+/* count a shorter list.  With q(d) = A dx^2 + 2 B dx dy + C dy^2 the conic's */
+/* quadratic form (power = -q/2), alpha >= 1/255 needs q <= qm,               */
+/* qm = 2 ln(255 alpha_hat); the sets below use the widened ellipse           */
+/*   E = { d : q(d) <= thr },  thr = qm + 2e-4 |qm| + 1e-3,                    */
+/* whose margin covers an FP32 evaluation of alpha.  D = AC - B^2 > 0.        */
+/*   mode 1: the rectangle of step 5 cut to the tiles that meet E's bounding  */
+/*           box, x in px +- sqrt(thr C / D), y in py +- sqrt(thr A / D);     */
+/*           no tile at all when thr <= 0 (alpha_hat below about 1/255).     */
+/*   mode 2: mode 1, then a rectangle of at most OR_SPAN_ROWS tile rows and   */
+/*           OR_SPAN_COLS tile columns keeps, in tile row ty, only the        */
+/*           columns tx whose pixel centres x in [16 tx, 16 tx + 15] come     */
+/*           within OR_SPAN_SLACK px of E's x-extent over the band            */
+/*           y in [16 ty - 0.5, 16 ty + 15.5] (a row whose band misses E's    */
+/*           y-range by more than the slack keeps none).                      */
+/* Every pixel with q <= thr lies in a kept tile (its row's band holds it and */
+/* its x lies in the chord of E at its y).  E's chord at offset y is           */
+/* x in ((-B y - h) / A, (-B y + h) / A), h = sqrt(A thr - D y^2); its right   */
+/* end is concave in y with maximum sqrt(thr C / D) at y = -B sqrt(thr C/D)/C,*/
+/* and the left end mirrors it, so over a band the extreme is either that     */
+/* point or the chord at one of the band's ends (clamped into E's y-range).   */
+/* Records that keep no tile are culled.  spans (V*n, OR_SPAN_ROWS, 2) hold  */
+/* absolute [first, end) columns per row of the rectangle; OR_F_SPANS in      */
+/* flags marks the records that use them.                                     */
+/* ------------------------------------------------------------------------ */
+#define OR_SPAN_ROWS 4
+#define OR_SPAN_COLS 15
+#define OR_SPAN_SLACK 1e-3
+#define OR_F_SPANS 64u
+
+static double clamp_d(double x, double lo, double hi) { return x < lo ? lo : (x > hi ? hi : x); }
+
+/* ends of E's chord at offset y (clamped into E's y-range [-ey, ey]) */
+static void chord_ends(double A, double B, double D, double thr, double ey, double y, double* xl,
+                       double* xr, double* yc) {
+  const double yy = clamp_d(y, -ey, ey);
+  double hh = A * thr - D * yy * yy;
+  if (hh < 0.0) hh = 0.0;
+  const double h = sqrt(hh);
+  *xr = (-B * yy + h) / A;
+  *xl = (-B * yy - h) / A;
+  *yc = yy;
+}
+
+void or_tile_sets(int V, int n, const int* camwh, const double* mean2d, const double* conic,
+                  const double* alpha_hat, int mode, int* rect, int* tiles, int* spans,
+                  uint8_t* flags) {
+  for (int v = 0; v < V; ++v) {
+    const double TX = (double)tiles_x(camwh[2 * v]), TY = (double)tiles_x(camwh[2 * v + 1]);
+#pragma omp parallel for schedule(static)
+    for (int i = 0; i < n; ++i) {
+      const size_t j = (size_t)v * n + i;
+      int* sp = spans + (size_t)2 * OR_SPAN_ROWS * j;
+      for (int k = 0; k < 2 * OR_SPAN_ROWS; ++k) sp[k] = 0;
+      if (mode <= 0 || tiles[j] <= 0) continue;
+      const double px = mean2d[2 * j], py = mean2d[2 * j + 1];
+      const double A = conic[3 * j], B = conic[3 * j + 1], C = conic[3 * j + 2];
+      const double D = A * C - B * B;
+      const double qm = 2.0 * (log(255.0) + log(alpha_hat[j]));
+      const double thr = qm + 2e-4 * fabs(qm) + 1e-3;
+      int* r = rect + 4 * j;
+      double x0 = r[0], y0 = r[1], x1 = r[2], y1 = r[3];
+      double ex = 0.0, ey = 0.0;
+      if (thr > 0.0) {
+        ex = sqrt(thr * C / D);
+        ey = sqrt(thr * A / D);
+        x0 = fmax(x0, clamp_d(floor((px - ex) / (double)OR_TILE), 0.0, TX));
+        x1 = fmin(x1, clamp_d(floor((px + ex) / (double)OR_TILE) + 1.0, 0.0, TX));
+        y0 = fmax(y0, clamp_d(floor((py - ey) / (double)OR_TILE), 0.0, TY));
+        y1 = fmin(y1, clamp_d(floor((py + ey) / (double)OR_TILE) + 1.0, 0.0, TY));
+      } else {
+        x1 = x0;
+      }
+      int cnt = 0;
+      if (x1 > x0 && y1 > y0) {
+        cnt = (int)((x1 - x0) * (y1 - y0));
+        if (mode >= 2 && y1 - y0 <= OR_SPAN_ROWS && x1 - x0 <= OR_SPAN_COLS) {
+          const double ys = -B * ex / C; /* offset of E's rightmost point */
+          cnt = 0;
+          for (int row = 0; row < (int)(y1 - y0); ++row) {
+            const double ty = y0 + row;
+            const double lo = ((double)OR_TILE * ty - 0.5) - py;
+            const double hi = ((double)OR_TILE * ty + 15.5) - py;
+            if (lo > ey + OR_SPAN_SLACK || hi < -ey - OR_SPAN_SLACK) continue;
+            double l0, r0, c0, l1, r1, c1;
+            chord_ends(A, B, D, thr, ey, lo, &l0, &r0, &c0);
+            chord_ends(A, B, D, thr, ey, hi, &l1, &r1, &c1);
+            const double xmax = (ys >= c0 && ys <= c1) ? ex : fmax(r0, r1);
+            const double xmin = (-ys >= c0 && -ys <= c1) ? -ex : fmin(l0, l1);
+            const double a =
+                fmax(x0, ceil((((px + xmin) - OR_SPAN_SLACK) - (double)(OR_TILE - 1)) /
+                              (double)OR_TILE));
+            const double b = fmin(x1, floor(((px + xmax) + OR_SPAN_SLACK) / (double)OR_TILE) + 1.0);
+            if (b > a) {
+              sp[2 * row] = (int)a;
+              sp[2 * row + 1] = (int)b;
+              cnt += (int)(b - a);
+            }
+          }
+          flags[j] |= OR_F_SPANS;
+        }
+      }
+      if (cnt <= 0) {
+        r[0] = r[1] = r[2] = r[3] = 0;
+        tiles[j] = 0;
+        flags[j] = 0;
+        for (int k = 0; k < 2 * OR_SPAN_ROWS; ++k) sp[k] = 0;
+        continue;
+      }
+      r[0] = (int)x0;
+      r[1] = (int)y0;
+      r[2] = (int)x1;
+      r[3] = (int)y1;
+      tiles[j] = cnt;
+    }
+  }
+}
+
+/* Column range [*a, *b) of tile row ty in record j's tile set. */
+static void row_columns(const int* r, const int* sp, int spanned, int ty, int* a, int* b) {
+  if (spanned) {
+    *a = sp[2 * (ty - r[1])];
+    *b = sp[2 * (ty - r[1]) + 1];
+  } else {
+    *a = r[0];
+    *b = r[2];
+  }
+}
+
+/* ------------------------------------------------------------------------ */
 /* Step 7: binning and depth-keyed ordering.  Every (Gaussian, tile) pair of  */
-/* a visible Gaussian's rectangle is one instance, key = (segment << 32) |    */
+/* a visible Gaussian's tile set (its rectangle, or per-row spans of step 5b) */
+/* is one instance, key = (segment << 32) |                                   */
 /* depth bits, segment = seg_base[v] + ty*TX_v + tx.  The defining order is   */
 /* ascending (key, Gaussian id); a comparison sort on that pair gives it.      */
 /* ------------------------------------------------------------------------ */
@@ -493,8 +628,8 @@ int64_t or_count_instances(int V, int n, const int* tiles) {
 /* seg_base (V) = first segment of each view; TXv (V) = tiles per row.
  * keys/vals have room for M = or_count_instances(...); ranges (n_seg, 2). */
 void or_bin_sort(int V, int n, const uint32_t* depth_bits, const int* rect, const int* tiles,
-                 const int64_t* seg_base, const int* TXv, int64_t n_seg, uint64_t* keys,
-                 uint32_t* vals, uint32_t* ranges) {
+                 const int* spans, const uint8_t* flags, const int64_t* seg_base, const int* TXv,
+                 int64_t n_seg, uint64_t* keys, uint32_t* vals, uint32_t* ranges) {
   int64_t M = or_count_instances(V, n, tiles);
   or_inst* a = (or_inst*)malloc(sizeof(or_inst) * (size_t)(M > 0 ? M : 1));
   int64_t w = 0;
@@ -503,13 +638,17 @@ void or_bin_sort(int V, int n, const uint32_t* depth_bits, const int* rect, cons
       const size_t j = (size_t)v * n + i;
       if (tiles[j] <= 0) continue;
       const int* r = rect + 4 * j;
-      for (int ty = r[1]; ty < r[3]; ++ty)
-        for (int tx = r[0]; tx < r[2]; ++tx) {
+      const int spanned = spans && flags && (flags[j] & OR_F_SPANS);
+      for (int ty = r[1]; ty < r[3]; ++ty) {
+        int c0, c1;
+        row_columns(r, spans ? spans + (size_t)2 * OR_SPAN_ROWS * j : NULL, spanned, ty, &c0, &c1);
+        for (int tx = c0; tx < c1; ++tx) {
           uint64_t seg = (uint64_t)(seg_base[v] + (int64_t)ty * TXv[v] + tx);
           a[w].key = (seg << 32) | (uint64_t)depth_bits[j];
           a[w].val = (uint32_t)i;
           ++w;
         }
+      }
     }
   qsort(a, (size_t)M, sizeof(or_inst), inst_cmp);
   for (int64_t s = 0; s < n_seg; ++s) {
@@ -633,8 +772,9 @@ void or_render_fwd(int V, int n, const double* mean2d, const double* conic, cons
 }
 
 /* Brute-force render of one view straight from the plain definition: for
- * every pixel, the contributing set is every visible Gaussian whose
- * rectangle contains the pixel's tile, ordered by (FP32 depth, id). */
+ * every pixel, the contributing set is every visible Gaussian whose tile set
+ * (rectangle, or per-row spans) contains the pixel's tile, ordered by (FP32
+ * depth, id). */
 typedef struct {
   uint32_t d;
   uint32_t id;
@@ -649,8 +789,8 @@ static int did_cmp(const void* pa, const void* pb) {
 
 void or_render_brute(int n, const double* mean2d, const double* conic, const double* rgb,
                      const double* alpha_hat, const uint32_t* depth_bits, const int* rect,
-                     const int* tiles, int W, int H, const double* bg, double* image,
-                     double* final_T, int* n_contrib) {
+                     const int* tiles, const int* spans, const uint8_t* flags, int W, int H,
+                     const double* bg, double* image, double* final_T, int* n_contrib) {
   or_splats S = {mean2d, conic, rgb, alpha_hat};
   or_did* lst = (or_did*)malloc(sizeof(or_did) * (size_t)(n > 0 ? n : 1));
   uint32_t* ids = (uint32_t*)malloc(sizeof(uint32_t) * (size_t)(n > 0 ? n : 1));
@@ -662,7 +802,11 @@ void or_render_brute(int n, const double* mean2d, const double* conic, const dou
       for (int i = 0; i < n; ++i) {
         if (tiles[i] <= 0) continue;
         const int* r = rect + 4 * i;
-        if (tx >= r[0] && tx < r[2] && ty >= r[1] && ty < r[3]) {
+        if (ty < r[1] || ty >= r[3]) continue;
+        int c0, c1;
+        row_columns(r, spans ? spans + (size_t)2 * OR_SPAN_ROWS * i : NULL,
+                    spans && flags && (flags[i] & OR_F_SPANS), ty, &c0, &c1);
+        if (tx >= c0 && tx < c1) {
           lst[len].d = depth_bits[i];
           lst[len].id = (uint32_t)i;
           ++len;
@@ -1057,7 +1201,7 @@ double or_forward_loss(int n, int ld, int deg, const float* mean, const float* l
     uint32_t* vals = (uint32_t*)malloc(sizeof(uint32_t) * (size_t)(M > 0 ? M : 1));
     uint32_t* ranges = (uint32_t*)malloc(sizeof(uint32_t) * 2 * (size_t)nseg);
     const int64_t sb = 0;
-    or_bin_sort(1, n, db, rc, tl, &sb, &TX, nseg, keys, vals, ranges);
+    or_bin_sort(1, n, db, rc, tl, NULL, NULL, &sb, &TX, nseg, keys, vals, ranges);
     or_splats S = {m2, co, rg, ah};
     const size_t pix = (size_t)W * H;
     for (int y = 0; y < H; ++y)

@@ -23,6 +23,7 @@ constexpr float kY3b = 2.8906114426405538f;   // xyz
 constexpr float kY3c = 0.45704579946446572f;  // y(5z^2-1), x(5z^2-1)
 constexpr float kY3d = 0.37317633259011540f;  // z(5z^2-3)
 constexpr float kY3e = 1.4453057213202769f;   // z(x^2-y^2)
+constexpr double kLn255d = 5.541263545158426;  // ln 255
 
 template <int DEG>
 __device__ __forceinline__ void sh_eval(float x, float y, float z, float* Y) {
@@ -128,6 +129,14 @@ __global__ __launch_bounds__(256) void k_project(
       S[3 * r + c] = (M[3 * r + 0] * M[3 * c + 0] + M[3 * r + 1] * M[3 * c + 1]) +
                      M[3 * r + 2] * M[3 * c + 2];
   const float alpha_hat = 1.f / (1.f + __expf(-opac[i]));
+  // threshold of the opacity-aware tile sets: alpha >= 1/255 needs
+  // q(d) <= 2 ln(255 opacity) (in FP64 from the logit, one per Gaussian)
+  double thr = 0.0;
+  if (tight) {
+    const double ahd = 1.0 / (1.0 + exp(-(double)opac[i]));
+    const double qm = 2.0 * (kLn255d + log(ahd));
+    thr = qm + 2e-4 * fabs(qm) + 1e-3;
+  }
   float shv[K * 3];
 #pragma unroll
   for (int k = 0; k < K * 3; ++k) shv[k] = sh[(size_t)k * L + i];
@@ -197,16 +206,19 @@ __global__ __launch_bounds__(256) void k_project(
         double t1 = clampd(floor((py - rad) / (double)kTile), 0.0, TY);
         double t3 = clampd(floor((py + rad) / (double)kTile) + 1.0, 0.0, TY);
         if (tight) {
-          // alpha >= 1/255 needs q = A dx^2 + 2B dx dy + C dy^2 <= 2 ln(255
-          // opacity); with the renderer's quadrant-test margin on top, the
-          // ellipse q <= thr has half-extents sqrt(thr C / Q), sqrt(thr A / Q)
-          const double qm = 2.0 * (log(255.0) + log((double)alpha_hat));
-          const double thr = qm + 2e-4 * fabs(qm) + 1e-3;
-          double ex_thr = 0.0, ey_thr = 0.0;  // half-extents of that ellipse
+          // A tile none of whose pixels reaches alpha >= 1/255 composites
+          // nothing of this Gaussian.  alpha >= 1/255 needs q(d) = A dx^2 +
+          // 2B dx dy + C dy^2 <= 2 ln(255 opacity); with a margin that covers
+          // FP32 evaluation of alpha, the kept tiles are those meeting the
+          // ellipse q <= thr (bounding box x +- sqrt(thr C / Dq), y +-
+          // sqrt(thr A / Dq), Dq = AC - B^2).  Everything here is IEEE FP64
+          // in a fixed operation order, opacity included, so that the tile
+          // sets are a deterministic function of the FP64 binning geometry.
+          const double Dq = A * C - B * B;
+          double ex = 0.0, ey = 0.0;  // half-extents of that ellipse
           if (thr > 0.0) {
-            const double ex = sqrt(thr * C / detq), ey = sqrt(thr * A / detq);
-            ex_thr = ex;
-            ey_thr = ey;
+            ex = sqrt(thr * C / Dq);
+            ey = sqrt(thr * A / Dq);
             t0 = fmax(t0, clampd(floor((px - ex) / (double)kTile), 0.0, TX));
             t2 = fmin(t2, clampd(floor((px + ex) / (double)kTile) + 1.0, 0.0, TX));
             t1 = fmax(t1, clampd(floor((py - ey) / (double)kTile), 0.0, TY));
@@ -218,53 +230,44 @@ __global__ __launch_bounds__(256) void k_project(
                                   : make_int4(0, 0, 0, 0);
           nt = (rc.z - rc.x) * (rc.w - rc.y);
           if (spans && nt > 0 && rc.w - rc.y <= kSpanRows && rc.z - rc.x <= kSpanWidth) {
-            // Per tile row, the columns whose pixel box meets the same
-            // ellipse.  Row r takes the band of y within half a pixel of its
-            // pixel centres, so neighbouring rows share an edge: over a band,
-            // the ellipse's right end x(y) is concave with its maximum ex at
-            // y = dys (its rightmost point) and the left end is the mirror
-            // image, so each extreme is ex (or -ex) when that point lies in
-            // the band and otherwise the larger (smaller) of the band edges'
-            // values.  The hardware square root and reciprocal (relative
-            // error near 2^-23) move an end by under 1e-4 px at these sizes
-            // (chord ends within 120 px of the centre), inside the kSpanEps
-            // slack.
-            const double ey = ey_thr, iA = __builtin_amdgcn_rcp(A);
-            const double dys = -B * ex_thr / C;
-            const double ath = A * thr;
-            // ends of the ellipse's chord at offset dy (clamped into it)
-            auto chord = [&](double dy, double& xl, double& xr) {
-              const double y = clampd(dy, -ey, ey);
-              const double hw = __builtin_amdgcn_sqrt(fmax(0.0, ath - detq * y * y));
-              xr = (-B * y + hw) * iA;
-              xl = (-B * y - hw) * iA;
-              return y;
+            // Per tile row, the columns whose pixel centres come within
+            // kSpanEps of the ellipse's x-extent over the row's band (pixel
+            // centres +- 0.5 px in y, so neighbouring rows share an edge).
+            // The chord at offset y spans x in ((-By - h)/A, (-By + h)/A),
+            // h = sqrt(A thr - Dq y^2); its right end is concave in y with
+            // maximum ex at y = -B ex / C and the left end mirrors it, so
+            // over a band the extreme is that point or the chord at a band
+            // end (clamped into [-ey, ey]).
+            const double ys = -B * ex / C;
+            auto chord = [&](double y, double& xl, double& xr) {
+              const double yy = clampd(y, -ey, ey);
+              double hh = A * thr - Dq * yy * yy;
+              if (hh < 0.0) hh = 0.0;
+              const double h = sqrt(hh);
+              xr = (-B * yy + h) / A;
+              xl = (-B * yy - h) / A;
+              return yy;
             };
-            double e0 = (double)(rc.y * kTile) - 0.5 - py;
-            double xl0, xr0;
-            double y0 = chord(e0, xl0, xr0);
             uint32_t packed = 0;
             int cnt = 0;
             for (int r = 0; r < rc.w - rc.y; ++r) {
-              const double e1 = e0 + (double)kTile;
-              double xl1, xr1;
-              const double y1 = chord(e1, xl1, xr1);
-              if (!(e0 > ey + kSpanEps || e1 < -ey - kSpanEps)) {
-                const double xmax = (dys >= y0 && dys <= y1) ? ex_thr : fmax(xr0, xr1);
-                const double xmin = (-dys >= y0 && -dys <= y1) ? -ex_thr : fmin(xl0, xl1);
-                const double xs = fmax(t0, ceil((px + xmin - kSpanEps - (double)(kTile - 1)) *
-                                                (1.0 / kTile)));
-                const double xe = fmin(t2, floor((px + xmax + kSpanEps) * (1.0 / kTile)) + 1.0);
-                if (xe > xs) {
-                  const uint32_t a0 = (uint32_t)(xs - t0), a1 = (uint32_t)(xe - t0);
-                  packed |= (a0 | a1 << 4) << (8 * r);
-                  cnt += (int)(a1 - a0);
-                }
+              const double tyd = (double)(rc.y + r);
+              const double lo = ((double)kTile * tyd - 0.5) - py;
+              const double hi = ((double)kTile * tyd + 15.5) - py;
+              if (lo > ey + kSpanEps || hi < -ey - kSpanEps) continue;
+              double l0, r0, l1, r1;
+              const double c0 = chord(lo, l0, r0);
+              const double c1 = chord(hi, l1, r1);
+              const double xmax = (ys >= c0 && ys <= c1) ? ex : fmax(r0, r1);
+              const double xmin = (-ys >= c0 && -ys <= c1) ? -ex : fmin(l0, l1);
+              const double xs = fmax(
+                  t0, ceil((((px + xmin) - kSpanEps) - (double)(kTile - 1)) / (double)kTile));
+              const double xe = fmin(t2, floor(((px + xmax) + kSpanEps) / (double)kTile) + 1.0);
+              if (xe > xs) {
+                const uint32_t a0 = (uint32_t)(xs - t0), a1 = (uint32_t)(xe - t0);
+                packed |= (a0 | a1 << 4) << (8 * r);
+                cnt += (int)(a1 - a0);
               }
-              e0 = e1;
-              y0 = y1;
-              xl0 = xl1;
-              xr0 = xr1;
             }
             span_word = packed;
             span_mode = true;

@@ -27,7 +27,31 @@ def projected_to_oracle(p: gs.Projected):
         depth=s[..., 9], detq=s[..., 10],
         rect=p.rect[:, :n].cpu().numpy(), tiles=p.tiles_touched[:, :n].cpu().numpy(),
         depth_bits=p.depth_bits[:, :n].cpu().numpy().view(np.uint32),
-        flags=p.flags[:, :n].cpu().numpy())
+        flags=p.flags[:, :n].cpu().numpy(),
+        words=p.splat[:, :n].cpu().numpy().view(np.uint32).reshape(p.V, n, 16))
+
+
+def span_rows(P):
+    """Per-row tile columns (V, n, 4, 2) of span-mode records, absolute
+    [first, end), empty rows (0, 0), from either side's projection: the
+    oracle stores them as they are, the HIP record packs them relative to
+    the rectangle's first column in word 15 (flag in bit 31 of word 13)."""
+    if "spans" in P:
+        sp = np.asarray(P["spans"], np.int64).copy()
+        spanned = (np.asarray(P["flags"]) & 64) > 0
+    else:
+        w = P["words"]
+        spanned = (w[..., 13] >> 31).astype(bool)
+        x0 = P["rect"][..., 0].astype(np.int64)
+        m = w[..., 15].astype(np.int64)
+        sp = np.zeros(m.shape + (4, 2), np.int64)
+        for r in range(4):
+            a = (m >> (8 * r)) & 15
+            b = (m >> (8 * r + 4)) & 15
+            sp[..., r, 0] = np.where(b > a, x0 + a, 0)
+            sp[..., r, 1] = np.where(b > a, x0 + b, 0)
+    sp[~spanned] = 0
+    return spanned, sp
 
 
 def lists_to_numpy(L: gs.TileLists):

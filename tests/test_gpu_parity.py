@@ -18,7 +18,7 @@ from paper_2512_20943_amd import gs, scenes
 from paper_2512_20943_amd.raster import GSFrameRender, GSRender, Rasterizer, frame_of
 from tests.gpu_helpers import (IMG_ATOL, MEAN2D_ATOL, NEAR_ATOL, NEAR_FRAC_CAP, assert_close_rel,
                                assert_grad_close, compare_images, gpu_forward, lists_to_numpy,
-                               projected_to_oracle, require_gpu)
+                               projected_to_oracle, require_gpu, span_rows)
 
 pytestmark = pytest.mark.gpu
 
@@ -83,24 +83,37 @@ def test_apply_bit_exact(n, level):
 
 
 @pytest.mark.parametrize("which", ["plain_10k", "frame_20k_4v"])
-def test_projection_and_lists_bit_exact(which):
+@pytest.mark.parametrize("tileset", ["rect", "tight", "spans"])
+def test_projection_and_lists_bit_exact(which, tileset):
+    """Projection records, tile sets (rectangles, or the opacity-aware
+    rectangles and per-row spans the benchmark bins with), keys, lists and
+    ranges against the oracle's; then images, final_T and n_contrib (list
+    positions in these lists) against the oracle's render of the same lists."""
     require_gpu()
-    say(f"projection+lists {which}")
+    say(f"projection+lists {which} {tileset}")
     if which == "plain_10k":
         scene, cams, _ = scenes.workload_plain_10k(0)
     else:
         scene, cams = small_frame_workload(1)
-    g, gc, r, out = gpu_forward(scene, cams)
-    P_or = oracle.project(scene, cams)
+    g, gc, r, out = gpu_forward(scene, cams, tight_rect=tileset != "rect",
+                                tile_spans=tileset == "spans")
+    P_or = oracle.project(scene, cams, tileset)
     P_g = projected_to_oracle(out["proj"])
     nvis = compare_projection(P_g, P_or)
     assert nvis > 0
+    sp_g, rows_g = span_rows(P_g)
+    sp_o, rows_o = span_rows(P_or)
+    np.testing.assert_array_equal(sp_g, sp_o)
+    np.testing.assert_array_equal(rows_g, rows_o)
+    assert sp_o.any() == (tileset == "spans")
     L_or = oracle.bin_sort(P_or, cams)
     L_g = lists_to_numpy(out["lists"])
     assert L_g["count"] == L_or["count"] > 0
     np.testing.assert_array_equal(L_g["keys"], L_or["keys"])
     np.testing.assert_array_equal(L_g["vals"], L_or["vals"])
     np.testing.assert_array_equal(L_g["ranges"], L_or["ranges"])
+    img_or = oracle.render_fwd(P_or, L_or, cams)
+    compare_images(out, img_or, which)
 
 
 @pytest.mark.parametrize("which", ["plain_10k", "frame_20k_4v"])
@@ -766,6 +779,27 @@ def test_full_frame_300k_20_views_sampled():
     assert 0 < out_s["lists"].count < out["lists"].count
     assert torch.equal(out_s["image"], out["image"])
     assert torch.equal(out_s["final_T"], out["final_T"])
+    # the benchmark's tile sets: every record's spans, view 0's lists bit for
+    # bit, and n_contrib as positions in those lists
+    P_s = oracle.project(scene, cams, "spans")
+    Pg_s = projected_to_oracle(out_s["proj"])
+    np.testing.assert_array_equal(Pg_s["tiles"], P_s["tiles"])
+    vis = (P_s["flags"] & 32) > 0
+    np.testing.assert_array_equal(Pg_s["rect"][vis], P_s["rect"][vis])
+    for a, b in zip(span_rows(Pg_s), span_rows(P_s)):
+        np.testing.assert_array_equal(a, b)
+    del Pg_s
+    P0s = {k: (v[:1] if isinstance(v, np.ndarray) else v) for k, v in P_s.items()}
+    P0s["V"] = 1
+    del P_s
+    L0s = oracle.bin_sort(P0s, cam0)
+    L_s = lists_to_numpy(out_s["lists"])
+    rg = L_s["ranges"][:nseg0]
+    np.testing.assert_array_equal(rg, L0s["ranges"])
+    np.testing.assert_array_equal(L_s["vals"][:int(rg[:, 1].max())], L0s["vals"])
+    img0s = oracle.render_fwd(P0s, L0s, cam0)
+    out0s = {k: out_s[k][:1] for k in ("image", "final_T", "n_contrib")}
+    compare_images(out0s, img0s, "frame_300k_view0")
 
 
 def _sparse_tile_gradient(img_shape, n_tiles, seed, W, H):
