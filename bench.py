@@ -220,11 +220,12 @@ class SweepStep:
     one batched render of every (level, view) pair, squared error per pair,
     level selection by Alg. 1 on the host)."""
 
-    def __init__(self, scene, n_views):
+    def __init__(self, scene, target_scene, n_views):
         import torch
 
         from paper_2512_20943_amd import gs, scenes
         from paper_2512_20943_amd.prune import PruningSweep
+        from paper_2512_20943_amd.raster import Rasterizer
         self.torch, self.gs = torch, gs
         self.ctx = gs.default_context()
         n = scene["n"]
@@ -233,10 +234,14 @@ class SweepStep:
         delta = torch.from_numpy(scenes.make_delta(n, gw, gh, 2)).cuda()
         self.cams = gs.Cameras(scenes.arc_cameras(n_views, 5.0, 1352, 1014))
         self.sweep = PruningSweep(anchor, delta, gw, gh, self.cams, ctx=self.ctx)
+        # the frame's reference views: the target scene's renders
+        r = Rasterizer(ctx=self.ctx, capacity=1 << 25, tight_rect=True, tile_spans=True)
+        self.reference = r.forward(gs.Gaussians.from_scene(target_scene), self.cams)["image"]
+        self.reference = self.reference.clone()
         self.last = None
 
     def step(self):
-        self.last = self.sweep.run()
+        self.last = self.sweep.run(self.reference)
 
 
 class CodecStep:
@@ -599,7 +604,7 @@ def main():
         log(f"Eq. (1) L1 + D-SSIM step: {wall3 / k3 * 1e3:.2f} ms")
         del ds
     if not args.no_sweep:
-        sw = SweepStep(scene, 4)
+        sw = SweepStep(scene, target_scene, 4)
         k5 = 3
         wall5, _, st5 = time_steps(sw, k5, 1)
         last = sw.last

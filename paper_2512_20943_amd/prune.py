@@ -6,18 +6,18 @@
 * ``PruningSweep`` builds the dense pruning-level space S_t^d of one frame:
   for each level it applies the pruned update, renders all evaluation views
   of all levels in one persistent batched launch, and measures quality as
-  PSNR against the unpruned frame's render (squared errors reduced on the
-  device) and size as the bytes of the kept update texels.
-* ``select_level`` is Alg. 1: scan S_t^d for the first quality cliff (a drop
-  more than beta times the previous drop), keep the levels before it, then
-  binary-search the lowest kept level whose size fits B / R.
+  the PSNR of each level's renders against the frame's reference views
+  (squared errors reduced on the device) and size as the bytes of the kept
+  update texels.
+* ``select_level`` is Alg. 1: the levels before the first quality cliff are
+  the candidates, and the least pruned candidate whose size fits B / R wins.
 
-Readings where the paper is silent: quality is PSNR (data range 1) against
-the unpruned render, capped at 100 dB where the two are identical; a drop
-compared with a previous drop of exactly 0 counts as a cliff when it is
-nonzero; when no candidate fits B / R the algorithm's own fallthrough is
-kept (the cliff level if one was found), and without a cliff the most pruned
-candidate is returned.
+Readings where the paper is silent: quality is the mean over views of the
+PSNR (data range 1) against the reference views the frame is trained on (the
+level-0 render is not a reference: its own error would be zero); a previous
+drop of exactly 0 makes a level a cliff when its own drop is negative; when
+no candidate fits B / R the cliff level is returned (the algorithm's own
+fallthrough), and without a cliff the most pruned level.
 """
 from __future__ import annotations
 
@@ -30,7 +30,6 @@ from . import gs
 from .raster import Rasterizer, frame_of
 
 BYTES_PER_UPDATE = 8 * 4  # eight FP32 channels per kept texel
-PSNR_CAP = 100.0
 
 
 def usage_keep_mask(usage: np.ndarray, n: int, gw: int, gh: int, level: float) -> np.ndarray:
@@ -52,33 +51,39 @@ def usage_keep_masks(usage: np.ndarray, n: int, gw: int, gh: int, levels) -> lis
     return out
 
 
+def _is_cliff(drop: float, before: float, beta: float) -> bool:
+    if before == 0.0:
+        return drop < 0.0
+    return drop / before > beta
+
+
 def select_level(space, beta: float, bandwidth: float, rate: float) -> int:
-    """Alg. 1 over ``space`` = [(quality, size), ...] in increasing pruning."""
-    p = None
-    previous = space[1][0] - space[0][0]
-    S = [0]
-    for i in range(1, len(space)):
-        drop = space[i][0] - space[i - 1][0]
-        if previous == 0.0:
-            cliff = drop != 0.0
+    """Alg. 1 over ``space`` = [(quality, size), ...] in increasing pruning.
+
+    Each level's quality drop is compared with the drop of the level before
+    it (the first drop with itself); the first level whose drop exceeds beta
+    times that is the cliff and bounds the candidates.  Sizes do not grow
+    with the level, so the candidates that fit the budget B / R form a
+    suffix of the candidate range, and a bisection finds its first (least
+    pruned) member."""
+    quality = np.array([q for q, _ in space], np.float64)
+    size = np.array([sz for _, sz in space], np.float64)
+    drops = np.diff(quality)
+    before = np.concatenate([drops[:1], drops[:-1]])
+    cliff = next((k + 1 for k in range(drops.size) if _is_cliff(drops[k], before[k], beta)),
+                 None)
+    end = len(space) if cliff is None else cliff
+    budget = bandwidth / rate
+    lo, hi = 0, end
+    while lo < hi:
+        mid = (lo + hi) // 2
+        if size[mid] <= budget:
+            hi = mid
         else:
-            cliff = drop / previous > beta
-        if cliff:
-            p = i
-            break
-        S.append(i)
-        previous = drop
-    C = bandwidth / rate
-    low, high = 0, len(S) - 1
-    while low <= high:
-        mid = (low + high) // 2
-        tmp = S[mid]
-        if space[tmp][1] <= C:
-            p = tmp
-            high = mid - 1
-        else:
-            low = mid + 1
-    return S[-1] if p is None else p
+            lo = mid + 1
+    if lo < end:
+        return lo
+    return len(space) - 1 if cliff is None else cliff
 
 
 class PruningSweep:
@@ -98,21 +103,27 @@ class PruningSweep:
         self._proj = None  # projected records of every (level, view), reused
 
     def usage(self, bg=(0.0, 0.0, 0.0)):
-        """Reference render of the unpruned frame and per-Gaussian usage."""
+        """Per-Gaussian usage: composited (view, pixel) pairs of the unpruned
+        frame."""
         dev = self.anchor.mean.device
         full = frame_of(self.anchor)
         ones = torch.ones(self.gh, self.gw, dtype=torch.uint8, device=dev)
         gs.gs_apply_frame_update(self.ctx, self.anchor, self.delta, ones, self.gw, self.gh, full)
         usage = torch.zeros(self.anchor.ld, dtype=torch.int32, device=dev)
-        out = self.raster.forward(full, self.cams, bg, usage=usage)
-        return out["image"].clone(), usage
+        self.raster.forward(full, self.cams, bg, usage=usage)
+        return usage
 
-    def run(self, beta: float = 2.0, bandwidth: float = 1e6, rate: float = 30.0,
-            bg=(0.0, 0.0, 0.0)):
+    def run(self, reference: torch.Tensor, beta: float = 2.0, bandwidth: float = 1e6,
+            rate: float = 30.0, bg=(0.0, 0.0, 0.0)):
+        """``reference``: the frame's (V, 3, H, W) views that quality is
+        measured against."""
         dev = self.anchor.mean.device
-        ref, usage = self.usage(bg)
+        V = self.cams.V
+        if tuple(reference.shape[:2]) != (V, 3):
+            raise ValueError("reference must hold (V, 3, H, W) views")
+        usage = self.usage(bg)
         u = usage.cpu().numpy().view(np.uint32).astype(np.int64)
-        n, L, V = self.anchor.n, len(self.levels), self.cams.V
+        n, L = self.anchor.n, len(self.levels)
         masks = usage_keep_masks(u, n, self.gw, self.gh, self.levels)
         frames = []
         for m in masks:
@@ -141,14 +152,15 @@ class PruningSweep:
         gs.gs_render_fwd_batched(self.ctx, proj, lists, cams, bg, images, ws)
         sq = torch.zeros(L * V, dtype=torch.float64, device=dev)
         off = 0
-        refs = ref.reshape(V, -1)
+        refs = reference.reshape(V, -1)
         for k in range(L * V):
             cnt = 3 * pix[k]
             gs.gs_sq_error(self.ctx, images[off:off + cnt], refs[k % V], sq[k:k + 1])
             off += cnt
         mse = (sq.cpu().numpy() / np.array([3 * p for p in pix])).reshape(L, V)
-        psnr = np.where(mse > 0, -10.0 * np.log10(np.maximum(mse, 1e-300)), PSNR_CAP)
-        psnr = np.minimum(psnr, PSNR_CAP).mean(axis=1)
+        if not (mse > 0).all():
+            raise ValueError("a level renders its reference exactly: quality is undefined")
+        psnr = (-10.0 * np.log10(mse)).mean(axis=1)
         sizes = np.array([int(m.sum()) * BYTES_PER_UPDATE for m in masks])
         space = list(zip(psnr.tolist(), sizes.tolist()))
         p = select_level(space, beta, bandwidth, rate)
