@@ -257,7 +257,8 @@ gs_status gs_apply_frame_update(gs_ctx* ctx, const gs_gaussians* anchor, const f
                                 const uint8_t* mask, int gw, int gh, gs_gaussians* frame,
                                 void* stream);
 
-/* EWA projection (Sec. II renderer): camera transform, near cull (z <= 0.2),
+/* EWA projection (Sec. II renderer): camera transform, near cull (z <= 0.2,
+ * a fixed plane: the paper names none),
  * 3D covariance R_q diag(exp s)^2 R_q^T, 2D covariance J W Sigma W^T J^T
  * with a 1.3x guard band on J and +0.3 px^2 dilation, conic, screen mean,
  * radius ceil(3 sqrt(lambda_max)) (eigenvalue floor 0.1), 16x16 tile
@@ -268,7 +269,9 @@ gs_status gs_apply_frame_update(gs_ctx* ctx, const gs_gaussians* anchor, const f
 gs_status gs_project(gs_ctx* ctx, const gs_gaussians* g, const gs_camera* cams_host,
                      const gs_camera* cams_dev, int n_views, gs_projected* out, void* stream);
 
-/* Binning and depth ordering: every (visible Gaussian, tile of its
+/* Binning and depth ordering of the splatting renderer the paper cites in
+ * Sec. II (its tile-based rasterizer sorts splats per 16x16 tile by depth):
+ * every (visible Gaussian, tile of its
  * rectangle, or of its per-row spans when the record carries them, see
  * GS_PROJECT_TILE_SPANS) pair is an instance; instances are ordered by
  * (segment, FP32 depth, Gaussian id) with an LDS-resident onesweep radix
@@ -283,7 +286,9 @@ gs_status gs_bin_sort(gs_ctx* ctx, const gs_projected* proj, const gs_camera* ca
                       const gs_camera* cams_dev, int n_views, gs_tile_lists* lists,
                       void* workspace, size_t ws_bytes, void* stream);
 
-/* Front-to-back compositing per pixel over its tile's list:
+/* Front-to-back alpha compositing per pixel over its tile's list (the
+ * renderer of Sec. II, run for every training view and every delivered
+ * view, Sec. IV-B):
  * alpha = min(0.99, opacity * exp(power)); skip if power > 0 or alpha <
  * 1/255; stop before compositing an entry that would take the
  * transmittance below 1e-4.  Views must share width and height.
@@ -344,7 +349,9 @@ gs_status gs_render_fwd_batched(gs_ctx* ctx, const gs_projected* proj,
                                 const gs_camera* cams_dev, int n_views, const gs_opts* opts,
                                 float* images, void* workspace, size_t ws_bytes, void* stream);
 
-/* Backward of gs_project + gs_render_fwd for dL/dimage (V, 3, H, W):
+/* Backward of gs_project + gs_render_fwd for dL/dimage (V, 3, H, W) (the
+ * differentiable renderer of Sec. II through which Eq. (1) trains the
+ * Gaussians and, with `upd`, the delta images of Eq. (12)):
  * transmittance is recovered by walking each pixel's list back from
  * n_contrib.  proj and lists must be the ones gs_bin_sort last processed
  * together (the backward reads the emission bases that call stores in the
