@@ -8,11 +8,16 @@ depth sort, render forward, L1 loss, render backward, projection backward,
 fused Adam over all 59 parameter planes.  Inputs are resident in HBM before
 timing starts.  ``value`` = training iterations/s on one GPU.
 
-The same JSON line also carries: the temporal frame-update step (apply the
-548x548 delta images, render, L1 + the temporal term of Eq. (7) with
-lambda_t = 1e-3, backward to the deltas, Adam on the deltas);
-per-stage device times from HIP events; the roofline of the dominant kernel;
-and the FP64 CPU oracle timed on a bounded sample of the same workload.
+The same JSON line also carries: the median, p10 and p90 of the per-step
+device time; the temporal frame-update step (apply the 548x548 delta images,
+render, L1 + the temporal term of Eq. (7) with lambda_t = 1e-3, backward to
+the deltas, Adam on the deltas); per-stage device times from HIP events; the
+roofline of the dominant kernel from the work its kernels execute (counted
+by the library's counting kernel instances in one untimed step); the
+2M-Gaussian scene (8 views at 1920x1080 forward + backward + Adam, then
+3840x2160 serving); the serving loop at 200-2,000 requests/s against the
+plain renderer; and the FP64 CPU oracle timed on one full iteration of the
+workload.
 
     python bench.py [--steps K] [--warmup W] [--no-cpu-baseline]
 """
@@ -31,20 +36,23 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
-# Published MI355X FP32 vector peak.  The library is compiled without packed
-# FP32 instructions, which caps the rate of executed FP32 arithmetic at half
-# of it (78.6 TFLOP/s); the fraction is still reported against the published
-# figure, and it counts the pairs the compositing definition evaluates, some
-# of which the kernels skip cheaply (whole quadrants below alpha 1/255).
+# Published MI355X FP32 vector peak: 256 CUs x 128 FP32 FMA lanes x 2 FLOP x
+# 2.4 GHz (an FMA counted as 2 FLOP).
 PEAK_ALU_TFLOPS = 157.3
+# The same rate in operations that each count once (an FMA, a compare or a
+# transcendental is one operation): 256 x 128 x 2.4 GHz = 78.6e12 lane
+# operations/s, the ceiling for the per-pair operation counts below.  The
+# render kernels' SQ counters show them retiring more than 16 FP32 lanes per
+# SIMD per clock without packed instructions, so half of it is not a bound.
+ISSUE_PEAK_TOPS = 256 * 128 * 2.4e9 / 1e12
 
-# Algorithmic FP32 operations per (pixel, entry) pair, FMA counted as 2 and
-# a transcendental as 1, on the definition's own formulas: forward = offsets,
-# quadratic form, exp, alpha cap and the two tests, T update, weight and three
-# colour FMAs; backward = that recompute plus the T recovery, colour, alpha
-# and power gradients and their moments.
-FLOP_PER_PAIR_FWD = 26
-FLOP_PER_PAIR_BWD = 68
+# Operations per executed (pixel, entry) pair of the compositing loops, each
+# counted once (an FMA or a transcendental is one operation): forward about
+# 20 VALU operations + 1 exp, backward about 45 VALU operations + 1 exp + 1
+# reciprocal.  Pairs are counted, not estimated: 64 x the slot evaluations
+# the kernels' counting instances report (a slot = one 8x8 quadrant of a
+# tile, one pixel per lane).
+OPS_PER_PAIR = {"render_fwd": 21, "render_bwd": 47}
 
 
 def log(msg):
@@ -54,8 +62,8 @@ def log(msg):
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-frame-step", action="store_true")
     # opacity-aware rectangles only, without the per-row spans (comparison)
@@ -67,11 +75,18 @@ def parse():
     ap.add_argument("--no-dssim-step", action="store_true")
     ap.add_argument("--no-sweep", action="store_true",
                     help="skip the pruning-sweep and sent-update codec legs")
-    ap.add_argument("--serve-rates", default="500,2000,4000",
+    ap.add_argument("--serve-rates", default="200,500,1000,2000",
                     help="aggregate Poisson arrival rates (requests/s)")
-    ap.add_argument("--serve-seconds", type=float, default=2.0)
-    ap.add_argument("--serve-warmup", type=float, default=0.5)
+    ap.add_argument("--serve-seconds", type=float, default=10.0)
+    ap.add_argument("--serve-warmup", type=float, default=1.0)
     ap.add_argument("--serve-frames", type=int, default=300)
+    ap.add_argument("--no-large", action="store_true",
+                    help="skip the 2M-Gaussian training and 3840x2160 serving legs")
+    ap.add_argument("--large-steps", type=int, default=20)
+    ap.add_argument("--large-serve-rates", default="50,200",
+                    help="3840x2160 request rates on the 2M scene (requests/s)")
+    ap.add_argument("--large-serve-seconds", type=float, default=5.0)
+    ap.add_argument("--large-serve-frames", type=int, default=30)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of known size (counter calibration)")
     return ap.parse_args()
@@ -292,11 +307,14 @@ class CodecStep:
 
 class CompactStep:
     """Keyframe compaction (Sec. III-B): cull the Gaussians whose opacity is
-    below 0.005 (kept-index list, count read back) and gather all 59
-    parameter planes of the kept ones into a dense set."""
+    below a threshold (kept-index list, count read back) and gather all 59
+    parameter planes of the kept ones into a dense set.  The synthetic
+    opacity logits are N(0, 1); the threshold sigmoid(z_0.1) = 0.2173 (z_0.1
+    the standard normal's 10 % quantile) culls 10 % of them in expectation,
+    so the leg measures a real compaction rather than a plain copy."""
 
     PLANES = 59
-    EPS = 0.005
+    EPS = 0.2173
 
     def __init__(self, scene):
         import torch
@@ -324,70 +342,94 @@ class CompactStep:
 
 
 def time_steps(ts, steps, warmup):
+    """Warm up, then time exactly ``steps`` steps between two device
+    synchronisations.  Returns (wall s, device s, stage times, per-step device
+    ms from HIP events recorded between the steps on the launch stream)."""
     torch = ts.torch
     for _ in range(warmup):
         ts.step()
     torch.cuda.synchronize()
     ts.ctx.set_timing(True)
     ts.ctx.collect_timing()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    e0.record()
+    ev[0].record()
     for k in range(steps):
         ts.step()
-    e1.record()
+        ev[k + 1].record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     stages = ts.ctx.collect_timing()
     ts.ctx.set_timing(False)
-    return wall, e0.elapsed_time(e1) / 1e3, stages
+    per_step = [ev[k].elapsed_time(ev[k + 1]) for k in range(steps)]
+    return wall, sum(per_step) / 1e3, stages, per_step
+
+
+def step_stats(per_step):
+    a = np.asarray(per_step, np.float64)
+    med = float(np.median(a))
+    return {"median_ms": round(med, 4), "p10_ms": round(float(np.percentile(a, 10)), 4),
+            "p90_ms": round(float(np.percentile(a, 90)), 4),
+            "iters_per_s_at_median": round(1e3 / med, 3) if med > 0 else None}
+
+
+def count_work(ts):
+    """Work tallies of one step run through the library's counting kernel
+    instances (same decisions as the timed kernels), outside any timed
+    region: entries staged and visited, slot evaluations and alpha-passing
+    pairs of the forward and the backward compositing."""
+    from paper_2512_20943_amd import gs
+    torch = ts.torch
+    torch.cuda.synchronize()
+    c = torch.zeros(gs.WORK_COUNTERS, dtype=torch.int64, device="cuda")
+    ts.ctx.set_work_counters(c)
+    try:
+        ts.step()
+    finally:
+        ts.ctx.set_work_counters(None)
+    torch.cuda.synchronize()
+    return dict(zip(gs.WORK_COUNTER_NAMES, (int(x) for x in c.tolist())))
 
 
 def definition_pairs(ts):
     """Sum over pixels of n_contrib for full (3-sigma) tile rectangles: the
-    (pixel, entry) pairs the compositing definition evaluates up to each
-    pixel's last contributor.  The training step's opacity-aware rectangles
-    leave out entries that every pixel skips, which shortens the lists and
-    lowers n_contrib without changing the work the definition prescribes, so
-    the count comes from one extra full-rectangle forward of the current
-    parameters, outside the timed region."""
+    (pixel, entry) pairs the compositing definition examines up to each
+    pixel's last contributor, from one extra full-rectangle forward of the
+    current parameters, outside the timed region.  Reported beside the
+    executed pairs; the roofline uses the executed ones."""
     if getattr(ts, "_def_pairs", None) is None:
         from paper_2512_20943_amd.raster import Rasterizer
-        out = Rasterizer(capacity=1 << 26).forward(ts.g if ts.frame_update is None else ts.frame,
-                                                   ts.cams)
+        out = Rasterizer(ctx=ts.ctx, capacity=1 << 26).forward(
+            ts.g if ts.frame_update is None else ts.frame, ts.cams)
         ts._def_pairs = float(out["n_contrib"].sum(dtype=ts.torch.float64).item())
         ts._def_instances = out["lists"].count
     return ts._def_pairs
 
 
 def algorithmic_work(stage, ts, steps):
-    """(amount per launch, unit, bound) for a stage of one step."""
+    """(amount per step, unit, bound) for an HBM-bound stage of one step."""
     n, V, K = ts.g.n, ts.cams.V, (ts.g.deg + 1) ** 2
     M = ts.last["lists"].count
     pbytes = 4 * (11 + 3 * K)
-    if stage == "render_fwd" or stage == "render_bwd":
-        pairs = definition_pairs(ts)
-        f = FLOP_PER_PAIR_FWD if stage == "render_fwd" else FLOP_PER_PAIR_BWD
-        return pairs * f, "flop", "alu", pairs
     if stage == "project":
-        return n * pbytes + V * n * 89.0, "byte", "hbm", None
+        return n * pbytes + V * n * 89.0, "byte", "hbm"
     if stage == "project_bwd":
-        return 2 * n * pbytes + V * n * (36.0 + 20 + 1), "byte", "hbm", None
+        return 2 * n * pbytes + V * n * (36.0 + 20 + 1), "byte", "hbm"
     if stage == "segment_sort":
         passes = math.ceil(math.ceil(math.log2(max(ts.cams.n_segments(), 2))) / 8)
-        return M * (16.0 * passes + 4.0), "byte", "hbm", None
+        return M * (16.0 * passes + 4.0), "byte", "hbm"
     if stage == "depth_sort":
         passes = math.ceil((32 + math.ceil(math.log2(max(V, 1)) if V > 1 else 0)) / 8)
-        return V * n * (24.0 * passes + 8 + 4 + 8 + 4), "byte", "hbm", None
+        return V * n * (24.0 * passes + 8 + 4 + 8 + 4), "byte", "hbm"
     if stage == "adam":
-        return 28.0 * ts.nparam, "byte", "hbm", None
+        return 28.0 * ts.nparam, "byte", "hbm"
     if stage == "l1":
-        return 12.0 * ts.target.numel(), "byte", "hbm", None
+        return 12.0 * ts.target.numel(), "byte", "hbm"
     if stage == "dssim":
-        return 44.0 * ts.target.numel(), "byte", "hbm", None
+        return 44.0 * ts.target.numel(), "byte", "hbm"
     if stage == "emit":
-        return V * n * 8.0 + M * 8.0, "byte", "hbm", None
+        return V * n * 8.0 + M * 8.0, "byte", "hbm"
     return None
 
 
@@ -420,105 +462,194 @@ def counted_traffic(stage):
     return None
 
 
-def roofline(stages, ts, steps):
+def alu_roofline(stage, ms, launches, steps, work, def_pairs=None, traffic=True):
+    """Roofline of a compositing kernel from the pairs it executes."""
+    pre = "fwd" if stage == "render_fwd" else "bwd"
+    per_launch_s = ms / launches / 1e3
+    launches_per_step = launches / steps
+    pairs = 64.0 * work[f"{pre}_slots"] / launches_per_step
+    ops = OPS_PER_PAIR[stage]
+    achieved = pairs * ops / per_launch_s / 1e12
+    rf = dict(bound="alu", achieved=round(achieved, 3), peak=PEAK_ALU_TFLOPS, unit="TFLOP/s",
+              frac=round(achieved / PEAK_ALU_TFLOPS, 4),
+              traffic=counted_traffic(stage) if traffic else None, kernel=stage,
+              launch_ms=round(per_launch_s * 1e3, 4), pairs_executed=pairs,
+              pairs_alpha_pass=work[f"{pre}_used"] / launches_per_step,
+              entries_visited=work[f"{pre}_visits"] / launches_per_step,
+              ops_per_pair=ops, issue_peak_tops=round(ISSUE_PEAK_TOPS, 2),
+              frac_issue=round(achieved / ISSUE_PEAK_TOPS, 4),
+              pairs_per_s=round(pairs / per_launch_s, 1),
+              pair_ceiling_per_s=round(ISSUE_PEAK_TOPS * 1e12 / ops, 1))
+    if def_pairs is not None:
+        rf["pairs_definition"] = def_pairs / launches_per_step
+    return rf
+
+
+def hbm_roofline(stage, ms, launches, ts, steps):
+    w = algorithmic_work(stage, ts, steps)
+    if w is None:
+        return None
+    amount, _, bound = w
+    per_launch_s = ms / launches / 1e3
+    amount_per_launch = amount * steps / launches
+    achieved = amount_per_launch / per_launch_s / 1e9
+    return dict(bound=bound, achieved=round(achieved, 2), peak=PEAK_HBM_GBS, unit="GB/s",
+                frac=round(achieved / PEAK_HBM_GBS, 4), traffic=counted_traffic(stage),
+                kernel=stage, launch_ms=round(per_launch_s * 1e3, 4),
+                bytes_per_launch=amount_per_launch)
+
+
+def roofline(stages, ts, steps, work):
+    """Roofline of the dominant kernel of the step, plus every stage's own
+    bound (per-stage "frac") and the step's sum of bound times."""
     busy = {k: v for k, v in stages.items() if v[1] > 0}
     dom = max(busy, key=lambda k: busy[k][0])
+    per_stage = {}
+    bound_ms = 0.0
+    for k, (ms, launches) in busy.items():
+        if k in OPS_PER_PAIR:
+            rf = alu_roofline(k, ms, launches, steps, work, traffic=False)
+        else:
+            rf = hbm_roofline(k, ms, launches, ts, steps)
+        if rf is None:
+            continue
+        per_stage[k] = {"bound": rf["bound"], "frac": rf.get("frac_issue", rf["frac"]),
+                        "ms_per_step": round(ms / steps, 4)}
+        bound_ms += ms / steps * per_stage[k]["frac"]
     ms, launches = busy[dom]
-    per_launch_s = ms / launches / 1e3
-    w = algorithmic_work(dom, ts, steps)
-    if w is None:
-        return dom, None
-    amount, unit, bound, pairs = w
-    launches_per_step = launches / steps
-    amount_per_launch = amount / launches_per_step
-    if unit == "byte":
-        achieved = amount_per_launch / per_launch_s / 1e9
-        rf = dict(bound=bound, achieved=round(achieved, 2), peak=PEAK_HBM_GBS, unit="GB/s",
-                  frac=round(achieved / PEAK_HBM_GBS, 4), traffic=counted_traffic(dom))
+    if dom in OPS_PER_PAIR:
+        rf = alu_roofline(dom, ms, launches, steps, work, definition_pairs(ts))
     else:
-        achieved = amount_per_launch / per_launch_s / 1e12
-        rf = dict(bound=bound, achieved=round(achieved, 3), peak=PEAK_ALU_TFLOPS, unit="TFLOP/s",
-                  frac=round(achieved / PEAK_ALU_TFLOPS, 4), traffic=counted_traffic(dom))
-    rf["kernel"] = dom
-    rf["launch_ms"] = round(per_launch_s * 1e3, 4)
-    if pairs is not None:
-        rf["pairs_per_launch"] = pairs / launches_per_step
-    return dom, rf
+        rf = hbm_roofline(dom, ms, launches, ts, steps)
+    step_ms = sum(v[0] for v in busy.values()) / steps
+    summary = {"stages": per_stage,
+               "bound_ms_per_step": round(bound_ms, 4),
+               "device_ms_per_step": round(step_ms, 4),
+               "frac": round(bound_ms / step_ms, 4) if step_ms > 0 else None}
+    return dom, rf, summary
 
 
 def cpu_baseline(scene, cams, target_scene):
-    """FP64 oracle (as it stands) on one of the 20 views of the frame step:
-    projection, bin + sort, render, L1, render backward, projection backward;
-    plus Adam over all parameters once.  Scaled to a 20-view iteration."""
-    import numpy as np
-
+    """The FP64 oracle (as it stands) on one full iteration of the frame step:
+    all views projected, binned and sorted, rendered, the L1 term, render
+    backward, projection backward, and Adam over every parameter.  The
+    target images (the perturbed scene's renders) are made first and not
+    counted."""
     import oracle
     oracle.build(force=False)
-    cam1 = {k: v[:1] for k, v in cams.items()}
     t0 = time.perf_counter()
-    _, _, timg = oracle.forward(target_scene, cam1)
+    _, _, timg = oracle.forward(target_scene, cams)
     t_target = time.perf_counter() - t0
     t0 = time.perf_counter()
-    P, L, img = oracle.forward(scene, cam1)
+    P, L, img = oracle.forward(scene, cams)
     _, gI = oracle.l1(img["image"], timg["image"])
-    _, grads = oracle.backward(scene, cam1, P, L, gI)
-    t_view = time.perf_counter() - t0
-    t0 = time.perf_counter()
+    _, grads = oracle.backward(scene, cams, P, L, gI)
     flat = np.concatenate([scene[k].ravel() for k in ("mean", "log_scale", "quat", "opacity",
                                                         "sh")]).astype(np.float64)
     gflat = np.concatenate([grads[k].ravel() for k in ("mean", "log_scale", "quat", "opacity",
                                                          "sh")])
     oracle.adam(flat, gflat, np.zeros_like(flat), np.zeros_like(flat), 1)
-    t_adam = time.perf_counter() - t0
+    t_iter = time.perf_counter() - t0
     V = cams["R"].shape[0]
-    t_iter = V * t_view + t_adam
     cores = int(os.environ.get("OMP_NUM_THREADS", "0")) or len(os.sched_getaffinity(0))
     return dict(value=round(1.0 / t_iter, 6), unit="iters/s", cores=cores, kind="oracle",
-                sample=(f"1 of {V} views of the 300k-Gaussian frame step (project, bin+sort, "
-                        f"render, L1, render bwd, project bwd: {t_view:.2f} s) x {V} + Adam over "
-                        f"all parameters ({t_adam:.2f} s); target render {t_target:.2f} s "
-                        f"not counted"))
+                sample=(f"one full iteration of the {scene['n']}-Gaussian frame step, all {V} "
+                        f"views (project, bin+sort, render, L1, render bwd, project bwd, "
+                        f"Adam): {t_iter:.2f} s; the target renders ({t_target:.2f} s) are "
+                        f"made first and not counted"))
 
 
-def serving(args, scene):
-    """Served views/s and p50/p99 latency of the continuous-batching server
-    vs the plain one-request-per-launch renderer on the same Poisson trace:
-    300 resident frames of the 300k-Gaussian sequence, 64 viewers, random
-    viewpoints on a sphere of radius 4-6, resolutions 640x480 / 1280x720 /
-    1920x1080."""
+def serve_rates(seq, rates, seconds, warmup, resolutions, seed_base=0, budget=32 << 30,
+                max_batch=32):
+    """Served views/s and p50/p99 latency of the continuous-batching server vs
+    the plain one-request-per-launch renderer on the same open-loop Poisson
+    trace per rate: 64 viewers, random viewpoints on a sphere of radius 4-6,
+    resolution uniform over ``resolutions``; latencies of the requests that
+    arrive after ``warmup`` seconds."""
     import copy
 
     import torch
 
     from paper_2512_20943_amd import serve
+    server = serve.Server(seq, budget_bytes=budget, max_batch=max_batch)
+    plain = serve.PlainRenderer(seq)
+    # warm both paths (allocations, first launches)
+    wt = serve.make_trace(16, 1e6, None, 64, seq.n_frames, 99 + seed_base,
+                          resolutions=resolutions)
+    server.run(copy.deepcopy(wt))
+    serve.run_plain(plain, copy.deepcopy(wt[:4]))
+    out = {"frames": seq.n_frames, "viewers": 64, "budget_gib": budget / 2**30,
+           "resident_gib": round(seq.device_bytes() / 2**30, 3), "max_batch": max_batch,
+           "resolutions": [f"{w}x{h}" for (w, h) in resolutions],
+           "seconds": seconds, "warmup_s": warmup, "rates": {}}
+    for rate in rates:
+        trace = serve.make_trace(None, rate, warmup + seconds, 64, seq.n_frames,
+                                 int(rate) + seed_base, resolutions=resolutions)
+        tb = copy.deepcopy(trace)
+        server.batches.clear()
+        server.run(tb)
+        sb = serve.summarize(tb, warmup)
+        sb["mean_batch"] = round(float(np.mean(server.batches)), 2)
+        tp = copy.deepcopy(trace)
+        serve.run_plain(plain, tp)
+        sp = serve.summarize(tp, warmup)
+        out["rates"][str(int(rate))] = {"requests": len(trace), "batched": sb, "plain": sp}
+        log(f"serving {out['resolutions']} @ {rate:.0f} req/s: batched {sb}  plain {sp}")
+        torch.cuda.synchronize()
+    del server, plain
+    return out
+
+
+def serving(args, scene):
+    """The serving loop on 300 resident frames of the 300k-Gaussian sequence
+    at 640x480 / 1280x720 / 1920x1080."""
+    from paper_2512_20943_amd import serve
     t0 = time.perf_counter()
     seq = serve.ResidentSequence(scene, args.serve_frames, seed=0)
     log(f"resident sequence: {args.serve_frames} frames, {seq.device_bytes() / 2**30:.2f} GiB "
         f"({time.perf_counter() - t0:.1f} s to generate)")
-    budget = 32 << 30
-    server = serve.Server(seq, budget_bytes=budget, max_batch=32)
-    plain = serve.PlainRenderer(seq)
-    # warm both paths (allocations, first launches)
-    wt = serve.make_trace(64, 1e6, None, 64, seq.n_frames, 99)
-    server.run(copy.deepcopy(wt))
-    serve.run_plain(plain, copy.deepcopy(wt[:8]))
-    out = {"frames": seq.n_frames, "viewers": 64, "budget_gib": budget / 2**30,
-           "resident_gib": round(seq.device_bytes() / 2**30, 3), "max_batch": 32,
-           "seconds": args.serve_seconds, "warmup_s": args.serve_warmup, "rates": {}}
-    for rate in [float(x) for x in args.serve_rates.split(",")]:
-        trace = serve.make_trace(None, rate, args.serve_warmup + args.serve_seconds, 64,
-                                 seq.n_frames, int(rate))
-        tb = copy.deepcopy(trace)
-        server.batches.clear()
-        server.run(tb)
-        sb = serve.summarize(tb, args.serve_warmup)
-        sb["mean_batch"] = round(float(np.mean(server.batches)), 2)
-        tp = copy.deepcopy(trace)
-        serve.run_plain(plain, tp)
-        sp = serve.summarize(tp, args.serve_warmup)
-        out["rates"][str(int(rate))] = {"requests": len(trace), "batched": sb, "plain": sp}
-        log(f"serving @ {rate:.0f} req/s: batched {sb}  plain {sp}")
-        torch.cuda.synchronize()
+    rates = [float(x) for x in args.serve_rates.split(",")]
+    return serve_rates(seq, rates, args.serve_seconds, args.serve_warmup, serve.RESOLUTIONS)
+
+
+def large_scene(args):
+    """The 2M-Gaussian scene: an 8-view 1920x1080 training iteration
+    (project, bin + sort, render fwd with L1, render bwd, project bwd, Adam),
+    then the serving loop with every request at 3840x2160 on a resident
+    sequence of that anchor."""
+    import torch
+
+    from paper_2512_20943_amd import scenes, serve
+    t0 = time.perf_counter()
+    scene, cams, target_scene = scenes.workload_large_2m(0)
+    log(f"2M-Gaussian workload generated in {time.perf_counter() - t0:.1f} s")
+    ts = TrainStep(scene, cams, target_scene)
+    steps = args.large_steps
+    wall, _, stages, per_step = time_steps(ts, steps, 3)
+    work = count_work(ts)
+    _, rf, summary = roofline(stages, ts, steps, work)
+    out = {"workload": "2,000,000 Gaussians SH3 (means U[-6,6]^3, log-scales N(-4.5,0.7)), "
+                       "8 views 1920x1080, L1 + Adam",
+           "iters_per_s": round(steps / wall, 4), "ms_per_step": round(wall / steps * 1e3, 3),
+           "steps": steps, "warmup": 3, "step_device_ms": step_stats(per_step),
+           "instances_per_step": ts.last["lists"].count,
+           "stage_ms_per_step": {k: round(v[0] / steps, 4) for k, v in stages.items()
+                                 if v[1] > 0},
+           "roofline": rf, "step_roofline": summary, "work_counts": work}
+    log(f"2M x 8 views 1080p step: {wall / steps * 1e3:.2f} ms")
+    del ts
+    torch.cuda.empty_cache()
+    if args.no_serve:
+        return out
+    t0 = time.perf_counter()
+    seq = serve.ResidentSequence(scene, args.large_serve_frames, seed=7)
+    log(f"resident 2M sequence: {args.large_serve_frames} frames, "
+        f"{seq.device_bytes() / 2**30:.2f} GiB ({time.perf_counter() - t0:.1f} s to generate)")
+    rates = [float(x) for x in args.large_serve_rates.split(",")]
+    out["serving_4k"] = serve_rates(seq, rates, args.large_serve_seconds, 1.0,
+                                    ((3840, 2160),), seed_base=7000)
+    del seq
+    torch.cuda.empty_cache()
     return out
 
 
@@ -540,12 +671,14 @@ def main():
     scene, cams, target_scene = scenes.workload_frame_300k(0, n=args.gaussians, n_views=args.views)
     ts = TrainStep(scene, cams, target_scene, tile_spans=not args.no_tile_spans)
     log(f"instances per step: {ts.r.forward(ts.g, ts.cams)['lists'].count}")
-    wall, dev_s, stages = time_steps(ts, args.steps, args.warmup)
+    wall, dev_s, stages, per_step = time_steps(ts, args.steps, args.warmup)
     ms_per_step = wall / args.steps * 1e3
     value = args.steps / wall
     log(f"train step: {ms_per_step:.2f} ms ({value:.2f} it/s)")
-    dom, rf = roofline(stages, ts, args.steps)
+    work = count_work(ts)
+    dom, rf, summary = roofline(stages, ts, args.steps, work)
     stage_ms = {k: round(v[0] / args.steps, 4) for k, v in stages.items() if v[1] > 0}
+    fwd_ms, fwd_n = stages["render_fwd"]
     result = {
         "metric": "fwd+bwd train iters/s", "value": round(value, 4), "unit": "iters/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -557,13 +690,17 @@ def main():
                    "height": 1014, "instances_per_step": ts.last["lists"].count,
                    "instances_full_rectangles": getattr(ts, "_def_instances", None),
                    "tile_spans": not args.no_tile_spans},
+        "step_device_ms": step_stats(per_step),
         "stage_ms_per_step": stage_ms,
         "roofline": rf,
+        "roofline_render_fwd": alu_roofline("render_fwd", fwd_ms, fwd_n, args.steps, work),
+        "step_roofline": summary,
+        "work_counts": work,
     }
     if not args.no_autograd_step:
         ag = AutogradTrainStep(ts)
         k4 = max(args.steps // 2, 3)
-        wall4, _, st4 = time_steps(ag, k4, 2)
+        wall4, _, st4, _ = time_steps(ag, k4, 2)
         result["autograd_step"] = {
             "iters_per_s": round(k4 / wall4, 4), "ms_per_step": round(wall4 / k4 * 1e3, 3),
             "path": "GSRender and GSL1Loss torch.autograd.Functions, loss.backward(), Adam",
@@ -579,11 +716,12 @@ def main():
         mask = scenes.prune_mask(d, n, 0.3)
         fs = TrainStep(scene, cams, target_scene, frame_update=(d, mask, gw, gh),
                        tile_spans=not args.no_tile_spans)
-        wall2, _, st2 = time_steps(fs, max(args.steps // 2, 3), 2)
+        wall2, _, st2, ps2 = time_steps(fs, max(args.steps // 2, 3), 2)
         k2 = max(args.steps // 2, 3)
         result["frame_update_step"] = {
             "iters_per_s": round(k2 / wall2, 4), "ms_per_step": round(wall2 / k2 * 1e3, 3),
             "grid": [gh, gw], "prune_level": 0.3, "loss": "L1 + 1e-3 L_temp (Eq. (7))",
+            "step_device_ms": step_stats(ps2),
             "stage_ms_per_step": {k: round(v[0] / k2, 4) for k, v in st2.items() if v[1] > 0}}
         log(f"frame-update step: {wall2 / k2 * 1e3:.2f} ms")
         del fs
@@ -591,7 +729,7 @@ def main():
         ds = TrainStep(scene, cams, target_scene, loss="l1_dssim",
                        tile_spans=not args.no_tile_spans)
         k3 = max(args.steps // 2, 3)
-        wall3, _, st3 = time_steps(ds, k3, 2)
+        wall3, _, st3, _ = time_steps(ds, k3, 2)
         ms3, n3 = st3.get("dssim", (0.0, 0))
         launch_s = ms3 / max(n3, 1) / 1e3
         bytes_per_launch = algorithmic_work("dssim", ds, k3)[0] * k3 / max(n3, 1)
@@ -606,7 +744,7 @@ def main():
     if not args.no_sweep:
         sw = SweepStep(scene, target_scene, 4)
         k5 = 3
-        wall5, _, st5 = time_steps(sw, k5, 1)
+        wall5, _, st5, _ = time_steps(sw, k5, 1)
         last = sw.last
         result["pruning_sweep"] = {
             "sweeps_per_s": round(k5 / wall5, 4), "ms_per_sweep": round(wall5 / k5 * 1e3, 3),
@@ -617,7 +755,7 @@ def main():
         del sw
         cs = CodecStep(scene)
         k6 = 50
-        wall6, dev6, st6 = time_steps(cs, k6, 3)
+        wall6, dev6, st6, _ = time_steps(cs, k6, 3)
         nbytes = CodecStep.BYTES_PER_TEXEL * cs.n
         result["sent_update_codec"] = {
             "frames_per_s": round(k6 / wall6, 2), "device_ms_per_frame": round(dev6 / k6 * 1e3, 4),
@@ -629,7 +767,7 @@ def main():
         del cs
         kc = CompactStep(scene)
         k7 = 50
-        wall7, dev7, st7 = time_steps(kc, k7, 3)
+        wall7, dev7, st7, _ = time_steps(kc, k7, 3)
         # algorithmic bytes: the opacity plane read once per pass (count,
         # write), 59 planes gathered (read + write) per kept Gaussian, 4-B
         # indices written and read
@@ -638,14 +776,18 @@ def main():
             "per_s": round(k7 / wall7, 2), "ms_wall": round(wall7 / k7 * 1e3, 4),
             "device_ms": round(dev7 / k7 * 1e3, 4), "gaussians": kc.n, "kept": int(kc.kept),
             "min_opacity": CompactStep.EPS, "planes": CompactStep.PLANES,
+            "culled_fraction": round(1.0 - kc.kept / kc.n, 4),
             "algorithmic_bytes": nb7, "device_GBps": round(nb7 / (dev7 / k7) / 1e9, 1),
             "stage_ms": {k: round(v[0] / k7, 4) for k, v in st7.items() if v[1] > 0}}
         log(f"keyframe compaction: {dev7 / k7 * 1e3:.3f} ms device time")
         del kc
     if not args.no_serve:
         result["serving"] = serving(args, scene)
+        torch.cuda.empty_cache()
+    if not args.no_large:
+        result["large_scene"] = large_scene(args)
     if not args.no_cpu_baseline:
-        log("timing the FP64 oracle on one view")
+        log("timing the FP64 oracle on one full iteration")
         result["cpu_baseline"] = cpu_baseline(scene, cams, target_scene)
     print(json.dumps(result))
 

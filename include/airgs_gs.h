@@ -242,6 +242,25 @@ gs_status gs_set_timing(gs_ctx* ctx, int enable);
 gs_status gs_collect_timing(gs_ctx* ctx, double* ms, int64_t* launches);
 const char* gs_stage_name(int stage);
 
+/* Work counting for roofline accounting.  With `counters` non-NULL (a device
+ * array of GS_WORK_COUNTERS uint64 values that the caller zeroes and owns),
+ * the compositing calls gs_render_fwd, gs_render_fwd_l1 and gs_render_bwd
+ * on this context launch counting instances of their kernels: the same
+ * arithmetic and the same per-entry decisions, plus per-tile tallies added
+ * to the array at each tile's end.  A wave evaluates one "slot" (an 8x8
+ * pixel quadrant of its 16x16 tile, one pixel per lane) per (entry, slot)
+ * pair it does not skip, so 64 x slots is the number of (pixel, entry)
+ * pairs it executes.  Counters:
+ *   0 fwd entries staged, 1 fwd entries visited (some slot evaluated),
+ *   2 fwd slot evaluations, 3 fwd pairs with T > 0 and alpha >= 1/255,
+ *   4 bwd entries staged, 5 bwd entries visited, 6 bwd slot evaluations,
+ *   7 bwd pairs inside the pixel's list prefix with alpha >= 1/255.
+ * The counting kernels are slower (one 64-bit atomic per counter per tile)
+ * and are meant for runs outside any timed region.  NULL switches counting
+ * off.  Other calls ignore the setting. */
+#define GS_WORK_COUNTERS 8
+gs_status gs_set_work_counters(gs_ctx* ctx, uint64_t* counters);
+
 /* ---- hot path ----------------------------------------------------------- */
 
 /* Apply a decoded frame update to anchor Gaussians (Eq. (2)/(5)/(12): frame

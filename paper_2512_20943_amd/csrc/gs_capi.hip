@@ -12,6 +12,7 @@
 
 namespace gs {
 thread_local StageTimer* g_timer = nullptr;
+thread_local unsigned long long* g_work = nullptr;
 }
 
 namespace {
@@ -95,17 +96,24 @@ struct gs_ctx {
   bool timing;
   EventTimer timer;
   double* scratch_dev;  // device address of `scratch` on this context's device
+  unsigned long long* work;  // GS_WORK_COUNTERS device words, or null
   char err[512];
 };
 
 namespace {
-// Makes the context's timer active for the duration of one C ABI call.
+// Makes the context's timer and work counters active for the duration of
+// one C ABI call.
 struct TimerGuard {
   gs::StageTimer* prev;
-  explicit TimerGuard(gs_ctx* c) : prev(gs::g_timer) {
+  unsigned long long* prev_work;
+  explicit TimerGuard(gs_ctx* c) : prev(gs::g_timer), prev_work(gs::g_work) {
     gs::g_timer = (c && c->timing) ? &c->timer : nullptr;
+    gs::g_work = c ? c->work : nullptr;
   }
-  ~TimerGuard() { gs::g_timer = prev; }
+  ~TimerGuard() {
+    gs::g_timer = prev;
+    gs::g_work = prev_work;
+  }
 };
 }  // namespace
 
@@ -223,6 +231,7 @@ gs_status gs_create(gs_ctx** out, int device) {
   if (!c) return fail(nullptr, GS_ERR_OOM, "context allocation failed");
   c->device = device;
   c->timing = false;
+  c->work = nullptr;
   c->err[0] = 0;
   int prev = 0;
   hipGetDevice(&prev);
@@ -257,6 +266,14 @@ const char* gs_last_error(const gs_ctx* c) { return c ? c->err : g_err; }
 gs_status gs_set_timing(gs_ctx* c, int enable) {
   if (!c) return fail(nullptr, GS_ERR_INVALID_ARG, "ctx is NULL");
   c->timing = enable != 0;
+  return GS_OK;
+}
+
+gs_status gs_set_work_counters(gs_ctx* c, uint64_t* counters) {
+  if (!c) return fail(nullptr, GS_ERR_INVALID_ARG, "ctx is NULL");
+  if (reinterpret_cast<uintptr_t>(counters) % 8 != 0)
+    return fail(c, GS_ERR_INVALID_ARG, "work counters must be 8-byte aligned");
+  c->work = reinterpret_cast<unsigned long long*>(counters);
   return GS_OK;
 }
 

@@ -54,6 +54,15 @@ struct StageTimer {
 // Active timer of the C ABI call running on this host thread (or null).
 extern thread_local StageTimer* g_timer;
 
+// Work counters of the counting render instances (GS_WORK_COUNTERS device
+// words, or null: the plain kernels run).
+enum WorkCounter {
+  kWkFwdStaged = 0, kWkFwdVisits, kWkFwdSlots, kWkFwdUsed, kWkBwdStaged, kWkBwdVisits,
+  kWkBwdSlots, kWkBwdUsed, kWorkCount
+};
+static_assert(kWorkCount == GS_WORK_COUNTERS, "work counter table out of sync with the header");
+extern thread_local unsigned long long* g_work;
+
 struct StageScope {
   int stage;
   hipStream_t stream;

@@ -205,8 +205,10 @@ struct L1Out {
 // final_T / n_contrib at its (H, W) planes or are null.
 // With USAGE, the number of the tile's pixels that composite each entry is
 // added to usage[Gaussian id].  With L1, dL/dimage = sign(image - target) /
-// count is written and the tile's sum of |image - target| stored.
-template <bool USAGE, bool L1 = false>
+// count is written and the tile's sum of |image - target| stored.  With
+// COUNT, the tile's work tallies (entries staged and visited, slot
+// evaluations, pairs with T > 0 and alpha >= 1/255) are added to cnt[0..3].
+template <bool USAGE, bool L1 = false, bool COUNT = false>
 __device__ __forceinline__ void render_tile_fwd(FwdShared& sh, UsageShared* us,
                                                 const float4* __restrict__ sv,
                                                 const uint32_t* __restrict__ vals, uint2 rg,
@@ -215,8 +217,11 @@ __device__ __forceinline__ void render_tile_fwd(FwdShared& sh, UsageShared* us,
                                                 float* __restrict__ final_T,
                                                 int32_t* __restrict__ n_contrib,
                                                 uint32_t* __restrict__ usage,
-                                                const L1Out* l1 = nullptr) {
+                                                const L1Out* l1 = nullptr,
+                                                unsigned long long* cnt = nullptr) {
   const int lane = threadIdx.x;
+  uint32_t wk_staged = 0, wk_visits = 0, wk_slots = 0;
+  unsigned long long wk_used = 0;
   // slot w's pixel is (x0 + 8 (w & 1), y0 + 8 (w >> 1))
   const int x0 = tx * kTile + (lane & 7), y0 = ty * kTile + (lane >> 3);
   const float fx0 = (float)x0, fy0 = (float)y0;
@@ -256,9 +261,11 @@ __device__ __forceinline__ void render_tile_fwd(FwdShared& sh, UsageShared* us,
     }
     __syncthreads();
     const int nb = (int)((rg.y - b0) < (uint32_t)kFwdBatch ? (rg.y - b0) : (uint32_t)kFwdBatch);
+    if constexpr (COUNT) wk_staged += (uint32_t)nb;
     for (int k = 0; k < nb; ++k) {
       const uint32_t m = __builtin_amdgcn_readfirstlane(sh.m[k]) & live;
       if (m == 0) continue;
+      if constexpr (COUNT) ++wk_visits;
       uint32_t used = 0;
       const float4 a = sh.a[k];
       const float4 b = sh.b[k];
@@ -287,6 +294,10 @@ __device__ __forceinline__ void render_tile_fwd(FwdShared& sh, UsageShared* us,
           st.T = comp ? Tn : (stop ? -Tk : Tk);
           st.last = comp ? posv : st.last;
           if constexpr (USAGE) used += (uint32_t)__popcll(__builtin_amdgcn_ballot_w64(comp));
+          if constexpr (COUNT) {
+            ++wk_slots;
+            wk_used += (unsigned long long)__popcll(__builtin_amdgcn_ballot_w64(use));
+          }
           if (__builtin_amdgcn_ballot_w64(stop) != 0) {  // once per pixel
             if (__builtin_amdgcn_ballot_w64(st.T > 0.f) == 0) live &= ~(1u << w);
           }
@@ -345,41 +356,52 @@ __device__ __forceinline__ void render_tile_fwd(FwdShared& sh, UsageShared* us,
     for (int off = 32; off >= 1; off >>= 1) l1sum += __shfl_xor(l1sum, off, 64);
     if (lane == 0) *l1->partial = l1sum;
   }
+  if constexpr (COUNT) {
+    if (lane == 0) {
+      atomicAdd(cnt + kWkFwdStaged, (unsigned long long)wk_staged);
+      atomicAdd(cnt + kWkFwdVisits, (unsigned long long)wk_visits);
+      atomicAdd(cnt + kWkFwdSlots, (unsigned long long)wk_slots);
+      atomicAdd(cnt + kWkFwdUsed, wk_used);
+    }
+  }
 }
 
+template <bool COUNT>
 __global__ __launch_bounds__(64) void k_render_fwd(
     const float4* __restrict__ splat, int ld, const uint32_t* __restrict__ vals,
     const uint2* __restrict__ ranges, int W, int H, int TX, int tiles_per_view, float bg0,
     float bg1, float bg2, float* __restrict__ image, float* __restrict__ final_T,
-    int32_t* __restrict__ n_contrib) {
+    int32_t* __restrict__ n_contrib, unsigned long long* __restrict__ cnt) {
   __shared__ FwdShared sh;
   const int seg = blockIdx.x;
   const int v = seg / tiles_per_view, tile = seg - v * tiles_per_view;
   const int ty = tile / TX, tx = tile - ty * TX;
   const size_t pix = (size_t)W * H;
-  render_tile_fwd<false>(sh, nullptr, splat + kSplatF4 * (size_t)v * ld, vals, ranges[seg], tx,
-                         ty, W, H, bg0, bg1, bg2, image + 3 * pix * v, final_T + pix * v,
-                         n_contrib + pix * v, nullptr);
+  render_tile_fwd<false, false, COUNT>(sh, nullptr, splat + kSplatF4 * (size_t)v * ld, vals,
+                                       ranges[seg], tx, ty, W, H, bg0, bg1, bg2,
+                                       image + 3 * pix * v, final_T + pix * v,
+                                       n_contrib + pix * v, nullptr, nullptr, cnt);
 }
 
 // Forward with the L1 term fused: per tile, the pixels' dL/dimage and the sum
 // of |image - target| (added up by k_l1_tile_sum).
+template <bool COUNT>
 __global__ __launch_bounds__(64) void k_render_fwd_l1(
     const float4* __restrict__ splat, int ld, const uint32_t* __restrict__ vals,
     const uint2* __restrict__ ranges, int W, int H, int TX, int tiles_per_view, float bg0,
     float bg1, float bg2, float* __restrict__ image, float* __restrict__ final_T,
     int32_t* __restrict__ n_contrib, const float* __restrict__ target, float* __restrict__ grad,
-    float inv_count, double* __restrict__ partial) {
+    float inv_count, double* __restrict__ partial, unsigned long long* __restrict__ cnt) {
   __shared__ FwdShared sh;
   const int seg = blockIdx.x;
   const int v = seg / tiles_per_view, tile = seg - v * tiles_per_view;
   const int ty = tile / TX, tx = tile - ty * TX;
   const size_t pix = (size_t)W * H;
   const L1Out o{target + 3 * pix * v, grad + 3 * pix * v, inv_count, partial + seg};
-  render_tile_fwd<false, true>(sh, nullptr, splat + kSplatF4 * (size_t)v * ld, vals, ranges[seg],
-                               tx, ty, W, H, bg0, bg1, bg2,
-                               image ? image + 3 * pix * v : nullptr, final_T + pix * v,
-                               n_contrib + pix * v, nullptr, &o);
+  render_tile_fwd<false, true, COUNT>(sh, nullptr, splat + kSplatF4 * (size_t)v * ld, vals,
+                                      ranges[seg], tx, ty, W, H, bg0, bg1, bg2,
+                                      image ? image + 3 * pix * v : nullptr, final_T + pix * v,
+                                      n_contrib + pix * v, nullptr, &o, cnt);
 }
 
 // loss += (sum of the per-tile partials) / count, in one block.
@@ -509,11 +531,16 @@ __device__ __forceinline__ int wave_max(int x) {
   return x;
 }
 
+// With COUNT, the tile's work tallies (entries staged and visited, slot
+// evaluations, pairs inside the pixel's prefix with alpha >= 1/255) are
+// added to cnt[4..7].
+template <bool COUNT>
 __global__ __launch_bounds__(64) void k_render_bwd(
     const float4* __restrict__ splat, int ld, const uint32_t* __restrict__ vals,
     const uint2* __restrict__ ranges, int W, int H, int TX, int tiles_per_view, float bg0,
     float bg1, float bg2, const float* __restrict__ final_T, const int32_t* __restrict__ n_contrib,
-    const float* __restrict__ dL_dimage, float* __restrict__ rows) {
+    const float* __restrict__ dL_dimage, float* __restrict__ rows,
+    unsigned long long* __restrict__ cnt) {
   __shared__ BwdShared sh;
   const int seg = blockIdx.x;
   const int v = seg / tiles_per_view, tile = seg - v * tiles_per_view;
@@ -555,9 +582,12 @@ __global__ __launch_bounds__(64) void k_render_bwd(
   const int acc_lane = 4 * (u0 ? 8 : 4 * (int)u1 + 2 * (int)u2 + (int)u3) + (lane >> 4);
   const bool acc_writer = !u0 || (lane & 15) == 1;
   float* acc = reinterpret_cast<float*>(sh.acc4);
+  uint32_t wk_staged = 0, wk_visits = 0, wk_slots = 0;
+  unsigned long long wk_used = 0;
 
   for (int hi = jmax; hi > 0; hi -= kBwdBatch) {
     const int lo = hi > kBwdBatch ? hi - kBwdBatch : 0;
+    if constexpr (COUNT) wk_staged += (uint32_t)(hi - lo);
     __syncthreads();
     for (int k = lane; k < kBwdBatch; k += 64) {
       if (lo + k < hi) {
@@ -583,6 +613,7 @@ __global__ __launch_bounds__(64) void k_render_bwd(
       for (int w = 0; w < 4; ++w)
         if (j >= wmax[w]) m &= ~(1u << w);
       if (m == 0) continue;
+      if constexpr (COUNT) ++wk_visits;
       const float4 a = sh.a[k];
       const float4 b = sh.b[k];
       const float4 c = sh.c[k];
@@ -621,6 +652,10 @@ __global__ __launch_bounds__(64) void k_render_bwd(
           S[w] = fmaf(au, gcb, S[w]);
           T[w] = Tk;
           contrib = contrib || use;
+          if constexpr (COUNT) {
+            ++wk_slots;
+            wk_used += (unsigned long long)__popcll(__builtin_amdgcn_ballot_w64(use));
+          }
         }
       }
       if (__builtin_amdgcn_ballot_w64(contrib) == 0) continue;
@@ -656,12 +691,20 @@ __global__ __launch_bounds__(64) void k_render_bwd(
     }
   }
   // entries behind every pixel's last contributor carry zero gradient
-  const int cnt = (int)(rg.y - rg.x);
-  for (int j = jmax + lane; j < cnt; j += 64) {
+  const int n_entries = (int)(rg.y - rg.x);
+  for (int j = jmax + lane; j < n_entries; j += 64) {
     const uint32_t g = vals[rg.x + (uint32_t)j];
     float* dst = rows + (size_t)instance_row(sv[kSplatF4 * (size_t)g + 3], tx, ty) * kRowFloats;
 #pragma unroll
     for (int cc = 0; cc < 9; ++cc) dst[cc] = 0.f;
+  }
+  if constexpr (COUNT) {
+    if (lane == 0) {
+      atomicAdd(cnt + kWkBwdStaged, (unsigned long long)wk_staged);
+      atomicAdd(cnt + kWkBwdVisits, (unsigned long long)wk_visits);
+      atomicAdd(cnt + kWkBwdSlots, (unsigned long long)wk_slots);
+      atomicAdd(cnt + kWkBwdUsed, wk_used);
+    }
   }
 }
 
@@ -775,11 +818,16 @@ void launch_render_fwd(const gs_projected& proj, const gs_tile_lists& lists, int
                        reinterpret_cast<const float4*>(proj.splat), proj.ld, lists.vals,
                        reinterpret_cast<const uint2*>(lists.ranges), W, H, TX, tpv, bg[0], bg[1],
                        bg[2], image, final_T, n_contrib, usage);
-  else
-    hipLaunchKernelGGL(k_render_fwd, dim3(blocks), dim3(64), 0, s,
+  else if (g_work)
+    hipLaunchKernelGGL(k_render_fwd<true>, dim3(blocks), dim3(64), 0, s,
                        reinterpret_cast<const float4*>(proj.splat), proj.ld, lists.vals,
                        reinterpret_cast<const uint2*>(lists.ranges), W, H, TX, tpv, bg[0], bg[1],
-                       bg[2], image, final_T, n_contrib);
+                       bg[2], image, final_T, n_contrib, g_work);
+  else
+    hipLaunchKernelGGL(k_render_fwd<false>, dim3(blocks), dim3(64), 0, s,
+                       reinterpret_cast<const float4*>(proj.splat), proj.ld, lists.vals,
+                       reinterpret_cast<const uint2*>(lists.ranges), W, H, TX, tpv, bg[0], bg[1],
+                       bg[2], image, final_T, n_contrib, nullptr);
 }
 
 size_t render_fwd_l1_workspace_bytes(int V, int W, int H) {
@@ -797,11 +845,18 @@ void launch_render_fwd_l1(const gs_projected& proj, const gs_tile_lists& lists, 
   const double count = 3.0 * (double)V * (double)W * (double)H;
   double* partial = static_cast<double*>(ws);
   StageScope scope(kStRenderFwd, s);
-  hipLaunchKernelGGL(k_render_fwd_l1, dim3(blocks), dim3(64), 0, s,
-                     reinterpret_cast<const float4*>(proj.splat), proj.ld, lists.vals,
-                     reinterpret_cast<const uint2*>(lists.ranges), W, H, TX, tpv, bg[0], bg[1],
-                     bg[2], image, final_T, n_contrib, target, grad, (float)(1.0 / count),
-                     partial);
+  if (g_work)
+    hipLaunchKernelGGL(k_render_fwd_l1<true>, dim3(blocks), dim3(64), 0, s,
+                       reinterpret_cast<const float4*>(proj.splat), proj.ld, lists.vals,
+                       reinterpret_cast<const uint2*>(lists.ranges), W, H, TX, tpv, bg[0], bg[1],
+                       bg[2], image, final_T, n_contrib, target, grad, (float)(1.0 / count),
+                       partial, g_work);
+  else
+    hipLaunchKernelGGL(k_render_fwd_l1<false>, dim3(blocks), dim3(64), 0, s,
+                       reinterpret_cast<const float4*>(proj.splat), proj.ld, lists.vals,
+                       reinterpret_cast<const uint2*>(lists.ranges), W, H, TX, tpv, bg[0], bg[1],
+                       bg[2], image, final_T, n_contrib, target, grad, (float)(1.0 / count),
+                       partial, nullptr);
   hipLaunchKernelGGL(k_l1_tile_sum, dim3(1), dim3(1024), 0, s, (const double*)partial,
                      (uint32_t)blocks, 1.0 / count, loss);
 }
@@ -849,10 +904,16 @@ void launch_render_bwd(const gs_projected& proj, const gs_tile_lists& lists, int
   if (blocks == 0) return;
   {
     StageScope scope(kStRenderBwd, s);
-    hipLaunchKernelGGL(k_render_bwd, dim3(blocks), dim3(64), 0, s,
-                       reinterpret_cast<const float4*>(proj.splat), proj.ld, lists.vals,
-                       reinterpret_cast<const uint2*>(lists.ranges), W, H, TX, tpv, bg[0], bg[1],
-                       bg[2], final_T, n_contrib, dL_dimage, rows);
+    if (g_work)
+      hipLaunchKernelGGL(k_render_bwd<true>, dim3(blocks), dim3(64), 0, s,
+                         reinterpret_cast<const float4*>(proj.splat), proj.ld, lists.vals,
+                         reinterpret_cast<const uint2*>(lists.ranges), W, H, TX, tpv, bg[0],
+                         bg[1], bg[2], final_T, n_contrib, dL_dimage, rows, g_work);
+    else
+      hipLaunchKernelGGL(k_render_bwd<false>, dim3(blocks), dim3(64), 0, s,
+                         reinterpret_cast<const float4*>(proj.splat), proj.ld, lists.vals,
+                         reinterpret_cast<const uint2*>(lists.ranges), W, H, TX, tpv, bg[0],
+                         bg[1], bg[2], final_T, n_contrib, dL_dimage, rows, nullptr);
   }
   const size_t nv = (size_t)proj.n * (size_t)V;
   if (nv == 0) return;

@@ -32,6 +32,9 @@ GS_PROJECT_TIGHT_RECT = 1
 GS_PROJECT_TILE_SPANS = 2
 GRAD2D_FLOATS = 12
 STAGE_COUNT = 18
+WORK_COUNTERS = 8  # GS_WORK_COUNTERS
+WORK_COUNTER_NAMES = ("fwd_staged", "fwd_visits", "fwd_slots", "fwd_used", "bwd_staged",
+                      "bwd_visits", "bwd_slots", "bwd_used")
 
 c_int32, c_int64, c_void_p, c_double, c_float = (ctypes.c_int32, ctypes.c_int64, ctypes.c_void_p,
                                                  ctypes.c_double, ctypes.c_float)
@@ -168,6 +171,8 @@ def load() -> ctypes.CDLL:
                                           ctypes.c_size_t, c_void_p]
     lib.gs_render_fwd_batched.restype = c_int32
     lib.gs_set_timing.argtypes = [c_void_p, ctypes.c_int]
+    lib.gs_set_work_counters.argtypes = [c_void_p, c_void_p]
+    lib.gs_set_work_counters.restype = c_int32
     lib.gs_collect_timing.argtypes = [c_void_p, P(c_double), P(c_int64)]
     lib.gs_stage_name.argtypes = [ctypes.c_int]
     lib.gs_stage_name.restype = ctypes.c_char_p
@@ -190,7 +195,7 @@ def exported_symbols():
             "gs_l1_dssim_loss_grad", "gs_keyframe_temporal_l1", "gs_cull_workspace_size",
             "gs_cull_low_opacity", "gs_gather_planes", "gs_residual_delta",
             "gs_quantize_delta", "gs_apply_quantized_update", "gs_render_fwd_l1_workspace_size",
-            "gs_render_fwd_l1", "gs_render_fwd_l1_noalloc"]
+            "gs_render_fwd_l1", "gs_render_fwd_l1_noalloc", "gs_set_work_counters"]
 
 
 def _ptr(t):
@@ -224,6 +229,14 @@ class Context:
 
     def set_timing(self, on: bool):
         self.check(self.lib.gs_set_timing(self.handle, 1 if on else 0))
+
+    def set_work_counters(self, counters):
+        """counters: a zeroed int64 device tensor of WORK_COUNTERS values that
+        the render calls of this context add their work tallies to, or None
+        to switch counting off."""
+        if counters is not None:
+            assert counters.dtype == torch.int64 and counters.numel() >= WORK_COUNTERS
+        self.check(self.lib.gs_set_work_counters(self.handle, _ptr(counters)))
 
     def collect_timing(self) -> dict:
         """{stage name: (total ms, launches)} since the last collection."""

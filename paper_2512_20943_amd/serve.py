@@ -15,7 +15,10 @@ viewpoint, resolution).  The server
   (the request is the high part of the segment id), and one persistent
   render launch over the shared (request, tile) queue;
 * keeps two workers so one batch's projection and sorting overlap another
-  batch's rendering on the device.
+  batch's rendering on the device;
+* renders a batch of one request with the plain kernel sequence (the same
+  image bit for bit; it skips the batch bookkeeping launch and the shared
+  queue, which only pay off when requests share a launch).
 
 ``PlainRenderer`` is the comparison: one request at a time, each with its own
 apply, project, bin_sort and render launches.
@@ -28,6 +31,7 @@ from __future__ import annotations
 import collections
 import concurrent.futures
 import math
+import queue
 import threading
 import time
 from dataclasses import dataclass, field
@@ -48,6 +52,7 @@ class Request:
     cam: tuple          # (R, t, f, (W, H)) host camera
     arrival: float      # seconds on the trace clock
     viewer: int = 0
+    t_start: float = math.nan   # its batch began rendering (trace clock)
     t_done: float = math.nan
     image: torch.Tensor | None = field(default=None, repr=False)
 
@@ -123,6 +128,7 @@ class BatchWorker:
         self.frames: list[gs.Gaussians] = []
         self._proj = None
         self._ws = None
+        self._aux = None  # final T and last-contributor planes of render_one
         self.instances_per_tile = 600.0
 
     def _frame_buffers(self, k):
@@ -136,9 +142,37 @@ class BatchWorker:
             self._proj.options = gs.GS_PROJECT_TIGHT_RECT | gs.GS_PROJECT_TILE_SPANS
         return self._proj.slice(0, B)
 
+    def render_one(self, r: Request):
+        """A batch of one request: apply, project, bin + sort and the plain
+        compositing launch on the worker's stream."""
+        seq = self.seq
+        with torch.cuda.stream(self.stream):
+            fb = self._frame_buffers(1)[0]
+            gs.gs_apply_frame_update(self.ctx, seq.anchor, seq.deltas[r.frame], seq.masks[r.frame],
+                                     seq.gw, seq.gh, fb, self.stream)
+            cams = gs.Cameras.from_list([r.cam], self.device)
+            proj = self._projected(1)
+            gs.gs_project(self.ctx, fb, cams, proj, self.stream)
+            lists = self.raster.bin_sort(proj, cams, self.stream)
+            w, h = r.wh
+            image = torch.empty(3 * w * h, device=self.device)
+            if self._aux is None or self._aux[0].numel() < w * h:
+                self._aux = (torch.empty(w * h, device=self.device),
+                             torch.empty(w * h, dtype=torch.int32, device=self.device))
+            gs.gs_render_fwd(self.ctx, proj, lists, cams, self.bg, image.view(1, 3, h, w),
+                             self._aux[0][:w * h], self._aux[1][:w * h], stream=self.stream)
+            done = torch.cuda.Event()
+            done.record(self.stream)
+        done.synchronize()
+        tiles = math.ceil(w / 16) * math.ceil(h / 16)
+        self.instances_per_tile = 0.8 * self.instances_per_tile + 0.2 * lists.count / max(tiles, 1)
+        return image, [image.view(3, h, w)]
+
     def render(self, reqs: list[Request]):
         """Render a batch; returns the packed image buffer and per-request
         views (request order as given)."""
+        if len(reqs) == 1:
+            return self.render_one(reqs[0])
         seq = self.seq
         order = sorted(range(len(reqs)), key=lambda k: reqs[k].frame)
         reqs_o = [reqs[k] for k in order]
@@ -242,26 +276,26 @@ class Server:
         return request_bytes(r, self.seq.anchor.ld, ipt)
 
     def run(self, trace: list[Request], clock_start: float | None = None):
-        """Serve ``trace`` in real time; fills each request's t_done.  One
-        long-lived thread per worker takes batches from its inbox, so a batch
-        starts without a thread being created for it."""
+        """Serve ``trace`` in real time; fills each request's t_start and
+        t_done.  One long-lived thread per worker blocks on its own queue, so
+        handing it a batch wakes only that thread."""
         t0 = time.perf_counter() if clock_start is None else clock_start
         pending = collections.deque()
         free = collections.deque(self.workers)
-        inbox = {id(w): collections.deque() for w in self.workers}
-        stop = [False]
+        inbox = {id(w): queue.SimpleQueue() for w in self.workers}
         next_idx = 0
         done_count = [0]
 
         def serve_loop(worker):
             box = inbox[id(worker)]
             while True:
-                with self.lock:
-                    while not box and not stop[0]:
-                        self.lock.wait()
-                    if not box:
-                        return
-                    batch, nbytes = box.popleft()
+                item = box.get()
+                if item is None:
+                    return
+                batch, nbytes = item
+                start = time.perf_counter() - t0
+                for r in batch:
+                    r.t_start = start
                 try:
                     _, imgs = worker.render(batch)
                     now = time.perf_counter() - t0
@@ -308,8 +342,7 @@ class Server:
                             self.max_in_flight_bytes = max(self.max_in_flight_bytes,
                                                            self.in_flight_bytes)
                             self.batches.append(len(batch))
-                            inbox[id(worker)].append((batch, nbytes))
-                            self.lock.notify_all()
+                            inbox[id(worker)].put((batch, nbytes))
                             launched = True
                     if not launched:
                         wait = 0.05
@@ -317,9 +350,8 @@ class Server:
                             wait = min(wait, max(trace[next_idx].arrival - now, 0.0))
                         self.lock.wait(timeout=wait if wait > 0 else 0.0005)
         finally:
-            with self.lock:
-                stop[0] = True
-                self.lock.notify_all()
+            for w in self.workers:
+                inbox[id(w)].put(None)
             for th in threads:
                 th.join()
         if self.errors:
@@ -335,6 +367,7 @@ def run_plain(renderer: PlainRenderer, trace: list[Request], clock_start: float 
         now = time.perf_counter() - t0
         if r.arrival > now:
             time.sleep(r.arrival - now)
+        r.t_start = time.perf_counter() - t0
         img = renderer.render(r)
         r.t_done = time.perf_counter() - t0
         if keep_images:
@@ -348,7 +381,13 @@ def summarize(trace: list[Request], warmup: float = 0.0) -> dict:
     if len(meas) == 0:
         return dict(views=0)
     span = max(r.t_done for r in meas) - min(r.arrival for r in meas)
-    return dict(views=len(meas), views_per_s=round(len(meas) / span, 2),
-                p50_ms=round(float(np.percentile(lat, 50)), 3),
-                p99_ms=round(float(np.percentile(lat, 99)), 3),
-                mean_ms=round(float(lat.mean()), 3))
+    out = dict(views=len(meas), views_per_s=round(len(meas) / span, 2),
+               p50_ms=round(float(np.percentile(lat, 50)), 3),
+               p99_ms=round(float(np.percentile(lat, 99)), 3),
+               mean_ms=round(float(lat.mean()), 3))
+    wait = np.array([r.t_start - r.arrival for r in meas]) * 1e3
+    if np.all(np.isfinite(wait)):
+        # arrival -> its batch starts, and the batch's own render time
+        out["mean_wait_ms"] = round(float(wait.mean()), 3)
+        out["mean_render_ms"] = round(float((lat - wait).mean()), 3)
+    return out
