@@ -1,12 +1,18 @@
 // EWA projection of anisotropic Gaussians with spherical-harmonic colour,
 // and its backward pass (the splatting renderer AirGS cites in Sec. II).
 //
-// One thread per Gaussian walks every view, so the SoA parameters (56 B at
-// SH degree 0, 236 B at degree 3) are read from HBM once per launch and the
+// A thread takes one Gaussian and a group of consecutive views; a workgroup
+// takes 256 consecutive Gaussians and one view group.  All view groups of a
+// chunk of Gaussians land on one XCD (workgroups are dealt to the 8 XCDs
+// round-robin by index), so the SoA parameters (56 B at SH degree 0, 236 B
+// at degree 3) come from HBM once and from that XCD's L2 for the other
+// groups, while the view groups multiply the waves in flight; the
 // per-(view, Gaussian) records are written coalesced.  The quantities that
 // decide integers downstream -- depth key, radius, tile rectangle -- are
 // evaluated in FP64 with contraction off and a fixed operation order, so
 // that tile lists are reproducible exactly.  Colour is FP32.
+#include <algorithm>
+
 #include "gs_internal.h"
 
 namespace gs {
@@ -89,13 +95,20 @@ template <int DEG>
 __global__ __launch_bounds__(256) void k_project(
     int n, int ld, const float* __restrict__ mean, const float* __restrict__ lsc,
     const float* __restrict__ quat, const float* __restrict__ opac, const float* __restrict__ sh,
-    const gs_camera* __restrict__ cams, int n_views, float4* __restrict__ splat,
-    int4* __restrict__ rect, int32_t* __restrict__ tiles, uint32_t* __restrict__ depth_bits,
-    uint8_t* __restrict__ flags, bool tight, bool spans) {
+    const gs_camera* __restrict__ cams, int n_views, int groups, int per_group,
+    float4* __restrict__ splat, int4* __restrict__ rect, int32_t* __restrict__ tiles,
+    uint32_t* __restrict__ depth_bits, uint8_t* __restrict__ flags, bool tight, bool spans) {
 #pragma clang fp contract(off)
   constexpr int K = (DEG + 1) * (DEG + 1);
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  // workgroup b: XCD b % 8; chunk = 8 (b / (8 groups)) + b % 8, view group
+  // (b / 8) % groups
+  const int b = blockIdx.x;
+  const int chunk = 8 * (b / (8 * groups)) + (b & 7);
+  const int vg = (b >> 3) % groups;
+  const int i = chunk * blockDim.x + threadIdx.x;
   if (i >= n) return;
+  const int v_begin = vg * per_group;
+  const int v_end = min(n_views, v_begin + per_group);
   const size_t L = (size_t)ld;
   const double m0 = mean[i], m1 = mean[L + i], m2 = mean[2 * L + i];
   double qw = quat[i], qx = quat[L + i], qy = quat[2 * L + i], qz = quat[3 * L + i];
@@ -141,7 +154,7 @@ __global__ __launch_bounds__(256) void k_project(
 #pragma unroll
   for (int k = 0; k < K * 3; ++k) shv[k] = sh[(size_t)k * L + i];
 
-  for (int v = 0; v < n_views; ++v) {
+  for (int v = v_begin; v < v_end; ++v) {
     const gs_camera& cam = cams[v];
     const double* R = cam.R;
     const size_t j = (size_t)v * L + i;
@@ -250,14 +263,31 @@ __global__ __launch_bounds__(256) void k_project(
             };
             uint32_t packed = 0;
             int cnt = 0;
+            // a row's upper band edge is the next row's lower one (the same
+            // FP64 value), so its chord is reused
+            bool have = false;
+            double pl = 0.0, pr = 0.0, pc = 0.0;
             for (int r = 0; r < rc.w - rc.y; ++r) {
               const double tyd = (double)(rc.y + r);
               const double lo = ((double)kTile * tyd - 0.5) - py;
               const double hi = ((double)kTile * tyd + 15.5) - py;
-              if (lo > ey + kSpanEps || hi < -ey - kSpanEps) continue;
-              double l0, r0, l1, r1;
-              const double c0 = chord(lo, l0, r0);
+              if (lo > ey + kSpanEps || hi < -ey - kSpanEps) {
+                have = false;
+                continue;
+              }
+              double l0, r0, l1, r1, c0;
+              if (have) {
+                l0 = pl;
+                r0 = pr;
+                c0 = pc;
+              } else {
+                c0 = chord(lo, l0, r0);
+              }
               const double c1 = chord(hi, l1, r1);
+              pl = l1;
+              pr = r1;
+              pc = c1;
+              have = true;
               const double xmax = (ys >= c0 && ys <= c1) ? ex : fmax(r0, r1);
               const double xmin = (-ys >= c0 && -ys <= c1) ? -ex : fmin(l0, l1);
               const double xs = fmax(
@@ -562,16 +592,23 @@ __global__ __launch_bounds__(256) void k_project_bwd(
 
 void launch_project(const gs_gaussians& g, const gs_camera* cams, int V, const gs_projected& o,
                     hipStream_t s) {
-  const int blocks = (g.n + 255) / 256;
-  if (blocks == 0) return;
+  const int chunks = (g.n + 255) / 256;
+  if (chunks == 0 || V <= 0) return;
+  // enough view groups for about 16 waves per SIMD (1024 SIMDs), each group
+  // at least one view
+  const int64_t waves = 4 * (int64_t)chunks;
+  int groups = (int)std::min<int64_t>(V, std::max<int64_t>(1, (16384 + waves - 1) / waves));
+  const int per_group = (V + groups - 1) / groups;
+  groups = (V + per_group - 1) / per_group;
+  const int64_t blocks = (int64_t)((chunks + 7) / 8) * 8 * groups;
   StageScope scope(kStProject, s);
   float4* sp = reinterpret_cast<float4*>(o.splat);
   int4* rc = reinterpret_cast<int4*>(o.rect);
-#define GS_PROJ(D)                                                                           \
-  hipLaunchKernelGGL(k_project<D>, dim3(blocks), dim3(256), 0, s, g.n, g.ld, g.mean,        \
-                     g.log_scale, g.quat, g.opacity, g.sh, cams, V, sp, rc, o.tiles_touched, \
-                     o.depth_bits, o.flags,                                              \
-                     (o.options & (GS_PROJECT_TIGHT_RECT | GS_PROJECT_TILE_SPANS)) != 0,    \
+#define GS_PROJ(D)                                                                             \
+  hipLaunchKernelGGL(k_project<D>, dim3((unsigned)blocks), dim3(256), 0, s, g.n, g.ld, g.mean, \
+                     g.log_scale, g.quat, g.opacity, g.sh, cams, V, groups, per_group, sp, rc, \
+                     o.tiles_touched, o.depth_bits, o.flags,                                   \
+                     (o.options & (GS_PROJECT_TIGHT_RECT | GS_PROJECT_TILE_SPANS)) != 0,      \
                      (o.options & GS_PROJECT_TILE_SPANS) != 0)
   switch (g.sh_degree) {
     case 0: GS_PROJ(0); break;

@@ -337,7 +337,10 @@ class Server:
                             batch.append(pending.popleft())
                             nbytes += need
                         if batch:
-                            worker = free.popleft()
+                            # the most recently freed worker: at low load one
+                            # worker serves every request, so its buffers stay
+                            # warm in the caches and its TLB entries resident
+                            worker = free.pop()
                             self.in_flight_bytes += nbytes
                             self.max_in_flight_bytes = max(self.max_in_flight_bytes,
                                                            self.in_flight_bytes)
