@@ -80,6 +80,8 @@ def parse():
     ap.add_argument("--serve-seconds", type=float, default=10.0)
     ap.add_argument("--serve-warmup", type=float, default=1.0)
     ap.add_argument("--serve-frames", type=int, default=300)
+    ap.add_argument("--no-small", action="store_true",
+                    help="skip the 10k-Gaussian single-view 128x128 leg")
     ap.add_argument("--no-large", action="store_true",
                     help="skip the 2M-Gaussian training and 3840x2160 serving legs")
     ap.add_argument("--large-steps", type=int, default=20)
@@ -612,6 +614,44 @@ def serving(args, scene):
     return serve_rates(seq, rates, args.serve_seconds, args.serve_warmup, serve.RESOLUTIONS)
 
 
+def small_scene(args):
+    """The 10k-Gaussian scene (SH 0, means U[-1,1]^3, one 128x128 camera at
+    distance 4): forward with the L1 term, backward, Adam; and the oracle on
+    one iteration of it."""
+    import torch
+
+    from paper_2512_20943_amd import scenes
+    scene, cams, target_scene = scenes.workload_plain_10k(0)
+    ts = TrainStep(scene, cams, target_scene)
+    steps = 200
+    wall, _, stages, per_step = time_steps(ts, steps, 20)
+    out = {"workload": "10,000 Gaussians SH0, one 128x128 view, L1 + Adam",
+           "iters_per_s": round(steps / wall, 2), "ms_per_step": round(wall / steps * 1e3, 4),
+           "steps": steps, "warmup": 20, "step_device_ms": step_stats(per_step),
+           "instances_per_step": ts.last["lists"].count,
+           "stage_ms_per_step": {k: round(v[0] / steps, 4) for k, v in stages.items()
+                                 if v[1] > 0}}
+    log(f"10k x 1 view 128x128 step: {wall / steps * 1e3:.3f} ms")
+    del ts
+    torch.cuda.empty_cache()
+    if not args.no_cpu_baseline:
+        import oracle
+        oracle.build(force=False)
+        _, _, timg = oracle.forward(target_scene, cams)
+        t0 = time.perf_counter()
+        P, L, img = oracle.forward(scene, cams)
+        _, gI = oracle.l1(img["image"], timg["image"])
+        _, grads = oracle.backward(scene, cams, P, L, gI)
+        flat = np.concatenate([scene[k].ravel() for k in ("mean", "log_scale", "quat",
+                                                            "opacity", "sh")]).astype(np.float64)
+        gflat = np.concatenate([grads[k].ravel() for k in ("mean", "log_scale", "quat",
+                                                             "opacity", "sh")])
+        oracle.adam(flat, gflat, np.zeros_like(flat), np.zeros_like(flat), 1)
+        t_iter = time.perf_counter() - t0
+        out["oracle_iters_per_s"] = round(1.0 / t_iter, 3)
+    return out
+
+
 def large_scene(args):
     """The 2M-Gaussian scene: an 8-view 1920x1080 training iteration
     (project, bin + sort, render fwd with L1, render bwd, project bwd, Adam),
@@ -784,6 +824,8 @@ def main():
     if not args.no_serve:
         result["serving"] = serving(args, scene)
         torch.cuda.empty_cache()
+    if not args.no_small:
+        result["small_scene"] = small_scene(args)
     if not args.no_large:
         result["large_scene"] = large_scene(args)
     if not args.no_cpu_baseline:

@@ -20,6 +20,7 @@ class FakeWorker:
         self.batches = []
         self.fail_on = fail_on
         self.active = 0
+        self.threads = []
         self.lock = threading.Lock()
         self.max_active = 0
 
@@ -28,6 +29,7 @@ class FakeWorker:
             self.active += 1
             self.max_active = max(self.max_active, self.active)
         self.batches.append([r.rid for r in reqs])
+        self.threads.append(threading.current_thread())
         time.sleep(self.delay)
         with self.lock:
             self.active -= 1
@@ -100,3 +102,26 @@ def test_summary_percentiles():
     st = serve.summarize(tr)
     assert st["views"] == 10
     assert abs(st["p50_ms"] - np.percentile(np.arange(1, 11), 50)) < 1e-9
+
+
+def test_lone_requests_on_an_idle_server_render_on_the_scheduler_thread():
+    """Sparse arrivals: every batch holds one request and finds both workers
+    idle, so it is rendered on the calling thread; switched off, the worker
+    threads render them.  Both ways every request completes in order."""
+    tr = serve.make_trace(None, 50.0, 0.3, 64, 10, 4, resolutions=((64, 48),))
+    assert len(tr) >= 5
+    ws = [FakeWorker(0.001), FakeWorker(0.001)]
+    srv = serve.Server(fake_seq(), budget_bytes=1 << 40, max_batch=8, workers=ws)
+    srv.run(tr)
+    assert all(math.isfinite(r.t_done) and r.t_done >= r.t_start >= r.arrival for r in tr)
+    me = threading.current_thread()
+    assert all(len(b) == 1 for w in ws for b in w.batches)
+    assert all(t is me for w in ws for t in w.threads)
+
+    tr2 = serve.make_trace(None, 50.0, 0.3, 64, 10, 4, resolutions=((64, 48),))
+    ws2 = [FakeWorker(0.001), FakeWorker(0.001)]
+    srv2 = serve.Server(fake_seq(), budget_bytes=1 << 40, max_batch=8, workers=ws2,
+                        inline_singletons=False)
+    srv2.run(tr2)
+    assert all(math.isfinite(r.t_done) for r in tr2)
+    assert all(t is not me for w in ws2 for t in w.threads)
