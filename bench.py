@@ -81,6 +81,8 @@ def parse():
     ap.add_argument("--serve-seconds", type=float, default=10.0)
     ap.add_argument("--serve-warmup", type=float, default=1.0)
     ap.add_argument("--serve-frames", type=int, default=300)
+    ap.add_argument("--no-peaks", action="store_true",
+                    help="skip the peak-rate probes")
     ap.add_argument("--no-small", action="store_true",
                     help="skip the 10k-Gaussian single-view 128x128 leg")
     ap.add_argument("--no-large", action="store_true",
@@ -93,6 +95,41 @@ def parse():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of known size (counter calibration)")
     return ap.parse_args()
+
+
+# Spec figures the probes are compared with: LDS 128 B per clock per CU;
+# exp2 at a quarter of the FP32 lane rate.
+SPEC_LDS_TBPS = 256 * 128 * 2.4e9 / 1e12
+SPEC_EXP_TOPS = 256 * 128 / 4 * 2.4e9 / 1e12
+
+
+def peaks():
+    """Measured peak rates of the library's probes (best of three launches)
+    beside the spec figures they bound."""
+    import torch
+
+    from paper_2512_20943_amd import gs
+    ctx = gs.default_context()
+    out = {}
+    plan = [("copy", 2 << 30, 1, 1e9, "GB/s", PEAK_HBM_GBS),
+            ("read", (1 << 30) + gs.peak_min_bytes("read"), 1, 1e9, "GB/s", PEAK_HBM_GBS),
+            ("lds", gs.peak_min_bytes("lds"), 64, 1e12, "TB/s", SPEC_LDS_TBPS),
+            ("fma", gs.peak_min_bytes("fma"), 4096, 1e12, "TFLOP/s", PEAK_ALU_TFLOPS),
+            ("exp", gs.peak_min_bytes("exp"), 1024, 1e12, "T exp2/s", SPEC_EXP_TOPS),
+            ("atomic_spread", gs.peak_min_bytes("atomic_spread"), 16, 1e9, "G atomics/s", None),
+            ("atomic_same", gs.peak_min_bytes("atomic_same"), 2, 1e9, "G atomics/s", None)]
+    for kind, nbytes, iters, scale, unit, spec in plan:
+        buf = torch.zeros(nbytes // 4, dtype=torch.float32, device="cuda")
+        best = None
+        for _ in range(3):
+            ms, work = gs.gs_peak_run(ctx, kind, buf, iters)
+            rate = work / (ms / 1e3) / scale
+            best = rate if best is None else max(best, rate)
+        out[kind] = {"rate": round(best, 2), "unit": unit, "spec": spec,
+                     "frac_of_spec": round(best / spec, 4) if spec else None}
+        del buf
+    torch.cuda.empty_cache()
+    return out
 
 
 def copy_calibration():
@@ -721,6 +758,15 @@ def main():
     work = count_work(ts)
     dom, rf, summary = roofline(stages, ts, args.steps, work)
     stage_ms = {k: round(v[0] / args.steps, 4) for k, v in stages.items() if v[1] > 0}
+    pk = None if args.no_peaks else peaks()
+    if pk is not None and rf is not None:
+        # the same bound against the probe-measured peak
+        if rf["bound"] == "alu":
+            measured = pk["fma"]["rate"] / 2.0  # FMA counted once
+        else:
+            measured = pk["copy"]["rate"]
+        rf["peak_measured"] = round(measured, 2)
+        rf["frac_measured"] = round(rf["achieved"] / measured, 4)
     fwd_ms, fwd_n = stages["render_fwd"]
     result = {
         "metric": "fwd+bwd train iters/s", "value": round(value, 4), "unit": "iters/s",
@@ -740,6 +786,8 @@ def main():
         "step_roofline": summary,
         "work_counts": work,
     }
+    if pk is not None:
+        result["peaks"] = pk
     if not args.no_autograd_step:
         ag = AutogradTrainStep(ts)
         k4 = max(args.steps // 2, 3)

@@ -261,6 +261,37 @@ const char* gs_stage_name(int stage);
 #define GS_WORK_COUNTERS 8
 gs_status gs_set_work_counters(gs_ctx* ctx, uint64_t* counters);
 
+/* Peak-rate probes for the roofline (measurement support, not the hot
+ * path).  Runs one launch of probe `kind` on `stream`, waits for it, and
+ * returns its event-timed duration in *ms and its work in *work:
+ *   GS_PEAK_COPY      device copy of the first half of `buf` into the second
+ *                     half; work = bytes read + written;
+ *   GS_PEAK_READ      read of `buf` (its tail holds 4 MiB of per-thread
+ *                     sums); work = bytes read;
+ *   GS_PEAK_LDS       `iters` sweeps over 64 KB of LDS per workgroup, 16-byte
+ *                     conflict-free reads; work = LDS bytes read;
+ *   GS_PEAK_FMA       16 independent FP32 FMA chains per lane, `iters`
+ *                     rounds; work = FLOP (an FMA counted as 2);
+ *   GS_PEAK_EXP       8 independent exp2 chains per lane; work = exp2 count;
+ *   GS_PEAK_ATOMIC_SPREAD / GS_PEAK_ATOMIC_SAME
+ *                     float atomic adds without return, `iters` per thread,
+ *                     each thread on its own address / on one of 64
+ *                     addresses; work = atomics (buf receives the sums).
+ * 1,048,576 threads (4,096 workgroups of 256) in every probe.  `buf` is
+ * device memory of `bytes` bytes, at least gs_peak_min_bytes(kind); its
+ * contents are overwritten.  GS_ERR_INVALID_ARG for an unknown kind, a
+ * short buffer or iters < 1. */
+#define GS_PEAK_COPY 0
+#define GS_PEAK_READ 1
+#define GS_PEAK_LDS 2
+#define GS_PEAK_FMA 3
+#define GS_PEAK_EXP 4
+#define GS_PEAK_ATOMIC_SPREAD 5
+#define GS_PEAK_ATOMIC_SAME 6
+size_t gs_peak_min_bytes(int kind);
+gs_status gs_peak_run(gs_ctx* ctx, int kind, void* buf, size_t bytes, int iters, double* ms,
+                      double* work, void* stream);
+
 /* ---- hot path ----------------------------------------------------------- */
 
 /* Apply a decoded frame update to anchor Gaussians (Eq. (2)/(5)/(12): frame

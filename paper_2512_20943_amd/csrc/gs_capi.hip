@@ -277,6 +277,35 @@ gs_status gs_set_work_counters(gs_ctx* c, uint64_t* counters) {
   return GS_OK;
 }
 
+size_t gs_peak_min_bytes(int kind) { return gs::peak_min_bytes(kind, 1); }
+
+gs_status gs_peak_run(gs_ctx* c, int kind, void* buf, size_t bytes, int iters, double* ms,
+                      double* work, void* stream) {
+  if (!c) return fail(nullptr, GS_ERR_INVALID_ARG, "ctx is NULL");
+  if (!buf || !ms || !work) return fail(c, GS_ERR_INVALID_ARG, "NULL argument");
+  const size_t need = gs::peak_min_bytes(kind, iters);
+  if (need == 0) return fail(c, GS_ERR_INVALID_ARG, "unknown probe %d", kind);
+  if (bytes < need)
+    return fail(c, GS_ERR_INVALID_ARG, "probe %d needs %zu bytes, got %zu", kind, need, bytes);
+  if (iters < 1) return fail(c, GS_ERR_INVALID_ARG, "iters must be >= 1");
+  GS_TRY(use_device(c));
+  hipStream_t s = (hipStream_t)stream;
+  hipEvent_t a = nullptr, b = nullptr;
+  hipError_t e = hipEventCreate(&a);
+  if (e == hipSuccess) e = hipEventCreate(&b);
+  if (e == hipSuccess) e = hipEventRecord(a, s);
+  if (e == hipSuccess) e = gs::launch_peak(kind, buf, bytes, iters, work, s);
+  if (e == hipSuccess) e = hipEventRecord(b, s);
+  if (e == hipSuccess) e = hipEventSynchronize(b);
+  float t = 0.f;
+  if (e == hipSuccess) e = hipEventElapsedTime(&t, a, b);
+  if (a) hipEventDestroy(a);
+  if (b) hipEventDestroy(b);
+  if (e != hipSuccess) return hip_fail(c, e, "peak probe");
+  *ms = (double)t;
+  return GS_OK;
+}
+
 gs_status gs_collect_timing(gs_ctx* c, double* ms, int64_t* launches) {
   if (!c || !ms || !launches) return fail(c, GS_ERR_INVALID_ARG, "NULL argument");
   const hipError_t e = c->timer.collect(ms, launches);

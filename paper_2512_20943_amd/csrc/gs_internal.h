@@ -146,6 +146,10 @@ void launch_l1_dssim(const float* image, const float* target, int planes, int H,
 void launch_sq_error(const float* a, const float* b, int64_t count, double* sum, hipStream_t s);
 void launch_adam(float* p, const float* g, float* m, float* v, int64_t count, float lr, float b1,
                  float b2, float eps, float bc1, float bc2, hipStream_t s);
+// peak-rate probes
+hipError_t launch_peak(int kind, void* buf, size_t bytes, int iters, double* work,
+                       hipStream_t s);
+size_t peak_min_bytes(int kind, int iters);
 void launch_fill_u32(uint32_t* p, uint32_t value, int64_t count, hipStream_t s);
 void launch_fill_f32(float* p, float value, int64_t count, hipStream_t s);
 

@@ -173,6 +173,11 @@ def load() -> ctypes.CDLL:
     lib.gs_set_timing.argtypes = [c_void_p, ctypes.c_int]
     lib.gs_set_work_counters.argtypes = [c_void_p, c_void_p]
     lib.gs_set_work_counters.restype = c_int32
+    lib.gs_peak_min_bytes.argtypes = [ctypes.c_int]
+    lib.gs_peak_min_bytes.restype = ctypes.c_size_t
+    lib.gs_peak_run.argtypes = [c_void_p, ctypes.c_int, c_void_p, ctypes.c_size_t, ctypes.c_int,
+                                P(c_double), P(c_double), c_void_p]
+    lib.gs_peak_run.restype = c_int32
     lib.gs_collect_timing.argtypes = [c_void_p, P(c_double), P(c_int64)]
     lib.gs_stage_name.argtypes = [ctypes.c_int]
     lib.gs_stage_name.restype = ctypes.c_char_p
@@ -195,7 +200,8 @@ def exported_symbols():
             "gs_l1_dssim_loss_grad", "gs_keyframe_temporal_l1", "gs_cull_workspace_size",
             "gs_cull_low_opacity", "gs_gather_planes", "gs_residual_delta",
             "gs_quantize_delta", "gs_apply_quantized_update", "gs_render_fwd_l1_workspace_size",
-            "gs_render_fwd_l1", "gs_render_fwd_l1_noalloc", "gs_set_work_counters"]
+            "gs_render_fwd_l1", "gs_render_fwd_l1_noalloc", "gs_set_work_counters",
+            "gs_peak_min_bytes", "gs_peak_run"]
 
 
 def _ptr(t):
@@ -517,6 +523,23 @@ def gs_render_bwd(ctx: Context, frame: Gaussians, proj: Projected, lists: TileLi
                                     ctypes.byref(opts), _ptr(final_T), _ptr(n_contrib),
                                     _ptr(dL_dimage), ctypes.byref(gc), uc, _ptr(dL_ddelta),
                                     _ptr(workspace), workspace.numel(), _stream(stream)))
+
+
+PEAK_KINDS = {"copy": 0, "read": 1, "lds": 2, "fma": 3, "exp": 4, "atomic_spread": 5,
+              "atomic_same": 6}
+
+
+def peak_min_bytes(kind: str) -> int:
+    return int(load().gs_peak_min_bytes(PEAK_KINDS[kind]))
+
+
+def gs_peak_run(ctx: Context, kind: str, buf: torch.Tensor, iters: int = 1, stream=None):
+    """One timed launch of a peak-rate probe: (milliseconds, work)."""
+    ms, work = c_double(), c_double()
+    ctx.check(ctx.lib.gs_peak_run(ctx.handle, PEAK_KINDS[kind], _ptr(buf),
+                                  buf.numel() * buf.element_size(), int(iters),
+                                  ctypes.byref(ms), ctypes.byref(work), _stream(stream)))
+    return ms.value, work.value
 
 
 def gs_l1_loss_grad(ctx: Context, image, target, grad, loss_dev, stream=None):

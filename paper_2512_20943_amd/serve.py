@@ -19,11 +19,13 @@ viewpoint, resolution).  The server
 * renders a batch of one request with the plain kernel sequence (the same
   image bit for bit; it skips the batch bookkeeping launch and the shared
   queue, which only pay off when requests share a launch);
-* when every worker is idle and a single request is waiting, renders it on
-  the scheduler's own thread with a free worker's stream and buffers: a
-  lone request then pays no hand-off to another thread (measured at about
-  0.07 ms of extra render time there), and requests arriving meanwhile wait
-  at most one render for their batch.
+* when every worker is idle, a single request is waiting and arrivals are
+  sparse (the observed mean gap between arrivals is more than 2.5 times
+  the observed render time of a lone request), renders it on the
+  scheduler's own thread with a plain renderer of its own: a lone request
+  then pays no hand-off to another thread (measured at about 0.07 ms of
+  extra render time there); at higher rates a request arriving during such
+  a render would wait for it, so the workers take every batch.
 
 ``PlainRenderer`` is the comparison: one request at a time, each with its own
 apply, project, bin_sort and render launches.
@@ -263,6 +265,7 @@ class Server:
         # server (its own context and stream)
         self.solo = (PlainRenderer(seq, device) if inline_singletons and workers is None
                      else None)
+        self.solo_ms = 0.5  # running estimate of a lone request's render time
         self.lock = threading.Condition()
         self.in_flight_bytes = 0
         self.max_in_flight_bytes = 0
@@ -284,6 +287,9 @@ class Server:
         inbox = {id(w): queue.SimpleQueue() for w in self.workers}
         next_idx = 0
         done_count = [0]
+        # mean gap between the arrivals seen so far (exponential average)
+        gap_ema = [math.inf]
+        last_arrival = [None]
 
         def render_batch(worker, batch, nbytes, solo=False):
             start = time.perf_counter() - t0
@@ -291,7 +297,9 @@ class Server:
                 r.t_start = start
             try:
                 if solo:
+                    t_solo = time.perf_counter()
                     imgs = [self.solo.render(batch[0])]
+                    self.solo_ms = 0.8 * self.solo_ms + 0.2 * (time.perf_counter() - t_solo) * 1e3
                 else:
                     _, imgs = worker.render(batch)
                 now = time.perf_counter() - t0
@@ -327,6 +335,11 @@ class Server:
                 with self.lock:
                     now = time.perf_counter() - t0
                     while next_idx < len(trace) and trace[next_idx].arrival <= now:
+                        a = trace[next_idx].arrival
+                        if last_arrival[0] is not None:
+                            g = a - last_arrival[0]
+                            gap_ema[0] = g if math.isinf(gap_ema[0]) else 0.9 * gap_ema[0] + 0.1 * g
+                        last_arrival[0] = a
                         pending.append(trace[next_idx])
                         next_idx += 1
                     if done_count[0] >= len(trace):
@@ -351,7 +364,8 @@ class Server:
                                                            self.in_flight_bytes)
                             self.batches.append(len(batch))
                             if (self.inline_singletons and len(batch) == 1
-                                    and len(free) == len(self.workers) - 1):
+                                    and len(free) == len(self.workers) - 1
+                                    and gap_ema[0] > 2.5 * self.solo_ms * 1e-3):
                                 inline = (worker, batch, nbytes, self.solo is not None)
                             else:
                                 inbox[id(worker)].put((batch, nbytes))
