@@ -603,24 +603,24 @@ def cpu_baseline(scene, cams, target_scene):
 
 def serve_rates(seq, rates, seconds, warmup, resolutions, seed_base=0, budget=32 << 30,
                 max_batch=32):
-    """Served views/s and p50/p99 latency of the continuous-batching server vs
-    the plain one-request-per-launch renderer on the same open-loop Poisson
-    trace per rate: 64 viewers, random viewpoints on a sphere of radius 4-6,
-    resolution uniform over ``resolutions``; latencies of the requests that
-    arrive after ``warmup`` seconds."""
+    """Served views/s and p50/p99 latency of the library's native
+    continuous-batching server vs its plain one-request-at-a-time mode on the
+    same open-loop Poisson trace per rate: 64 viewers, random viewpoints on a
+    sphere of radius 4-6, resolution uniform over ``resolutions``; latencies
+    of the requests that arrive after ``warmup`` seconds."""
     import copy
 
     import torch
 
     from paper_2512_20943_amd import serve
-    server = serve.Server(seq, budget_bytes=budget, max_batch=max_batch)
-    plain = serve.PlainRenderer(seq)
-    # warm both paths (allocations, first launches)
-    wt = serve.make_trace(16, 1e6, None, 64, seq.n_frames, 99 + seed_base,
+    server = serve.NativeServer(seq, budget_bytes=budget, max_batch=max_batch)
+    # warm both modes (buffer growth, first launches)
+    wt = serve.make_trace(32, 1e6, None, 64, seq.n_frames, 99 + seed_base,
                           resolutions=resolutions)
     server.run(copy.deepcopy(wt))
-    serve.run_plain(plain, copy.deepcopy(wt[:4]))
-    out = {"frames": seq.n_frames, "viewers": 64, "budget_gib": budget / 2**30,
+    server.run(copy.deepcopy(wt[:4]), plain=True)
+    out = {"server": "native (C++ scheduler and worker threads, gs_server_run)",
+           "frames": seq.n_frames, "viewers": 64, "budget_gib": budget / 2**30,
            "resident_gib": round(seq.device_bytes() / 2**30, 3), "max_batch": max_batch,
            "resolutions": [f"{w}x{h}" for (w, h) in resolutions],
            "seconds": seconds, "warmup_s": warmup, "rates": {}}
@@ -628,17 +628,19 @@ def serve_rates(seq, rates, seconds, warmup, resolutions, seed_base=0, budget=32
         trace = serve.make_trace(None, rate, warmup + seconds, 64, seq.n_frames,
                                  int(rate) + seed_base, resolutions=resolutions)
         tb = copy.deepcopy(trace)
-        server.batches.clear()
         server.run(tb)
         sb = serve.summarize(tb, warmup)
-        sb["mean_batch"] = round(float(np.mean(server.batches)), 2)
+        st = server.stats()
+        sb["mean_batch"] = st["mean_batch"]
+        sb["max_batch"] = st["max_batch"]
+        sb["inline_requests"] = st["inline_requests"]
         tp = copy.deepcopy(trace)
-        serve.run_plain(plain, tp)
+        server.run(tp, plain=True)
         sp = serve.summarize(tp, warmup)
         out["rates"][str(int(rate))] = {"requests": len(trace), "batched": sb, "plain": sp}
         log(f"serving {out['resolutions']} @ {rate:.0f} req/s: batched {sb}  plain {sp}")
         torch.cuda.synchronize()
-    del server, plain
+    server.close()
     return out
 
 

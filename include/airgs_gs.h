@@ -399,6 +399,83 @@ gs_status gs_render_fwd_batched(gs_ctx* ctx, const gs_projected* proj,
                                 const gs_camera* cams_dev, int n_views, const gs_opts* opts,
                                 float* images, void* workspace, size_t ws_bytes, void* stream);
 
+/* ---- view server ------------------------------------------------------ */
+
+/* A resident dynamic scene: frame f = anchor + masked delta images f (Eq.
+ * (12); one texel per Gaussian, Eq. (3)).  All pointers are device memory
+ * owned by the caller and must outlive the server:
+ *   deltas (n_frames, 8, gh, gw) FP32 channels as in gs_apply_frame_update,
+ *   masks (n_frames, gh, gw) uint8, 1 = apply. */
+typedef struct gs_sequence {
+  gs_gaussians anchor;
+  const float* deltas;
+  const uint8_t* masks;
+  int32_t n_frames;
+  int32_t gw, gh;
+  int32_t reserved;
+} gs_sequence;
+
+/* One view request: host camera (its width and height are the resolution),
+ * frame index, arrival time in seconds after gs_server_run starts. */
+typedef struct gs_request {
+  gs_camera cam;
+  int32_t frame;
+  int32_t reserved;
+  double arrival_s;
+} gs_request;
+
+/* max_batch: requests per batch (1..4096); n_workers: batches in flight
+ * (1..16), each on its own host thread, context and stream; options:
+ * gs_projected.options of the projections (tile sets); inline_singletons:
+ * nonzero lets the scheduler's thread render a lone request itself while
+ * the server is idle and arrivals are sparse (mean gap above 2.5 times the
+ * render time of a lone request); budget_bytes: device-memory budget for
+ * admission (each request is charged an estimate: projected records and
+ * sort buffers per Gaussian, 1.5x the observed instances per tile times its
+ * tiles, its image; one request is always admitted when nothing is in
+ * flight); bg: background colour. */
+typedef struct gs_server_config {
+  int32_t max_batch;
+  int32_t n_workers;
+  int32_t options;
+  int32_t inline_singletons;
+  int64_t budget_bytes;
+  float bg[3];
+  float reserved;
+} gs_server_config;
+
+typedef struct gs_server gs_server;
+
+/* Continuous-batching server (view delivery, Sec. IV-B; the renderer of
+ * Sec. II): create it on `device` for `seq` (contexts, streams and pinned
+ * camera slots are made here; device buffers grow on demand and are held
+ * until gs_server_destroy).  GS_ERR_INVALID_ARG for a bad configuration or
+ * sequence; GS_ERR_HIP / GS_ERR_OOM if resources cannot be made. */
+gs_status gs_server_create(gs_server** out, int device, const gs_sequence* seq,
+                           const gs_server_config* cfg);
+void gs_server_destroy(gs_server* server);
+const char* gs_server_last_error(const gs_server* server);
+
+/* Serve n requests (host array, arrival_s non-decreasing) in real time on
+ * the calling thread's clock, returning when all are done.  plain = 0:
+ * continuous batching (requests that arrive while batches are on the device
+ * join later batches; batches overlap on the device).  plain = 1: the
+ * comparison renderer, one request at a time in arrival order, each with
+ * its own apply, projection, binning and compositing launches.  t_start,
+ * t_done (host, n): seconds after the start when the request's batch began
+ * and when its image was complete (INFINITY if its batch failed).  images
+ * (host array of n device pointers, nullable, entries nullable): request
+ * i's (3, H, W) image is copied to images[i].  Returns the first error of
+ * any batch (text via gs_server_last_error); the other requests are still
+ * served.  Not reentrant on one server. */
+gs_status gs_server_run(gs_server* server, const gs_request* reqs, int n, int plain,
+                        double* t_start, double* t_done, float* const* images);
+
+/* Statistics of the last run (host array of 5): batches formed, requests
+ * rendered by worker threads, requests rendered inline, largest batch,
+ * peak estimated bytes in flight. */
+gs_status gs_server_stats(const gs_server* server, int64_t* out);
+
 /* Backward of gs_project + gs_render_fwd for dL/dimage (V, 3, H, W) (the
  * differentiable renderer of Sec. II through which Eq. (1) trains the
  * Gaussians and, with `upd`, the delta images of Eq. (12)):

@@ -78,6 +78,22 @@ class GsFrameUpdate(ctypes.Structure):
 assert ctypes.sizeof(GsCamera) == 144
 
 
+class GsSequence(ctypes.Structure):
+    _fields_ = [("anchor", GsGaussians), ("deltas", c_void_p), ("masks", c_void_p),
+                ("n_frames", c_int32), ("gw", c_int32), ("gh", c_int32), ("reserved", c_int32)]
+
+
+class GsRequest(ctypes.Structure):
+    _fields_ = [("cam", GsCamera), ("frame", c_int32), ("reserved", c_int32),
+                ("arrival_s", c_double)]
+
+
+class GsServerConfig(ctypes.Structure):
+    _fields_ = [("max_batch", c_int32), ("n_workers", c_int32), ("options", c_int32),
+                ("inline_singletons", c_int32), ("budget_bytes", c_int64),
+                ("bg", c_float * 3), ("reserved", c_float)]
+
+
 class GsError(RuntimeError):
     def __init__(self, code: int, msg: str):
         super().__init__(f"gs error {code}: {msg}")
@@ -173,6 +189,17 @@ def load() -> ctypes.CDLL:
     lib.gs_set_timing.argtypes = [c_void_p, ctypes.c_int]
     lib.gs_set_work_counters.argtypes = [c_void_p, c_void_p]
     lib.gs_set_work_counters.restype = c_int32
+    lib.gs_server_create.argtypes = [P(c_void_p), ctypes.c_int, P(GsSequence),
+                                     P(GsServerConfig)]
+    lib.gs_server_create.restype = c_int32
+    lib.gs_server_destroy.argtypes = [c_void_p]
+    lib.gs_server_last_error.argtypes = [c_void_p]
+    lib.gs_server_last_error.restype = ctypes.c_char_p
+    lib.gs_server_run.argtypes = [c_void_p, P(GsRequest), ctypes.c_int, ctypes.c_int,
+                                  P(c_double), P(c_double), P(c_void_p)]
+    lib.gs_server_run.restype = c_int32
+    lib.gs_server_stats.argtypes = [c_void_p, P(c_int64)]
+    lib.gs_server_stats.restype = c_int32
     lib.gs_peak_min_bytes.argtypes = [ctypes.c_int]
     lib.gs_peak_min_bytes.restype = ctypes.c_size_t
     lib.gs_peak_run.argtypes = [c_void_p, ctypes.c_int, c_void_p, ctypes.c_size_t, ctypes.c_int,
@@ -201,7 +228,8 @@ def exported_symbols():
             "gs_cull_low_opacity", "gs_gather_planes", "gs_residual_delta",
             "gs_quantize_delta", "gs_apply_quantized_update", "gs_render_fwd_l1_workspace_size",
             "gs_render_fwd_l1", "gs_render_fwd_l1_noalloc", "gs_set_work_counters",
-            "gs_peak_min_bytes", "gs_peak_run"]
+            "gs_peak_min_bytes", "gs_peak_run", "gs_server_create", "gs_server_destroy",
+            "gs_server_last_error", "gs_server_run", "gs_server_stats"]
 
 
 def _ptr(t):

@@ -419,3 +419,85 @@ def summarize(trace: list[Request], warmup: float = 0.0) -> dict:
         out["mean_wait_ms"] = round(float(wait.mean()), 3)
         out["mean_render_ms"] = round(float((lat - wait).mean()), 3)
     return out
+
+
+class NativeServer:
+    """The library's native server (gs_server_*): the scheduler runs in C++
+    on the calling thread (the ctypes call releases the interpreter lock) and
+    every worker is a native thread with its own context, stream and
+    buffers; ``run(..., plain=True)`` is the one-request-at-a-time
+    comparison on the same native path."""
+
+    def __init__(self, seq: ResidentSequence, budget_bytes: int, max_batch: int = 32,
+                 n_workers: int = 2, inline_singletons: bool = True, bg=(0.0, 0.0, 0.0),
+                 options: int = gs.GS_PROJECT_TIGHT_RECT | gs.GS_PROJECT_TILE_SPANS):
+        import ctypes
+        self.ct = ctypes
+        self.lib = gs.load()
+        self.seq = seq  # keeps the resident device buffers alive
+        sq = gs.GsSequence(seq.anchor.c(), ctypes.c_void_p(seq.deltas.data_ptr()),
+                           ctypes.c_void_p(seq.masks.data_ptr()), seq.n_frames, seq.gw, seq.gh, 0)
+        cfg = gs.GsServerConfig(int(max_batch), int(n_workers), int(options),
+                                1 if inline_singletons else 0, int(budget_bytes),
+                                (ctypes.c_float * 3)(*[float(x) for x in bg]), 0.0)
+        h = ctypes.c_void_p()
+        torch.cuda.synchronize()
+        st = self.lib.gs_server_create(ctypes.byref(h), torch.cuda.current_device(),
+                                       ctypes.byref(sq), ctypes.byref(cfg))
+        if st != gs.GS_OK:
+            raise gs.GsError(st, "gs_server_create failed")
+        self.handle = h
+        self.max_batch = max_batch
+
+    @staticmethod
+    def _camera(cam, c):
+        R, t, f, (W, H) = cam
+        c.R[:] = np.asarray(R, np.float64).reshape(9).tolist()
+        c.t[:] = np.asarray(t, np.float64).reshape(3).tolist()
+        c.fx, c.fy, c.cx, c.cy = (float(x) for x in np.asarray(f, np.float64).reshape(4))
+        c.width, c.height = int(W), int(H)
+
+    def run(self, trace: list[Request], plain: bool = False, keep_images: bool = False):
+        """Serve ``trace`` (arrivals non-decreasing) in real time; fills each
+        request's t_start and t_done (and image with ``keep_images``)."""
+        ct = self.ct
+        n = len(trace)
+        reqs = (gs.GsRequest * n)()
+        for k, r in enumerate(trace):
+            self._camera(r.cam, reqs[k].cam)
+            reqs[k].frame = int(r.frame)
+            reqs[k].arrival_s = float(r.arrival)
+        ts = (ct.c_double * n)()
+        td = (ct.c_double * n)()
+        imgs, ptrs = None, None
+        if keep_images:
+            imgs = [torch.empty(3, r.wh[1], r.wh[0], device="cuda") for r in trace]
+            ptrs = (ct.c_void_p * n)(*[t.data_ptr() for t in imgs])
+        torch.cuda.synchronize()
+        st = self.lib.gs_server_run(self.handle, reqs, n, 1 if plain else 0, ts, td, ptrs)
+        for k, r in enumerate(trace):
+            r.t_start, r.t_done = ts[k], td[k]
+            if keep_images:
+                r.image = imgs[k]
+        if st != gs.GS_OK:
+            raise gs.GsError(st, self.lib.gs_server_last_error(self.handle).decode())
+        return trace
+
+    def stats(self) -> dict:
+        out = (self.ct.c_int64 * 5)()
+        self.lib.gs_server_stats(self.handle, out)
+        b, wr, inl, mx, peak = (int(x) for x in out)
+        return {"batches": b, "worker_requests": wr, "inline_requests": inl, "max_batch": mx,
+                "mean_batch": round((wr + inl) / b, 3) if b else None,
+                "peak_in_flight_bytes": peak}
+
+    def close(self):
+        if getattr(self, "handle", None):
+            self.lib.gs_server_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:  # noqa: BLE001 - interpreter shutdown
+            pass

@@ -8,7 +8,7 @@ import pytest
 import torch
 
 import oracle
-from paper_2512_20943_amd import scenes, serve
+from paper_2512_20943_amd import gs, scenes, serve
 from tests.gpu_helpers import compare_image_only, require_gpu
 
 pytestmark = pytest.mark.gpu
@@ -102,3 +102,55 @@ def test_serving_4k_requests_on_the_2m_scene():
     err = compare_image_only(imgs[0].cpu().numpy(), ref["image"][0], ref["near_threshold"][0],
                              "served_4k_2m")
     say(f"  4K request 0: max image error {err:.2e}")
+
+
+def test_native_server_images_equal_the_plain_renderer(seq):
+    """The native server's images, batched and in its plain mode, are the
+    plain Python-driven renderer's bit for bit; requests share batches."""
+    s, _ = seq
+    trace = serve.make_trace(None, 400.0, 0.25, 64, s.n_frames, 17, resolutions=SMALL_RES)
+    assert len(trace) > 20
+    srv = serve.NativeServer(s, budget_bytes=8 << 30, max_batch=16)
+    plain = serve.PlainRenderer(s)
+    for mode in (False, True):
+        tr = [serve.Request(r.rid, r.frame, r.cam, r.arrival, r.viewer) for r in trace]
+        srv.run(tr, plain=mode, keep_images=True)
+        assert all(np.isfinite(r.t_done) and r.t_done >= r.t_start >= 0.0 for r in tr)
+        st = srv.stats()
+        say(f"  native {'plain' if mode else 'batched'}: {serve.summarize(tr)} {st}")
+        for r in tr:
+            assert torch.equal(r.image, plain.render(r)), f"request {r.rid} (plain={mode})"
+    srv.close()
+
+
+def test_native_server_batches_a_burst_and_respects_the_budget(seq):
+    s, _ = seq
+    burst = serve.make_trace(24, 1e6, None, 8, s.n_frames, 18, resolutions=SMALL_RES)
+    srv = serve.NativeServer(s, budget_bytes=8 << 30, max_batch=16, inline_singletons=False)
+    srv.run(burst)
+    st = srv.stats()
+    assert st["max_batch"] > 1 and st["inline_requests"] == 0
+    assert all(np.isfinite(r.t_done) for r in burst)
+    one = max(serve.request_bytes(r, s.anchor.ld, 600.0) for r in burst)
+    tight = serve.NativeServer(s, budget_bytes=int(one * 1.2), max_batch=16)
+    tr = serve.make_trace(24, 1e6, None, 8, s.n_frames, 19, resolutions=SMALL_RES)
+    tight.run(tr)
+    assert tight.stats()["max_batch"] <= 2
+    assert all(np.isfinite(r.t_done) for r in tr)
+    srv.close()
+    tight.close()
+
+
+def test_native_server_rejects_bad_requests(seq):
+    s, _ = seq
+    srv = serve.NativeServer(s, budget_bytes=8 << 30)
+    tr = serve.make_trace(3, 1000.0, None, 4, s.n_frames, 20, resolutions=SMALL_RES)
+    bad = [serve.Request(r.rid, r.frame, r.cam, r.arrival) for r in tr]
+    bad[1].frame = s.n_frames
+    with pytest.raises(gs.GsError):
+        srv.run(bad)
+    late = [serve.Request(r.rid, r.frame, r.cam, r.arrival) for r in tr]
+    late[0].arrival, late[2].arrival = late[2].arrival, late[0].arrival
+    with pytest.raises(gs.GsError):
+        srv.run(late)
+    srv.close()
