@@ -54,7 +54,8 @@ typedef int32_t gs_status;
 #define GS_TILE 16           /* tile side in pixels */
 #define GS_MAX_SH_DEGREE 3
 /* Largest instance capacity and largest n_views * ld that gs_bin_sort takes:
- * the radix sort's look-back words carry 30-bit prefix counts. */
+ * the binning's instance indices, offsets and counts are 32-bit, and this
+ * bound keeps them and the sums formed from them clear of overflow. */
 #define GS_MAX_INSTANCES (((int64_t)1 << 30) - 1)
 
 typedef struct gs_ctx gs_ctx;

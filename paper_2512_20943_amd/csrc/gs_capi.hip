@@ -184,10 +184,10 @@ gs_status use_device(gs_ctx* c) {
   return GS_OK;
 }
 
-// Sizes gs_bin_sort accepts: the look-back words of its radix sort carry
-// 30-bit prefix counts, so the instance capacity (which bounds the count
-// that is sorted) and the number of (view, Gaussian) depth keys stay below
-// 2^30; segment ids are 31-bit.
+// Sizes gs_bin_sort accepts: its instance indices, offsets and counts are
+// 32-bit, so the instance capacity (which bounds the count that is sorted)
+// and the number of (view, Gaussian) depth keys stay below 2^30, clear of
+// overflow in the sums formed from them; segment ids are 31-bit.
 bool bin_sort_sizes_ok(int V, int ld, int64_t capacity, int64_t n_segments) {
   return V > 0 && ld > 0 && capacity >= 0 && capacity <= GS_MAX_INSTANCES &&
          (int64_t)V * ld <= GS_MAX_INSTANCES && n_segments >= 0 &&

@@ -2,9 +2,10 @@
 //
 // The order the renderer needs is, per tile segment, the instances sorted by
 // (FP32 depth, Gaussian id).  It is reached in two sorts that both use the
-// same LDS-resident onesweep LSD radix sort (stable, 8- or 9-bit digits, one
-// global histogram pass, then one pass per digit with decoupled look-back
-// over dynamically numbered partitions):
+// same LDS-resident LSD radix sort (stable, 8- or 9-bit digits; per digit,
+// per-partition counts, their scan, then LDS ranking and an LDS-staged
+// scatter with those bases; partitions are laid out XCD by XCD, so each of
+// the 8 L2s sees a contiguous range):
 //   1. the (view, depth) keys of the V*n projected Gaussians -- 32-bit keys
 //      view * span + (depth bits - min) when the views times the visible
 //      depth-bit range fit (a first pass reduces that range together with
@@ -26,23 +27,11 @@ namespace {
 
 constexpr int kBlock = 256;
 constexpr int kItems = 32;
-constexpr int kPart = kBlock * kItems;  // keys per onesweep partition
+constexpr int kPart = kBlock * kItems;  // keys per radix-sort partition
 constexpr int kCountItems = 8;          // entries per thread in the instance count and scan
 constexpr int kCountChunk = kBlock * kCountItems;
-constexpr uint32_t kFlagAgg = 1u << 30;
-constexpr uint32_t kFlagPre = 2u << 30;
-constexpr uint32_t kValMask = (1u << 30) - 1u;
-constexpr int kMaxPasses = 8;
-constexpr int kLookWin = 8;    // look-back window (partitions loaded together)
 
 __device__ __forceinline__ uint64_t wave_ballot(bool p) { return __builtin_amdgcn_ballot_w64(p); }
-
-__device__ __forceinline__ uint32_t ld_relaxed(const uint32_t* p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ void st_relaxed(uint32_t* p, uint32_t v) {
-  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
 
 template <int BITS, typename K>
 __device__ __forceinline__ uint32_t digit_of(K key, int shift) {
@@ -69,92 +58,112 @@ __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t x, uint32_t* s
 }
 
 // ------------------------------------------------------------ radix sort
-// Digits are BITS wide (8 or 9): the pass count is chosen per sort so
-// that the key's significant bits take as few passes as possible.
+// Per-partition digit counts, digit-major: cnt[d * parts + p].
 template <typename K, int BITS>
-__global__ __launch_bounds__(kBlock) void k_histogram(const K* __restrict__ keys, uint32_t n,
-                                                      int passes, uint32_t* __restrict__ hist) {
+__global__ __launch_bounds__(kBlock) void k_part_count(const K* __restrict__ keys, uint32_t n,
+                                                       int shift, uint32_t parts,
+                                                       uint32_t* __restrict__ cnt) {
   constexpr int R = 1 << BITS;
-  __shared__ uint32_t h[kMaxPasses * R];
-  for (int t = threadIdx.x; t < passes * R; t += kBlock) h[t] = 0;
+  __shared__ uint32_t h[R];
+  for (int t = threadIdx.x; t < R; t += kBlock) h[t] = 0;
   __syncthreads();
-  // 8 keys per thread per round, loaded before they are counted, so that
-  // each wave keeps several loads in flight
-  constexpr int U = 8;
-  const uint32_t stride = gridDim.x * kBlock;
-  for (uint32_t i0 = blockIdx.x * kBlock + threadIdx.x; i0 < n; i0 += U * stride) {
-    K kk[U];
+  // XCD-aware: workgroup b runs on XCD b % 8; each XCD takes a contiguous
+  // range of partitions, so one L2 merges the count rows' neighbouring words
+  const uint32_t per = (parts + 7) / 8;
+  const uint32_t part = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+  if (part >= parts) return;
+  const uint32_t base = part * (uint32_t)kPart;
+  K kk[kItems];
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const uint32_t i = i0 + u * stride;
-      kk[u] = i < n ? keys[i] : K(0);
-    }
+  for (int j = 0; j < kItems; ++j) {
+    const uint32_t i = base + (uint32_t)j * kBlock + threadIdx.x;
+    kk[j] = i < n ? keys[i] : K(0);
+  }
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-      if (i0 + u * stride >= n) break;
-      for (int p = 0; p < passes; ++p)
-        atomicAdd(&h[p * R + digit_of<BITS>(kk[u], BITS * p)], 1u);
-    }
+  for (int j = 0; j < kItems; ++j) {
+    const uint32_t i = base + (uint32_t)j * kBlock + threadIdx.x;
+    if (i < n) atomicAdd(&h[digit_of<BITS>(kk[j], shift)], 1u);
   }
   __syncthreads();
-  for (int t = threadIdx.x; t < passes * R; t += kBlock)
-    if (h[t]) atomicAdd(&hist[t], h[t]);
+  for (int t = threadIdx.x; t < R; t += kBlock) cnt[(size_t)t * parts + part] = h[t];
 }
 
-// Exclusive scan of each pass's histogram (one block; thread t owns the R/256
-// consecutive bins starting at t*R/256).
-template <int BITS>
-__global__ __launch_bounds__(kBlock) void k_hist_scan(const uint32_t* __restrict__ hist,
-                                                      int passes, uint32_t* __restrict__ off) {
-  constexpr int R = 1 << BITS, DPT = R / kBlock;
+// Exclusive scan of each digit's row of partition counts (one block per
+// digit); the row total goes to tot[d].
+__global__ __launch_bounds__(kBlock) void k_part_scan_rows(uint32_t* __restrict__ cnt,
+                                                           uint32_t parts,
+                                                           uint32_t* __restrict__ tot) {
+  constexpr int kIpt = 16;  // consecutive counts per thread
   __shared__ uint32_t s_wave[4];
-  for (int p = 0; p < passes; ++p) {
-    uint32_t x[DPT], sum = 0;
+  uint32_t* row = cnt + (size_t)blockIdx.x * parts;
+  uint32_t carry = 0;
+  for (uint32_t b0 = 0; b0 < parts; b0 += kBlock * kIpt) {
+    const uint32_t e0 = b0 + threadIdx.x * kIpt;
+    uint32_t x[kIpt], sum = 0;
 #pragma unroll
-    for (int i = 0; i < DPT; ++i) {
-      x[i] = hist[p * R + threadIdx.x * DPT + i];
+    for (int i = 0; i < kIpt; ++i) {
+      x[i] = e0 + i < parts ? row[e0 + i] : 0u;
       sum += x[i];
     }
-    uint32_t run = block_exclusive_scan(sum, s_wave, nullptr);
+    uint32_t t;
+    uint32_t run = carry + block_exclusive_scan(sum, s_wave, &t);
 #pragma unroll
-    for (int i = 0; i < DPT; ++i) {
-      off[p * R + threadIdx.x * DPT + i] = run;
+    for (int i = 0; i < kIpt; ++i) {
+      if (e0 + i < parts) row[e0 + i] = run;
       run += x[i];
     }
+    carry += t;
+  }
+  if (threadIdx.x == 0) tot[blockIdx.x] = carry;
+}
+
+// Exclusive scan of the digit totals in place (one block).
+template <int BITS>
+__global__ __launch_bounds__(kBlock) void k_digit_scan(uint32_t* __restrict__ tot) {
+  constexpr int R = 1 << BITS, DPT = R / kBlock;
+  __shared__ uint32_t s_wave[4];
+  uint32_t x[DPT], sum = 0;
+#pragma unroll
+  for (int i = 0; i < DPT; ++i) {
+    x[i] = tot[threadIdx.x * DPT + i];
+    sum += x[i];
+  }
+  uint32_t run = block_exclusive_scan(sum, s_wave, nullptr);
+#pragma unroll
+  for (int i = 0; i < DPT; ++i) {
+    tot[threadIdx.x * DPT + i] = run;
+    run += x[i];
   }
 }
 
-// One digit pass.  Each block takes the next partition id, ranks its keys
-// stably by digit in LDS (wave ballots find equal digits among the 64 lanes
-// of a wave, per-wave counters in LDS carry the rank across items and
-// waves), publishes its per-digit counts, looks back over earlier
-// partitions for the global prefix, then scatters through LDS so that the
-// global writes come out in digit-contiguous runs.  Thread t owns the R/256
-// consecutive digits starting at t*R/256 in the per-digit phase.
+// One digit pass with bases from the scans: each wave ranks its keys stably
+// by digit with ballots (lanes holding the same digit) and per-wave
+// counters in LDS, the block scatters them through LDS into digit order,
+// and the global writes come out as runs at (digit start + this
+// partition's prefix).  No partition waits for another.
 template <typename K, int BITS>
-__global__ __launch_bounds__(kBlock) void k_onesweep(
+__global__ __launch_bounds__(kBlock) void k_scatter_pass(
     const K* __restrict__ kin, const uint32_t* __restrict__ vin, K* __restrict__ kout,
-    uint32_t* __restrict__ vout, uint32_t n, int shift, const uint32_t* __restrict__ dig_off,
-    uint32_t* lookback, uint32_t* counter) {
+    uint32_t* __restrict__ vout, uint32_t n, int shift, uint32_t parts,
+    const uint32_t* __restrict__ pbase, const uint32_t* __restrict__ dstart_g) {
   constexpr int R = 1 << BITS, DPT = R / kBlock;
-  __shared__ uint32_t s_part;
   __shared__ uint32_t s_wh[4][R];
   __shared__ uint32_t s_dstart[R];
   __shared__ uint32_t s_gbase[R];
   __shared__ uint32_t s_wave[4];
   __shared__ K s_k[kPart];
   __shared__ uint32_t s_v[kPart];
-
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  if (tid == 0) s_part = atomicAdd(counter, 1u);
+  // XCD-aware as in k_part_count: neighbouring partitions, whose runs of
+  // one digit are adjacent in the output, share an L2
+  const uint32_t per = (parts + 7) / 8;
+  const uint32_t part = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+  if (part >= parts) return;
   for (int t = tid; t < 4 * R; t += kBlock) (&s_wh[0][0])[t] = 0;
   __syncthreads();
-  const uint32_t part = s_part;
   const uint32_t base = part * (uint32_t)kPart + (uint32_t)wave * 64u * kItems;
-
   K k[kItems];
   uint32_t val[kItems], rank[kItems], dig[kItems];
-  // every partition but the last is full: no bounds tests on its loads
   const bool full = part * (uint64_t)kPart + kPart <= n;
   if (full) {
     const K* kb = kin + base + lane;
@@ -183,8 +192,6 @@ __global__ __launch_bounds__(kBlock) void k_onesweep(
   for (int j = 0; j < kItems; ++j) {
     const bool valid = full || base + j * 64 + lane < n;
     const uint32_t d = valid ? digit_of<BITS>(k[j], shift) : 0u;
-    // lanes holding the same digit: for each bit, keep the lanes whose bit
-    // agrees with this lane's (flip = all ones when this lane's bit is 0)
     const uint64_t vmask = wave_ballot(valid);
     uint32_t pl = (uint32_t)vmask, ph = (uint32_t)(vmask >> 32);
     const uint32_t nd = ~d;
@@ -218,50 +225,13 @@ __global__ __launch_bounds__(kBlock) void k_onesweep(
       }
       run[i] = r;
       tsum += r;
-      st_relaxed(lookback + (size_t)part * R + d, (part == 0 ? kFlagPre : kFlagAgg) | r);
     }
     uint32_t dstart = block_exclusive_scan(tsum, s_wave, nullptr);
 #pragma unroll
     for (int i = 0; i < DPT; ++i) {
       const int d = tid * DPT + i;
       s_dstart[d] = dstart;
-      uint32_t excl = 0;
-      if (part > 0) {
-        // look back over a window of up to kLookWin predecessors at a time:
-        // their flags are loaded together, then the window is consumed up to
-        // the nearest inclusive prefix (or entirely, if it holds only
-        // aggregates); a window with a not-yet-published entry before that
-        // point is loaded again
-        int64_t p = (int64_t)part - 1;
-        while (true) {
-          uint32_t w[kLookWin];
-#pragma unroll
-          for (int h = 0; h < kLookWin; ++h)
-            w[h] = (p - h >= 0) ? ld_relaxed(lookback + (size_t)(p - h) * R + d) : kFlagPre;
-          uint32_t sum = 0;
-          int state = 0;  // 0 all aggregates, 1 prefix reached, 2 must wait
-#pragma unroll
-          for (int h = 0; h < kLookWin; ++h) {
-            if (state == 0) {
-              if ((w[h] & ~kValMask) == 0u) {
-                state = 2;
-              } else {
-                sum += w[h] & kValMask;
-                if (w[h] & kFlagPre) state = 1;
-              }
-            }
-          }
-          if (state == 2) {
-            __builtin_amdgcn_s_sleep(1);
-            continue;
-          }
-          excl += sum;
-          if (state == 1) break;
-          p -= kLookWin;
-        }
-        st_relaxed(lookback + (size_t)part * R + d, kFlagPre | (excl + run[i]));
-      }
-      s_gbase[d] = dig_off[d] + excl - dstart;
+      s_gbase[d] = dstart_g[d] + pbase[(size_t)d * parts + part] - dstart;
       dstart += run[i];
     }
   }
@@ -706,8 +676,8 @@ inline int depth_key_bits(int V) { return 32 + bits_for((uint64_t)V); }
 inline uint32_t cdiv(uint64_t a, uint64_t b) { return (uint32_t)((a + b - 1) / b); }
 
 struct Layout {
-  size_t dk0, dk1, dv0, dv1, cnt, offs, chunks, segk0, segk1, segv_alt, hist, digoff, counters,
-      dparts, vparts, lookback, seg_base, txv, total, stats, bytes;
+  size_t dk0, dk1, dv0, dv1, cnt, offs, chunks, segk0, segk1, segv_alt, pcount, dtotal, dparts,
+      vparts, seg_base, txv, total, stats, bytes;
 };
 
 Layout make_layout(int V, int ld, int64_t cap, int64_t nseg) {
@@ -721,8 +691,9 @@ Layout make_layout(int V, int ld, int64_t cap, int64_t nseg) {
   const size_t N = (size_t)V * (size_t)ld;
   const DigitPlan dp = plan_digits(depth_key_bits(V));
   const DigitPlan sp = plan_digits(bits_for((uint64_t)nseg));
-  const size_t lb_depth = (size_t)dp.passes * cdiv(N, kPart) * ((size_t)1 << dp.bits);
-  const size_t lb_seg = (size_t)sp.passes * cdiv((uint64_t)cap, kPart) * ((size_t)1 << sp.bits);
+  // per-partition digit counts of one pass (reused by every pass)
+  const size_t pc_depth = (size_t)cdiv(N, kPart) * ((size_t)1 << dp.bits);
+  const size_t pc_seg = (size_t)cdiv((uint64_t)cap, kPart) * ((size_t)1 << sp.bits);
   L.dk0 = take(N * 8);
   L.dk1 = take(N * 8);
   L.dv0 = take(N * 4);
@@ -733,10 +704,8 @@ Layout make_layout(int V, int ld, int64_t cap, int64_t nseg) {
   L.segk0 = take((size_t)cap * 4);
   L.segk1 = take((size_t)cap * 4);
   L.segv_alt = take((size_t)cap * 4);
-  L.hist = take(kMaxPasses * 1024 * 4);
-  L.digoff = take(kMaxPasses * 1024 * 4);
-  L.counters = take(kMaxPasses * 4);
-  L.lookback = take((lb_depth > lb_seg ? lb_depth : lb_seg) * 4 + 4);
+  L.pcount = take((pc_depth > pc_seg ? pc_depth : pc_seg) * 4 + 4);
+  L.dtotal = take(1024 * 4);
   L.seg_base = take(((size_t)V + 1) * 4);
   L.txv = take((size_t)V * 4);
   L.total = take(16);
@@ -755,30 +724,27 @@ T* at(void* ws, size_t off) {
 }
 
 // Stable LSD radix sort of (key, value) pairs on bits [0, bits), ping-pong
-// between buffer pair 0 and 1; returns the index (0/1) holding the result.
+// between buffer pair 0 and 1.  Per digit pass: per-partition digit counts,
+// their exclusive scan (per digit over the partitions, then over the
+// digits), and the ranking + scatter with those bases.
 template <typename K, int BITS>
 void radix_passes(K* k0, K* k1, uint32_t* v0, uint32_t* v1, uint32_t n, int passes, void* ws,
                   const Layout& L, hipStream_t s) {
   constexpr int R = 1 << BITS;
-  uint32_t* hist = at<uint32_t>(ws, L.hist);
-  uint32_t* off = at<uint32_t>(ws, L.digoff);
-  uint32_t* counters = at<uint32_t>(ws, L.counters);
-  uint32_t* lb = at<uint32_t>(ws, L.lookback);
+  uint32_t* cnt = at<uint32_t>(ws, L.pcount);
+  uint32_t* tot = at<uint32_t>(ws, L.dtotal);
   const uint32_t parts = cdiv(n, kPart);
-  launch_fill_u32(hist, 0u, (int64_t)passes * R, s);
-  launch_fill_u32(counters, 0u, kMaxPasses, s);
-  launch_fill_u32(lb, 0u, (int64_t)passes * parts * R, s);
-  const uint32_t hblocks = std::min<uint32_t>(cdiv(n, kBlock * 8), 2048u);
-  hipLaunchKernelGGL((k_histogram<K, BITS>), dim3(hblocks), dim3(kBlock), 0, s, k0, n, passes,
-                     hist);
-  hipLaunchKernelGGL((k_hist_scan<BITS>), dim3(1), dim3(kBlock), 0, s, hist, passes, off);
+  const uint32_t grid = (parts + 7) / 8 * 8;  // whole XCD rounds
   K* kb[2] = {k0, k1};
   uint32_t* vb[2] = {v0, v1};
   for (int p = 0; p < passes; ++p) {
     const int src = p & 1;
-    hipLaunchKernelGGL((k_onesweep<K, BITS>), dim3(parts), dim3(kBlock), 0, s, kb[src], vb[src],
-                       kb[src ^ 1], vb[src ^ 1], n, BITS * p, off + p * R,
-                       lb + (size_t)p * parts * R, counters + p);
+    hipLaunchKernelGGL((k_part_count<K, BITS>), dim3(grid), dim3(kBlock), 0, s, kb[src], n,
+                       BITS * p, parts, cnt);
+    hipLaunchKernelGGL(k_part_scan_rows, dim3(R), dim3(kBlock), 0, s, cnt, parts, tot);
+    hipLaunchKernelGGL((k_digit_scan<BITS>), dim3(1), dim3(kBlock), 0, s, tot);
+    hipLaunchKernelGGL((k_scatter_pass<K, BITS>), dim3(grid), dim3(kBlock), 0, s, kb[src],
+                       vb[src], kb[src ^ 1], vb[src ^ 1], n, BITS * p, parts, cnt, tot);
   }
 }
 

@@ -79,8 +79,8 @@ def test_binding_constants_match_header():
 
 
 def test_bin_sort_size_guard(lib_path):
-    """The radix sort's look-back words carry 30-bit prefix counts: the
-    sizes query (the same guard gs_bin_sort applies) refuses an instance
+    """The binning's 32-bit indices and offsets are kept clear of overflow:
+    the sizes query (the same guard gs_bin_sort applies) refuses an instance
     capacity or a number of (view, Gaussian) keys of 2^30 and accepts
     2^30 - 1."""
     import ctypes
