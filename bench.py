@@ -381,15 +381,21 @@ class CompactStep:
         gs.gs_gather_planes(self.ctx, self.src, self.idx, self.kept, self.dst)
 
 
-def time_steps(ts, steps, warmup):
+def time_steps(ts, steps, warmup, stages=None):
     """Warm up, then time exactly ``steps`` steps between two device
     synchronisations.  Returns (wall s, device s, stage times, per-step device
-    ms from HIP events recorded between the steps on the launch stream)."""
+    ms from HIP events recorded between the steps on the launch stream).
+    ``stages``: the stages bracketed with HIP events (None = all of them;
+    every bracket adds a small device-side gap, so the headline region times
+    only the kernels its roofline needs)."""
     torch = ts.torch
     for _ in range(warmup):
         ts.step()
     torch.cuda.synchronize()
-    ts.ctx.set_timing(True)
+    if stages is None:
+        ts.ctx.set_timing(True)
+    else:
+        ts.ctx.set_timing_stages(stages)
     ts.ctx.collect_timing()
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
     torch.cuda.synchronize()
@@ -753,10 +759,19 @@ def main():
     scene, cams, target_scene = scenes.workload_frame_300k(0, n=args.gaussians, n_views=args.views)
     ts = TrainStep(scene, cams, target_scene, tile_spans=not args.no_tile_spans)
     log(f"instances per step: {ts.r.forward(ts.g, ts.cams)['lists'].count}")
-    wall, dev_s, stages, per_step = time_steps(ts, args.steps, args.warmup)
+    # the headline region brackets only the two render kernels (the roofline's)
+    wall, dev_s, stages_r, per_step = time_steps(ts, args.steps, args.warmup,
+                                                 stages=["render_fwd", "render_bwd"])
     ms_per_step = wall / args.steps * 1e3
     value = args.steps / wall
     log(f"train step: {ms_per_step:.2f} ms ({value:.2f} it/s)")
+    # the per-stage breakdown from a second region with every stage bracketed
+    k_all = min(args.steps, 30)
+    _, _, stages_all, _ = time_steps(ts, k_all, 2)
+    stages = {k: (v[0] * args.steps / k_all, v[1] * args.steps // k_all)
+              for k, v in stages_all.items()}
+    for k in ("render_fwd", "render_bwd"):
+        stages[k] = stages_r[k]
     work = count_work(ts)
     dom, rf, summary = roofline(stages, ts, args.steps, work)
     stage_ms = {k: round(v[0] / args.steps, 4) for k, v in stages.items() if v[1] > 0}

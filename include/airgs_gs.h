@@ -237,6 +237,10 @@ size_t gs_render_bwd_workspace_size(int n_views, int ld, int64_t instances);
  *   (per-Gaussian sums of the backward's instance rows). */
 #define GS_STAGE_COUNT 18
 gs_status gs_set_timing(gs_ctx* ctx, int enable);
+/* Timing of the stages whose bit (1 << stage) is set only (0 = off): each
+ * pair of event records adds device-side gaps, so a timed region can bracket
+ * just the stages it needs. */
+gs_status gs_set_timing_mask(gs_ctx* ctx, uint32_t stage_mask);
 /* Sum of event-measured milliseconds and number of launches per stage since
  * the previous collection (host arrays of GS_STAGE_COUNT); blocks until the
  * recorded events have completed, then resets the counters. */

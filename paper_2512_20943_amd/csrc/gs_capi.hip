@@ -26,6 +26,7 @@ struct EventTimer final : gs::StageTimer {
   std::vector<hipEvent_t> pool;
   std::vector<Rec> recs;
   std::vector<size_t> open;
+  uint32_t mask = ~0u;  // stages that are timed
 
   hipEvent_t take() {
     if (!pool.empty()) {
@@ -38,13 +39,14 @@ struct EventTimer final : gs::StageTimer {
     return e;
   }
   void begin(int stage, hipStream_t s) override {
+    if (!(mask >> stage & 1u)) return;
     Rec r{stage, take(), take()};
     if (r.a) hipEventRecord(r.a, s);
     open.push_back(recs.size());
     recs.push_back(r);
   }
   void end(int stage, hipStream_t s) override {
-    (void)stage;
+    if (!(mask >> stage & 1u)) return;
     if (open.empty()) return;
     Rec& r = recs[open.back()];
     open.pop_back();
@@ -266,6 +268,14 @@ const char* gs_last_error(const gs_ctx* c) { return c ? c->err : g_err; }
 gs_status gs_set_timing(gs_ctx* c, int enable) {
   if (!c) return fail(nullptr, GS_ERR_INVALID_ARG, "ctx is NULL");
   c->timing = enable != 0;
+  c->timer.mask = ~0u;
+  return GS_OK;
+}
+
+gs_status gs_set_timing_mask(gs_ctx* c, uint32_t stage_mask) {
+  if (!c) return fail(nullptr, GS_ERR_INVALID_ARG, "ctx is NULL");
+  c->timing = stage_mask != 0;
+  c->timer.mask = stage_mask;
   return GS_OK;
 }
 

@@ -404,13 +404,21 @@ __global__ __launch_bounds__(64) void k_render_fwd_l1(
                                       n_contrib + pix * v, nullptr, &o, cnt);
 }
 
-// loss += (sum of the per-tile partials) / count, in one block.
+// loss += (sum of the per-tile partials) / count, in one block.  Each
+// thread keeps eight independent sums over a fixed stride pattern, so eight
+// loads are in flight at a time and the order of additions is fixed.
 __global__ __launch_bounds__(1024) void k_l1_tile_sum(const double* __restrict__ partial,
                                                       uint32_t n, double inv_count,
                                                       double* __restrict__ loss) {
   __shared__ double s[16];
-  double acc = 0.0;
-  for (uint32_t i = threadIdx.x; i < n; i += 1024) acc += partial[i];
+  double a[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  uint32_t i = threadIdx.x;
+  for (; i + 7 * 1024 < n; i += 8 * 1024) {
+#pragma unroll
+    for (int u = 0; u < 8; ++u) a[u] += partial[i + u * 1024];
+  }
+  for (int u = 0; i < n; i += 1024, ++u) a[u] += partial[i];
+  double acc = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
   for (int off = 32; off >= 1; off >>= 1) acc += __shfl_xor(acc, off, 64);
   if ((threadIdx.x & 63) == 0) s[threadIdx.x >> 6] = acc;
   __syncthreads();

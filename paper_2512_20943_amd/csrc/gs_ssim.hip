@@ -193,8 +193,15 @@ __global__ __launch_bounds__(1024) void k_sum_partials(const double* __restrict_
                                                        size_t nb, float lambda,
                                                        double* __restrict__ loss) {
   __shared__ double s[16];
-  double acc = 0.0;
-  for (size_t i = threadIdx.x; i < nb; i += 1024) acc += partial[i];
+  // eight independent sums per thread (fixed order, eight loads in flight)
+  double a[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  size_t i = threadIdx.x;
+  for (; i + 7 * 1024 < nb; i += 8 * 1024) {
+#pragma unroll
+    for (int u = 0; u < 8; ++u) a[u] += partial[i + u * 1024];
+  }
+  for (int u = 0; i < nb; i += 1024, ++u) a[u] += partial[i];
+  double acc = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
   for (int off = 32; off >= 1; off >>= 1) acc += __shfl_xor(acc, off, 64);
   if ((threadIdx.x & 63) == 0) s[threadIdx.x >> 6] = acc;
   __syncthreads();

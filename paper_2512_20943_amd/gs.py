@@ -187,6 +187,8 @@ def load() -> ctypes.CDLL:
                                           ctypes.c_size_t, c_void_p]
     lib.gs_render_fwd_batched.restype = c_int32
     lib.gs_set_timing.argtypes = [c_void_p, ctypes.c_int]
+    lib.gs_set_timing_mask.argtypes = [c_void_p, ctypes.c_uint32]
+    lib.gs_set_timing_mask.restype = c_int32
     lib.gs_set_work_counters.argtypes = [c_void_p, c_void_p]
     lib.gs_set_work_counters.restype = c_int32
     lib.gs_server_create.argtypes = [P(c_void_p), ctypes.c_int, P(GsSequence),
@@ -229,7 +231,7 @@ def exported_symbols():
             "gs_quantize_delta", "gs_apply_quantized_update", "gs_render_fwd_l1_workspace_size",
             "gs_render_fwd_l1", "gs_render_fwd_l1_noalloc", "gs_set_work_counters",
             "gs_peak_min_bytes", "gs_peak_run", "gs_server_create", "gs_server_destroy",
-            "gs_server_last_error", "gs_server_run", "gs_server_stats"]
+            "gs_server_last_error", "gs_server_run", "gs_server_stats", "gs_set_timing_mask"]
 
 
 def _ptr(t):
@@ -263,6 +265,14 @@ class Context:
 
     def set_timing(self, on: bool):
         self.check(self.lib.gs_set_timing(self.handle, 1 if on else 0))
+
+    def set_timing_stages(self, names):
+        """Time only the named stages (an empty list switches timing off)."""
+        mask = 0
+        for nm in names:
+            k = [self.lib.gs_stage_name(i).decode() for i in range(STAGE_COUNT)].index(nm)
+            mask |= 1 << k
+        self.check(self.lib.gs_set_timing_mask(self.handle, mask))
 
     def set_work_counters(self, counters):
         """counters: a zeroed int64 device tensor of WORK_COUNTERS values that
