@@ -1,5 +1,6 @@
 // C ABI of the rasterizer: argument validation, workspace accounting and
 // kernel launches.  No C++ exception crosses this boundary.
+#include <algorithm>
 #include <cstdarg>
 #include <cstdio>
 #include <cmath>
@@ -201,6 +202,13 @@ int64_t segments_of(const gs_camera* h, int V) {
   for (int v = 0; v < V; ++v)
     s += (int64_t)gs::tiles_across(h[v].width) * gs::tiles_across(h[v].height);
   return s;
+}
+
+int max_tiles_of(const gs_camera* h, int V) {
+  int64_t m = 0;
+  for (int v = 0; v < V; ++v)
+    m = std::max<int64_t>(m, (int64_t)gs::tiles_across(h[v].width) * gs::tiles_across(h[v].height));
+  return (int)m;
 }
 
 #define GS_TRY(expr)              \
@@ -411,7 +419,7 @@ gs_status gs_bin_sort(gs_ctx* c, const gs_projected* proj, const gs_camera* ch,
                 (long long)lists->capacity, (long long)V * proj->ld, (long long)nseg);
   if (!ws) return fail(c, GS_ERR_INVALID_ARG, "workspace is NULL");
   GS_TRY(check_ws_align(c, ws));
-  gs::BinSortPlan plan{V, proj->n, proj->ld, lists->capacity, nseg};
+  gs::BinSortPlan plan{V, proj->n, proj->ld, lists->capacity, nseg, max_tiles_of(ch, V)};
   const size_t need = gs::bin_sort_workspace_bytes(V, proj->ld, lists->capacity, nseg);
   if (ws_bytes < need)
     return fail(c, GS_ERR_OOM, "bin_sort workspace %zu < %zu bytes", ws_bytes, need);

@@ -93,6 +93,7 @@ struct BinSortPlan {
   int ld;
   int64_t capacity;
   int64_t n_segments;
+  int max_tiles;  // most tiles of one view
 };
 size_t bin_sort_workspace_bytes(int n_views, int ld, int64_t capacity, int64_t n_segments);
 // Stage 1 reduces the visible pairs' depth-bit range and instance count

@@ -5,19 +5,24 @@
 // same LDS-resident LSD radix sort (stable, 8- or 9-bit digits; per digit,
 // per-partition counts, their scan, then LDS ranking and an LDS-staged
 // scatter with those bases; partitions are laid out XCD by XCD, so each of
-// the 8 L2s sees a contiguous range):
-//   1. the (view, depth) keys of the V*n projected Gaussians -- 32-bit keys
-//      view * span + (depth bits - min) when the views times the visible
-//      depth-bit range fit (a first pass reduces that range together with
-//      the instance count, which the host reads back), 64-bit keys
-//      (view << 32 | depth bits) otherwise;
-//   2. after emitting every Gaussian's tiles in that depth order, the
-//      instances by their segment id only.
+// the 8 L2s sees a contiguous range).  Both sorts run inside views: the
+// elements of view v stay in a range of their own whose start is known
+// before the sort, so the digits cover only what varies inside a view:
+//   1. the depth keys of the V*n projected Gaussians (only the visible
+//      pairs, gathered view by view), on the bits of the visible depth-bit
+//      range (a first pass reduces that range together with the instance
+//      count, which the host reads back); the key also carries the view
+//      above those bits, in 32 bits when it fits, else in the high word of
+//      a 64-bit key;
+//   2. after emitting every Gaussian's tiles in that depth order (views in
+//      order), the instances by their tile index inside the view, on the
+//      bits of the largest view's tile count; the last pass turns tile
+//      indices into segment ids.
 // Stability of (2) keeps the depth order of (1) inside each segment, and
 // stability of (1) keeps ascending ids for equal depths, so the result is
 // the (segment, depth, id) order -- while the per-instance sort moves only
-// ceil(log2(segments)/9) digits of 32-bit keys instead of 5-7 digits of
-// 64-bit keys.
+// ceil(log2(tiles per view)/9) digits of 32-bit keys instead of 5-7 digits
+// of 64-bit keys.
 #include <algorithm>
 
 #include "gs_internal.h"
@@ -57,81 +62,159 @@ __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t x, uint32_t* s
   return pre + v - x;
 }
 
-// ------------------------------------------------------------ radix sort
-// Per-partition digit counts, digit-major: cnt[d * parts + p].
-template <typename K, int BITS>
-__global__ __launch_bounds__(kBlock) void k_part_count(const K* __restrict__ keys, uint32_t n,
-                                                       int shift, uint32_t parts,
-                                                       uint32_t* __restrict__ cnt) {
-  constexpr int R = 1 << BITS;
-  __shared__ uint32_t h[R];
-  for (int t = threadIdx.x; t < R; t += kBlock) h[t] = 0;
-  __syncthreads();
-  // XCD-aware: workgroup b runs on XCD b % 8; each XCD takes a contiguous
-  // range of partitions, so one L2 merges the count rows' neighbouring words
-  const uint32_t per = (parts + 7) / 8;
-  const uint32_t part = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
-  if (part >= parts) return;
-  const uint32_t base = part * (uint32_t)kPart;
-  K kk[kItems];
-#pragma unroll
-  for (int j = 0; j < kItems; ++j) {
-    const uint32_t i = base + (uint32_t)j * kBlock + threadIdx.x;
-    kk[j] = i < n ? keys[i] : K(0);
-  }
-#pragma unroll
-  for (int j = 0; j < kItems; ++j) {
-    const uint32_t i = base + (uint32_t)j * kBlock + threadIdx.x;
-    if (i < n) atomicAdd(&h[digit_of<BITS>(kk[j], shift)], 1u);
-  }
-  __syncthreads();
-  for (int t = threadIdx.x; t < R; t += kBlock) cnt[(size_t)t * parts + part] = h[t];
-}
-
-// Exclusive scan of each digit's row of partition counts (one block per
-// digit); the row total goes to tot[d].
-__global__ __launch_bounds__(kBlock) void k_part_scan_rows(uint32_t* __restrict__ cnt,
-                                                           uint32_t parts,
-                                                           uint32_t* __restrict__ tot) {
-  constexpr int kIpt = 16;  // consecutive counts per thread
+// Exclusive scan of row[0, n) in place by one block, 16 consecutive values
+// per thread per round; returns the total (to every thread).
+__device__ uint32_t block_scan_inplace(uint32_t* __restrict__ row, uint32_t n) {
+  constexpr int kIpt = 16;
   __shared__ uint32_t s_wave[4];
-  uint32_t* row = cnt + (size_t)blockIdx.x * parts;
   uint32_t carry = 0;
-  for (uint32_t b0 = 0; b0 < parts; b0 += kBlock * kIpt) {
+  for (uint32_t b0 = 0; b0 < n; b0 += kBlock * kIpt) {
     const uint32_t e0 = b0 + threadIdx.x * kIpt;
     uint32_t x[kIpt], sum = 0;
 #pragma unroll
     for (int i = 0; i < kIpt; ++i) {
-      x[i] = e0 + i < parts ? row[e0 + i] : 0u;
+      x[i] = e0 + i < n ? row[e0 + i] : 0u;
       sum += x[i];
     }
     uint32_t t;
     uint32_t run = carry + block_exclusive_scan(sum, s_wave, &t);
 #pragma unroll
     for (int i = 0; i < kIpt; ++i) {
-      if (e0 + i < parts) row[e0 + i] = run;
+      if (e0 + i < n) row[e0 + i] = run;
       run += x[i];
     }
     carry += t;
   }
-  if (threadIdx.x == 0) tot[blockIdx.x] = carry;
+  return carry;
 }
 
-// Exclusive scan of the digit totals in place (one block).
+// ------------------------------------------------------------ radix sort
+// Every sort here orders keys inside views: view v's elements occupy
+// [start(v), start(v + 1)) of the array before and after the sort, with
+// start(v) = vstart[v * vstride] for v < V and start(V) = n.  Each view's
+// range is cut into partitions of at most kPart keys (none straddles two
+// views), so the digits only cover the bits that vary inside a view.
+
+__device__ __forceinline__ uint32_t view_start(const uint32_t* __restrict__ vstart,
+                                               uint32_t vstride, int V, uint32_t n, int v) {
+  return v < V ? vstart[(size_t)v * vstride] : n;
+}
+
+// First partition of each view, pfirst[v] (v < V), and the number of
+// partitions, pfirst[V].  One block.
+__global__ __launch_bounds__(kBlock) void k_part_first(const uint32_t* __restrict__ vstart,
+                                                       uint32_t vstride, int V, uint32_t n,
+                                                       uint32_t* __restrict__ pfirst) {
+  __shared__ uint32_t s_wave[4];
+  uint32_t carry = 0;
+  for (int v0 = 0; v0 < V; v0 += kBlock) {
+    const int v = v0 + (int)threadIdx.x;
+    uint32_t np = 0;
+    if (v < V) {
+      const uint32_t len = view_start(vstart, vstride, V, n, v + 1) -
+                           view_start(vstart, vstride, V, n, v);
+      np = (len + kPart - 1) / kPart;
+    }
+    uint32_t tot;
+    const uint32_t e = block_exclusive_scan(np, s_wave, &tot);
+    if (v < V) pfirst[v] = carry + e;
+    carry += tot;
+  }
+  if (threadIdx.x == 0) pfirst[V] = carry;
+}
+
+// Partition p's {view, first element, end, first partition of its view},
+// one thread per partition.
+__global__ __launch_bounds__(kBlock) void k_part_desc(const uint32_t* __restrict__ vstart,
+                                                      uint32_t vstride, int V, uint32_t n,
+                                                      const uint32_t* __restrict__ pfirst,
+                                                      uint4* __restrict__ desc) {
+  const uint32_t p = blockIdx.x * kBlock + threadIdx.x;
+  if (p >= pfirst[V]) return;
+  int lo = 0, hi = V - 1;  // last view whose first partition is <= p
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (pfirst[mid] <= p) lo = mid; else hi = mid - 1;
+  }
+  const uint32_t pf = pfirst[lo];
+  const uint32_t b = view_start(vstart, vstride, V, n, lo) + (p - pf) * (uint32_t)kPart;
+  const uint32_t e = view_start(vstart, vstride, V, n, lo + 1);
+  desc[p] = make_uint4((uint32_t)lo, b, min(b + (uint32_t)kPart, e), pf);
+}
+
+// XCD-aware partition of workgroup b: workgroup b runs on XCD b % 8, and
+// each XCD takes a contiguous range of partitions, so one L2 merges the
+// neighbouring words of the count rows and the adjacent output runs of a
+// digit.
+__device__ __forceinline__ uint32_t xcd_part(uint32_t pmax) {
+  const uint32_t per = (pmax + 7) / 8;
+  return (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+}
+
+// Per-partition digit counts, digit-major: cnt[d * pmax + p].
+template <typename K, int BITS>
+__global__ __launch_bounds__(kBlock) void k_part_count(const K* __restrict__ keys, int shift,
+                                                       uint32_t pmax,
+                                                       const uint32_t* __restrict__ n_parts,
+                                                       const uint4* __restrict__ desc,
+                                                       uint32_t* __restrict__ cnt) {
+  constexpr int R = 1 << BITS;
+  __shared__ uint32_t h[R];
+  const uint32_t part = xcd_part(pmax);
+  if (part >= *n_parts) return;
+  for (int t = threadIdx.x; t < R; t += kBlock) h[t] = 0;
+  __syncthreads();
+  const uint4 ds = desc[part];
+  K kk[kItems];
+#pragma unroll
+  for (int j = 0; j < kItems; ++j) {
+    const uint32_t i = ds.y + (uint32_t)j * kBlock + threadIdx.x;
+    kk[j] = i < ds.z ? keys[i] : K(0);
+  }
+#pragma unroll
+  for (int j = 0; j < kItems; ++j) {
+    const uint32_t i = ds.y + (uint32_t)j * kBlock + threadIdx.x;
+    if (i < ds.z) atomicAdd(&h[digit_of<BITS>(kk[j], shift)], 1u);
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < R; t += kBlock) cnt[(size_t)t * pmax + part] = h[t];
+}
+
+// Exclusive scan of each digit's row of partition counts over all
+// partitions (one block per digit); the row total goes to tot[d].
+__global__ __launch_bounds__(kBlock) void k_part_scan_rows(uint32_t* __restrict__ cnt,
+                                                           uint32_t pmax,
+                                                           const uint32_t* __restrict__ n_parts,
+                                                           uint32_t* __restrict__ tot) {
+  const uint32_t t = block_scan_inplace(cnt + (size_t)blockIdx.x * pmax, *n_parts);
+  if (threadIdx.x == 0) tot[blockIdx.x] = t;
+}
+
+// Start of each digit inside each view (one block per view):
+// dstart[v * R + d] = start(v) + the view's keys with a smaller digit, the
+// view's count of digit d being the difference of the scanned row at its
+// first partition and at the next view's.
 template <int BITS>
-__global__ __launch_bounds__(kBlock) void k_digit_scan(uint32_t* __restrict__ tot) {
+__global__ __launch_bounds__(kBlock) void k_view_digit_scan(
+    const uint32_t* __restrict__ cnt, uint32_t pmax, const uint32_t* __restrict__ tot,
+    const uint32_t* __restrict__ pfirst, const uint32_t* __restrict__ vstart, uint32_t vstride,
+    int V, uint32_t n, uint32_t* __restrict__ dstart) {
   constexpr int R = 1 << BITS, DPT = R / kBlock;
   __shared__ uint32_t s_wave[4];
+  const int v = blockIdx.x;
+  const uint32_t P = pfirst[V], a = pfirst[v], b = pfirst[v + 1];
   uint32_t x[DPT], sum = 0;
 #pragma unroll
   for (int i = 0; i < DPT; ++i) {
-    x[i] = tot[threadIdx.x * DPT + i];
+    const int d = threadIdx.x * DPT + i;
+    const uint32_t* row = cnt + (size_t)d * pmax;
+    x[i] = a == b ? 0u : (b < P ? row[b] : tot[d]) - row[a];
     sum += x[i];
   }
-  uint32_t run = block_exclusive_scan(sum, s_wave, nullptr);
+  uint32_t run = view_start(vstart, vstride, V, n, v) + block_exclusive_scan(sum, s_wave, nullptr);
 #pragma unroll
   for (int i = 0; i < DPT; ++i) {
-    tot[threadIdx.x * DPT + i] = run;
+    dstart[(size_t)v * R + threadIdx.x * DPT + i] = run;
     run += x[i];
   }
 }
@@ -139,58 +222,60 @@ __global__ __launch_bounds__(kBlock) void k_digit_scan(uint32_t* __restrict__ to
 // One digit pass with bases from the scans: each wave ranks its keys stably
 // by digit with ballots (lanes holding the same digit) and per-wave
 // counters in LDS, the block scatters them through LDS into digit order,
-// and the global writes come out as runs at (digit start + this
-// partition's prefix).  No partition waits for another.
-template <typename K, int BITS>
+// and the global writes come out as runs at (the view's digit start + this
+// partition's prefix inside the view).  No partition waits for another.
+// With VALS the values move with the keys; without, the keys carry their
+// value in the bits below `shift` of the first pass, and a pass given vout
+// splits each key on the way out: value = key & umask to vout, key >> ushift
+// to kout.  add (optional, last pass): add[view] is added to every key
+// written.
+template <typename K, int BITS, bool VALS>
 __global__ __launch_bounds__(kBlock) void k_scatter_pass(
     const K* __restrict__ kin, const uint32_t* __restrict__ vin, K* __restrict__ kout,
-    uint32_t* __restrict__ vout, uint32_t n, int shift, uint32_t parts,
-    const uint32_t* __restrict__ pbase, const uint32_t* __restrict__ dstart_g) {
+    uint32_t* __restrict__ vout, int shift, uint32_t pmax, const uint32_t* __restrict__ n_parts,
+    const uint4* __restrict__ desc, const uint32_t* __restrict__ pbase,
+    const uint32_t* __restrict__ dstart_v, const uint32_t* __restrict__ add, int ushift,
+    uint32_t umask) {
   constexpr int R = 1 << BITS, DPT = R / kBlock;
   __shared__ uint32_t s_wh[4][R];
   __shared__ uint32_t s_dstart[R];
   __shared__ uint32_t s_gbase[R];
   __shared__ uint32_t s_wave[4];
   __shared__ K s_k[kPart];
-  __shared__ uint32_t s_v[kPart];
+  __shared__ uint32_t s_v[VALS ? kPart : 1];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  // XCD-aware as in k_part_count: neighbouring partitions, whose runs of
-  // one digit are adjacent in the output, share an L2
-  const uint32_t per = (parts + 7) / 8;
-  const uint32_t part = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
-  if (part >= parts) return;
+  const uint32_t part = xcd_part(pmax);
+  if (part >= *n_parts) return;
+  const uint4 ds = desc[part];
+  const uint32_t view = ds.x, end = ds.z, pf = ds.w;
   for (int t = tid; t < 4 * R; t += kBlock) (&s_wh[0][0])[t] = 0;
   __syncthreads();
-  const uint32_t base = part * (uint32_t)kPart + (uint32_t)wave * 64u * kItems;
+  const uint32_t base = ds.y + (uint32_t)wave * 64u * kItems;
   K k[kItems];
   uint32_t val[kItems], rank[kItems], dig[kItems];
-  const bool full = part * (uint64_t)kPart + kPart <= n;
+  const bool full = end - ds.y == (uint32_t)kPart;
   if (full) {
     const K* kb = kin + base + lane;
-    const uint32_t* vb = vin + base + lane;
 #pragma unroll
-    for (int j = 0; j < kItems; ++j) {
-      k[j] = kb[j * 64];
-      val[j] = vb[j * 64];
+    for (int j = 0; j < kItems; ++j) k[j] = kb[j * 64];
+    if constexpr (VALS) {
+      const uint32_t* vb = vin + base + lane;
+#pragma unroll
+      for (int j = 0; j < kItems; ++j) val[j] = vb[j * 64];
     }
   } else {
 #pragma unroll
     for (int j = 0; j < kItems; ++j) {
       const uint32_t idx = base + j * 64 + lane;
-      if (idx < n) {
-        k[j] = kin[idx];
-        val[j] = vin[idx];
-      } else {
-        k[j] = 0;
-        val[j] = 0;
-      }
+      k[j] = idx < end ? kin[idx] : K(0);
+      if constexpr (VALS) val[j] = idx < end ? vin[idx] : 0u;
     }
   }
   const uint32_t lower_lo = lane >= 32 ? ~0u : ((1u << lane) - 1u);
   const uint32_t lower_hi = lane <= 32 ? 0u : (~0u >> (64 - lane));
 #pragma unroll
   for (int j = 0; j < kItems; ++j) {
-    const bool valid = full || base + j * 64 + lane < n;
+    const bool valid = full || base + j * 64 + lane < end;
     const uint32_t d = valid ? digit_of<BITS>(k[j], shift) : 0u;
     const uint64_t vmask = wave_ballot(valid);
     uint32_t pl = (uint32_t)vmask, ph = (uint32_t)(vmask >> 32);
@@ -230,28 +315,43 @@ __global__ __launch_bounds__(kBlock) void k_scatter_pass(
 #pragma unroll
     for (int i = 0; i < DPT; ++i) {
       const int d = tid * DPT + i;
+      const uint32_t* row = pbase + (size_t)d * pmax;
       s_dstart[d] = dstart;
-      s_gbase[d] = dstart_g[d] + pbase[(size_t)d * parts + part] - dstart;
+      s_gbase[d] = dstart_v[(size_t)view * R + d] + (row[part] - row[pf]) - dstart;
       dstart += run[i];
     }
   }
   __syncthreads();
 #pragma unroll
   for (int j = 0; j < kItems; ++j) {
-    if (base + j * 64 + lane < n) {
+    if (base + j * 64 + lane < end) {
       const uint32_t lp = s_dstart[dig[j]] + s_wh[wave][dig[j]] + rank[j];
       s_k[lp] = k[j];
-      s_v[lp] = val[j];
+      if constexpr (VALS) s_v[lp] = val[j];
     }
   }
   __syncthreads();
-  const uint32_t start = part * (uint32_t)kPart;
-  const uint32_t nvalid = (n - start) < (uint32_t)kPart ? (n - start) : (uint32_t)kPart;
-  for (uint32_t t = tid; t < nvalid; t += kBlock) {
-    const K kk = s_k[t];
-    const uint32_t g = s_gbase[digit_of<BITS>(kk, shift)] + t;
-    kout[g] = kk;
-    vout[g] = s_v[t];
+  const uint32_t nvalid = end - ds.y;
+  const K kadd = add ? (K)add[view] : K(0);
+  if constexpr (VALS) {
+    for (uint32_t t = tid; t < nvalid; t += kBlock) {
+      const K kk = s_k[t];
+      const uint32_t g = s_gbase[digit_of<BITS>(kk, shift)] + t;
+      kout[g] = kk + kadd;
+      vout[g] = s_v[t];
+    }
+  } else if (vout) {
+    for (uint32_t t = tid; t < nvalid; t += kBlock) {
+      const K kk = s_k[t];
+      const uint32_t g = s_gbase[digit_of<BITS>(kk, shift)] + t;
+      kout[g] = (kk >> ushift) + kadd;
+      vout[g] = (uint32_t)kk & umask;
+    }
+  } else {
+    for (uint32_t t = tid; t < nvalid; t += kBlock) {
+      const K kk = s_k[t];
+      kout[s_gbase[digit_of<BITS>(kk, shift)] + t] = kk + kadd;
+    }
   }
 }
 
@@ -273,13 +373,15 @@ __global__ void k_view_info(const gs_camera* __restrict__ cams, int V, uint32_t*
 // Per chunk of kCountChunk Gaussians of one view (grid x; views on grid y,
 // looping past 65535 of them), chunk c = v * gridDim.x + blockIdx.x: the
 // range of the depth bits of its visible pairs and their instance count,
-// part[c] = {min bits, max bits, count lo, count hi}, and the number of its
-// visible pairs, vis[c].  Thread t owns Gaussians 8t .. 8t + 7.
+// part[c] = {min bits, max bits, count lo, count hi}, the number of its
+// visible pairs, vis[c], and the count's low word again, icnt[c] (scanned,
+// it places each view's instances).  Thread t owns Gaussians 8t .. 8t + 7.
 __global__ __launch_bounds__(kBlock) void k_depth_range(int n, int ld, int V,
                                                         const uint32_t* __restrict__ depth_bits,
                                                         const int32_t* __restrict__ tiles,
                                                         uint4* __restrict__ part,
-                                                        uint32_t* __restrict__ vis) {
+                                                        uint32_t* __restrict__ vis,
+                                                        uint32_t* __restrict__ icnt) {
   __shared__ uint32_t s_min[4], s_max[4], s_cnt[4];
   __shared__ unsigned long long s_sum[4];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -321,6 +423,7 @@ __global__ __launch_bounds__(kBlock) void k_depth_range(int n, int ld, int V,
       const size_t c = (size_t)v * gridDim.x + blockIdx.x;
       part[c] = make_uint4(mn, mx, (uint32_t)sum, (uint32_t)(sum >> 32));
       vis[c] = (s_cnt[0] + s_cnt[1]) + (s_cnt[2] + s_cnt[3]);
+      icnt[c] = (uint32_t)sum;
     }
     __syncthreads();
   }
@@ -364,174 +467,163 @@ __global__ __launch_bounds__(kBlock) void k_stats_reduce(const uint4* __restrict
 
 // Keys of the visible (view, Gaussian) pairs only, in (view, Gaussian)
 // order: chunk c (as in k_depth_range) writes its visible pairs from
-// chunk_off[c] on.  KeyOf(v, bits) gives the key.
+// chunk_off[c] on.  KeyOf(v, bits) gives the key; the value is the
+// Gaussian id, with the pair's tile count above bit cpack when cpack >= 0.
 template <typename K, typename KeyOf>
 __device__ __forceinline__ void visible_keys(int n, int ld, int V,
                                              const uint32_t* __restrict__ depth_bits,
                                              const int32_t* __restrict__ tiles,
                                              const uint32_t* __restrict__ chunk_off, KeyOf key,
-                                             K* __restrict__ keys, uint32_t* __restrict__ vals) {
+                                             int cpack, K* __restrict__ keys,
+                                             uint32_t* __restrict__ vals) {
   __shared__ uint32_t s_wave[4];
   for (int v = blockIdx.y; v < V; v += gridDim.y) {
     const int32_t* tv = tiles + (size_t)v * ld;
     const uint32_t* dv = depth_bits + (size_t)v * ld;
     const uint32_t i0 = blockIdx.x * (uint32_t)kCountChunk + threadIdx.x * kCountItems;
-    uint32_t mask = 0, c = 0;
+    uint32_t c = 0, t[kCountItems];
 #pragma unroll
     for (int j = 0; j < kCountItems; ++j) {
       const uint32_t i = i0 + j;
-      if (i < (uint32_t)n && tv[i] > 0) {
-        mask |= 1u << j;
-        ++c;
-      }
+      t[j] = i < (uint32_t)n ? (uint32_t)max(tv[i], 0) : 0u;
+      c += t[j] > 0 ? 1u : 0u;
     }
     uint32_t r = chunk_off[(size_t)v * gridDim.x + blockIdx.x] +
                  block_exclusive_scan(c, s_wave, nullptr);
 #pragma unroll
     for (int j = 0; j < kCountItems; ++j) {
-      if (mask & (1u << j)) {
+      if (t[j] > 0) {
         keys[r] = key((uint32_t)v, dv[i0 + j]);
-        vals[r] = i0 + j;
+        vals[r] = cpack >= 0 ? (i0 + j) | (t[j] << cpack) : i0 + j;
         ++r;
       }
     }
   }
 }
 
-// 32-bit (view, depth) keys when they fit: view * span + (bits - min bits).
+// 32-bit (view, depth) keys when they fit: view << vshift | (bits - min
+// bits), vshift the bits of the visible depth-bit range.
 __global__ __launch_bounds__(kBlock) void k_depth_keys32(int n, int ld, int V,
                                                          const uint32_t* __restrict__ depth_bits,
                                                          const int32_t* __restrict__ tiles,
                                                          const uint32_t* __restrict__ chunk_off,
-                                                         uint32_t dmin, uint32_t span,
+                                                         uint32_t dmin, uint32_t vshift,
+                                                         int cpack,
                                                          uint32_t* __restrict__ keys,
                                                          uint32_t* __restrict__ vals) {
-  visible_keys<uint32_t>(n, ld, V, depth_bits, tiles, chunk_off,
-                         [=](uint32_t v, uint32_t d) { return v * span + (d - dmin); }, keys,
-                         vals);
+  visible_keys<uint32_t>(
+      n, ld, V, depth_bits, tiles, chunk_off,
+      [=](uint32_t v, uint32_t d) { return (uint32_t)((uint64_t)v << vshift) | (d - dmin); },
+      cpack, keys, vals);
 }
 
-// View of a depth-sorted key: the high word of a 64-bit key, key / span of
-// a 32-bit one.
+// View of a depth-sorted key: the high word of a 64-bit key, the bits from
+// vshift up of a 32-bit one.
 __device__ __forceinline__ uint32_t view_of(uint64_t key, uint32_t) {
   return (uint32_t)(key >> 32);
 }
-__device__ __forceinline__ uint32_t view_of(uint32_t key, uint32_t span) { return key / span; }
+__device__ __forceinline__ uint32_t view_of(uint32_t key, uint32_t vshift) {
+  return (uint32_t)((uint64_t)key >> vshift);
+}
 
-// 64-bit (view << 32 | depth bits) keys otherwise.
+// 64-bit (view << 32 | bits - min bits) keys otherwise.
 __global__ __launch_bounds__(kBlock) void k_depth_keys(int n, int ld, int V,
                                                        const uint32_t* __restrict__ depth_bits,
                                                        const int32_t* __restrict__ tiles,
                                                        const uint32_t* __restrict__ chunk_off,
+                                                       uint32_t dmin, int cpack,
                                                        uint64_t* __restrict__ keys,
                                                        uint32_t* __restrict__ vals) {
-  visible_keys<uint64_t>(n, ld, V, depth_bits, tiles, chunk_off,
-                         [](uint32_t v, uint32_t d) { return ((uint64_t)v << 32) | d; }, keys,
-                         vals);
+  visible_keys<uint64_t>(
+      n, ld, V, depth_bits, tiles, chunk_off,
+      [=](uint32_t v, uint32_t d) { return ((uint64_t)v << 32) | (d - dmin); }, cpack, keys,
+      vals);
 }
 
-// Instance count of each depth-sorted entry, and partial sums per chunk.
+// Instance count of each depth-sorted entry and the sums per block of
+// kBlock entries: from the value's bits above cpack when the count travels
+// there (cpack >= 0), else from tiles_touched (kept in cnt for the emit).
 template <typename K>
-__global__ __launch_bounds__(kBlock) void k_count_reduce(uint32_t N, int ld, uint32_t span,
+__global__ __launch_bounds__(kBlock) void k_count_reduce(uint32_t N, int ld, uint32_t vshift,
                                                          const K* __restrict__ keys,
                                                          const uint32_t* __restrict__ vals,
                                                          const int32_t* __restrict__ tiles,
-                                                         uint32_t* __restrict__ cnt,
+                                                         int cpack, uint32_t* __restrict__ cnt,
                                                          uint32_t* __restrict__ chunk_sums) {
   __shared__ uint32_t s_wave[4];
-  const uint32_t c0 = blockIdx.x * (uint32_t)kCountChunk;
-  uint32_t acc = 0;
-#pragma unroll
-  for (int j = 0; j < kCountItems; ++j) {
-    const uint32_t e = c0 + j * kBlock + threadIdx.x;
-    if (e < N) {
-      const uint32_t v = view_of(keys[e], span);
-      const uint32_t c = (uint32_t)tiles[(size_t)v * ld + vals[e]];
+  const uint32_t e = blockIdx.x * kBlock + threadIdx.x;
+  uint32_t c = 0;
+  if (e < N) {
+    if (cpack >= 0) {
+      c = vals[e] >> cpack;
+    } else {
+      const uint32_t v = view_of(keys[e], vshift);
+      c = (uint32_t)tiles[(size_t)v * ld + vals[e]];
       cnt[e] = c;
-      acc += c;
     }
   }
   uint32_t tot;
-  block_exclusive_scan(acc, s_wave, &tot);
+  block_exclusive_scan(c, s_wave, &tot);
   if (threadIdx.x == 0) chunk_sums[blockIdx.x] = tot;
 }
 
-// Exclusive scan of the chunk sums in place (one block); total to *total.
+// Exclusive scan of sums[0, nb) in place (one block); total to *total.
 __global__ __launch_bounds__(kBlock) void k_chunk_scan(uint32_t* __restrict__ sums, uint32_t nb,
                                                        uint32_t* __restrict__ total) {
-  __shared__ uint32_t s_wave[4];
-  uint32_t carry = 0;
-  for (uint32_t b0 = 0; b0 < nb; b0 += kBlock) {
-    const uint32_t b = b0 + threadIdx.x;
-    const uint32_t x = b < nb ? sums[b] : 0u;
-    uint32_t tot;
-    const uint32_t e = block_exclusive_scan(x, s_wave, &tot);
-    if (b < nb) sums[b] = carry + e;
-    carry += tot;
-  }
-  if (threadIdx.x == 0) *total = carry;
+  const uint32_t t = block_scan_inplace(sums, nb);
+  if (threadIdx.x == 0) *total = t;
 }
 
-// Exclusive offsets of every entry: chunk offset + scan inside the chunk.
-// Thread t of a block owns entries c0 + 16t .. c0 + 16t + 15.
-__global__ __launch_bounds__(kBlock) void k_count_scan(uint32_t N, const uint32_t* __restrict__ cnt,
-                                                       const uint32_t* __restrict__ chunk_off,
-                                                       uint32_t* __restrict__ offs) {
-  __shared__ uint32_t s_wave[4];
-  const uint32_t e0 = blockIdx.x * (uint32_t)kCountChunk + threadIdx.x * kCountItems;
-  uint32_t c[kCountItems];
-  uint32_t acc = 0;
-#pragma unroll
-  for (int j = 0; j < kCountItems; ++j) {
-    c[j] = (e0 + j < N) ? cnt[e0 + j] : 0u;
-    acc += c[j];
-  }
-  uint32_t run = chunk_off[blockIdx.x] + block_exclusive_scan(acc, s_wave, nullptr);
-#pragma unroll
-  for (int j = 0; j < kCountItems; ++j) {
-    if (e0 + j < N) offs[e0 + j] = run;
-    run += c[j];
-  }
-}
-
-// Emit (segment, Gaussian id) for each tile of each depth-sorted entry, row
-// by row over its tile rectangle, or over its per-row spans when the record
-// carries them (the rectangle and spans come from the record's words 12, 13
-// and 15); optionally record where each (view, Gaussian) starts in this
-// order.  Each wave takes 64 consecutive entries,
-// whose instances form one contiguous output range, and spreads that range
-// over its lanes (instance f on lane f mod 64), so that large and small
-// rectangles balance and the stores coalesce.
+// Emit (tile of the view, Gaussian id) for each tile of each depth-sorted
+// entry, row by row over its tile rectangle, or over its per-row spans when
+// the record carries them (the rectangle and spans come from the record's
+// words 12, 13 and 15); optionally record where each (view, Gaussian)
+// starts in this order.  Each wave takes 64 consecutive entries, whose
+// instances form one contiguous output range, and spreads that range over
+// its lanes (instance f on lane f mod 64), so that large and small
+// rectangles balance and the stores coalesce.  With pack >= 0 each
+// instance is one word, tile << pack | id, in seg_out (id_out unused).
 template <typename K>
-__global__ __launch_bounds__(kBlock) void k_emit(uint32_t N, int ld, uint32_t span,
+__global__ __launch_bounds__(kBlock) void k_emit(uint32_t N, int ld, uint32_t vshift,
                                                  const K* __restrict__ keys,
                                                  const uint32_t* __restrict__ vals,
-                                                 const uint32_t* __restrict__ cnt,
-                                                 const uint32_t* __restrict__ offs,
-                                                 const uint32_t* __restrict__ seg_base,
+                                                 const uint32_t* __restrict__ cnt, int cpack,
+                                                 const uint32_t* __restrict__ chunk_off,
                                                  const int32_t* __restrict__ txv,
                                                  uint32_t* __restrict__ seg_out,
                                                  uint32_t* __restrict__ id_out,
                                                  uint32_t* __restrict__ gv_base,
-                                                 uint32_t* __restrict__ splat_words) {
+                                                 uint32_t* __restrict__ splat_words,
+                                                 int pack) {
   __shared__ uint32_t s_pre[4][64];
-  __shared__ uint32_t s_seg0[4][64];  // segment of the rectangle's first tile
+  __shared__ uint32_t s_seg0[4][64];  // the rectangle's first tile in its view
   __shared__ uint32_t s_id[4][64];
   __shared__ uint32_t s_w[4][64];     // rectangle width in tiles | kSpanFlag
   __shared__ uint32_t s_sp[4][64];    // per-row spans (record word 15)
   __shared__ uint32_t s_row[4][64];   // tiles per view row
+  __shared__ uint32_t s_bwave[4];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const uint32_t e = blockIdx.x * kBlock + threadIdx.x;
-  uint32_t c = 0, o0 = 0;
+  uint32_t c = 0, g = 0;
   if (e < N) {
-    c = cnt[e];
-    o0 = offs[e];
+    const uint32_t w = vals[e];
+    if (cpack >= 0) {
+      c = w >> cpack;
+      g = w & ((1u << cpack) - 1u);
+    } else {
+      c = cnt[e];
+      g = w;
+    }
+  }
+  // this entry's first instance: the block's offset + the scan inside it
+  const uint32_t o0 = chunk_off[blockIdx.x] + block_exclusive_scan(c, s_bwave, nullptr);
+  if (e < N) {
     if (c > 0) {
-      const uint32_t v = view_of(keys[e], span), g = vals[e];
+      const uint32_t v = view_of(keys[e], vshift);
       uint32_t* rw = splat_words + ((size_t)v * ld + g) * (4 * kSplatF4) + 12;
       const uint4 q3 = *reinterpret_cast<const uint4*>(rw);  // o, w | flag, e, spans
       const uint32_t tx = (uint32_t)txv[v];
-      s_seg0[wave][lane] = seg_base[v] + (q3.x >> 16) * tx + (q3.x & 0xFFFFu);
+      s_seg0[wave][lane] = (q3.x >> 16) * tx + (q3.x & 0xFFFFu);
       s_id[wave][lane] = g;
       s_w[wave][lane] = q3.y;
       s_sp[wave][lane] = q3.w;
@@ -572,8 +664,13 @@ __global__ __launch_bounds__(kBlock) void k_emit(uint32_t N, int ld, uint32_t sp
       dy = l / w;
       dx = l - dy * w;
     }
-    seg_out[first + f] = s_seg0[wave][q] + dy * s_row[wave][q] + dx;
-    id_out[first + f] = s_id[wave][q];
+    const uint32_t tile = s_seg0[wave][q] + dy * s_row[wave][q] + dx;
+    if (pack >= 0) {
+      seg_out[first + f] = (tile << pack) | s_id[wave][q];
+    } else {
+      seg_out[first + f] = tile;
+      id_out[first + f] = s_id[wave][q];
+    }
   }
 }
 
@@ -671,16 +768,19 @@ inline DigitPlan plan_digits(int key_bits) {
   if (b < 8) b = 8;
   return {passes, b};
 }
-inline int depth_key_bits(int V) { return 32 + bits_for((uint64_t)V); }
-
 inline uint32_t cdiv(uint64_t a, uint64_t b) { return (uint32_t)((a + b - 1) / b); }
 
 struct Layout {
-  size_t dk0, dk1, dv0, dv1, cnt, offs, chunks, segk0, segk1, segv_alt, pcount, dtotal, dparts,
-      vparts, seg_base, txv, total, stats, bytes;
+  size_t dk0, dk1, dv0, dv1, cnt, chunks, segk0, segk1, segv_alt, pcount, dtotal, dstart,
+      pfirst, pdesc, dparts, vparts, iparts, seg_base, txv, total, stats, bytes;
 };
 
+// Bound on the partitions of n keys cut per view (at most one partial
+// partition per view).
+inline size_t max_parts(size_t n, int V) { return (size_t)cdiv(n, kPart) + (size_t)V; }
+
 Layout make_layout(int V, int ld, int64_t cap, int64_t nseg) {
+  (void)nseg;
   Layout L{};
   size_t o = 0;
   auto take = [&](size_t bytes) {
@@ -689,31 +789,34 @@ Layout make_layout(int V, int ld, int64_t cap, int64_t nseg) {
     return at;
   };
   const size_t N = (size_t)V * (size_t)ld;
-  const DigitPlan dp = plan_digits(depth_key_bits(V));
-  const DigitPlan sp = plan_digits(bits_for((uint64_t)nseg));
-  // per-partition digit counts of one pass (reused by every pass)
-  const size_t pc_depth = (size_t)cdiv(N, kPart) * ((size_t)1 << dp.bits);
-  const size_t pc_seg = (size_t)cdiv((uint64_t)cap, kPart) * ((size_t)1 << sp.bits);
+  const size_t pmax = max_parts(std::max(N, (size_t)cap), V);
+  constexpr size_t kMaxDigits = 512;
   L.dk0 = take(N * 8);
   L.dk1 = take(N * 8);
   L.dv0 = take(N * 4);
   L.dv1 = take(N * 4);
   L.cnt = take(N * 4);
-  L.offs = take(N * 4);
-  L.chunks = take(((size_t)cdiv(N, kCountChunk) + 1) * 4);
+  L.chunks = take(((size_t)cdiv(N, kBlock) + 1) * 4);
   L.segk0 = take((size_t)cap * 4);
   L.segk1 = take((size_t)cap * 4);
   L.segv_alt = take((size_t)cap * 4);
-  L.pcount = take((pc_depth > pc_seg ? pc_depth : pc_seg) * 4 + 4);
-  L.dtotal = take(1024 * 4);
+  // per-partition digit counts of one pass (reused by every pass), the row
+  // totals, each view's digit starts, the partition table
+  L.pcount = take(kMaxDigits * pmax * 4);
+  L.dtotal = take(kMaxDigits * 4);
+  L.dstart = take((size_t)V * kMaxDigits * 4);
+  L.pfirst = take(((size_t)V + 1) * 4);
+  L.pdesc = take(pmax * 16);
   L.seg_base = take(((size_t)V + 1) * 4);
   L.txv = take((size_t)V * 4);
   L.total = take(16);
-  // {min bits, max bits, instances lo, hi, visible pairs}
+  // {min bits, max bits, instances lo, hi, visible pairs, instances (low
+  // word, scanned)}
   L.stats = take(32);
   const size_t nchunk = (size_t)V * cdiv((uint64_t)ld, kCountChunk);
   L.dparts = take(nchunk * 16);
   L.vparts = take((nchunk + 1) * 4);
+  L.iparts = take((nchunk + 1) * 4);
   L.bytes = o;
   return L;
 }
@@ -723,39 +826,80 @@ T* at(void* ws, size_t off) {
   return reinterpret_cast<T*>(static_cast<char*>(ws) + off);
 }
 
-// Stable LSD radix sort of (key, value) pairs on bits [0, bits), ping-pong
-// between buffer pair 0 and 1.  Per digit pass: per-partition digit counts,
-// their exclusive scan (per digit over the partitions, then over the
-// digits), and the ranking + scatter with those bases.
+// Where each view's elements start: vstart[v * vstride] for v < V (the
+// chunk scans of stage 1 with stride = chunks per view), n for v = V.
+struct ViewStarts {
+  const uint32_t* vstart;
+  uint32_t vstride;
+  int V;
+};
+
+// Stable LSD radix sort of (key, value) pairs inside each view on bits
+// [shift0, shift0 + BITS * passes), ping-pong between buffer pair 0 and 1.
+// First the partition table, then per digit pass: per-partition digit
+// counts, their exclusive scan per digit over the partitions, the per-view
+// digit starts, and the ranking + scatter with those bases.  Without values
+// (v0 == NULL) the keys carry them in their low bits and the last pass
+// splits them: key >> shift0 to the key buffer, key & (2^shift0 - 1) to
+// vout_last.  add_last (optional): added per view to the keys the last pass
+// writes.
+struct SortSpec {
+  int shift0;
+  const uint32_t* add_last;
+  uint32_t* vout_last;  // keys-only sorts
+};
+
 template <typename K, int BITS>
-void radix_passes(K* k0, K* k1, uint32_t* v0, uint32_t* v1, uint32_t n, int passes, void* ws,
-                  const Layout& L, hipStream_t s) {
+void radix_passes(K* k0, K* k1, uint32_t* v0, uint32_t* v1, uint32_t n, int passes,
+                  const ViewStarts& vs, const SortSpec& sp, void* ws, const Layout& L,
+                  hipStream_t s) {
   constexpr int R = 1 << BITS;
   uint32_t* cnt = at<uint32_t>(ws, L.pcount);
   uint32_t* tot = at<uint32_t>(ws, L.dtotal);
-  const uint32_t parts = cdiv(n, kPart);
-  const uint32_t grid = (parts + 7) / 8 * 8;  // whole XCD rounds
+  uint32_t* dstart = at<uint32_t>(ws, L.dstart);
+  uint32_t* pfirst = at<uint32_t>(ws, L.pfirst);
+  uint4* desc = at<uint4>(ws, L.pdesc);
+  const uint32_t pmax = (uint32_t)max_parts(n, vs.V);
+  const uint32_t grid = (pmax + 7) / 8 * 8;  // whole XCD rounds
+  const uint32_t* n_parts = pfirst + vs.V;
+  hipLaunchKernelGGL(k_part_first, dim3(1), dim3(kBlock), 0, s, vs.vstart, vs.vstride, vs.V, n,
+                     pfirst);
+  hipLaunchKernelGGL(k_part_desc, dim3(cdiv(pmax, kBlock)), dim3(kBlock), 0, s, vs.vstart,
+                     vs.vstride, vs.V, n, pfirst, desc);
   K* kb[2] = {k0, k1};
   uint32_t* vb[2] = {v0, v1};
+  const uint32_t umask = sp.shift0 >= 32 ? ~0u : ((1u << sp.shift0) - 1u);
   for (int p = 0; p < passes; ++p) {
     const int src = p & 1;
-    hipLaunchKernelGGL((k_part_count<K, BITS>), dim3(grid), dim3(kBlock), 0, s, kb[src], n,
-                       BITS * p, parts, cnt);
-    hipLaunchKernelGGL(k_part_scan_rows, dim3(R), dim3(kBlock), 0, s, cnt, parts, tot);
-    hipLaunchKernelGGL((k_digit_scan<BITS>), dim3(1), dim3(kBlock), 0, s, tot);
-    hipLaunchKernelGGL((k_scatter_pass<K, BITS>), dim3(grid), dim3(kBlock), 0, s, kb[src],
-                       vb[src], kb[src ^ 1], vb[src ^ 1], n, BITS * p, parts, cnt, tot);
+    const int shift = sp.shift0 + BITS * p;
+    const bool last = p == passes - 1;
+    hipLaunchKernelGGL((k_part_count<K, BITS>), dim3(grid), dim3(kBlock), 0, s, kb[src], shift,
+                       pmax, n_parts, desc, cnt);
+    hipLaunchKernelGGL(k_part_scan_rows, dim3(R), dim3(kBlock), 0, s, cnt, pmax, n_parts, tot);
+    hipLaunchKernelGGL((k_view_digit_scan<BITS>), dim3(vs.V), dim3(kBlock), 0, s, cnt, pmax, tot,
+                       pfirst, vs.vstart, vs.vstride, vs.V, n, dstart);
+    const uint32_t* add = last ? sp.add_last : nullptr;
+    if (v0)
+      hipLaunchKernelGGL((k_scatter_pass<K, BITS, true>), dim3(grid), dim3(kBlock), 0, s,
+                         kb[src], vb[src], kb[src ^ 1], vb[src ^ 1], shift, pmax, n_parts, desc,
+                         cnt, dstart, add, 0, 0u);
+    else
+      hipLaunchKernelGGL((k_scatter_pass<K, BITS, false>), dim3(grid), dim3(kBlock), 0, s,
+                         kb[src], nullptr, kb[src ^ 1], last ? sp.vout_last : nullptr, shift,
+                         pmax, n_parts, desc, cnt, dstart, add, sp.shift0, umask);
   }
 }
 
+// Returns which key buffer holds the result (0 or 1).
 template <typename K>
-int radix_sort(K* k0, K* k1, uint32_t* v0, uint32_t* v1, uint32_t n, int bits, void* ws,
-               const Layout& L, hipStream_t s) {
+int radix_sort(K* k0, K* k1, uint32_t* v0, uint32_t* v1, uint32_t n, int bits,
+               const ViewStarts& vs, const SortSpec& sp, void* ws, const Layout& L,
+               hipStream_t s) {
   const DigitPlan dp = plan_digits(bits);
   if (n == 0 || dp.passes == 0) return 0;
   switch (dp.bits) {
-    case 8: radix_passes<K, 8>(k0, k1, v0, v1, n, dp.passes, ws, L, s); break;
-    default: radix_passes<K, 9>(k0, k1, v0, v1, n, dp.passes, ws, L, s); break;
+    case 8: radix_passes<K, 8>(k0, k1, v0, v1, n, dp.passes, vs, sp, ws, L, s); break;
+    default: radix_passes<K, 9>(k0, k1, v0, v1, n, dp.passes, vs, sp, ws, L, s); break;
   }
   return dp.passes & 1;
 }
@@ -801,22 +945,31 @@ hipError_t bin_sort_stage1(const BinSortPlan& p, const gs_projected& proj,
   const uint32_t nchunk = gx * (uint32_t)p.n_views;
   uint4* part = at<uint4>(ws, L.dparts);
   uint32_t* vis = at<uint32_t>(ws, L.vparts);
+  uint32_t* icnt = at<uint32_t>(ws, L.iparts);
   hipLaunchKernelGGL(k_depth_range, dim3(gx, gy), dim3(kBlock), 0, s, p.n, p.ld, p.n_views,
-                     proj.depth_bits, proj.tiles_touched, part, vis);
+                     proj.depth_bits, proj.tiles_touched, part, vis, icnt);
   hipLaunchKernelGGL(k_stats_reduce, dim3(1), dim3(kBlock), 0, s, part, (int)nchunk, stats);
   // where each chunk's visible pairs go in the depth sort's input; stats[4]
   // = their number
   hipLaunchKernelGGL(k_chunk_scan, dim3(1), dim3(kBlock), 0, s, vis, nchunk, stats + 4);
+  // where each chunk's instances start in emission order, which keeps the
+  // views in order (only read once the host has checked that the total
+  // fits 32 bits)
+  hipLaunchKernelGGL(k_chunk_scan, dim3(1), dim3(kBlock), 0, s, icnt, nchunk, stats + 5);
   return hipGetLastError();
 }
 
 namespace {
-// Depth sort of the (view, Gaussian) pairs with keys K, instance offsets and
-// emission into (segk0, v0); span is the 32-bit key's per-view range.
+// Depth sort of the (view, Gaussian) pairs with keys K inside each view on
+// their dbits low bits, instance offsets and emission into (segk0, v0), or
+// packed into segk0 alone with pack >= 0; vshift is where a 32-bit key's
+// view starts; with cpack >= 0 each pair's tile count rides above bit
+// cpack of its value through the sort.
 template <typename K>
 void depth_count_emit(const BinSortPlan& p, const gs_projected& proj, const Layout& L, void* ws,
-                      uint32_t N, uint32_t dmin, uint32_t span, int bits, uint32_t* segk0,
-                      uint32_t* v0, uint32_t* gv_base, hipStream_t s) {
+                      uint32_t N, uint32_t dmin, uint32_t vshift, int dbits, int cpack,
+                      uint32_t* segk0, uint32_t* v0, int pack, uint32_t* gv_base,
+                      hipStream_t s) {
   K* k0 = at<K>(ws, L.dk0);
   K* k1 = at<K>(ws, L.dk1);
   uint32_t* dv0 = at<uint32_t>(ws, L.dv0);
@@ -830,30 +983,33 @@ void depth_count_emit(const BinSortPlan& p, const gs_projected& proj, const Layo
     const uint32_t* vis_off = at<uint32_t>(ws, L.vparts);
     if constexpr (sizeof(K) == 4)
       hipLaunchKernelGGL(k_depth_keys32, key_grid, dim3(kBlock), 0, s, p.n, p.ld, p.n_views,
-                         proj.depth_bits, proj.tiles_touched, vis_off, dmin, span, k0, dv0);
+                         proj.depth_bits, proj.tiles_touched, vis_off, dmin, vshift, cpack, k0,
+                         dv0);
     else
       hipLaunchKernelGGL(k_depth_keys, key_grid, dim3(kBlock), 0, s, p.n, p.ld, p.n_views,
-                         proj.depth_bits, proj.tiles_touched, vis_off, k0, dv0);
-    which = radix_sort<K>(k0, k1, dv0, dv1, N, bits, ws, L, s);
+                         proj.depth_bits, proj.tiles_touched, vis_off, dmin, cpack, k0, dv0);
+    const ViewStarts vs{vis_off, key_grid.x, p.n_views};
+    which = radix_sort<K>(k0, k1, dv0, dv1, N, dbits, vs, SortSpec{0, nullptr, nullptr}, ws, L,
+                          s);
   }
   const K* sk = which ? k1 : k0;
   const uint32_t* sv = which ? dv1 : dv0;
   uint32_t* cnt = at<uint32_t>(ws, L.cnt);
   uint32_t* chunks = at<uint32_t>(ws, L.chunks);
-  const uint32_t nch = cdiv(N, kCountChunk);
+  const uint32_t nch = cdiv(N, kBlock);
   {
+    // instance counts per block of kBlock entries and their scan; the emit
+    // finishes the offsets inside its block
     StageScope scope(kStCountScan, s);
-    hipLaunchKernelGGL((k_count_reduce<K>), dim3(nch), dim3(kBlock), 0, s, N, p.ld, span, sk, sv,
-                       proj.tiles_touched, cnt, chunks);
+    hipLaunchKernelGGL((k_count_reduce<K>), dim3(nch), dim3(kBlock), 0, s, N, p.ld, vshift, sk,
+                       sv, proj.tiles_touched, cpack, cnt, chunks);
     hipLaunchKernelGGL(k_chunk_scan, dim3(1), dim3(kBlock), 0, s, chunks, nch,
                        at<uint32_t>(ws, L.total));
-    hipLaunchKernelGGL(k_count_scan, dim3(nch), dim3(kBlock), 0, s, N, cnt, chunks,
-                       at<uint32_t>(ws, L.offs));
   }
   StageScope scope(kStEmit, s);
-  hipLaunchKernelGGL((k_emit<K>), dim3(cdiv(N, kBlock)), dim3(kBlock), 0, s, N, p.ld, span, sk,
-                     sv, cnt, at<uint32_t>(ws, L.offs), at<uint32_t>(ws, L.seg_base), at<int32_t>(ws, L.txv), segk0, v0, gv_base,
-                     reinterpret_cast<uint32_t*>(proj.splat));
+  hipLaunchKernelGGL((k_emit<K>), dim3(nch), dim3(kBlock), 0, s, N, p.ld, vshift, sk, sv, cnt,
+                     cpack, chunks, at<int32_t>(ws, L.txv), segk0, v0, gv_base,
+                     reinterpret_cast<uint32_t*>(proj.splat), pack);
 }
 }  // namespace
 
@@ -864,28 +1020,43 @@ hipError_t bin_sort_stage2(const BinSortPlan& p, const gs_projected& proj,
   const Layout L = make_layout(p.n_views, p.ld, p.capacity, p.n_segments);
   launch_fill_u32(lists.ranges, 0u, 2 * p.n_segments, s);
   if (M == 0) return hipGetLastError();
-  const int sbits = bits_for((uint64_t)p.n_segments);
+  // the tile sort runs inside each view on the bits of its tile index (at
+  // least one pass: the last one turns tile indices into segment ids)
+  const int sbits = std::max(1, bits_for((uint64_t)p.max_tiles));
   const int spasses = plan_digits(sbits).passes;
   uint32_t* segk0 = at<uint32_t>(ws, L.segk0);
   uint32_t* segk1 = at<uint32_t>(ws, L.segk1);
   uint32_t* alt = at<uint32_t>(ws, L.segv_alt);
-  // emit into the buffer that makes the sorted ids land in lists.vals
-  uint32_t* v0 = (spasses & 1) ? alt : lists.vals;
-  uint32_t* v1 = (spasses & 1) ? lists.vals : alt;
-  // (view, depth) keys fit 32 bits when the views times the visible depth
-  // bit range (plus one spare slot) do; only the N visible pairs are sorted
-  const uint64_t span = (uint64_t)dmax - (uint64_t)dmin + 2u;
-  const uint64_t range = (uint64_t)p.n_views * span;
-  if (dmax >= dmin && range <= ((uint64_t)1 << 32))
-    depth_count_emit<uint32_t>(p, proj, L, ws, N, dmin, (uint32_t)span, bits_for(range), segk0,
-                               v0, lists.gv_base, s);
+  // when a tile index and a Gaussian id fit one word together, the emit
+  // writes tile << idbits | id and the tile sort moves those words only
+  // (the last pass splits them); otherwise keys and ids move side by side,
+  // emitted into the buffer that makes the sorted ids land in lists.vals
+  const int idbits = bits_for((uint64_t)p.ld);
+  const bool packed = idbits + sbits <= 32;
+  uint32_t* v0 = packed ? nullptr : ((spasses & 1) ? alt : lists.vals);
+  uint32_t* v1 = packed ? nullptr : ((spasses & 1) ? lists.vals : alt);
+  const int pack = packed ? idbits : -1;
+  // likewise each pair's tile count (at most the largest view's tiles) rides
+  // above its Gaussian id through the depth sort when both fit one word
+  const int cpack = idbits + bits_for((uint64_t)p.max_tiles + 1u) <= 32 ? idbits : -1;
+  // the depth sort runs inside each view on the bits of the visible depth
+  // range; (view, depth) keys are 32-bit when the views fit above those bits
+  // (M > 0 means some pair is visible, so dmax >= dmin); only the N visible
+  // pairs are sorted
+  const int dbits = bits_for((uint64_t)dmax - (uint64_t)dmin + 1u);
+  if (((uint64_t)p.n_views << dbits) <= ((uint64_t)1 << 32))
+    depth_count_emit<uint32_t>(p, proj, L, ws, N, dmin, (uint32_t)dbits, dbits, cpack, segk0,
+                               v0, pack, lists.gv_base, s);
   else
-    depth_count_emit<uint64_t>(p, proj, L, ws, N, 0u, 1u, depth_key_bits(p.n_views), segk0, v0,
+    depth_count_emit<uint64_t>(p, proj, L, ws, N, dmin, 32u, dbits, cpack, segk0, v0, pack,
                                lists.gv_base, s);
   int which2;
   {
     StageScope scope(kStSegmentSort, s);
-    which2 = radix_sort<uint32_t>(segk0, segk1, v0, v1, M, sbits, ws, L, s);
+    const ViewStarts vs{at<uint32_t>(ws, L.iparts), cdiv((uint64_t)p.n, kCountChunk), p.n_views};
+    const SortSpec sp{packed ? idbits : 0, at<uint32_t>(ws, L.seg_base),
+                      packed ? lists.vals : nullptr};
+    which2 = radix_sort<uint32_t>(segk0, segk1, v0, v1, M, sbits, vs, sp, ws, L, s);
   }
   const uint32_t* seg_sorted = which2 ? segk1 : segk0;
   StageScope scope(kStRanges, s);
