@@ -2,17 +2,22 @@
 // with SSIM over an 11x11 Gaussian window (sigma 1.5), zero padding,
 // C1 = 0.01^2, C2 = 0.03^2, averaged over every image value.
 //
-// Two tiled passes, each a separable 11-tap window over a 32x32 output tile
-// whose 42x42 input footprint is staged in LDS (horizontal pass: 8 columns
-// per thread, vertical pass: 4 rows per thread, sliding in registers):
+// Two streaming passes.  A workgroup owns a strip of kSW output columns (one
+// per thread) and a band of kBand output rows; it walks the band's input
+// rows top to bottom, staging each row of the strip plus its kR-column
+// margins in LDS (two row buffers, the next row's loads in flight while the
+// current one is summed), takes each thread's horizontal 11-tap sums, and
+// keeps the last 11 rows of those sums in registers, so that every row
+// after the first 2 kR yields one output row of vertical sums:
 //   1. windowed statistics of x, y, x^2, y^2, xy -> per-pixel SSIM index and
 //      the partials A1 = dS/dmu_x - 2 mu_x dS/dvar_x - mu_y dS/dcov,
 //      A2 = dS/dvar_x, A3 = dS/dcov (written to the workspace), one loss
-//      partial per tile (summed by one workgroup afterwards);
+//      partial per workgroup (summed by one workgroup afterwards);
 //   2. the adjoint window over A1..A3 -> dL/dx = ((1 - lambda) sign(x - y)
 //      - lambda (w*A1 + 2 x w*A2 + y w*A3)) / count.
 // HBM-bound: 8 B read + 12 B written per value in pass 1, 20 B read + 4 B
-// written in pass 2.
+// written in pass 2 (plus the margins: (kSW + 2 kR) / kSW columns and
+// (kBand + 2 kR) / kBand rows of input).
 #include <cmath>
 
 #include "gs_internal.h"
@@ -20,175 +25,166 @@
 namespace gs {
 namespace {
 
-constexpr int kR = 5;             // window radius
-constexpr int kT = 32;            // output tile side
-constexpr int kI = kT + 2 * kR;   // staged footprint side (42)
-constexpr int kIP = kI + 1;       // padded LDS row stride of the staged input
-constexpr int kTP = kT + 1;       // padded LDS row stride of the horizontal sums
-constexpr int kSeg = 8;           // columns per thread in the horizontal pass
-constexpr int kRows = 4;          // output rows per thread in the vertical pass
+constexpr int kR = 5;               // window radius
+constexpr int kTaps = 2 * kR + 1;
+constexpr int kSW = 128;            // strip width: output columns, one per thread
+constexpr int kBand = 64;           // output rows per workgroup
+constexpr int kSI = kSW + 2 * kR;   // staged columns of one input row
 constexpr float kC1 = 0.01f * 0.01f, kC2 = 0.03f * 0.03f;
 
 struct Window {
-  float w[2 * kR + 1];
+  float w[kTaps];
 };
 
-// Stage a kI x kI footprint of NP planes with zero padding.  Every thread
-// issues all of its global loads before its first LDS store, so the loads of
-// one workgroup are in flight together.
+// One input row of the strip in registers: column x0 - kR + t, and for
+// t < 2 kR also column x0 - kR + kSW + t; zero outside the image.
 template <int NP>
-__device__ __forceinline__ void stage(float (*dst)[kI][kIP], const float* const* src, int W, int H,
-                                      int x0, int y0) {
-  constexpr int kPer = (kI * kI + 255) / 256;
-  float v[NP][kPer];
-#pragma unroll
-  for (int u = 0; u < kPer; ++u) {
-    const int t = threadIdx.x + u * 256;
-    const int r = t / kI, c = t - r * kI;
-    const int yy = y0 + r - kR, xx = x0 + c - kR;
-    const bool in = t < kI * kI && yy >= 0 && yy < H && xx >= 0 && xx < W;
-    const size_t p = in ? (size_t)yy * W + xx : 0;
-#pragma unroll
-    for (int q = 0; q < NP; ++q) v[q][u] = in ? src[q][p] : 0.f;
-  }
-#pragma unroll
-  for (int u = 0; u < kPer; ++u) {
-    const int t = threadIdx.x + u * 256;
-    if (t < kI * kI) {
-      const int r = t / kI, c = t - r * kI;
-#pragma unroll
-      for (int q = 0; q < NP; ++q) dst[q][r][c] = v[q][u];
-    }
-  }
-}
-
-// Horizontal window over the kI staged rows, kSeg consecutive output
-// columns per work item (kI rows x kT/kSeg segments), sliding in registers.
-// F maps the NP staged planes at one position to NS statistics.
-template <int NP, int NS, typename F>
-__device__ __forceinline__ void hpass(const float (*in)[kI][kIP], float (*out)[kI][kTP],
-                                      const Window& win, F stat) {
-  constexpr int kItems = kI * (kT / kSeg);
-  for (int t = threadIdx.x; t < kItems; t += blockDim.x) {
-    // consecutive threads take consecutive rows (with the padded strides
-    // their LDS accesses fall into different banks)
-    const int seg = t / kI, r = t - seg * kI, c0 = seg * kSeg;
-    float acc[kSeg][NS];
-#pragma unroll
-    for (int o = 0; o < kSeg; ++o)
-#pragma unroll
-      for (int q = 0; q < NS; ++q) acc[o][q] = 0.f;
-#pragma unroll
-    for (int i = 0; i < kSeg + 2 * kR; ++i) {
-      float v[NP];
-#pragma unroll
-      for (int p = 0; p < NP; ++p) v[p] = in[p][r][c0 + i];
-      float st[NS];
-      stat(v, st);
-#pragma unroll
-      for (int o = 0; o < kSeg; ++o) {
-        const int tap = i - o;
-        if (tap >= 0 && tap <= 2 * kR) {
-#pragma unroll
-          for (int q = 0; q < NS; ++q) acc[o][q] = fmaf(win.w[tap], st[q], acc[o][q]);
-        }
-      }
-    }
-#pragma unroll
-    for (int o = 0; o < kSeg; ++o)
-#pragma unroll
-      for (int q = 0; q < NS; ++q) out[q][r][c0 + o] = acc[o][q];
-  }
-}
-
-// Vertical window: thread (c, g) produces rows 4g..4g+3 of column c.
-template <int NS>
-__device__ __forceinline__ void vpass(const float (*h)[kI][kTP], const Window& win, int c, int g,
-                                      float (*res)[NS]) {
-#pragma unroll
-  for (int o = 0; o < kRows; ++o)
-#pragma unroll
-    for (int q = 0; q < NS; ++q) res[o][q] = 0.f;
-#pragma unroll
-  for (int j = 0; j < kRows + 2 * kR; ++j) {
-    float v[NS];
-#pragma unroll
-    for (int q = 0; q < NS; ++q) v[q] = h[q][kRows * g + j][c];
-#pragma unroll
-    for (int o = 0; o < kRows; ++o) {
-      const int tap = j - o;
-      if (tap >= 0 && tap <= 2 * kR) {
-#pragma unroll
-        for (int q = 0; q < NS; ++q) res[o][q] = fmaf(win.w[tap], v[q], res[o][q]);
-      }
-    }
-  }
-}
-
-struct StatsShared {
-  float in[2][kI][kIP];
-  float h[5][kI][kTP];
-  double red[4];
+struct RowRegs {
+  float a[NP], b[NP];
 };
 
-__global__ __launch_bounds__(256) void k_ssim_stats(const float* __restrict__ img,
+template <int NP>
+__device__ __forceinline__ void load_row(RowRegs<NP>& r, const float* const* src, int W, int H,
+                                         int x0, int y) {
+  const int t = threadIdx.x;
+  const int xa = x0 - kR + t, xb = xa + kSW;
+  const bool row_in = y >= 0 && y < H;
+  const size_t base = (size_t)(row_in ? y : 0) * (size_t)W;
+  const bool a_in = row_in && xa >= 0 && xa < W;
+  const bool b_in = row_in && t < 2 * kR && xb < W;
+#pragma unroll
+  for (int q = 0; q < NP; ++q) {
+    r.a[q] = a_in ? src[q][base + xa] : 0.f;
+    r.b[q] = b_in ? src[q][base + xb] : 0.f;
+  }
+}
+
+template <int NP>
+__device__ __forceinline__ void store_row(float (*buf)[kSI], const RowRegs<NP>& r) {
+  const int t = threadIdx.x;
+#pragma unroll
+  for (int q = 0; q < NP; ++q) {
+    buf[q][t] = r.a[q];
+    if (t < 2 * kR) buf[q][kSW + t] = r.b[q];
+  }
+}
+
+// The band walk shared by both passes.  For input row i of the band
+// (image row y0 - kR + i), Horiz(in, hs) forms the thread's NS horizontal
+// sums from the staged row (in[q][t + k], k = 0 .. 2 kR, is tap k of plane
+// q); once 2 kR + 1 rows are in, Out(y, vs) receives the vertical sums of
+// output row y = y0 + i - 2 kR.  Centre(i, in) sees every staged row.  The
+// next row's loads are in flight while a row is summed; the ring slot of
+// row i is i mod 11, and the rows are unrolled by 11 so that every slot
+// index is static.
+template <int NP, int NS, typename Horiz, typename Out, typename Centre>
+__device__ __forceinline__ void walk_band(const float* const* src, int W, int H, int x0, int y0,
+                                          const Window& win, float (*buf)[NP][kSI], Horiz horiz,
+                                          Out out, Centre centre) {
+  const int rows = min(kBand, H - y0) + 2 * kR;  // same for the whole workgroup
+  float ring[kTaps][NS];
+  RowRegs<NP> nx;
+  load_row<NP>(nx, src, W, H, x0, y0 - kR);
+  store_row<NP>(buf[0], nx);
+  __syncthreads();
+  for (int i0 = 0; i0 < rows; i0 += kTaps) {
+#pragma unroll
+    for (int u = 0; u < kTaps; ++u) {
+      const int i = i0 + u;
+      if (i < rows) {
+        // the next row's loads go out before this row is summed
+        if (i + 1 < rows) load_row<NP>(nx, src, W, H, x0, y0 - kR + i + 1);
+        const float (*in)[kSI] = buf[i & 1];
+        horiz(in, ring[u]);
+        centre(i, in);
+        if (i >= 2 * kR) {
+          float vs[NS];
+#pragma unroll
+          for (int q = 0; q < NS; ++q) vs[q] = 0.f;
+#pragma unroll
+          for (int k = 0; k < kTaps; ++k) {
+            // row i - 2 kR + k sits in slot (u + 1 + k) mod 11
+#pragma unroll
+            for (int q = 0; q < NS; ++q)
+              vs[q] = fmaf(win.w[k], ring[(u + 1 + k) % kTaps][q], vs[q]);
+          }
+          out(y0 + i - 2 * kR, vs);
+        }
+        if (i + 1 < rows) store_row<NP>(buf[(i + 1) & 1], nx);
+        __syncthreads();
+      }
+    }
+  }
+}
+
+__global__ __launch_bounds__(kSW) void k_ssim_stats(const float* __restrict__ img,
                                                    const float* __restrict__ tgt, int W, int H,
                                                    Window win, float lambda, float inv_count,
                                                    float* __restrict__ amaps,
                                                    double* __restrict__ partial) {
-  __shared__ StatsShared sh;
+  __shared__ float buf[2][2][kSI];
+  __shared__ double red[kSW / 64];
   const size_t plane = (size_t)W * H;
-  const int pl = blockIdx.z;
-  const int x0 = blockIdx.x * kT, y0 = blockIdx.y * kT;
+  const int pl = blockIdx.z, t = threadIdx.x;
+  const int x0 = blockIdx.x * kSW, y0 = blockIdx.y * kBand;
+  const int x = x0 + t;
   const float* srcs[2] = {img + pl * plane, tgt + pl * plane};
-  stage<2>(sh.in, srcs, W, H, x0, y0);
-  __syncthreads();
-  hpass<2, 5>(sh.in, sh.h, win, [](const float* v, float* st) {
-    st[0] = v[0];
-    st[1] = v[1];
-    st[2] = v[0] * v[0];
-    st[3] = v[1] * v[1];
-    st[4] = v[0] * v[1];
-  });
-  __syncthreads();
-  const int c = threadIdx.x % kT, g = threadIdx.x / kT;
-  float res[kRows][5];
-  vpass<5>(sh.h, win, c, g, res);
-  double part = 0.0;
   float* a = amaps + (size_t)pl * 3 * plane;
+  double part = 0.0;
+  const int rows = min(kBand, H - y0) + 2 * kR;
+  walk_band<2, 5>(
+      srcs, W, H, x0, y0, win, buf,
+      [&](const float (*in)[kSI], float* hs) {
 #pragma unroll
-  for (int o = 0; o < kRows; ++o) {
-    const int x = x0 + c, y = y0 + kRows * g + o;
-    if (x < W && y < H) {
-      const float mx = res[o][0], my = res[o][1];
-      const float sxx = res[o][2] - mx * mx, syy = res[o][3] - my * my, sxy = res[o][4] - mx * my;
-      const float N1 = 2.f * mx * my + kC1, N2 = 2.f * sxy + kC2;
-      const float D1 = mx * mx + my * my + kC1, D2 = sxx + syy + kC2;
-      const float iD = 1.f / (D1 * D2);
-      const float S = N1 * N2 * iD;
-      const float dS_dmx = 2.f * my * N2 * iD - S * 2.f * mx / D1;
-      const float dS_dsxx = -S / D2;
-      const float dS_dsxy = 2.f * N1 * iD;
-      const size_t p = (size_t)y * W + x;
-      a[p] = dS_dmx - 2.f * mx * dS_dsxx - my * dS_dsxy;
-      a[plane + p] = dS_dsxx;
-      a[2 * plane + p] = dS_dsxy;
-      const int ly = kRows * g + o + kR, lx = c + kR;
-      const float d = sh.in[0][ly][lx] - sh.in[1][ly][lx];
-      part += (double)(1.f - lambda) * fabs((double)d) - (double)lambda * (double)S;
-    }
-  }
+        for (int q = 0; q < 5; ++q) hs[q] = 0.f;
+#pragma unroll
+        for (int k = 0; k < kTaps; ++k) {
+          const float xv = in[0][t + k], yv = in[1][t + k], w = win.w[k];
+          hs[0] = fmaf(w, xv, hs[0]);
+          hs[1] = fmaf(w, yv, hs[1]);
+          hs[2] = fmaf(w, xv * xv, hs[2]);
+          hs[3] = fmaf(w, yv * yv, hs[3]);
+          hs[4] = fmaf(w, xv * yv, hs[4]);
+        }
+      },
+      [&](int y, const float* st) {
+        if (x >= W) return;
+        const float mx = st[0], my = st[1];
+        const float sxx = st[2] - mx * mx, syy = st[3] - my * my, sxy = st[4] - mx * my;
+        const float N1 = 2.f * mx * my + kC1, N2 = 2.f * sxy + kC2;
+        const float D1 = mx * mx + my * my + kC1, D2 = sxx + syy + kC2;
+        // hardware reciprocals (1 ulp); D1 and D2 are at least C1 and C2
+        const float iD1 = __builtin_amdgcn_rcpf(D1), iD2 = __builtin_amdgcn_rcpf(D2);
+        const float iD = iD1 * iD2;
+        const float S = N1 * N2 * iD;
+        const float dS_dmx = 2.f * my * N2 * iD - S * 2.f * mx * iD1;
+        const float dS_dsxx = -S * iD2;
+        const float dS_dsxy = 2.f * N1 * iD;
+        const size_t p = (size_t)y * W + x;
+        a[p] = dS_dmx - 2.f * mx * dS_dsxx - my * dS_dsxy;
+        a[plane + p] = dS_dsxx;
+        a[2 * plane + p] = dS_dsxy;
+        part -= (double)lambda * (double)S;
+      },
+      [&](int i, const float (*in)[kSI]) {
+        // the L1 term of the band's own rows
+        if (i >= kR && i < rows - kR && x < W)
+          part += (double)(1.f - lambda) * fabs((double)(in[0][t + kR] - in[1][t + kR]));
+      });
   for (int off = 32; off >= 1; off >>= 1) part += __shfl_xor(part, off, 64);
-  if ((threadIdx.x & 63) == 0) sh.red[threadIdx.x >> 6] = part;
+  if ((t & 63) == 0) red[t >> 6] = part;
   __syncthreads();
-  if (threadIdx.x == 0) {
+  if (t == 0) {
+    double s = 0.0;
+#pragma unroll
+    for (int w = 0; w < kSW / 64; ++w) s += red[w];
     const size_t b = ((size_t)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
-    partial[b] = ((sh.red[0] + sh.red[1]) + (sh.red[2] + sh.red[3])) * (double)inv_count;
+    partial[b] = s * (double)inv_count;
   }
 }
 
-// One workgroup adds the per-tile partials (fixed order per thread, then a
-// tree), plus lambda for the constant of 1 - SSIM, into *loss.
+// One workgroup adds the per-workgroup partials (fixed order per thread,
+// then a tree), plus lambda for the constant of 1 - SSIM, into *loss.
 __global__ __launch_bounds__(1024) void k_sum_partials(const double* __restrict__ partial,
                                                        size_t nb, float lambda,
                                                        double* __restrict__ loss) {
@@ -212,45 +208,40 @@ __global__ __launch_bounds__(1024) void k_sum_partials(const double* __restrict_
   }
 }
 
-struct GradShared {
-  float in[3][kI][kIP];
-  float h[3][kI][kTP];
-};
-
-__global__ __launch_bounds__(256) void k_ssim_grad(const float* __restrict__ img,
+__global__ __launch_bounds__(kSW) void k_ssim_grad(const float* __restrict__ img,
                                                   const float* __restrict__ tgt, int W, int H,
                                                   Window win, float lambda, float inv_count,
                                                   const float* __restrict__ amaps,
                                                   float* __restrict__ grad) {
-  __shared__ GradShared sh;
+  __shared__ float buf[2][3][kSI];
   const size_t plane = (size_t)W * H;
-  const int pl = blockIdx.z;
-  const int x0 = blockIdx.x * kT, y0 = blockIdx.y * kT;
+  const int pl = blockIdx.z, t = threadIdx.x;
+  const int x0 = blockIdx.x * kSW, y0 = blockIdx.y * kBand;
+  const int x = x0 + t;
   const float* a = amaps + (size_t)pl * 3 * plane;
   const float* srcs[3] = {a, a + plane, a + 2 * plane};
-  stage<3>(sh.in, srcs, W, H, x0, y0);
-  __syncthreads();
-  hpass<3, 3>(sh.in, sh.h, win, [](const float* v, float* st) {
-    st[0] = v[0];
-    st[1] = v[1];
-    st[2] = v[2];
-  });
-  __syncthreads();
-  const int c = threadIdx.x % kT, g = threadIdx.x / kT;
-  float res[kRows][3];
-  vpass<3>(sh.h, win, c, g, res);
+  walk_band<3, 3>(
+      srcs, W, H, x0, y0, win, buf,
+      [&](const float (*in)[kSI], float* hs) {
 #pragma unroll
-  for (int o = 0; o < kRows; ++o) {
-    const int x = x0 + c, y = y0 + kRows * g + o;
-    if (x < W && y < H) {
-      const size_t p = (size_t)pl * plane + (size_t)y * W + x;
-      const float xv = img[p], yv = tgt[p];
-      const float d = xv - yv;
-      const float sg = d > 0.f ? 1.f : (d < 0.f ? -1.f : 0.f);
-      const float gs = res[o][0] + 2.f * xv * res[o][1] + yv * res[o][2];
-      grad[p] = ((1.f - lambda) * sg - lambda * gs) * inv_count;
-    }
-  }
+        for (int q = 0; q < 3; ++q) hs[q] = 0.f;
+#pragma unroll
+        for (int k = 0; k < kTaps; ++k) {
+          const float w = win.w[k];
+#pragma unroll
+          for (int q = 0; q < 3; ++q) hs[q] = fmaf(w, in[q][t + k], hs[q]);
+        }
+      },
+      [&](int y, const float* r) {
+        if (x >= W) return;
+        const size_t p = (size_t)pl * plane + (size_t)y * W + x;
+        const float xv = img[p], yv = tgt[p];
+        const float d = xv - yv;
+        const float sg = d > 0.f ? 1.f : (d < 0.f ? -1.f : 0.f);
+        const float gs = r[0] + 2.f * xv * r[1] + yv * r[2];
+        grad[p] = ((1.f - lambda) * sg - lambda * gs) * inv_count;
+      },
+      [](int, const float (*)[kSI]) {});
 }
 
 Window make_window() {
@@ -267,7 +258,7 @@ Window make_window() {
 }  // namespace
 
 inline size_t tiles_of(int planes, int H, int W) {
-  return (size_t)planes * (size_t)((H + kT - 1) / kT) * (size_t)((W + kT - 1) / kT);
+  return (size_t)planes * (size_t)((H + kBand - 1) / kBand) * (size_t)((W + kSW - 1) / kSW);
 }
 
 size_t l1_dssim_workspace_bytes(int planes, int H, int W) {
@@ -281,16 +272,16 @@ void launch_l1_dssim(const float* image, const float* target, int planes, int H,
   const Window win = make_window();
   const double count = (double)planes * (double)H * (double)W;
   const float inv = (float)(1.0 / count);
-  const dim3 grid((W + kT - 1) / kT, (H + kT - 1) / kT, planes);
+  const dim3 grid((W + kSW - 1) / kSW, (H + kBand - 1) / kBand, planes);
   float* amaps = static_cast<float*>(ws);
   double* partial =
       reinterpret_cast<double*>(static_cast<char*>(ws) + (size_t)planes * 3 * H * W * sizeof(float));
   StageScope scope(kStDssim, s);
-  hipLaunchKernelGGL(k_ssim_stats, grid, dim3(256), 0, s, image, target, W, H, win, lambda, inv,
+  hipLaunchKernelGGL(k_ssim_stats, grid, dim3(kSW), 0, s, image, target, W, H, win, lambda, inv,
                      amaps, partial);
   hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(1024), 0, s, (const double*)partial,
                      tiles_of(planes, H, W), lambda, loss);
-  hipLaunchKernelGGL(k_ssim_grad, grid, dim3(256), 0, s, image, target, W, H, win, lambda, inv,
+  hipLaunchKernelGGL(k_ssim_grad, grid, dim3(kSW), 0, s, image, target, W, H, win, lambda, inv,
                      amaps, grad);
 }
 
