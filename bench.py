@@ -453,6 +453,33 @@ def definition_pairs(ts):
     return ts._def_pairs
 
 
+def bits_for(count):
+    """Bits that hold the values 0 .. count - 1."""
+    return max(int(count) - 1, 0).bit_length()
+
+
+def binning_shape(ts):
+    """What the binning of the last step sorted and packed, recomputed from
+    its projected records the way the library plans it: visible pairs N,
+    depth-sort passes and key bytes, tile-sort passes, whether (tile, id)
+    and (count, id) were packed into one word."""
+    torch = ts.torch
+    proj = ts.last["proj"]
+    V, n, ld = ts.cams.V, ts.g.n, ts.g.ld
+    tt = proj.tiles_touched[:, :n]
+    vis = tt > 0
+    N = int(vis.sum().item())
+    db = proj.depth_bits[:, :n][vis].to(torch.int64) & 0xFFFFFFFF
+    dbits = bits_for(int(db.max().item()) - int(db.min().item()) + 1) if N else 0
+    key_bytes = 4 if (V << dbits) <= (1 << 32) else 8
+    max_tiles = max(math.ceil(c.width / 16) * math.ceil(c.height / 16) for c in ts.cams.host)
+    sbits = max(1, bits_for(max_tiles))
+    idbits = bits_for(ld)
+    return {"N": N, "depth_passes": (dbits + 8) // 9, "key_bytes": key_bytes,
+            "tile_passes": (sbits + 8) // 9, "packed_tiles": idbits + sbits <= 32,
+            "packed_counts": idbits + bits_for(max_tiles + 1) <= 32}
+
+
 def algorithmic_work(stage, ts, steps):
     """(amount per step, unit, bound) for an HBM-bound stage of one step."""
     n, V, K = ts.g.n, ts.cams.V, (ts.g.deg + 1) ** 2
@@ -463,11 +490,20 @@ def algorithmic_work(stage, ts, steps):
     if stage == "project_bwd":
         return 2 * n * pbytes + V * n * (36.0 + 20 + 1), "byte", "hbm"
     if stage == "segment_sort":
-        passes = math.ceil(math.ceil(math.log2(max(ts.cams.n_segments(), 2))) / 8)
-        return M * (16.0 * passes + 4.0), "byte", "hbm"
+        b = binning_shape(ts)
+        if b["packed_tiles"]:
+            # per pass: 4 B counted, 4 B read, 4 B written; the last pass
+            # writes the segment id and the Gaussian id
+            return M * (12.0 * b["tile_passes"] + 4.0), "byte", "hbm"
+        return M * 20.0 * b["tile_passes"], "byte", "hbm"
     if stage == "depth_sort":
-        passes = math.ceil((32 + math.ceil(math.log2(max(V, 1)) if V > 1 else 0)) / 8)
-        return V * n * (24.0 * passes + 8 + 4 + 8 + 4), "byte", "hbm"
+        b = binning_shape(ts)
+        kb, N = b["key_bytes"], b["N"]
+        # depth range and key gather read depth bits and tile counts of all
+        # (view, Gaussian) pairs twice; the keys of the N visible pairs are
+        # written, then each pass counts, reads and writes them with values
+        return (V * n * 16.0 + N * (kb + 4) + N * b["depth_passes"] * (kb + 2 * (kb + 4)),
+                "byte", "hbm")
     if stage == "adam":
         return 28.0 * ts.nparam, "byte", "hbm"
     if stage == "l1":
@@ -475,7 +511,12 @@ def algorithmic_work(stage, ts, steps):
     if stage == "dssim":
         return 44.0 * ts.target.numel(), "byte", "hbm"
     if stage == "emit":
-        return V * n * 8.0 + M * 8.0, "byte", "hbm"
+        b = binning_shape(ts)
+        # per visible pair: key, value, the 16-B record quarter read and its
+        # emission index written (+ the gathered count when not packed);
+        # per instance one packed word or a (tile, id) pair
+        per_pair = b["key_bytes"] + 4 + 16 + 4 + (0 if b["packed_counts"] else 4)
+        return b["N"] * per_pair + M * (4.0 if b["packed_tiles"] else 8.0), "byte", "hbm"
     return None
 
 

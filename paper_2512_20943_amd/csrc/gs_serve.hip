@@ -325,6 +325,17 @@ gs_status gs_server_stats(const gs_server* s, int64_t* out) {
   return GS_OK;
 }
 
+// Sleeps until shortly before t, then polls the clock: a timed sleep alone
+// wakes tens of microseconds late (timer slack and the thread's wake-up),
+// which would add to every request's latency.  Both serving modes wait for
+// arrivals this way.
+constexpr auto kPollWindow = std::chrono::microseconds(200);
+static void wait_until_precise(Clock::time_point t) {
+  if (Clock::now() + kPollWindow < t) std::this_thread::sleep_until(t - kPollWindow);
+  while (Clock::now() < t) {
+  }
+}
+
 static gs_status server_run(gs_server* s, const gs_request* reqs, int n, int plain,
                            double* t_start, double* t_done, float* const* images) {
   if (!s || (n > 0 && (!reqs || !t_start || !t_done)) || n < 0) return GS_ERR_INVALID_ARG;
@@ -352,7 +363,7 @@ static gs_status server_run(gs_server* s, const gs_request* reqs, int n, int pla
 
   if (plain) {
     for (int i = 0; i < n; ++i) {
-      std::this_thread::sleep_until(at(reqs[i].arrival_s));
+      wait_until_precise(at(reqs[i].arrival_s));
       t_start[i] = since(Clock::now());
       const gs_status st = s->solo->render(reqs, &i, 1, images);
       t_done[i] = since(Clock::now());
@@ -424,6 +435,9 @@ static gs_status server_run(gs_server* s, const gs_request* reqs, int n, int pla
   {
     std::unique_lock<std::mutex> lk(mu);
     std::vector<int> pending;  // FIFO of arrived request indices
+    pending.reserve((size_t)n);
+    std::vector<int> batch;    // reused, so that forming a batch allocates nothing
+    batch.reserve((size_t)s->cfg.max_batch);
     size_t head = 0;
     int next = 0;
     while (done < n) {
@@ -439,7 +453,7 @@ static gs_status server_run(gs_server* s, const gs_request* reqs, int n, int pla
       if (head < pending.size() && !free_w.empty()) {
         double ipt = 0.0;
         for (double v : ipt_w) ipt = std::max(ipt, v);
-        std::vector<int> batch;
+        batch.clear();
         int64_t bytes = 0;
         while (head < pending.size() && (int)batch.size() < s->cfg.max_batch) {
           const int64_t need = request_bytes(reqs[pending[head]], ld, ipt);
@@ -470,7 +484,7 @@ static gs_status server_run(gs_server* s, const gs_request* reqs, int n, int pla
             s->batched_requests += (int64_t)batch.size();
             const int w = free_w.back();  // the most recently freed worker
             free_w.pop_back();
-            job[w].ids = std::move(batch);
+            job[w].ids.assign(batch.begin(), batch.end());
             job[w].bytes = bytes;
             job[w].has = true;
             cv_w[w].notify_one();
@@ -478,10 +492,25 @@ static gs_status server_run(gs_server* s, const gs_request* reqs, int n, int pla
           continue;
         }
       }
-      if (next < n)
-        cv_sched.wait_until(lk, std::min(at(reqs[next].arrival_s), Clock::now() + std::chrono::milliseconds(50)));
-      else
+      if (next < n) {
+        const auto t_next = at(reqs[next].arrival_s);
+        // requests that wait for a worker are served when one finishes
+        const bool queued = head < pending.size();
+        if (!queued && Clock::now() + kPollWindow >= t_next) {
+          // nothing queued and an arrival imminent: poll for it without the
+          // lock
+          lk.unlock();
+          wait_until_precise(t_next);
+          lk.lock();
+        } else {
+          // sleep until the poll window opens (or the arrival, with requests
+          // queued), or a worker finishes
+          const auto wake = queued ? t_next : t_next - kPollWindow;
+          cv_sched.wait_until(lk, std::min(wake, Clock::now() + std::chrono::milliseconds(50)));
+        }
+      } else {
         cv_sched.wait_for(lk, std::chrono::milliseconds(50));
+      }
     }
     stop = true;
     for (int w = 0; w < W; ++w) cv_w[w].notify_one();
