@@ -370,6 +370,40 @@ __global__ void k_view_info(const gs_camera* __restrict__ cams, int V, uint32_t*
   seg_base[V] = acc;
 }
 
+// The tile counts and depth bits of Gaussians i0 .. i0 + kCountItems - 1
+// of one view (0 past n): two 16-B loads per array when the rows are 16-B
+// aligned and the run is whole, else one word at a time.
+__device__ __forceinline__ void load_run(const int32_t* __restrict__ tv,
+                                         const uint32_t* __restrict__ dv, uint32_t i0, int n,
+                                         bool vec, uint32_t (&t)[kCountItems],
+                                         uint32_t (&d)[kCountItems]) {
+  static_assert(kCountItems == 8, "two 16-B loads per array");
+  if (vec && i0 + kCountItems <= (uint32_t)n) {
+    const int4 ta = *reinterpret_cast<const int4*>(tv + i0);
+    const int4 tb = *reinterpret_cast<const int4*>(tv + i0 + 4);
+    const uint4 da = *reinterpret_cast<const uint4*>(dv + i0);
+    const uint4 db = *reinterpret_cast<const uint4*>(dv + i0 + 4);
+    const int tt[8] = {ta.x, ta.y, ta.z, ta.w, tb.x, tb.y, tb.z, tb.w};
+    const uint32_t dd[8] = {da.x, da.y, da.z, da.w, db.x, db.y, db.z, db.w};
+#pragma unroll
+    for (int j = 0; j < kCountItems; ++j) {
+      t[j] = (uint32_t)max(tt[j], 0);
+      d[j] = dd[j];
+    }
+  } else {
+#pragma unroll
+    for (int j = 0; j < kCountItems; ++j) {
+      const uint32_t i = i0 + j;
+      t[j] = i < (uint32_t)n ? (uint32_t)max(tv[i], 0) : 0u;
+      d[j] = t[j] > 0 ? dv[i] : 0u;
+    }
+  }
+}
+
+__device__ __forceinline__ bool rows_aligned(int ld, const void* a, const void* b) {
+  return (ld & 3) == 0 && ((reinterpret_cast<uintptr_t>(a) | reinterpret_cast<uintptr_t>(b)) & 15) == 0;
+}
+
 // Per chunk of kCountChunk Gaussians of one view (grid x; views on grid y,
 // looping past 65535 of them), chunk c = v * gridDim.x + blockIdx.x: the
 // range of the depth bits of its visible pairs and their instance count,
@@ -385,21 +419,21 @@ __global__ __launch_bounds__(kBlock) void k_depth_range(int n, int ld, int V,
   __shared__ uint32_t s_min[4], s_max[4], s_cnt[4];
   __shared__ unsigned long long s_sum[4];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const bool vec = rows_aligned(ld, tiles, depth_bits);
   for (int v = blockIdx.y; v < V; v += gridDim.y) {
     const int32_t* tv = tiles + (size_t)v * ld;
     const uint32_t* dv = depth_bits + (size_t)v * ld;
     const uint32_t i0 = blockIdx.x * (uint32_t)kCountChunk + threadIdx.x * kCountItems;
     uint32_t mn = 0xFFFFFFFFu, mx = 0u, cnt = 0u;
     unsigned long long sum = 0;
+    uint32_t t[kCountItems], d[kCountItems];
+    load_run(tv, dv, i0, n, vec, t, d);
 #pragma unroll
     for (int j = 0; j < kCountItems; ++j) {
-      const uint32_t i = i0 + j;
-      const int t = i < (uint32_t)n ? tv[i] : 0;
-      if (t > 0) {
-        const uint32_t d = dv[i];
-        mn = min(mn, d);
-        mx = max(mx, d);
-        sum += (unsigned long long)t;
+      if (t[j] > 0) {
+        mn = min(mn, d[j]);
+        mx = max(mx, d[j]);
+        sum += (unsigned long long)t[j];
         ++cnt;
       }
     }
@@ -477,23 +511,21 @@ __device__ __forceinline__ void visible_keys(int n, int ld, int V,
                                              int cpack, K* __restrict__ keys,
                                              uint32_t* __restrict__ vals) {
   __shared__ uint32_t s_wave[4];
+  const bool vec = rows_aligned(ld, tiles, depth_bits);
   for (int v = blockIdx.y; v < V; v += gridDim.y) {
     const int32_t* tv = tiles + (size_t)v * ld;
     const uint32_t* dv = depth_bits + (size_t)v * ld;
     const uint32_t i0 = blockIdx.x * (uint32_t)kCountChunk + threadIdx.x * kCountItems;
-    uint32_t c = 0, t[kCountItems];
+    uint32_t c = 0, t[kCountItems], d[kCountItems];
+    load_run(tv, dv, i0, n, vec, t, d);
 #pragma unroll
-    for (int j = 0; j < kCountItems; ++j) {
-      const uint32_t i = i0 + j;
-      t[j] = i < (uint32_t)n ? (uint32_t)max(tv[i], 0) : 0u;
-      c += t[j] > 0 ? 1u : 0u;
-    }
+    for (int j = 0; j < kCountItems; ++j) c += t[j] > 0 ? 1u : 0u;
     uint32_t r = chunk_off[(size_t)v * gridDim.x + blockIdx.x] +
                  block_exclusive_scan(c, s_wave, nullptr);
 #pragma unroll
     for (int j = 0; j < kCountItems; ++j) {
       if (t[j] > 0) {
-        keys[r] = key((uint32_t)v, dv[i0 + j]);
+        keys[r] = key((uint32_t)v, d[j]);
         vals[r] = cpack >= 0 ? (i0 + j) | (t[j] << cpack) : i0 + j;
         ++r;
       }
