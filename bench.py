@@ -661,11 +661,12 @@ def serve_rates(seq, rates, seconds, warmup, resolutions, seed_base=0, budget=32
 
     from paper_2512_20943_amd import serve
     server = serve.NativeServer(seq, budget_bytes=budget, max_batch=max_batch)
-    # warm both modes (buffer growth, first launches)
+    # warm both modes alike (buffer growth of the workers and of the
+    # single-request renderer both modes share, first launches)
     wt = serve.make_trace(32, 1e6, None, 64, seq.n_frames, 99 + seed_base,
                           resolutions=resolutions)
     server.run(copy.deepcopy(wt))
-    server.run(copy.deepcopy(wt[:4]), plain=True)
+    server.run(copy.deepcopy(wt), plain=True)
     out = {"server": "native (C++ scheduler and worker threads, gs_server_run)",
            "frames": seq.n_frames, "viewers": 64, "budget_gib": budget / 2**30,
            "resident_gib": round(seq.device_bytes() / 2**30, 3), "max_batch": max_batch,

@@ -329,8 +329,9 @@ gs_status gs_project(gs_ctx* ctx, const gs_gaussians* g, const gs_camera* cams_h
  * every (visible Gaussian, tile of its
  * rectangle, or of its per-row spans when the record carries them, see
  * GS_PROJECT_TILE_SPANS) pair is an instance; instances are ordered by
- * (segment, FP32 depth, Gaussian id) with an LDS-resident onesweep radix
- * sort.  Reads the instance count back to the host (blocking).  Returns
+ * (segment, FP32 depth, Gaussian id) with LDS-resident radix sorts that
+ * run inside each view.  Reads the instance count back to the host
+ * (blocking).  Returns
  * GS_ERR_CAPACITY with lists->count = M when M > lists->capacity (nothing
  * else is written).
  * Besides the lists it writes word 14 of each listed record of proj->splat
