@@ -73,14 +73,16 @@ __device__ __forceinline__ void store_row(float (*buf)[kSI], const RowRegs<NP>& 
 // (image row y0 - kR + i), Horiz(in, hs) forms the thread's NS horizontal
 // sums from the staged row (in[q][t + k], k = 0 .. 2 kR, is tap k of plane
 // q); once 2 kR + 1 rows are in, Out(y, vs) receives the vertical sums of
-// output row y = y0 + i - 2 kR.  Centre(i, in) sees every staged row.  The
+// output row y = y0 + i - 2 kR.  Centre(i, in) sees every staged row, and
+// Ahead(i) runs right after the loads of row i + 1 are issued, so that the
+// caller can issue its own loads for the next output row with them.  The
 // next row's loads are in flight while a row is summed; the ring slot of
 // row i is i mod 11, and the rows are unrolled by 11 so that every slot
 // index is static.
-template <int NP, int NS, typename Horiz, typename Out, typename Centre>
+template <int NP, int NS, typename Horiz, typename Out, typename Centre, typename Ahead>
 __device__ __forceinline__ void walk_band(const float* const* src, int W, int H, int x0, int y0,
                                           const Window& win, float (*buf)[NP][kSI], Horiz horiz,
-                                          Out out, Centre centre) {
+                                          Out out, Centre centre, Ahead ahead) {
   const int rows = min(kBand, H - y0) + 2 * kR;  // same for the whole workgroup
   float ring[kTaps][NS];
   RowRegs<NP> nx;
@@ -94,6 +96,7 @@ __device__ __forceinline__ void walk_band(const float* const* src, int W, int H,
       if (i < rows) {
         // the next row's loads go out before this row is summed
         if (i + 1 < rows) load_row<NP>(nx, src, W, H, x0, y0 - kR + i + 1);
+        ahead(i);
         const float (*in)[kSI] = buf[i & 1];
         horiz(in, ring[u]);
         centre(i, in);
@@ -170,7 +173,8 @@ __global__ __launch_bounds__(kSW) void k_ssim_stats(const float* __restrict__ im
         // the L1 term of the band's own rows
         if (i >= kR && i < rows - kR && x < W)
           part += (double)(1.f - lambda) * fabs((double)(in[0][t + kR] - in[1][t + kR]));
-      });
+      },
+      [](int) {});
   for (int off = 32; off >= 1; off >>= 1) part += __shfl_xor(part, off, 64);
   if ((t & 63) == 0) red[t >> 6] = part;
   __syncthreads();
@@ -220,6 +224,10 @@ __global__ __launch_bounds__(kSW) void k_ssim_grad(const float* __restrict__ img
   const int x = x0 + t;
   const float* a = amaps + (size_t)pl * 3 * plane;
   const float* srcs[3] = {a, a + plane, a + 2 * plane};
+  const int rows = min(kBand, H - y0) + 2 * kR;
+  // x and y at this thread's pixel of the next output row, loaded a row
+  // ahead of their use
+  float xa = 0.f, ya = 0.f, xc = 0.f, yc = 0.f;
   walk_band<3, 3>(
       srcs, W, H, x0, y0, win, buf,
       [&](const float (*in)[kSI], float* hs) {
@@ -233,15 +241,26 @@ __global__ __launch_bounds__(kSW) void k_ssim_grad(const float* __restrict__ img
         }
       },
       [&](int y, const float* r) {
+        const float xv = xc, yv = yc;
         if (x >= W) return;
         const size_t p = (size_t)pl * plane + (size_t)y * W + x;
-        const float xv = img[p], yv = tgt[p];
         const float d = xv - yv;
         const float sg = d > 0.f ? 1.f : (d < 0.f ? -1.f : 0.f);
         const float gs = r[0] + 2.f * xv * r[1] + yv * r[2];
         grad[p] = ((1.f - lambda) * sg - lambda * gs) * inv_count;
       },
-      [](int, const float (*)[kSI]) {});
+      [](int, const float (*)[kSI]) {},
+      [&](int i) {
+        // the pixel of output row y0 + i - 2 kR was loaded last round; row
+        // i + 1 (if it yields output) is loaded now
+        xc = xa;
+        yc = ya;
+        if (i + 1 >= 2 * kR && i + 1 < rows && x < W) {
+          const size_t p = (size_t)pl * plane + (size_t)(y0 + i + 1 - 2 * kR) * W + x;
+          xa = img[p];
+          ya = tgt[p];
+        }
+      });
 }
 
 Window make_window() {
