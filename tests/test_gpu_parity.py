@@ -1007,3 +1007,66 @@ def test_lists_bit_exact_with_a_depth_range_beyond_32_bit_keys():
     np.testing.assert_array_equal(L_g["keys"], L_or["keys"])
     np.testing.assert_array_equal(L_g["vals"], L_or["vals"])
     np.testing.assert_array_equal(L_g["ranges"], L_or["ranges"])
+
+
+@pytest.mark.parametrize("tileset", ["rect", "spans"])
+def test_lists_bit_exact_with_views_that_see_nothing(tileset):
+    """Six views, four of them turned away from the scene (first, last and two
+    in a row): the binning sorts run inside each view, so views without a
+    visible Gaussian leave empty ranges in both sorts and their neighbours'
+    partitions must not shift.  Lists and keys are bit-exact against the
+    oracle; the empty views' tiles have empty ranges."""
+    require_gpu()
+    say(f"lists with empty views {tileset}")
+    scene = scenes.make_scene(8_000, 41, -1.0, 1.0, -4.0, 0.5, 0)
+    seen = scenes.arc_cameras(2, 5.0, 96, 64, azimuth_deg=40.0)
+    away = {k: v[:1].copy() for k, v in seen.items()}
+    away["t"] = away["t"] * -3.0  # the scene lies behind this camera
+    order = [away, {k: v[:1] for k, v in seen.items()}, away, away,
+             {k: v[1:] for k, v in seen.items()}, away]
+    cams = {k: np.concatenate([c[k] for c in order]) for k in seen}
+    g, gc, r, out = gpu_forward(scene, cams, capacity=1 << 18, tight_rect=tileset != "rect",
+                                tile_spans=tileset == "spans")
+    P_or = oracle.project(scene, cams, tileset)
+    vis = (P_or["tiles"] > 0).sum(axis=1)
+    assert list(vis > 0) == [False, True, False, False, True, False], vis
+    L_or = oracle.bin_sort(P_or, cams)
+    L_g = lists_to_numpy(out["lists"])
+    assert L_g["count"] == L_or["count"] > 0
+    np.testing.assert_array_equal(L_g["keys"], L_or["keys"])
+    np.testing.assert_array_equal(L_g["vals"], L_or["vals"])
+    np.testing.assert_array_equal(L_g["ranges"], L_or["ranges"])
+    tiles = (96 // 16) * (64 // 16)
+    rg = L_g["ranges"].reshape(6, tiles, 2)
+    assert (rg[[0, 2, 3, 5], :, 0] == rg[[0, 2, 3, 5], :, 1]).all()
+
+
+def _bits_for(count):
+    return max(int(count) - 1, 0).bit_length()
+
+
+@pytest.mark.parametrize("ld", [65_536, 131_072])
+def test_lists_bit_exact_when_tile_and_id_words_do_not_pack(ld):
+    """One 4096x4096 view (65,536 tiles, 16 tile bits).  With ld = 65,536 a
+    Gaussian id (16 bits) and a tile index fit one word but a tile count
+    (17 bits) does not, so the tile sort moves packed words while the depth
+    sort's values carry ids only; with ld = 131,072 neither packs and keys
+    and ids move side by side.  Lists and keys are bit-exact against the
+    oracle either way."""
+    require_gpu()
+    say(f"lists, unpacked words, ld {ld}")
+    scene = scenes.make_scene(5_000, 43, -1.0, 1.0, -4.0, 0.5, 0, ld=ld)
+    cams = scenes.axis_camera(4096, 4096, 4.0)
+    max_tiles = 256 * 256
+    idbits = _bits_for(ld)
+    packed_tiles = idbits + _bits_for(max_tiles) <= 32
+    packed_counts = idbits + _bits_for(max_tiles + 1) <= 32
+    assert (packed_tiles, packed_counts) == ((True, False) if ld == 65_536 else (False, False))
+    g, gc, r, out = gpu_forward(scene, cams, capacity=1 << 20)
+    P_or = oracle.project(scene, cams)
+    L_or = oracle.bin_sort(P_or, cams)
+    L_g = lists_to_numpy(out["lists"])
+    assert L_g["count"] == L_or["count"] > 0
+    np.testing.assert_array_equal(L_g["keys"], L_or["keys"])
+    np.testing.assert_array_equal(L_g["vals"], L_or["vals"])
+    np.testing.assert_array_equal(L_g["ranges"], L_or["ranges"])
