@@ -331,9 +331,8 @@ gs_status gs_project(gs_ctx* ctx, const gs_gaussians* g, const gs_camera* cams_h
  * GS_PROJECT_TILE_SPANS) pair is an instance; instances are ordered by
  * (segment, FP32 depth, Gaussian id) with LDS-resident radix sorts that
  * run inside each view.  Reads the instance count back to the host
- * (blocking).  Returns
- * GS_ERR_CAPACITY with lists->count = M when M > lists->capacity (nothing
- * else is written).
+ * (blocking).  Returns GS_ERR_CAPACITY with lists->count = M when
+ * M > lists->capacity (nothing else is written).
  * Besides the lists it writes word 14 of each listed record of proj->splat
  * (the pair's first instance in emission order, also stored in
  * lists->gv_base when that is given).
