@@ -984,9 +984,10 @@ def test_large_2m_backward_sparse_tiles():
 
 
 def test_lists_bit_exact_with_a_depth_range_beyond_32_bit_keys():
-    """Gaussians from z = 3 to z = 1e9 seen by 20 views: views times the
-    depth-bit range exceed 2^32, so the binning sorts 64-bit (view, depth)
-    keys; lists and keys stay bit-exact against the oracle."""
+    """Gaussians from z = 3 to z = 1e9 seen by 20 views: the view index does
+    not fit above the bits of the depth-bit range in 32 bits, so the binning
+    sorts 64-bit (view, depth) keys (on the depth bits only, inside each
+    view); lists and keys stay bit-exact against the oracle."""
     require_gpu()
     base = scenes.subset(scenes.make_scene(10_000, 7, -1.0, 1.0, -4.0, 0.5, 0), 2000)
     far = [(0.0, 0.0, 1e9), (2e7, 1e7, 1e9), (-3e7, 0.0, 5e8), (0.0, 0.0, 2e9)]
@@ -999,8 +1000,9 @@ def test_lists_bit_exact_with_a_depth_range_beyond_32_bit_keys():
     cams = {k: np.concatenate([v] * 20) for k, v in one.items()}
     g, gc, r, out = gpu_forward(sc, cams)
     P_or = oracle.project(sc, cams)
-    db = P_or["depth_bits"][P_or["tiles"] > 0]
-    assert 20 * (int(db.max()) - int(db.min()) + 2) > 2 ** 32
+    db = P_or["depth_bits"][P_or["tiles"] > 0].astype(np.int64) & 0xFFFFFFFF
+    dbits = (int(db.max()) - int(db.min())).bit_length()  # bits of the range
+    assert (20 << dbits) > 2 ** 32
     L_or = oracle.bin_sort(P_or, cams)
     L_g = lists_to_numpy(out["lists"])
     assert L_g["count"] == L_or["count"] > 0
