@@ -470,9 +470,11 @@ const char* gs_server_last_error(const gs_server* server);
  * t_done (host, n): seconds after the start when the request's batch began
  * and when its image was complete (INFINITY if its batch failed).  images
  * (host array of n device pointers, nullable, entries nullable): request
- * i's (3, H, W) image is copied to images[i].  Returns the first error of
- * any batch (text via gs_server_last_error); the other requests are still
- * served.  Not reentrant on one server. */
+ * i's (3, H, W) image is copied to images[i].  Both modes wait for an
+ * arrival by sleeping until 200 us before it and then polling the clock,
+ * so the calling thread spins for up to that long per arrival.  Returns
+ * the first error of any batch (text via gs_server_last_error); the other
+ * requests are still served.  Not reentrant on one server. */
 gs_status gs_server_run(gs_server* server, const gs_request* reqs, int n, int plain,
                         double* t_start, double* t_done, float* const* images);
 
