@@ -236,16 +236,18 @@ class TrainStep:
 
 class AutogradTrainStep:
     """The same training step written as a user of torch.autograd would: the
-    hand-written backward behind GSRender and the L1 term behind GSL1Loss,
-    loss.backward(), then the Adam kernel on the flat parameter buffer."""
+    hand-written backward behind GSRender and the L1 term behind GSL1Loss
+    (or, ``fused``, both behind GSRenderL1), loss.backward(), then the Adam
+    kernel on the flat parameter buffer."""
 
-    def __init__(self, ts):
+    def __init__(self, ts, fused=False):
         import torch
 
-        from paper_2512_20943_amd.raster import GSL1Loss, GSRender
+        from paper_2512_20943_amd.raster import GSL1Loss, GSRender, GSRenderL1
         self.torch, self.gs, self.ts = torch, ts.gs, ts
         self.ctx = ts.ctx
-        self.GSRender, self.GSL1Loss = GSRender, GSL1Loss
+        self.GSRender, self.GSL1Loss, self.GSRenderL1 = GSRender, GSL1Loss, GSRenderL1
+        self.fused = fused
         self.flat = ts.flat.detach().clone().requires_grad_(True)
         self.m = torch.zeros_like(ts.m)
         self.v = torch.zeros_like(ts.v)
@@ -263,8 +265,11 @@ class AutogradTrainStep:
             cnt = math.prod(shape)
             planes.append(self.flat[o:o + cnt].view(*shape))
             o += cnt
-        image = self.GSRender.apply(*planes, self.meta)
-        loss = self.GSL1Loss.apply(image, self.ts.target, self.ctx)
+        if self.fused:
+            loss = self.GSRenderL1.apply(*planes, self.ts.target, self.meta)
+        else:
+            image = self.GSRender.apply(*planes, self.meta)
+            loss = self.GSL1Loss.apply(image, self.ts.target, self.ctx)
         loss.backward()
         self.gs.gs_adam_step(self.ctx, self.flat.detach(), self.flat.grad, self.m, self.v,
                              self.t)
@@ -856,6 +861,15 @@ def main():
             "path": "GSRender and GSL1Loss torch.autograd.Functions, loss.backward(), Adam",
             "stage_ms_per_step": {k: round(v[0] / k4, 4) for k, v in st4.items() if v[1] > 0}}
         log(f"autograd step: {wall4 / k4 * 1e3:.2f} ms")
+        del ag
+        ag = AutogradTrainStep(ts, fused=True)
+        wall4, _, st4, _ = time_steps(ag, k4, 2)
+        result["autograd_step_fused"] = {
+            "iters_per_s": round(k4 / wall4, 4), "ms_per_step": round(wall4 / k4 * 1e3, 3),
+            "path": "GSRenderL1 torch.autograd.Function (render with the L1 term fused), "
+                    "loss.backward(), Adam",
+            "stage_ms_per_step": {k: round(v[0] / k4, 4) for k, v in st4.items() if v[1] > 0}}
+        log(f"autograd step, fused L1: {wall4 / k4 * 1e3:.2f} ms")
         del ag
     del ts
     torch.cuda.empty_cache()

@@ -142,14 +142,15 @@ class Rasterizer:
 
     def forward_l1(self, g: gs.Gaussians, cams: gs.Cameras, target: torch.Tensor,
                    dL_dimage: torch.Tensor, loss: torch.Tensor, bg=(0.0, 0.0, 0.0), stream=None,
-                   keep_image=False):
+                   keep_image=False, own_buffers=False):
         """Forward with the L1 term of Eq. (1) fused into the compositing:
         dL_dimage written, mean |image - target| added to ``loss``; the image
-        itself is written only with ``keep_image``."""
+        itself is written only with ``keep_image``.  ``own_buffers`` as in
+        ``forward``."""
         W, H = cams.wh[0]
         device = g.mean.device
-        proj = self.project(g, cams, stream)
-        lists = self.bin_sort(proj, cams, stream)
+        proj = self.project(g, cams, stream, own_buffers)
+        lists = self.bin_sort(proj, cams, stream, own_buffers)
         image = torch.empty(cams.V, 3, H, W, device=device) if keep_image else None
         final_T = torch.empty(cams.V, H, W, device=device)
         n_contrib = torch.empty(cams.V, H, W, dtype=torch.int32, device=device)
@@ -158,8 +159,8 @@ class Rasterizer:
             self._ws_l1 = torch.empty(need, dtype=torch.uint8, device=device)
         gs.gs_render_fwd_l1(self.ctx, proj, lists, cams, bg, target.contiguous(), image, final_T,
                             n_contrib, dL_dimage, loss, self._ws_l1, stream)
-        return self._state(False, image=image, final_T=final_T, n_contrib=n_contrib, proj=proj,
-                           lists=lists)
+        return self._state(own_buffers, image=image, final_T=final_T, n_contrib=n_contrib,
+                           proj=proj, lists=lists)
 
     def check_state(self, state: dict):
         """Raise when a forward state's shared buffers were reused since."""
@@ -226,6 +227,38 @@ class GSL1Loss(torch.autograd.Function):
     def backward(ctx, g):
         (grad,) = ctx.saved_tensors
         return grad * g.to(grad.dtype), None, None
+
+
+class GSRenderL1(torch.autograd.Function):
+    """loss = mean |render(mean, log_scale, quat, opacity, sh) - target|, the
+    L1 term of Eq. (1), in one fused forward (gs_render_fwd_l1: the image is
+    never written, dL/dimage comes out of the compositing epilogue); the
+    backward scales that saved gradient by the incoming one and runs the
+    render backward.  No gradient flows to ``target``."""
+
+    @staticmethod
+    def forward(ctx, mean, log_scale, quat, opacity, sh, target, meta):
+        raster, cams, n, deg, bg = meta
+        planes = [t.contiguous() for t in (mean, log_scale, quat, opacity, sh)]
+        g = gs.Gaussians(n, deg, mean.shape[-1], *planes)
+        W, H = cams.wh[0]
+        dimage = torch.empty(cams.V, 3, H, W, device=mean.device)
+        loss = torch.zeros(1, dtype=torch.float64, device=mean.device)
+        out = raster.forward_l1(g, cams, target, dimage, loss, bg, own_buffers=True)
+        ctx.meta = meta
+        ctx.save_for_backward(*planes)
+        ctx.state = out
+        ctx.dimage = dimage
+        return loss[0]
+
+    @staticmethod
+    def backward(ctx, gl):
+        raster, cams, n, deg, bg = ctx.meta
+        g = gs.Gaussians(n, deg, ctx.saved_tensors[0].shape[-1], *ctx.saved_tensors)
+        grad = gs.Gaussians.zeros_like(g)
+        dimage = ctx.dimage.mul_(gl.to(ctx.dimage.dtype))
+        raster.backward(g, cams, ctx.state, dimage, grad, bg)
+        return grad.mean, grad.log_scale, grad.quat, grad.opacity, grad.sh, None, None
 
 
 class GSFrameRender(torch.autograd.Function):
