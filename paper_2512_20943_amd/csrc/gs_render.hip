@@ -384,7 +384,7 @@ __global__ __launch_bounds__(64) void k_render_fwd(
 }
 
 // Forward with the L1 term fused: per tile, the pixels' dL/dimage and the sum
-// of |image - target| (added up by k_l1_tile_sum).
+// of |image - target| (added up by k_l1_chunk_sum and k_l1_chunks_total).
 template <bool COUNT>
 __global__ __launch_bounds__(64) void k_render_fwd_l1(
     const float4* __restrict__ splat, int ld, const uint32_t* __restrict__ vals,
@@ -404,29 +404,41 @@ __global__ __launch_bounds__(64) void k_render_fwd_l1(
                                       n_contrib + pix * v, nullptr, &o, cnt);
 }
 
-// loss += (sum of the per-tile partials) / count, in one block.  Each
-// thread keeps eight independent sums over a fixed stride pattern, so eight
-// loads are in flight at a time and the order of additions is fixed.
-__global__ __launch_bounds__(1024) void k_l1_tile_sum(const double* __restrict__ partial,
-                                                      uint32_t n, double inv_count,
-                                                      double* __restrict__ loss) {
-  __shared__ double s[16];
-  double a[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-  uint32_t i = threadIdx.x;
-  for (; i + 7 * 1024 < n; i += 8 * 1024) {
+// loss += (sum of the per-tile partials) / count in two fixed-order steps:
+// workgroup b adds partials [b chunk, (b + 1) chunk) (each thread a fixed
+// stride pattern, then a tree) and stores the sum over the first of them,
+// which no other workgroup reads; one wave then adds those chunk sums.
+// One workgroup reading all partials was bound by a single CU's bandwidth.
+constexpr int kL1Chunks = 64;
+
+__global__ __launch_bounds__(256) void k_l1_chunk_sum(double* __restrict__ partial, uint32_t n,
+                                                      uint32_t chunk) {
+  __shared__ double s[4];
+  const uint32_t b0 = blockIdx.x * chunk;
+  const uint32_t e = min(b0 + chunk, n);
+  double a[4] = {0.0, 0.0, 0.0, 0.0};
+  uint32_t i = b0 + threadIdx.x;
+  for (; i + 3 * 256 < e; i += 4 * 256) {
 #pragma unroll
-    for (int u = 0; u < 8; ++u) a[u] += partial[i + u * 1024];
+    for (int u = 0; u < 4; ++u) a[u] += partial[i + u * 256];
   }
-  for (int u = 0; i < n; i += 1024, ++u) a[u] += partial[i];
-  double acc = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
+  for (int u = 0; i < e; i += 256, ++u) a[u] += partial[i];
+  double acc = (a[0] + a[1]) + (a[2] + a[3]);
   for (int off = 32; off >= 1; off >>= 1) acc += __shfl_xor(acc, off, 64);
   if ((threadIdx.x & 63) == 0) s[threadIdx.x >> 6] = acc;
   __syncthreads();
-  if (threadIdx.x == 0) {
-    double t = 0.0;
-    for (int w = 0; w < 16; ++w) t += s[w];
-    atomicAdd(loss, t * inv_count);
-  }
+  if (threadIdx.x == 0 && b0 < n) partial[b0] = (s[0] + s[1]) + (s[2] + s[3]);
+}
+
+__global__ __launch_bounds__(64) void k_l1_chunks_total(const double* __restrict__ partial,
+                                                        uint32_t n, uint32_t chunk,
+                                                        uint32_t n_chunks, double inv_count,
+                                                        double* __restrict__ loss) {
+  double acc = 0.0;
+  for (uint32_t c = threadIdx.x; c < n_chunks; c += 64)
+    if (c * chunk < n) acc += partial[(size_t)c * chunk];
+  for (int off = 32; off >= 1; off >>= 1) acc += __shfl_xor(acc, off, 64);
+  if (threadIdx.x == 0) atomicAdd(loss, acc * inv_count);
 }
 
 __global__ __launch_bounds__(64) void k_render_fwd_usage(
@@ -865,8 +877,12 @@ void launch_render_fwd_l1(const gs_projected& proj, const gs_tile_lists& lists, 
                        reinterpret_cast<const uint2*>(lists.ranges), W, H, TX, tpv, bg[0], bg[1],
                        bg[2], image, final_T, n_contrib, target, grad, (float)(1.0 / count),
                        partial, nullptr);
-  hipLaunchKernelGGL(k_l1_tile_sum, dim3(1), dim3(1024), 0, s, (const double*)partial,
-                     (uint32_t)blocks, 1.0 / count, loss);
+  const uint32_t chunk = ((uint32_t)blocks + kL1Chunks - 1) / kL1Chunks;
+  const uint32_t n_chunks = ((uint32_t)blocks + chunk - 1) / chunk;
+  hipLaunchKernelGGL(k_l1_chunk_sum, dim3(n_chunks), dim3(256), 0, s, partial, (uint32_t)blocks,
+                     chunk);
+  hipLaunchKernelGGL(k_l1_chunks_total, dim3(1), dim3(64), 0, s, (const double*)partial,
+                     (uint32_t)blocks, chunk, n_chunks, 1.0 / count, loss);
 }
 
 size_t render_batched_workspace_bytes(int V) {
