@@ -62,10 +62,10 @@ __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t x, uint32_t* s
   return pre + v - x;
 }
 
-// Exclusive scan of row[0, n) in place by one block, 16 consecutive values
-// per thread per round; returns the total (to every thread).
+// Exclusive scan of row[0, n) in place by one block, kIpt consecutive
+// values per thread per round; returns the total (to every thread).
+template <int kIpt = 16>
 __device__ uint32_t block_scan_inplace(uint32_t* __restrict__ row, uint32_t n) {
-  constexpr int kIpt = 16;
   __shared__ uint32_t s_wave[4];
   uint32_t carry = 0;
   for (uint32_t b0 = 0; b0 < n; b0 += kBlock * kIpt) {
@@ -186,7 +186,7 @@ __global__ __launch_bounds__(kBlock) void k_part_scan_rows(uint32_t* __restrict_
                                                            uint32_t pmax,
                                                            const uint32_t* __restrict__ n_parts,
                                                            uint32_t* __restrict__ tot) {
-  const uint32_t t = block_scan_inplace(cnt + (size_t)blockIdx.x * pmax, *n_parts);
+  const uint32_t t = block_scan_inplace<16>(cnt + (size_t)blockIdx.x * pmax, *n_parts);
   if (threadIdx.x == 0) tot[blockIdx.x] = t;
 }
 
@@ -599,11 +599,17 @@ __global__ __launch_bounds__(kBlock) void k_count_reduce(uint32_t N, int ld, uin
   if (threadIdx.x == 0) chunk_sums[blockIdx.x] = tot;
 }
 
-// Exclusive scan of sums[0, nb) in place (one block); total to *total.
+// Exclusive scan of sums[0, nb) in place, 64 values per thread per round
+// (one round up to 16,384 values), total to *total; with a second array
+// (sums2, total2), a second workgroup scans it in the same launch.
 __global__ __launch_bounds__(kBlock) void k_chunk_scan(uint32_t* __restrict__ sums, uint32_t nb,
-                                                       uint32_t* __restrict__ total) {
-  const uint32_t t = block_scan_inplace(sums, nb);
-  if (threadIdx.x == 0) *total = t;
+                                                       uint32_t* __restrict__ total,
+                                                       uint32_t* __restrict__ sums2,
+                                                       uint32_t* __restrict__ total2) {
+  uint32_t* a = blockIdx.x == 0 ? sums : sums2;
+  uint32_t* out = blockIdx.x == 0 ? total : total2;
+  const uint32_t t = block_scan_inplace<64>(a, nb);
+  if (threadIdx.x == 0) *out = t;
 }
 
 // Emit (tile of the view, Gaussian id) for each tile of each depth-sorted
@@ -981,13 +987,12 @@ hipError_t bin_sort_stage1(const BinSortPlan& p, const gs_projected& proj,
   hipLaunchKernelGGL(k_depth_range, dim3(gx, gy), dim3(kBlock), 0, s, p.n, p.ld, p.n_views,
                      proj.depth_bits, proj.tiles_touched, part, vis, icnt);
   hipLaunchKernelGGL(k_stats_reduce, dim3(1), dim3(kBlock), 0, s, part, (int)nchunk, stats);
-  // where each chunk's visible pairs go in the depth sort's input; stats[4]
-  // = their number
-  hipLaunchKernelGGL(k_chunk_scan, dim3(1), dim3(kBlock), 0, s, vis, nchunk, stats + 4);
-  // where each chunk's instances start in emission order, which keeps the
-  // views in order (only read once the host has checked that the total
-  // fits 32 bits)
-  hipLaunchKernelGGL(k_chunk_scan, dim3(1), dim3(kBlock), 0, s, icnt, nchunk, stats + 5);
+  // where each chunk's visible pairs go in the depth sort's input (stats[4]
+  // = their number), and where each chunk's instances start in emission
+  // order, which keeps the views in order (only read once the host has
+  // checked that the total fits 32 bits)
+  hipLaunchKernelGGL(k_chunk_scan, dim3(2), dim3(kBlock), 0, s, vis, nchunk, stats + 4, icnt,
+                     stats + 5);
   return hipGetLastError();
 }
 
@@ -1036,7 +1041,7 @@ void depth_count_emit(const BinSortPlan& p, const gs_projected& proj, const Layo
     hipLaunchKernelGGL((k_count_reduce<K>), dim3(nch), dim3(kBlock), 0, s, N, p.ld, vshift, sk,
                        sv, proj.tiles_touched, cpack, cnt, chunks);
     hipLaunchKernelGGL(k_chunk_scan, dim3(1), dim3(kBlock), 0, s, chunks, nch,
-                       at<uint32_t>(ws, L.total));
+                       at<uint32_t>(ws, L.total), nullptr, nullptr);
   }
   StageScope scope(kStEmit, s);
   hipLaunchKernelGGL((k_emit<K>), dim3(nch), dim3(kBlock), 0, s, N, p.ld, vshift, sk, sv, cnt,
