@@ -533,6 +533,15 @@ __device__ __forceinline__ void visible_keys(int n, int ld, int V,
   }
 }
 
+// Zeroes zero[0, zero_n) over the whole grid (the tile ranges, cleared here
+// to save a launch of their own).
+__device__ __forceinline__ void grid_zero(uint32_t* __restrict__ zero, size_t zero_n) {
+  const size_t nthreads = (size_t)gridDim.x * gridDim.y * kBlock;
+  for (size_t z = ((size_t)blockIdx.y * gridDim.x + blockIdx.x) * kBlock + threadIdx.x;
+       z < zero_n; z += nthreads)
+    zero[z] = 0u;
+}
+
 // 32-bit (view, depth) keys when they fit: view << vshift | (bits - min
 // bits), vshift the bits of the visible depth-bit range.
 __global__ __launch_bounds__(kBlock) void k_depth_keys32(int n, int ld, int V,
@@ -542,7 +551,10 @@ __global__ __launch_bounds__(kBlock) void k_depth_keys32(int n, int ld, int V,
                                                          uint32_t dmin, uint32_t vshift,
                                                          int cpack,
                                                          uint32_t* __restrict__ keys,
-                                                         uint32_t* __restrict__ vals) {
+                                                         uint32_t* __restrict__ vals,
+                                                         uint32_t* __restrict__ zero,
+                                                         size_t zero_n) {
+  grid_zero(zero, zero_n);
   visible_keys<uint32_t>(
       n, ld, V, depth_bits, tiles, chunk_off,
       [=](uint32_t v, uint32_t d) { return (uint32_t)((uint64_t)v << vshift) | (d - dmin); },
@@ -565,7 +577,10 @@ __global__ __launch_bounds__(kBlock) void k_depth_keys(int n, int ld, int V,
                                                        const uint32_t* __restrict__ chunk_off,
                                                        uint32_t dmin, int cpack,
                                                        uint64_t* __restrict__ keys,
-                                                       uint32_t* __restrict__ vals) {
+                                                       uint32_t* __restrict__ vals,
+                                                       uint32_t* __restrict__ zero,
+                                                       size_t zero_n) {
+  grid_zero(zero, zero_n);
   visible_keys<uint64_t>(
       n, ld, V, depth_bits, tiles, chunk_off,
       [=](uint32_t v, uint32_t d) { return ((uint64_t)v << 32) | (d - dmin); }, cpack, keys,
@@ -1001,12 +1016,13 @@ namespace {
 // their dbits low bits, instance offsets and emission into (segk0, v0), or
 // packed into segk0 alone with pack >= 0; vshift is where a 32-bit key's
 // view starts; with cpack >= 0 each pair's tile count rides above bit
-// cpack of its value through the sort.
+// cpack of its value through the sort.  The key gather also clears
+// ranges[0, 2 n_segments).
 template <typename K>
 void depth_count_emit(const BinSortPlan& p, const gs_projected& proj, const Layout& L, void* ws,
                       uint32_t N, uint32_t dmin, uint32_t vshift, int dbits, int cpack,
                       uint32_t* segk0, uint32_t* v0, int pack, uint32_t* gv_base,
-                      hipStream_t s) {
+                      uint32_t* ranges, hipStream_t s) {
   K* k0 = at<K>(ws, L.dk0);
   K* k1 = at<K>(ws, L.dk1);
   uint32_t* dv0 = at<uint32_t>(ws, L.dv0);
@@ -1021,10 +1037,11 @@ void depth_count_emit(const BinSortPlan& p, const gs_projected& proj, const Layo
     if constexpr (sizeof(K) == 4)
       hipLaunchKernelGGL(k_depth_keys32, key_grid, dim3(kBlock), 0, s, p.n, p.ld, p.n_views,
                          proj.depth_bits, proj.tiles_touched, vis_off, dmin, vshift, cpack, k0,
-                         dv0);
+                         dv0, ranges, (size_t)2 * (size_t)p.n_segments);
     else
       hipLaunchKernelGGL(k_depth_keys, key_grid, dim3(kBlock), 0, s, p.n, p.ld, p.n_views,
-                         proj.depth_bits, proj.tiles_touched, vis_off, dmin, cpack, k0, dv0);
+                         proj.depth_bits, proj.tiles_touched, vis_off, dmin, cpack, k0, dv0,
+                         ranges, (size_t)2 * (size_t)p.n_segments);
     const ViewStarts vs{vis_off, key_grid.x, p.n_views};
     which = radix_sort<K>(k0, k1, dv0, dv1, N, dbits, vs, SortSpec{0, nullptr, nullptr}, ws, L,
                           s);
@@ -1055,8 +1072,10 @@ hipError_t bin_sort_stage2(const BinSortPlan& p, const gs_projected& proj,
                            uint32_t N, gs_tile_lists& lists, void* ws, hipStream_t s) {
   (void)cams_dev;
   const Layout L = make_layout(p.n_views, p.ld, p.capacity, p.n_segments);
-  launch_fill_u32(lists.ranges, 0u, 2 * p.n_segments, s);
-  if (M == 0) return hipGetLastError();
+  if (M == 0) {
+    launch_fill_u32(lists.ranges, 0u, 2 * p.n_segments, s);
+    return hipGetLastError();
+  }
   // the tile sort runs inside each view on the bits of its tile index (at
   // least one pass: the last one turns tile indices into segment ids)
   const int sbits = std::max(1, bits_for((uint64_t)p.max_tiles));
@@ -1083,10 +1102,10 @@ hipError_t bin_sort_stage2(const BinSortPlan& p, const gs_projected& proj,
   const int dbits = bits_for((uint64_t)dmax - (uint64_t)dmin + 1u);
   if (((uint64_t)p.n_views << dbits) <= ((uint64_t)1 << 32))
     depth_count_emit<uint32_t>(p, proj, L, ws, N, dmin, (uint32_t)dbits, dbits, cpack, segk0,
-                               v0, pack, lists.gv_base, s);
+                               v0, pack, lists.gv_base, lists.ranges, s);
   else
     depth_count_emit<uint64_t>(p, proj, L, ws, N, dmin, 32u, dbits, cpack, segk0, v0, pack,
-                               lists.gv_base, s);
+                               lists.gv_base, lists.ranges, s);
   int which2;
   {
     StageScope scope(kStSegmentSort, s);
