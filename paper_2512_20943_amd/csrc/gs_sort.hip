@@ -142,6 +142,25 @@ __global__ __launch_bounds__(kBlock) void k_part_desc(const uint32_t* __restrict
   desc[p] = make_uint4((uint32_t)lo, b, min(b + (uint32_t)kPart, e), pf);
 }
 
+// Partition table access.  With one view the table is not built: partition
+// p is [p kPart, min((p + 1) kPart, n1)) of view 0 and there are
+// ceil(n1 / kPart) of them (desc and pfirst are then NULL).
+struct PartTable {
+  const uint4* desc;
+  const uint32_t* pfirst;  // V + 1 entries
+  uint32_t n1;             // element count when desc is NULL
+  int V;
+  __device__ __forceinline__ uint32_t count() const {
+    return desc ? pfirst[V] : (n1 + kPart - 1) / kPart;
+  }
+  __device__ __forceinline__ uint4 at(uint32_t p) const {
+    if (desc) return desc[p];
+    const uint32_t b = p * (uint32_t)kPart;
+    return make_uint4(0u, b, min(b + (uint32_t)kPart, n1), 0u);
+  }
+  __device__ __forceinline__ uint32_t first_of_view(int v) const { return desc ? pfirst[v] : 0u; }
+};
+
 // XCD-aware partition of workgroup b: workgroup b runs on XCD b % 8, and
 // each XCD takes a contiguous range of partitions, so one L2 merges the
 // neighbouring words of the count rows and the adjacent output runs of a
@@ -154,17 +173,15 @@ __device__ __forceinline__ uint32_t xcd_part(uint32_t pmax) {
 // Per-partition digit counts, digit-major: cnt[d * pmax + p].
 template <typename K, int BITS>
 __global__ __launch_bounds__(kBlock) void k_part_count(const K* __restrict__ keys, int shift,
-                                                       uint32_t pmax,
-                                                       const uint32_t* __restrict__ n_parts,
-                                                       const uint4* __restrict__ desc,
+                                                       uint32_t pmax, PartTable pt,
                                                        uint32_t* __restrict__ cnt) {
   constexpr int R = 1 << BITS;
   __shared__ uint32_t h[R];
   const uint32_t part = xcd_part(pmax);
-  if (part >= *n_parts) return;
+  if (part >= pt.count()) return;
   for (int t = threadIdx.x; t < R; t += kBlock) h[t] = 0;
   __syncthreads();
-  const uint4 ds = desc[part];
+  const uint4 ds = pt.at(part);
   K kk[kItems];
 #pragma unroll
   for (int j = 0; j < kItems; ++j) {
@@ -183,10 +200,9 @@ __global__ __launch_bounds__(kBlock) void k_part_count(const K* __restrict__ key
 // Exclusive scan of each digit's row of partition counts over all
 // partitions (one block per digit); the row total goes to tot[d].
 __global__ __launch_bounds__(kBlock) void k_part_scan_rows(uint32_t* __restrict__ cnt,
-                                                           uint32_t pmax,
-                                                           const uint32_t* __restrict__ n_parts,
+                                                           uint32_t pmax, PartTable pt,
                                                            uint32_t* __restrict__ tot) {
-  const uint32_t t = block_scan_inplace<16>(cnt + (size_t)blockIdx.x * pmax, *n_parts);
+  const uint32_t t = block_scan_inplace<16>(cnt + (size_t)blockIdx.x * pmax, pt.count());
   if (threadIdx.x == 0) tot[blockIdx.x] = t;
 }
 
@@ -197,12 +213,13 @@ __global__ __launch_bounds__(kBlock) void k_part_scan_rows(uint32_t* __restrict_
 template <int BITS>
 __global__ __launch_bounds__(kBlock) void k_view_digit_scan(
     const uint32_t* __restrict__ cnt, uint32_t pmax, const uint32_t* __restrict__ tot,
-    const uint32_t* __restrict__ pfirst, const uint32_t* __restrict__ vstart, uint32_t vstride,
-    int V, uint32_t n, uint32_t* __restrict__ dstart) {
+    PartTable pt, const uint32_t* __restrict__ vstart, uint32_t vstride, int V, uint32_t n,
+    uint32_t* __restrict__ dstart) {
   constexpr int R = 1 << BITS, DPT = R / kBlock;
   __shared__ uint32_t s_wave[4];
   const int v = blockIdx.x;
-  const uint32_t P = pfirst[V], a = pfirst[v], b = pfirst[v + 1];
+  const uint32_t P = pt.count(), a = pt.first_of_view(v),
+                 b = pt.desc ? pt.first_of_view(v + 1) : P;
   uint32_t x[DPT], sum = 0;
 #pragma unroll
   for (int i = 0; i < DPT; ++i) {
@@ -232,10 +249,9 @@ __global__ __launch_bounds__(kBlock) void k_view_digit_scan(
 template <typename K, int BITS, bool VALS>
 __global__ __launch_bounds__(kBlock) void k_scatter_pass(
     const K* __restrict__ kin, const uint32_t* __restrict__ vin, K* __restrict__ kout,
-    uint32_t* __restrict__ vout, int shift, uint32_t pmax, const uint32_t* __restrict__ n_parts,
-    const uint4* __restrict__ desc, const uint32_t* __restrict__ pbase,
-    const uint32_t* __restrict__ dstart_v, const uint32_t* __restrict__ add, int ushift,
-    uint32_t umask) {
+    uint32_t* __restrict__ vout, int shift, uint32_t pmax, PartTable pt,
+    const uint32_t* __restrict__ pbase, const uint32_t* __restrict__ dstart_v,
+    const uint32_t* __restrict__ add, int ushift, uint32_t umask) {
   constexpr int R = 1 << BITS, DPT = R / kBlock;
   __shared__ uint32_t s_wh[4][R];
   __shared__ uint32_t s_dstart[R];
@@ -245,8 +261,8 @@ __global__ __launch_bounds__(kBlock) void k_scatter_pass(
   __shared__ uint32_t s_v[VALS ? kPart : 1];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const uint32_t part = xcd_part(pmax);
-  if (part >= *n_parts) return;
-  const uint4 ds = desc[part];
+  if (part >= pt.count()) return;
+  const uint4 ds = pt.at(part);
   const uint32_t view = ds.x, end = ds.z, pf = ds.w;
   for (int t = tid; t < 4 * R; t += kBlock) (&s_wh[0][0])[t] = 0;
   __syncthreads();
@@ -912,13 +928,17 @@ void radix_passes(K* k0, K* k1, uint32_t* v0, uint32_t* v1, uint32_t n, int pass
   uint32_t* dstart = at<uint32_t>(ws, L.dstart);
   uint32_t* pfirst = at<uint32_t>(ws, L.pfirst);
   uint4* desc = at<uint4>(ws, L.pdesc);
-  const uint32_t pmax = (uint32_t)max_parts(n, vs.V);
+  // one view: partitions follow from their index, no table to build
+  const bool one = vs.V == 1;
+  const uint32_t pmax = one ? cdiv(n, kPart) : (uint32_t)max_parts(n, vs.V);
   const uint32_t grid = (pmax + 7) / 8 * 8;  // whole XCD rounds
-  const uint32_t* n_parts = pfirst + vs.V;
-  hipLaunchKernelGGL(k_part_first, dim3(1), dim3(kBlock), 0, s, vs.vstart, vs.vstride, vs.V, n,
-                     pfirst);
-  hipLaunchKernelGGL(k_part_desc, dim3(cdiv(pmax, kBlock)), dim3(kBlock), 0, s, vs.vstart,
-                     vs.vstride, vs.V, n, pfirst, desc);
+  const PartTable pt{one ? nullptr : desc, one ? nullptr : pfirst, n, vs.V};
+  if (!one) {
+    hipLaunchKernelGGL(k_part_first, dim3(1), dim3(kBlock), 0, s, vs.vstart, vs.vstride, vs.V, n,
+                       pfirst);
+    hipLaunchKernelGGL(k_part_desc, dim3(cdiv(pmax, kBlock)), dim3(kBlock), 0, s, vs.vstart,
+                       vs.vstride, vs.V, n, pfirst, desc);
+  }
   K* kb[2] = {k0, k1};
   uint32_t* vb[2] = {v0, v1};
   const uint32_t umask = sp.shift0 >= 32 ? ~0u : ((1u << sp.shift0) - 1u);
@@ -927,19 +947,19 @@ void radix_passes(K* k0, K* k1, uint32_t* v0, uint32_t* v1, uint32_t n, int pass
     const int shift = sp.shift0 + BITS * p;
     const bool last = p == passes - 1;
     hipLaunchKernelGGL((k_part_count<K, BITS>), dim3(grid), dim3(kBlock), 0, s, kb[src], shift,
-                       pmax, n_parts, desc, cnt);
-    hipLaunchKernelGGL(k_part_scan_rows, dim3(R), dim3(kBlock), 0, s, cnt, pmax, n_parts, tot);
+                       pmax, pt, cnt);
+    hipLaunchKernelGGL(k_part_scan_rows, dim3(R), dim3(kBlock), 0, s, cnt, pmax, pt, tot);
     hipLaunchKernelGGL((k_view_digit_scan<BITS>), dim3(vs.V), dim3(kBlock), 0, s, cnt, pmax, tot,
-                       pfirst, vs.vstart, vs.vstride, vs.V, n, dstart);
+                       pt, vs.vstart, vs.vstride, vs.V, n, dstart);
     const uint32_t* add = last ? sp.add_last : nullptr;
     if (v0)
       hipLaunchKernelGGL((k_scatter_pass<K, BITS, true>), dim3(grid), dim3(kBlock), 0, s,
-                         kb[src], vb[src], kb[src ^ 1], vb[src ^ 1], shift, pmax, n_parts, desc,
-                         cnt, dstart, add, 0, 0u);
+                         kb[src], vb[src], kb[src ^ 1], vb[src ^ 1], shift, pmax, pt, cnt, dstart,
+                         add, 0, 0u);
     else
       hipLaunchKernelGGL((k_scatter_pass<K, BITS, false>), dim3(grid), dim3(kBlock), 0, s,
                          kb[src], nullptr, kb[src ^ 1], last ? sp.vout_last : nullptr, shift,
-                         pmax, n_parts, desc, cnt, dstart, add, sp.shift0, umask);
+                         pmax, pt, cnt, dstart, add, sp.shift0, umask);
   }
 }
 
