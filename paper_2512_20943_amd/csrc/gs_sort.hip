@@ -372,18 +372,37 @@ __global__ __launch_bounds__(kBlock) void k_scatter_pass(
 }
 
 // ------------------------------------------------------------ binning
-// Per-view tile geometry from the device cameras: seg_base (V+1), tx (V).
-__global__ void k_view_info(const gs_camera* __restrict__ cams, int V, uint32_t* seg_base,
-                            int32_t* txv) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  uint32_t acc = 0;
-  for (int v = 0; v < V; ++v) {
-    const int tx = tiles_across(cams[v].width), ty = tiles_across(cams[v].height);
-    seg_base[v] = acc;
-    txv[v] = tx;
-    acc += (uint32_t)(tx * ty);
+// Per-view tile geometry from the device cameras, seg_base (V+1) and tx
+// (V), one view per thread with a block scan; also initialises the
+// stage-1 statistics, stats = {min bits, max bits, count lo, hi, visible}
+// (all overwritten when some pair is visible).  One block.
+__global__ __launch_bounds__(kBlock) void k_view_info(const gs_camera* __restrict__ cams, int V,
+                                                      uint32_t* __restrict__ seg_base,
+                                                      int32_t* __restrict__ txv,
+                                                      uint32_t* __restrict__ stats) {
+  __shared__ uint32_t s_wave[4];
+  if (threadIdx.x == 0) {
+    stats[0] = 0xFFFFFFFFu;
+    stats[1] = 0u;
+    stats[2] = 0u;
+    stats[3] = 0u;
+    stats[4] = 0u;
   }
-  seg_base[V] = acc;
+  uint32_t carry = 0;
+  for (int v0 = 0; v0 < V; v0 += kBlock) {
+    const int v = v0 + (int)threadIdx.x;
+    uint32_t nt = 0;
+    if (v < V) {
+      const int tx = tiles_across(cams[v].width), ty = tiles_across(cams[v].height);
+      txv[v] = tx;
+      nt = (uint32_t)(tx * ty);
+    }
+    uint32_t tot;
+    const uint32_t e = block_exclusive_scan(nt, s_wave, &tot);
+    if (v < V) seg_base[v] = carry + e;
+    carry += tot;
+  }
+  if (threadIdx.x == 0) seg_base[V] = carry;
 }
 
 // The tile counts and depth bits of Gaussians i0 .. i0 + kCountItems - 1
@@ -793,16 +812,6 @@ __global__ __launch_bounds__(kBlock) void k_keys64(uint32_t M, int V, int ld,
   keys[j] = ((uint64_t)s << 32) | depth_bits[(size_t)lo * ld + ids[j]];
 }
 
-__global__ void k_stats_init(uint32_t* stats) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) {
-    stats[0] = 0xFFFFFFFFu;
-    stats[1] = 0u;
-    stats[2] = 0u;
-    stats[3] = 0u;
-    stats[4] = 0u;
-  }
-}
-
 __global__ void k_fill_u32(uint32_t* p, uint32_t value, size_t count) {
   for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
        i += (size_t)gridDim.x * blockDim.x)
@@ -1006,9 +1015,8 @@ hipError_t bin_sort_stage1(const BinSortPlan& p, const gs_projected& proj,
   const uint32_t N = (uint32_t)p.n_views * (uint32_t)p.n;
   uint32_t* stats = at<uint32_t>(ws, L.stats);
   *d_stats = stats;
-  hipLaunchKernelGGL(k_view_info, dim3(1), dim3(64), 0, s, cams_dev, p.n_views,
-                     at<uint32_t>(ws, L.seg_base), at<int32_t>(ws, L.txv));
-  hipLaunchKernelGGL(k_stats_init, dim3(1), dim3(1), 0, s, stats);
+  hipLaunchKernelGGL(k_view_info, dim3(1), dim3(kBlock), 0, s, cams_dev, p.n_views,
+                     at<uint32_t>(ws, L.seg_base), at<int32_t>(ws, L.txv), stats);
   if (N == 0) return hipGetLastError();
   StageScope scope(kStDepthSort, s);
   // chunks of kCountChunk Gaussians per view; views on grid rows (beyond
