@@ -251,7 +251,8 @@ __global__ __launch_bounds__(kBlock) void k_scatter_pass(
     const K* __restrict__ kin, const uint32_t* __restrict__ vin, K* __restrict__ kout,
     uint32_t* __restrict__ vout, int shift, uint32_t pmax, PartTable pt,
     const uint32_t* __restrict__ pbase, const uint32_t* __restrict__ dstart_v,
-    const uint32_t* __restrict__ add, int ushift, uint32_t umask) {
+    const uint32_t* __restrict__ tot, const uint32_t* __restrict__ add, int ushift,
+    uint32_t umask) {
   constexpr int R = 1 << BITS, DPT = R / kBlock;
   __shared__ uint32_t s_wh[4][R];
   __shared__ uint32_t s_dstart[R];
@@ -328,12 +329,30 @@ __global__ __launch_bounds__(kBlock) void k_scatter_pass(
       tsum += r;
     }
     uint32_t dstart = block_exclusive_scan(tsum, s_wave, nullptr);
+    // with one view (no partition table) the digit starts are the scan of
+    // the row totals, formed here instead of by a launch of their own
+    uint32_t gstart[DPT];
+    if (!pt.desc) {
+      uint32_t tt[DPT], ts = 0;
+#pragma unroll
+      for (int i = 0; i < DPT; ++i) {
+        tt[i] = tot[tid * DPT + i];
+        ts += tt[i];
+      }
+      uint32_t g = block_exclusive_scan(ts, s_wave, nullptr);
+#pragma unroll
+      for (int i = 0; i < DPT; ++i) {
+        gstart[i] = g;
+        g += tt[i];
+      }
+    }
 #pragma unroll
     for (int i = 0; i < DPT; ++i) {
       const int d = tid * DPT + i;
       const uint32_t* row = pbase + (size_t)d * pmax;
       s_dstart[d] = dstart;
-      s_gbase[d] = dstart_v[(size_t)view * R + d] + (row[part] - row[pf]) - dstart;
+      s_gbase[d] = (pt.desc ? dstart_v[(size_t)view * R + d] : gstart[i]) +
+                   (row[part] - row[pf]) - dstart;
       dstart += run[i];
     }
   }
@@ -937,7 +956,8 @@ void radix_passes(K* k0, K* k1, uint32_t* v0, uint32_t* v1, uint32_t n, int pass
   uint32_t* dstart = at<uint32_t>(ws, L.dstart);
   uint32_t* pfirst = at<uint32_t>(ws, L.pfirst);
   uint4* desc = at<uint4>(ws, L.pdesc);
-  // one view: partitions follow from their index, no table to build
+  // one view: partitions follow from their index, no table to build, and
+  // the scatter scans the digit totals itself
   const bool one = vs.V == 1;
   const uint32_t pmax = one ? cdiv(n, kPart) : (uint32_t)max_parts(n, vs.V);
   const uint32_t grid = (pmax + 7) / 8 * 8;  // whole XCD rounds
@@ -958,17 +978,18 @@ void radix_passes(K* k0, K* k1, uint32_t* v0, uint32_t* v1, uint32_t n, int pass
     hipLaunchKernelGGL((k_part_count<K, BITS>), dim3(grid), dim3(kBlock), 0, s, kb[src], shift,
                        pmax, pt, cnt);
     hipLaunchKernelGGL(k_part_scan_rows, dim3(R), dim3(kBlock), 0, s, cnt, pmax, pt, tot);
-    hipLaunchKernelGGL((k_view_digit_scan<BITS>), dim3(vs.V), dim3(kBlock), 0, s, cnt, pmax, tot,
-                       pt, vs.vstart, vs.vstride, vs.V, n, dstart);
+    if (!one)
+      hipLaunchKernelGGL((k_view_digit_scan<BITS>), dim3(vs.V), dim3(kBlock), 0, s, cnt, pmax,
+                         tot, pt, vs.vstart, vs.vstride, vs.V, n, dstart);
     const uint32_t* add = last ? sp.add_last : nullptr;
     if (v0)
       hipLaunchKernelGGL((k_scatter_pass<K, BITS, true>), dim3(grid), dim3(kBlock), 0, s,
                          kb[src], vb[src], kb[src ^ 1], vb[src ^ 1], shift, pmax, pt, cnt, dstart,
-                         add, 0, 0u);
+                         tot, add, 0, 0u);
     else
       hipLaunchKernelGGL((k_scatter_pass<K, BITS, false>), dim3(grid), dim3(kBlock), 0, s,
                          kb[src], nullptr, kb[src ^ 1], last ? sp.vout_last : nullptr, shift,
-                         pmax, pt, cnt, dstart, add, sp.shift0, umask);
+                         pmax, pt, cnt, dstart, tot, add, sp.shift0, umask);
   }
 }
 
