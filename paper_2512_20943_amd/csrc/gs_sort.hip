@@ -206,41 +206,13 @@ __global__ __launch_bounds__(kBlock) void k_part_scan_rows(uint32_t* __restrict_
   if (threadIdx.x == 0) tot[blockIdx.x] = t;
 }
 
-// Start of each digit inside each view (one block per view):
-// dstart[v * R + d] = start(v) + the view's keys with a smaller digit, the
-// view's count of digit d being the difference of the scanned row at its
-// first partition and at the next view's.
-template <int BITS>
-__global__ __launch_bounds__(kBlock) void k_view_digit_scan(
-    const uint32_t* __restrict__ cnt, uint32_t pmax, const uint32_t* __restrict__ tot,
-    PartTable pt, const uint32_t* __restrict__ vstart, uint32_t vstride, int V, uint32_t n,
-    uint32_t* __restrict__ dstart) {
-  constexpr int R = 1 << BITS, DPT = R / kBlock;
-  __shared__ uint32_t s_wave[4];
-  const int v = blockIdx.x;
-  const uint32_t P = pt.count(), a = pt.first_of_view(v),
-                 b = pt.desc ? pt.first_of_view(v + 1) : P;
-  uint32_t x[DPT], sum = 0;
-#pragma unroll
-  for (int i = 0; i < DPT; ++i) {
-    const int d = threadIdx.x * DPT + i;
-    const uint32_t* row = cnt + (size_t)d * pmax;
-    x[i] = a == b ? 0u : (b < P ? row[b] : tot[d]) - row[a];
-    sum += x[i];
-  }
-  uint32_t run = view_start(vstart, vstride, V, n, v) + block_exclusive_scan(sum, s_wave, nullptr);
-#pragma unroll
-  for (int i = 0; i < DPT; ++i) {
-    dstart[(size_t)v * R + threadIdx.x * DPT + i] = run;
-    run += x[i];
-  }
-}
-
 // One digit pass with bases from the scans: each wave ranks its keys stably
 // by digit with ballots (lanes holding the same digit) and per-wave
 // counters in LDS, the block scatters them through LDS into digit order,
 // and the global writes come out as runs at (the view's digit start + this
-// partition's prefix inside the view).  No partition waits for another.
+// partition's prefix inside the view); the view's digit starts come from
+// the scanned count rows at its first partition and the next view's.  No
+// partition waits for another.
 // With VALS the values move with the keys; without, the keys carry their
 // value in the bits below `shift` of the first pass, and a pass given vout
 // splits each key on the way out: value = key & umask to vout, key >> ushift
@@ -250,8 +222,8 @@ template <typename K, int BITS, bool VALS>
 __global__ __launch_bounds__(kBlock) void k_scatter_pass(
     const K* __restrict__ kin, const uint32_t* __restrict__ vin, K* __restrict__ kout,
     uint32_t* __restrict__ vout, int shift, uint32_t pmax, PartTable pt,
-    const uint32_t* __restrict__ pbase, const uint32_t* __restrict__ dstart_v,
-    const uint32_t* __restrict__ tot, const uint32_t* __restrict__ add, int ushift,
+    const uint32_t* __restrict__ pbase, const uint32_t* __restrict__ tot,
+    const uint32_t* __restrict__ add, int ushift,
     uint32_t umask) {
   constexpr int R = 1 << BITS, DPT = R / kBlock;
   __shared__ uint32_t s_wh[4][R];
@@ -329,31 +301,30 @@ __global__ __launch_bounds__(kBlock) void k_scatter_pass(
       tsum += r;
     }
     uint32_t dstart = block_exclusive_scan(tsum, s_wave, nullptr);
-    // with one view (no partition table) the digit starts are the scan of
-    // the row totals, formed here instead of by a launch of their own
-    uint32_t gstart[DPT];
-    if (!pt.desc) {
-      uint32_t tt[DPT], ts = 0;
+    // the view's digit starts: its start plus the exclusive scan over the
+    // digits of its counts, each the difference of the scanned row at the
+    // view's first partition and at the next view's (the row total past
+    // the last partition); formed here instead of by a launch of their own
+    const uint32_t P = pt.count();
+    const uint32_t pnext = pt.desc ? pt.first_of_view((int)view + 1) : P;
+    const uint32_t vstart0 = ds.y - (part - pf) * (uint32_t)kPart;
+    uint32_t tt[DPT], ts = 0;
 #pragma unroll
-      for (int i = 0; i < DPT; ++i) {
-        tt[i] = tot[tid * DPT + i];
-        ts += tt[i];
-      }
-      uint32_t g = block_exclusive_scan(ts, s_wave, nullptr);
-#pragma unroll
-      for (int i = 0; i < DPT; ++i) {
-        gstart[i] = g;
-        g += tt[i];
-      }
+    for (int i = 0; i < DPT; ++i) {
+      const int d = tid * DPT + i;
+      const uint32_t* row = pbase + (size_t)d * pmax;
+      tt[i] = (pnext < P ? row[pnext] : tot[d]) - row[pf];
+      ts += tt[i];
     }
+    uint32_t g = vstart0 + block_exclusive_scan(ts, s_wave, nullptr);
 #pragma unroll
     for (int i = 0; i < DPT; ++i) {
       const int d = tid * DPT + i;
       const uint32_t* row = pbase + (size_t)d * pmax;
       s_dstart[d] = dstart;
-      s_gbase[d] = (pt.desc ? dstart_v[(size_t)view * R + d] : gstart[i]) +
-                   (row[part] - row[pf]) - dstart;
+      s_gbase[d] = g + (row[part] - row[pf]) - dstart;
       dstart += run[i];
+      g += tt[i];
     }
   }
   __syncthreads();
@@ -868,7 +839,7 @@ inline DigitPlan plan_digits(int key_bits) {
 inline uint32_t cdiv(uint64_t a, uint64_t b) { return (uint32_t)((a + b - 1) / b); }
 
 struct Layout {
-  size_t dk0, dk1, dv0, dv1, cnt, chunks, segk0, segk1, segv_alt, pcount, dtotal, dstart,
+  size_t dk0, dk1, dv0, dv1, cnt, chunks, segk0, segk1, segv_alt, pcount, dtotal,
       pfirst, pdesc, dparts, vparts, iparts, seg_base, txv, total, stats, bytes;
 };
 
@@ -898,10 +869,9 @@ Layout make_layout(int V, int ld, int64_t cap, int64_t nseg) {
   L.segk1 = take((size_t)cap * 4);
   L.segv_alt = take((size_t)cap * 4);
   // per-partition digit counts of one pass (reused by every pass), the row
-  // totals, each view's digit starts, the partition table
+  // totals, the partition table
   L.pcount = take(kMaxDigits * pmax * 4);
   L.dtotal = take(kMaxDigits * 4);
-  L.dstart = take((size_t)V * kMaxDigits * 4);
   L.pfirst = take(((size_t)V + 1) * 4);
   L.pdesc = take(pmax * 16);
   L.seg_base = take(((size_t)V + 1) * 4);
@@ -933,9 +903,10 @@ struct ViewStarts {
 
 // Stable LSD radix sort of (key, value) pairs inside each view on bits
 // [shift0, shift0 + BITS * passes), ping-pong between buffer pair 0 and 1.
-// First the partition table, then per digit pass: per-partition digit
-// counts, their exclusive scan per digit over the partitions, the per-view
-// digit starts, and the ranking + scatter with those bases.  Without values
+// First the partition table (none with one view), then per digit pass:
+// per-partition digit counts, their exclusive scan per digit over the
+// partitions, and the ranking + scatter, which forms its view's digit
+// starts from the scanned counts.  Without values
 // (v0 == NULL) the keys carry them in their low bits and the last pass
 // splits them: key >> shift0 to the key buffer, key & (2^shift0 - 1) to
 // vout_last.  add_last (optional): added per view to the keys the last pass
@@ -953,7 +924,6 @@ void radix_passes(K* k0, K* k1, uint32_t* v0, uint32_t* v1, uint32_t n, int pass
   constexpr int R = 1 << BITS;
   uint32_t* cnt = at<uint32_t>(ws, L.pcount);
   uint32_t* tot = at<uint32_t>(ws, L.dtotal);
-  uint32_t* dstart = at<uint32_t>(ws, L.dstart);
   uint32_t* pfirst = at<uint32_t>(ws, L.pfirst);
   uint4* desc = at<uint4>(ws, L.pdesc);
   // one view: partitions follow from their index, no table to build, and
@@ -978,18 +948,15 @@ void radix_passes(K* k0, K* k1, uint32_t* v0, uint32_t* v1, uint32_t n, int pass
     hipLaunchKernelGGL((k_part_count<K, BITS>), dim3(grid), dim3(kBlock), 0, s, kb[src], shift,
                        pmax, pt, cnt);
     hipLaunchKernelGGL(k_part_scan_rows, dim3(R), dim3(kBlock), 0, s, cnt, pmax, pt, tot);
-    if (!one)
-      hipLaunchKernelGGL((k_view_digit_scan<BITS>), dim3(vs.V), dim3(kBlock), 0, s, cnt, pmax,
-                         tot, pt, vs.vstart, vs.vstride, vs.V, n, dstart);
     const uint32_t* add = last ? sp.add_last : nullptr;
     if (v0)
       hipLaunchKernelGGL((k_scatter_pass<K, BITS, true>), dim3(grid), dim3(kBlock), 0, s,
-                         kb[src], vb[src], kb[src ^ 1], vb[src ^ 1], shift, pmax, pt, cnt, dstart,
-                         tot, add, 0, 0u);
+                         kb[src], vb[src], kb[src ^ 1], vb[src ^ 1], shift, pmax, pt, cnt, tot,
+                         add, 0, 0u);
     else
       hipLaunchKernelGGL((k_scatter_pass<K, BITS, false>), dim3(grid), dim3(kBlock), 0, s,
                          kb[src], nullptr, kb[src ^ 1], last ? sp.vout_last : nullptr, shift,
-                         pmax, pt, cnt, dstart, tot, add, sp.shift0, umask);
+                         pmax, pt, cnt, tot, add, sp.shift0, umask);
   }
 }
 
