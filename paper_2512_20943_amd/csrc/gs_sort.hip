@@ -489,10 +489,10 @@ __global__ __launch_bounds__(kBlock) void k_depth_range(int n, int ld, int V,
 }
 
 // stats = {min bits, max bits, count lo, count hi} over the per-block
-// partials of k_depth_range (one block; device-wide atomics on three
+// partials of k_depth_range, by one block (device-wide atomics on three
 // addresses from every block serialise at the memory side).
-__global__ __launch_bounds__(kBlock) void k_stats_reduce(const uint4* __restrict__ part, int nb,
-                                                         uint32_t* __restrict__ stats) {
+__device__ __forceinline__ void stats_reduce(const uint4* __restrict__ part, int nb,
+                                             uint32_t* __restrict__ stats) {
   __shared__ uint32_t s_min[4], s_max[4];
   __shared__ unsigned long long s_sum[4];
   uint32_t mn = 0xFFFFFFFFu, mx = 0u;
@@ -639,17 +639,29 @@ __global__ __launch_bounds__(kBlock) void k_count_reduce(uint32_t N, int ld, uin
   if (threadIdx.x == 0) chunk_sums[blockIdx.x] = tot;
 }
 
-// Exclusive scan of sums[0, nb) in place, 64 values per thread per round
-// (one round up to 16,384 values), total to *total; with a second array
-// (sums2, total2), a second workgroup scans it in the same launch.
+// Exclusive scan of sums[0, nb) in place (one block), 64 values per thread
+// per round (one round up to 16,384 values); total to *total.
 __global__ __launch_bounds__(kBlock) void k_chunk_scan(uint32_t* __restrict__ sums, uint32_t nb,
-                                                       uint32_t* __restrict__ total,
-                                                       uint32_t* __restrict__ sums2,
-                                                       uint32_t* __restrict__ total2) {
-  uint32_t* a = blockIdx.x == 0 ? sums : sums2;
-  uint32_t* out = blockIdx.x == 0 ? total : total2;
-  const uint32_t t = block_scan_inplace<64>(a, nb);
-  if (threadIdx.x == 0) *out = t;
+                                                       uint32_t* __restrict__ total) {
+  const uint32_t t = block_scan_inplace<64>(sums, nb);
+  if (threadIdx.x == 0) *total = t;
+}
+
+// The end of stage 1 in one launch: block 0 reduces the chunk partials
+// into stats[0..3], blocks 1 and 2 scan the visible-pair and instance
+// counts per chunk (totals to stats[4] and stats[5]).
+__global__ __launch_bounds__(kBlock) void k_stage1_close(const uint4* __restrict__ part,
+                                                         uint32_t* __restrict__ vis,
+                                                         uint32_t* __restrict__ icnt,
+                                                         uint32_t nchunk,
+                                                         uint32_t* __restrict__ stats) {
+  if (blockIdx.x == 0) {
+    stats_reduce(part, (int)nchunk, stats);
+    return;
+  }
+  uint32_t* a = blockIdx.x == 1 ? vis : icnt;
+  const uint32_t t = block_scan_inplace<64>(a, nchunk);
+  if (threadIdx.x == 0) stats[3 + blockIdx.x] = t;
 }
 
 // Emit (tile of the view, Gaussian id) for each tile of each depth-sorted
@@ -1017,13 +1029,12 @@ hipError_t bin_sort_stage1(const BinSortPlan& p, const gs_projected& proj,
   uint32_t* icnt = at<uint32_t>(ws, L.iparts);
   hipLaunchKernelGGL(k_depth_range, dim3(gx, gy), dim3(kBlock), 0, s, p.n, p.ld, p.n_views,
                      proj.depth_bits, proj.tiles_touched, part, vis, icnt);
-  hipLaunchKernelGGL(k_stats_reduce, dim3(1), dim3(kBlock), 0, s, part, (int)nchunk, stats);
-  // where each chunk's visible pairs go in the depth sort's input (stats[4]
-  // = their number), and where each chunk's instances start in emission
-  // order, which keeps the views in order (only read once the host has
-  // checked that the total fits 32 bits)
-  hipLaunchKernelGGL(k_chunk_scan, dim3(2), dim3(kBlock), 0, s, vis, nchunk, stats + 4, icnt,
-                     stats + 5);
+  // the depth-bit range and instance count (stats[0..3]); where each
+  // chunk's visible pairs go in the depth sort's input (stats[4] = their
+  // number), and where each chunk's instances start in emission order,
+  // which keeps the views in order (only read once the host has checked
+  // that the total fits 32 bits)
+  hipLaunchKernelGGL(k_stage1_close, dim3(3), dim3(kBlock), 0, s, part, vis, icnt, nchunk, stats);
   return hipGetLastError();
 }
 
@@ -1074,7 +1085,7 @@ void depth_count_emit(const BinSortPlan& p, const gs_projected& proj, const Layo
     hipLaunchKernelGGL((k_count_reduce<K>), dim3(nch), dim3(kBlock), 0, s, N, p.ld, vshift, sk,
                        sv, proj.tiles_touched, cpack, cnt, chunks);
     hipLaunchKernelGGL(k_chunk_scan, dim3(1), dim3(kBlock), 0, s, chunks, nch,
-                       at<uint32_t>(ws, L.total), nullptr, nullptr);
+                       at<uint32_t>(ws, L.total));
   }
   StageScope scope(kStEmit, s);
   hipLaunchKernelGGL((k_emit<K>), dim3(nch), dim3(kBlock), 0, s, N, p.ld, vshift, sk, sv, cnt,
