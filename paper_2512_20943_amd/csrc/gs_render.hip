@@ -115,6 +115,27 @@ __device__ __forceinline__ uint32_t quadrant_mask(float4 s0, float4 s1, float4 s
   return m;
 }
 
+// Bits 0 and 1 set when some pixel of the quadrant at (ox, oyq), resp.
+// (ox + 8, oyq), could reach alpha >= 1/255: the quadrant_mask test for one
+// row of quadrants (oyq = oy or oy + 8).
+__device__ __forceinline__ uint32_t quadrant_row_mask(float4 s0, float4 s1, float4 s2, float ox,
+                                                      float oyq) {
+  const float A = s0.z, B = s0.w, C = s1.x, dq = s2.z, op = s1.y;
+  const float qmax = 2.f * (kLn255 + __logf(op));
+  const float thr = qmax + 2e-4f * fabsf(qmax) + 1e-3f;
+  if (!(thr > 0.f)) return 0u;
+  const float iA = __builtin_amdgcn_rcpf(A), iC = __builtin_amdgcn_rcpf(C);
+  const float r1 = B * iA, r2 = B * iC, dA = dq * iA, dC = dq * iC;
+  const float v0 = oyq - s0.y;
+  uint32_t m = 0;
+#pragma unroll
+  for (int w = 0; w < 2; ++w) {
+    const float u0 = ox + (float)(w * 8) - s0.x;
+    if (box_min_q(A, C, r1, r2, dA, dC, u0, u0 + 7.f, v0, v0 + 7.f) <= thr) m |= 1u << w;
+  }
+  return m;
+}
+
 template <int CTRL, int ROW_MASK, bool BOUND>
 __device__ __forceinline__ float dpp_take(float x) {
   return __int_as_float(
@@ -128,6 +149,8 @@ __device__ __forceinline__ float dpp_take(float x) {
 // Afterwards, with b_k bit k of (lane & 15), a lane holds its row's sum of
 // value 4 b1 + 2 b2 + b3 when b0 = 0, and of value 8 when b0 = 1.  Must be
 // called with all lanes active; u_k = (lane & (1 << k)) != 0.
+constexpr int kDppMirror = 0x140, kDppHalfMirror = 0x141, kDppSwap2 = 0x4E, kDppSwap1 = 0xB1;
+
 template <int CTRL>
 __device__ __forceinline__ float pair_step(float lo, float hi, bool upper) {
   const float keep = upper ? hi : lo, send = upper ? lo : hi;
@@ -139,16 +162,46 @@ __device__ __forceinline__ float single_step(float v) {
   return v + dpp_take<CTRL, 0xF, true>(v);
 }
 
-__device__ __forceinline__ float row_sums9(const float (&x)[9], bool u3, bool u2, bool u1,
-                                           bool u0) {
-  constexpr int kMirror = 0x140, kHalfMirror = 0x141, kSwap2 = 0x4E, kSwap1 = 0xB1;
-  const float y0 = pair_step<kMirror>(x[0], x[1], u3), y1 = pair_step<kMirror>(x[2], x[3], u3),
-              y2 = pair_step<kMirror>(x[4], x[5], u3), y3 = pair_step<kMirror>(x[6], x[7], u3),
-              y4 = single_step<kMirror>(x[8]);
-  const float z0 = pair_step<kHalfMirror>(y0, y1, u2), z1 = pair_step<kHalfMirror>(y2, y3, u2),
-              z2 = single_step<kHalfMirror>(y4);
-  const float w0 = pair_step<kSwap2>(z0, z1, u1), w1 = single_step<kSwap2>(z2);
-  return pair_step<kSwap1>(w0, w1, u0);
+// pair_step for the two steps whose halves are whole DPP banks (four-lane
+// groups): every lane first adds hi across the pair, then the lanes of the
+// lower half (bank mask) overwrite that with the sum of lo while the others
+// keep it; two instructions per pair instead of two selects and an add.  The
+// wait states before and after cover a DPP read of a register a vector
+// instruction has just written (lo here, the results in the next step).
+__device__ __forceinline__ void pair_steps_mirror(const float (&x)[9], float (&y)[5]) {
+#pragma unroll
+  for (int i = 0; i < 4; ++i) y[i] = single_step<kDppMirror>(x[2 * i + 1]);
+  y[4] = single_step<kDppMirror>(x[8]);
+  asm("s_nop 1\n\t"
+      "v_add_f32_dpp %0, %4, %4 row_mirror row_mask:0xf bank_mask:0x3\n\t"
+      "v_add_f32_dpp %1, %5, %5 row_mirror row_mask:0xf bank_mask:0x3\n\t"
+      "v_add_f32_dpp %2, %6, %6 row_mirror row_mask:0xf bank_mask:0x3\n\t"
+      "v_add_f32_dpp %3, %7, %7 row_mirror row_mask:0xf bank_mask:0x3\n\t"
+      "s_nop 1"
+      : "+v"(y[0]), "+v"(y[1]), "+v"(y[2]), "+v"(y[3])
+      : "v"(x[0]), "v"(x[2]), "v"(x[4]), "v"(x[6]));
+}
+
+__device__ __forceinline__ void pair_steps_half_mirror(const float (&y)[5], float (&z)[3]) {
+  z[0] = single_step<kDppHalfMirror>(y[1]);
+  z[1] = single_step<kDppHalfMirror>(y[3]);
+  z[2] = single_step<kDppHalfMirror>(y[4]);
+  asm("s_nop 1\n\t"
+      "v_add_f32_dpp %0, %2, %2 row_half_mirror row_mask:0xf bank_mask:0x5\n\t"
+      "v_add_f32_dpp %1, %3, %3 row_half_mirror row_mask:0xf bank_mask:0x5\n\t"
+      "s_nop 1"
+      : "+v"(z[0]), "+v"(z[1])
+      : "v"(y[0]), "v"(y[2]));
+}
+
+__device__ __forceinline__ float row_sums9(const float (&x)[9], bool u1, bool u0) {
+  // lanes 0-7 of a row are the lower half of the mirror step (banks 0, 1),
+  // lanes 0-3 and 8-11 that of the half-row mirror step (banks 0, 2)
+  float y[5], z[3];
+  pair_steps_mirror(x, y);
+  pair_steps_half_mirror(y, z);
+  const float w0 = pair_step<kDppSwap2>(z[0], z[1], u1), w1 = single_step<kDppSwap2>(z[2]);
+  return pair_step<kDppSwap1>(w0, w1, u0);
 }
 
 // ---------------------------------------------------------------- forward
@@ -157,6 +210,7 @@ __device__ __forceinline__ float row_sums9(const float (&x)[9], bool u3, bool u2
 // quadrant mask selects slots uniformly across the wave.
 constexpr int kFwdBatch = 64;   // records staged per batch (1 per lane)
 constexpr int kBwdBatch = 32;   // records staged per backward batch
+static_assert(kBwdBatch == 32, "the backward stages one batch with two lanes per entry");
 
 struct FwdShared {
   float4 a[kFwdBatch];
@@ -539,7 +593,6 @@ struct BwdShared {
   float4 a[kBwdBatch];
   float4 b[kBwdBatch];
   float4 c[kBwdBatch];
-  uint32_t m[kBwdBatch];
   uint32_t g[kBwdBatch];
   float A[kBwdBatch];  // conic A, for the mean gradient at flush
   float4 acc4[(kBwdBatch * kAccStride + 3) / 4];
@@ -609,47 +662,66 @@ __global__ __launch_bounds__(64) void k_render_bwd(
     const int lo = hi > kBwdBatch ? hi - kBwdBatch : 0;
     if constexpr (COUNT) wk_staged += (uint32_t)(hi - lo);
     __syncthreads();
-    for (int k = lane; k < kBwdBatch; k += 64) {
+    // lanes k and k + 32 both load entry k; the lower lane stages it and
+    // tests the upper row of quadrants, the other lane the lower row
+    uint32_t qrow = 0;
+    {
+      const int k = lane & (kBwdBatch - 1), h = lane >> 5;
       if (lo + k < hi) {
         const uint32_t g = vals[rg.x + (uint32_t)(lo + k)];
         const float4 q0 = sv[kSplatF4 * (size_t)g], q1 = sv[kSplatF4 * (size_t)g + 1],
                      q2 = sv[kSplatF4 * (size_t)g + 2], q3 = sv[kSplatF4 * (size_t)g + 3];
-        const Rec rr = make_rec(q0, q1, q2);
-        sh.a[k] = rr.a;
-        sh.b[k] = rr.b;
-        sh.c[k] = rr.c;
-        sh.A[k] = q0.z;
-        sh.g[k] = instance_row(q3, tx, ty);
-        sh.m[k] = quadrant_mask(q0, q1, q2, ox, oy);
+        if (h == 0) {
+          const Rec rr = make_rec(q0, q1, q2);
+          sh.a[k] = rr.a;
+          sh.b[k] = rr.b;
+          sh.c[k] = rr.c;
+          sh.A[k] = q0.z;
+          sh.g[k] = instance_row(q3, tx, ty);
+        }
+        qrow = quadrant_row_mask(q0, q1, q2, ox, oy + (float)(8 * h));
+        // past every pixel's last contributor in a quadrant: nothing to do
+        if (lo + k >= (h ? wmax[2] : wmax[0])) qrow &= ~1u;
+        if (lo + k >= (h ? wmax[3] : wmax[1])) qrow &= ~2u;
       }
+    }
+    // bit k of qm[w]: entry lo + k is evaluated in quadrant w
+    uint32_t qm[4];
+    {
+      const unsigned long long b0 = __builtin_amdgcn_ballot_w64((qrow & 1u) != 0);
+      const unsigned long long b1 = __builtin_amdgcn_ballot_w64((qrow & 2u) != 0);
+      qm[0] = (uint32_t)b0;
+      qm[1] = (uint32_t)b1;
+      qm[2] = (uint32_t)(b0 >> 32);
+      qm[3] = (uint32_t)(b1 >> 32);
     }
     for (int t = lane; t < (kBwdBatch * kAccStride + 3) / 4; t += 64)
       sh.acc4[t] = make_float4(0.f, 0.f, 0.f, 0.f);
     __syncthreads();
-    for (int k = hi - lo - 1; k >= 0; --k) {
-      const int j = lo + k;  // position in the tile list
-      uint32_t m = __builtin_amdgcn_readfirstlane(sh.m[k]);
-#pragma unroll
-      for (int w = 0; w < 4; ++w)
-        if (j >= wmax[w]) m &= ~(1u << w);
-      if (m == 0) continue;
+    // entries back to front, only those evaluated somewhere
+    const int lo_u = __builtin_amdgcn_readfirstlane(lo);
+    for (uint32_t todo = qm[0] | qm[1] | qm[2] | qm[3]; todo != 0;) {
+      const int k = 31 - __builtin_clz(todo);
+      todo ^= 1u << k;
+      const int j = lo_u + k;  // position in the tile list
       if constexpr (COUNT) ++wk_visits;
       const float4 a = sh.a[k];
       const float4 b = sh.b[k];
       const float4 c = sh.c[k];
       const float dxl = a.x - fx0, dyt = a.y - fy0;
       float gr[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-      bool contrib = false;
+      unsigned long long contrib = 0;
 #pragma unroll
       for (int w = 0; w < 4; ++w) {
-        if (m & (1u << w)) {
+        if ((qm[w] >> k) & 1u) {
           // per-lane decisions as selects; an unused pair gets alpha 0, which
           // leaves T and B unchanged and contributes nothing
           const float dx = (w & 1) ? dxl - 8.f : dxl;
           const float dy = (w >> 1) ? dyt - 8.f : dyt;
           const float ea = eval_ea(a, row_q(b, dy), dx, dy);
           const float alpha = fminf(kAlphaMax, ea);
-          const bool use = j < nc[w] && alpha >= kAlphaMin;
+          const bool live = j < nc[w], vis = alpha >= kAlphaMin;
+          const bool use = live && vis;
           const float au = use ? alpha : 0.f;
           const float Tk = T[w] * __builtin_amdgcn_rcpf(1.f - au);
           const float wt = au * Tk;
@@ -658,29 +730,32 @@ __global__ __launch_bounds__(64) void k_render_bwd(
           gr[8] = fmaf(g2[w], wt, gr[8]);
           // g . (c - B) with B updated as B + au (c - B)
           const float gcb = fmaf(g2[w], c.x, fmaf(g1[w], b.w, fmaf(g0[w], b.z, -S[w])));
-          const float da = (use && ea < kAlphaMax) ? Tk * gcb : 0.f;
+          // gp = dL/dalpha * alpha = dL/dpower: dL/dalpha = Tk gcb where the
+          // pair is used and alpha is not clamped (then alpha = ea), else 0;
+          // wt = 0 where unused, so only the clamp needs a select
+          const float gp = ea < kAlphaMax ? wt * gcb : 0.f;
           // moments of dL/dpower: the conic and mean gradients are linear in
           // them with per-entry coefficients, applied once per entry at flush
-          const float gp = da * alpha;
           const float u = gp * dx, vv = gp * dy;
           gr[0] += u;
           gr[1] += vv;
           gr[2] = fmaf(u, dx, gr[2]);
           gr[3] = fmaf(u, dy, gr[3]);
           gr[4] = fmaf(vv, dy, gr[4]);
-          gr[5] = fmaf(da, ea, gr[5]);  // times 1/opacity at flush
+          gr[5] += gp;  // dL/dalpha * ea, times 1/opacity at flush
           S[w] = fmaf(au, gcb, S[w]);
           T[w] = Tk;
-          contrib = contrib || use;
+          // the ballots of the two compares, so the masks are used as they are
+          contrib |= __builtin_amdgcn_ballot_w64(live) & __builtin_amdgcn_ballot_w64(vis);
           if constexpr (COUNT) {
             ++wk_slots;
             wk_used += (unsigned long long)__popcll(__builtin_amdgcn_ballot_w64(use));
           }
         }
       }
-      if (__builtin_amdgcn_ballot_w64(contrib) == 0) continue;
+      if (contrib == 0) continue;
       // nine row sums per row, one per lane; the four rows are added at flush
-      const float rs = row_sums9(gr, u3, u2, u1, u0);
+      const float rs = row_sums9(gr, u1, u0);
       if (acc_writer) acc[k * kAccStride + acc_lane] = rs;
     }
     __syncthreads();
