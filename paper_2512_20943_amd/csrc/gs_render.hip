@@ -24,8 +24,6 @@
 // instance's index in the binning's emission order.  A second kernel sums
 // each (view, Gaussian)'s rows, which that order keeps contiguous: no
 // floating-point atomics, and the result does not depend on scheduling.
-#include <type_traits>
-
 #include "gs_internal.h"
 
 namespace gs {
@@ -212,12 +210,14 @@ constexpr int kFwdBatch = 64;   // records staged per batch (1 per lane)
 constexpr int kBwdBatch = 32;   // records staged per backward batch
 static_assert(kBwdBatch == 32, "the backward stages one batch with two lanes per entry");
 
+// c holds the record's blue in .x only: a float4 stride puts it at the
+// same offset from a[k] as b[k], so one address register serves all three
 struct FwdShared {
   float4 a[kFwdBatch];
   float4 b[kFwdBatch];
-  float c[kFwdBatch];
-  uint32_t m[kFwdBatch];
+  float4 c[kFwdBatch];
 };
+static_assert(kFwdBatch == 64, "the forward stages one record per lane");
 
 // Extra staging for per-Gaussian usage counts (composited pixels).
 struct UsageShared {
@@ -294,9 +294,9 @@ __device__ __forceinline__ void render_tile_fwd(FwdShared& sh, UsageShared* us,
   const float ox = (float)(tx * kTile), oy = (float)(ty * kTile);
   for (uint32_t b0 = rg.x; b0 < rg.y && live != 0; b0 += kFwdBatch) {
     __syncthreads();
-#pragma unroll
-    for (int r = 0; r < kFwdBatch / 64; ++r) {
-      const int k = r * 64 + lane;
+    uint32_t qmask = 0;
+    {
+      const int k = lane;
       const uint32_t e = b0 + (uint32_t)k;
       if (e < rg.y) {
         const uint32_t g = vals[e];
@@ -305,25 +305,37 @@ __device__ __forceinline__ void render_tile_fwd(FwdShared& sh, UsageShared* us,
         const Rec rr = make_rec(q0, q1, q2);
         sh.a[k] = rr.a;
         sh.b[k] = rr.b;
-        sh.c[k] = rr.c.x;
-        sh.m[k] = quadrant_mask(q0, q1, q2, ox, oy);
+        sh.c[k].x = rr.c.x;
+        qmask = quadrant_mask(q0, q1, q2, ox, oy);
         if constexpr (USAGE) {
           us->g[k] = g;
           us->u[k] = 0u;
         }
       }
     }
+    // bit k of qm[w]: entry b0 + k is evaluated in slot w (cleared for a
+    // slot once none of its pixels composites any more)
+    unsigned long long qm[4];
+#pragma unroll
+    for (int w = 0; w < 4; ++w)
+      qm[w] = (live >> w) & 1u ? __builtin_amdgcn_ballot_w64((qmask >> w) & 1u) : 0ull;
     __syncthreads();
-    const int nb = (int)((rg.y - b0) < (uint32_t)kFwdBatch ? (rg.y - b0) : (uint32_t)kFwdBatch);
-    if constexpr (COUNT) wk_staged += (uint32_t)nb;
-    for (int k = 0; k < nb; ++k) {
-      const uint32_t m = __builtin_amdgcn_readfirstlane(sh.m[k]) & live;
-      if (m == 0) continue;
+    if constexpr (COUNT) {
+      const uint32_t left = rg.y - b0;
+      wk_staged += left < (uint32_t)kFwdBatch ? left : (uint32_t)kFwdBatch;
+    }
+    // entries front to back, only those evaluated in a live slot
+    for (unsigned long long todo = qm[0] | qm[1] | qm[2] | qm[3]; todo != 0;) {
+      const int k = (int)__builtin_ctzll(todo);
+      todo &= todo - 1;
+      const unsigned long long bit = 1ull << k;
+      const uint32_t m = ((qm[0] & bit) ? 1u : 0u) | ((qm[1] & bit) ? 2u : 0u) |
+                         ((qm[2] & bit) ? 4u : 0u) | ((qm[3] & bit) ? 8u : 0u);
       if constexpr (COUNT) ++wk_visits;
       uint32_t used = 0;
       const float4 a = sh.a[k];
       const float4 b = sh.b[k];
-      const float cb = sh.c[k];
+      const float cb = sh.c[k].x;
       const int pos = (int)(b0 - rg.x) + k + 1;
       int posv;  // pos in a vector register, read by the per-slot selects
       asm("v_mov_b32 %0, %1" : "=v"(posv) : "s"(pos));
@@ -353,7 +365,10 @@ __device__ __forceinline__ void render_tile_fwd(FwdShared& sh, UsageShared* us,
             wk_used += (unsigned long long)__popcll(__builtin_amdgcn_ballot_w64(use));
           }
           if (__builtin_amdgcn_ballot_w64(stop) != 0) {  // once per pixel
-            if (__builtin_amdgcn_ballot_w64(st.T > 0.f) == 0) live &= ~(1u << w);
+            if (__builtin_amdgcn_ballot_w64(st.T > 0.f) == 0) {
+              live &= ~(1u << w);
+              qm[w] = 0;
+            }
           }
         }
       };
@@ -365,6 +380,8 @@ __device__ __forceinline__ void render_tile_fwd(FwdShared& sh, UsageShared* us,
         if (lane == 0 && used) us->u[k] = used;
       }
       if (live == 0) break;
+      // drop the entries left only in slots that stopped at this one
+      todo &= qm[0] | qm[1] | qm[2] | qm[3];
     }
     if constexpr (USAGE) {
       __syncthreads();
@@ -378,7 +395,9 @@ __device__ __forceinline__ void render_tile_fwd(FwdShared& sh, UsageShared* us,
   const size_t pix = (size_t)W * H;
   double l1sum = 0.0;
   auto write = [&](int w, const FwdSlot& st) {
-    const int x = x0 + 8 * (w & 1), y = y0 + 8 * (w >> 1);
+    // the pixel from its float coordinates (exact): the integer ones need
+    // not stay live over the entry loop, which reads only the floats
+    const int x = (int)fx0 + 8 * (w & 1), y = (int)fy0 + 8 * (w >> 1);
     if (!(x < W && y < H)) return;
     const size_t p = (size_t)y * W + x;
     const float Tf = fabsf(st.T);
