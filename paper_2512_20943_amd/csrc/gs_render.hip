@@ -737,7 +737,10 @@ __global__ __launch_bounds__(64) void k_render_bwd(
           // leaves T and B unchanged and contributes nothing
           const float dx = (w & 1) ? dxl - 8.f : dxl;
           const float dy = (w >> 1) ? dyt - 8.f : dyt;
-          const float ea = eval_ea(a, row_q(b, dy), dx, dy);
+          const float dy2 = dy * dy;
+          // t = dx + r1 dy, the coordinate the exponent squares (eval_ea)
+          const float t = fmaf(a.w, dy, dx);
+          const float ea = __builtin_amdgcn_exp2f(fmaf(a.z * t, t, fmaf(b.x, dy2, b.y)));
           const float alpha = fminf(kAlphaMax, ea);
           const bool live = j < nc[w], vis = alpha >= kAlphaMin;
           const bool use = live && vis;
@@ -753,14 +756,15 @@ __global__ __launch_bounds__(64) void k_render_bwd(
           // pair is used and alpha is not clamped (then alpha = ea), else 0;
           // wt = 0 where unused, so only the clamp needs a select
           const float gp = ea < kAlphaMax ? wt * gcb : 0.f;
-          // moments of dL/dpower: the conic and mean gradients are linear in
-          // them with per-entry coefficients, applied once per entry at flush
-          const float u = gp * dx, vv = gp * dy;
-          gr[0] += u;
-          gr[1] += vv;
-          gr[2] = fmaf(u, dx, gr[2]);
-          gr[3] = fmaf(u, dy, gr[3]);
-          gr[4] = fmaf(vv, dy, gr[4]);
+          // moments of dL/dpower in (t, dy), which the exponent already
+          // formed: the conic and mean gradients are linear in them with
+          // per-entry coefficients, applied once per entry at flush
+          const float pt = gp * t;
+          gr[0] += pt;
+          gr[1] = fmaf(gp, dy, gr[1]);
+          gr[2] = fmaf(pt, t, gr[2]);
+          gr[3] = fmaf(pt, dy, gr[3]);
+          gr[4] = fmaf(gp, dy2, gr[4]);
           gr[5] += gp;  // dL/dalpha * ea, times 1/opacity at flush
           S[w] = fmaf(au, gcb, S[w]);
           T[w] = Tk;
@@ -787,6 +791,13 @@ __global__ __launch_bounds__(64) void k_render_bwd(
           const float* r4 = acc + k * kAccStride + 4 * cc;
           mom[cc] = (r4[0] + r4[1]) + (r4[2] + r4[3]);
         }
+        // back from (t, dy) to (dx, dy) with dx = t - r1 dy: the sums of gp
+        // dx, dx^2 and dx dy
+        const float r1 = sh.a[k].w;
+        const float m_t = mom[0], m_tt = mom[2], m_ty = mom[3], m_yy = mom[4];
+        mom[0] = fmaf(-r1, mom[1], m_t);
+        mom[2] = fmaf(-r1, fmaf(-r1, m_yy, 2.f * m_ty), m_tt);
+        mom[3] = fmaf(-r1, m_yy, m_ty);
         // power = -(A dx^2 + C dy^2)/2 - B dx dy with dx = px - x, dy = py - y
         const float A = sh.A[k], B = sh.c[k].z, C = sh.c[k].w;
         float out[9];
