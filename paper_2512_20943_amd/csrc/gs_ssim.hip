@@ -142,12 +142,15 @@ __global__ __launch_bounds__(kSW) void k_ssim_stats(const float* __restrict__ im
         for (int q = 0; q < 5; ++q) hs[q] = 0.f;
 #pragma unroll
         for (int k = 0; k < kTaps; ++k) {
+          // the weighted values once, then each sum one instruction: seven
+          // per tap instead of three products and five multiply-adds
           const float xv = in[0][t + k], yv = in[1][t + k], w = win.w[k];
-          hs[0] = fmaf(w, xv, hs[0]);
-          hs[1] = fmaf(w, yv, hs[1]);
-          hs[2] = fmaf(w, xv * xv, hs[2]);
-          hs[3] = fmaf(w, yv * yv, hs[3]);
-          hs[4] = fmaf(w, xv * yv, hs[4]);
+          const float wx = w * xv, wy = w * yv;
+          hs[0] += wx;
+          hs[1] += wy;
+          hs[2] = fmaf(wx, xv, hs[2]);
+          hs[3] = fmaf(wy, yv, hs[3]);
+          hs[4] = fmaf(wx, yv, hs[4]);
         }
       },
       [&](int y, const float* st) {
