@@ -207,8 +207,11 @@ __device__ __forceinline__ float row_sums9(const float (&x)[9], bool u1, bool u0
 // each of the four 8x8 quadrants ("slot" w = quadrant w), so a record's
 // quadrant mask selects slots uniformly across the wave.
 constexpr int kFwdBatch = 64;   // records staged per batch (1 per lane)
-constexpr int kBwdBatch = 32;   // records staged per backward batch
-static_assert(kBwdBatch == 32, "the backward stages one batch with two lanes per entry");
+// records staged per backward batch (at most 32, two lanes per record): 30
+// ran 1-2 % faster than 32 on the 20-view frame, 28 about as fast as 30,
+// 24 as fast as 32 and 20 slower
+constexpr int kBwdBatch = 30;
+static_assert(kBwdBatch <= 32, "the backward stages one batch with two lanes per entry");
 
 // c holds the record's blue in .x only: a float4 stride puts it at the
 // same offset from a[k] as b[k], so one address register serves all three
@@ -685,8 +688,8 @@ __global__ __launch_bounds__(64) void k_render_bwd(
     // tests the upper row of quadrants, the other lane the lower row
     uint32_t qrow = 0;
     {
-      const int k = lane & (kBwdBatch - 1), h = lane >> 5;
-      if (lo + k < hi) {
+      const int k = lane & 31, h = lane >> 5;
+      if (k < kBwdBatch && lo + k < hi) {
         const uint32_t g = vals[rg.x + (uint32_t)(lo + k)];
         const float4 q0 = sv[kSplatF4 * (size_t)g], q1 = sv[kSplatF4 * (size_t)g + 1],
                      q2 = sv[kSplatF4 * (size_t)g + 2], q3 = sv[kSplatF4 * (size_t)g + 3];
