@@ -4,24 +4,27 @@
 // One 64-lane wave (one workgroup) per 16x16 tile.  Lane l owns pixel
 // (l & 7, l >> 3) of each of the tile's four 8x8 quadrants ("slots"), so a
 // slot is a compact 64-pixel block.  The tile's instance list is walked in
-// batches staged in LDS, one record per lane.  While staging a record, its
-// lane also tests the Gaussian's alpha >= 1/255 ellipse against each
-// quadrant's pixel box (exact box minimum of the quadratic form, with a
-// conservative margin): the wave skips, uniformly, every slot whose quadrant
-// the ellipse misses, which is exact because every such pair would be
-// skipped per pixel anyway.  A slot whose 64 pixels have all stopped is
-// dropped with a ballot; the tile ends when all four have.
+// batches staged in LDS (the forward one record per lane, the backward one
+// per two lanes).  While staging a record, its lane also tests the
+// Gaussian's alpha >= 1/255 ellipse against each quadrant's pixel box (exact
+// box minimum of the quadratic form, with a conservative margin); the
+// results are kept as one wave ballot per quadrant, and the wave walks the
+// set bits, skipping, uniformly, every slot whose quadrant the ellipse
+// misses, which is exact because every such pair would be skipped per pixel
+// anyway.  A slot whose 64 pixels have all stopped is dropped with a ballot;
+// the tile ends when all four have.
 //
 // The backward walks each pixel's list back to front from its last
 // contributor, recovering T_k = T_{k+1} / (1 - alpha_k); alpha is recomputed
 // by the same device functions as in the forward, so every skip and stop
 // decision is bit-identical.  Per entry it accumulates, per lane, the colour
-// gradients and five moments of dL/dpower (the mean and conic gradients are
-// linear in them with per-entry coefficients), sums the nine values over each
-// 16-lane row with DPP exchanges that leave one row sum per lane (27 adds and
-// selects, one LDS store), adds the four row sums when the batch is flushed,
-// and writes one 9-float gradient row per (tile, Gaussian) at the
-// instance's index in the binning's emission order.  A second kernel sums
+// gradients and five moments of dL/dpower in the exponent's coordinates (the
+// mean and conic gradients are linear in them with per-entry coefficients),
+// sums the nine values over each 16-lane row with DPP exchanges that leave
+// one row sum per lane (22 instructions, one LDS store), adds the four row
+// sums when the batch is flushed, and writes one 9-float gradient row per
+// (tile, Gaussian) at the instance's index in the binning's emission order.
+// A second kernel sums
 // each (view, Gaussian)'s rows, which that order keeps contiguous: no
 // floating-point atomics, and the result does not depend on scheduling.
 #include "gs_internal.h"
